@@ -1,0 +1,278 @@
+/*
+ * smppi.h -- C ABI of the MI355X (gfx950) Shield-MPPI sampled-rollout library.
+ *
+ * Paper: Yin, Dawson, Fan, Tsiotras, "Shield Model Predictive Path Integral: A
+ * Computationally Efficient Robust MPC Method Using Control Barrier Functions"
+ * (arXiv 2302.11719).  Notation: K samples per problem, T horizon steps, B
+ * independent problems (the paper writes M for samples and K for the horizon).
+ *
+ * Conventions for every call
+ *  - Pointers marked "device" are caller-owned device memory on the ctx's device
+ *    (for instance torch tensors' data pointers), contiguous, of the element type
+ *    named; "dtype" means float for SMPPI_F32 and double for SMPPI_F64.  The
+ *    library never frees or retains caller memory beyond the call (plans keep the
+ *    pointers they were created with, see smppi_plan_create).
+ *  - Struct arguments are host memory, read during the call only.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is
+ *    enqueued on it and the call returns without synchronising.  Validation
+ *    errors are detected before anything is enqueued.  Faults inside kernels
+ *    surface at the caller's next synchronisation.
+ *  - Scratch memory is owned by the ctx and grown on demand (a call that needs
+ *    more than the ctx holds allocates before it enqueues work; smppi_reserve
+ *    pre-sizes it).  A ctx is not thread-safe, and calls made on one ctx must be
+ *    ordered on one stream: they share the ctx's scratch.
+ *  - The library never aborts and never prints; smppi_last_error() describes the
+ *    last non-OK status of a ctx.
+ *
+ * Layouts (per problem b, with K_b = k_off[b+1]-k_off[b], T_b = t_off[b+1]-t_off[b]):
+ *  - state x: 6 values (p_x, p_y, psi, v_x, v_y, omega); x0 is [B][6].
+ *  - control sequence V: 2*T_b values at offset 2*t_off[b], steer row first:
+ *    V[2*t_off[b] + d*T_b + t], d = 0 steer, d = 1 throttle.
+ *  - per-sample arrays (S, w, grad_S) are indexed by k_off[b] + m.
+ */
+#ifndef SMPPI_H
+#define SMPPI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SMPPI_ABI_VERSION 1
+
+typedef enum {
+  SMPPI_OK = 0,
+  SMPPI_ERR_INVALID_ARGUMENT = 1, /* null pointer, bad parameter value */
+  SMPPI_ERR_SHAPE = 2,            /* sizes inconsistent or beyond a supported bound */
+  SMPPI_ERR_DTYPE = 3,            /* dtype not supported by this call */
+  SMPPI_ERR_NO_DEVICE = 4,        /* no HIP device (or not the one asked for) */
+  SMPPI_ERR_HIP = 5,              /* a HIP runtime call failed; see smppi_last_error */
+  SMPPI_ERR_UNSUPPORTED = 6,      /* valid request this build does not implement */
+  SMPPI_ERR_NONFINITE = 7         /* reserved: non-finite input detected on the host */
+} smppi_status;
+
+typedef enum { SMPPI_F32 = 0, SMPPI_F64 = 1 } smppi_dtype;
+
+typedef struct smppi_ctx_s* smppi_ctx;
+typedef struct smppi_plan_s* smppi_plan;
+
+/* Dynamics x_{k+1} = f(x_k, u_k) of eq. (1), realised as a six-state dynamic
+ * single-track vehicle with linear tyres integrated by classic RK4 over dt with
+ * the control held:
+ *   dp_x = v_x cos(psi) - v_y sin(psi),   dp_y = v_x sin(psi) + v_y cos(psi),
+ *   dpsi = omega,
+ *   dv_x = a_max tau - c_v v_x - F_f sin(delta)/m + v_y omega,
+ *   dv_y = (F_f cos(delta) + F_r)/m - v_x omega,
+ *   domega = (l_f F_f cos(delta) - l_r F_r)/I_z,
+ *   F_f = C_f (delta - (v_y + l_f omega)/v~),  F_r = -C_r (v_y - l_r omega)/v~,
+ *   v~ = max(v_x, v_min).
+ * Sampled controls are clipped to [u_lo, u_hi] (steer, throttle). */
+typedef struct {
+  double m, lf, lr, Iz, Cf, Cr, a_max, c_v, v_min, dt;
+  double u_lo[2], u_hi[2];
+} smppi_model;
+
+/* Trajectory cost (Algorithm 2; eqs. (8), (12), (17)-(20), (23)-(25)):
+ *   S~ = sum_{k<T} [ q(x_k) + lambda_u sum_d v_{k,d} u_{k,d} / sigma_d^2 ]
+ *        + phi_w q(x_T) + sum_{k=0}^{T} C_cbf(z_k),
+ *   q(x) = q_v (v_x - v_g)^2 + q_ey e_y^2 + C_obs [x outside the safe region],
+ *   C_cbf(z_k) = C_cbf sum_j max(alpha h_j(x_{k-1}) - h_j(x_k), 0), x_{-1} = x_0,
+ *   alpha = 1 - gamma (gamma is the class-kappa slope of eq. (15)).
+ * Barriers: h_0 = w^2 - e_y^2 (eq. (23)); per obstacle h_i = |p - c_i|^2 - r_eff_i^2.
+ * "Outside" = h_0 < 0 or inside any obstacle's physical radius.
+ * sigma also scales the sampled noise: eps = sigma (.) z, z ~ N(0, I). */
+typedef struct {
+  double v_g, q_v, q_ey, C_obs, phi_w;
+  double lambda_u;
+  double sigma[2];
+  double C_cbf, gamma;
+} smppi_cost;
+
+/* Noise: Philox4x32-10 (Salmon et al., SC'11) with key (seed, 0) and counter
+ * (t>>1, m, pid_base + b, iter[b]); words (0,1) feed step 2j and (2,3) step 2j+1
+ * through u = ((x>>8)+1) 2^-24 and Box-Muller (first normal steers).
+ * nominal != 0 replaces every sample's noise by zero (nominal rollouts). */
+typedef struct {
+  uint32_t seed;
+  int32_t nominal;
+} smppi_noise;
+
+/* A batch of B independent problems in CSR form. */
+typedef struct {
+  int32_t n_problems;   /* B >= 1 */
+  int32_t k_max;        /* host: max K_b (launch sizing); every K_b <= k_max */
+  int32_t t_max;        /* host: max T_b; every T_b <= t_max, 1 <= T_b */
+  int32_t pid_base;     /* problem id of problem 0 in the noise counter */
+  smppi_dtype dtype;
+  const int64_t* k_off; /* device [B+1], k_off[0] = 0, non-decreasing */
+  const int32_t* t_off; /* device [B+1], t_off[0] = 0, strictly increasing */
+} smppi_batch;
+
+/* Per-problem track: a circle (when the problem has no polyline vertices) or a
+ * closed polyline; e_y^2 is the squared distance to the nearest segment, found
+ * by a global search at x_0 and afterwards within +-window segments of the
+ * previous step's segment (offsets visited 0, -1, +1, -2, ...; first strict
+ * minimum wins). */
+typedef struct {
+  const int32_t* poly_off;  /* device [B+1] vertex offsets */
+  const void* poly;         /* device [sum N][5] dtype: a_x, a_y, d_x, d_y, 1/|d|^2 */
+  const void* circle;       /* device [B][3] dtype: c_x, c_y, R (used when N_b = 0) */
+  const void* half_width;   /* device [B] dtype: w */
+  const int32_t* obs_off;   /* device [B+1] obstacle offsets, or NULL for none */
+  const void* obs;          /* device [sum O][4] dtype: c_x, c_y, r_eff^2, r^2 */
+  int32_t window;           /* search half width, 1 <= window, 2*window+1 <= N_b */
+  int32_t poly_max;         /* host: max N_b (<= 4096) */
+  int32_t obs_max;          /* host: max O_b (<= 64) */
+} smppi_track;
+
+/* Differentiated objective of one trajectory (used by the adjoint and repair):
+ *   L = w_S S~' + w_sq sum_{j,t<T} viol_{j,t}^2 + w_lin sum_{j, t<n_lin} viol_{j,t},
+ *   viol_{j,t} = max(alpha h_j(x_t) - h_j(x_{t+1}), 0),
+ * S~' = S~ without the (piecewise constant) collision indicator.  The shield of
+ * Algorithm 1 / eq. (22) is w_S = w_sq = 0, w_lin = 1, n_lin = N+1. */
+typedef struct {
+  double w_S, w_sq, w_lin;
+  int32_t n_lin;
+} smppi_objective;
+
+/* Safety shield (Algorithm 1) as projected gradient descent on the objective
+ * evaluated on the nominal trajectory from x0: n_steps times
+ * V <- clip(V - step * dL/dV, u_lo, u_hi). */
+typedef struct {
+  int32_t n_steps;
+  double step;
+  smppi_objective objective;
+} smppi_repair_opts;
+
+/* ---- context ---------------------------------------------------------------- */
+
+/* Create a ctx bound to HIP device `device`.  SMPPI_ERR_NO_DEVICE when no GPU. */
+smppi_status smppi_create(int device, smppi_ctx* out);
+void smppi_destroy(smppi_ctx ctx);
+const char* smppi_last_error(smppi_ctx ctx);
+const char* smppi_status_string(smppi_status s);
+int smppi_abi_version(void);
+/* Pre-size the ctx scratch to at least `bytes` (optional). */
+smppi_status smppi_reserve(smppi_ctx ctx, uint64_t bytes);
+/* Synchronise the device, return (and clear) the OR of the input-bound errors
+ * kernels detected on device data since the last call: 1 = some T_b outside
+ * [1, t_max], 2 = some K_b outside [0, k_max], 4 = some polyline longer than
+ * poly_max or shorter than 2*window+1, 8 = more than obs_max obstacles.
+ * Problems with such data are skipped (their outputs are left unwritten). */
+smppi_status smppi_device_errors(smppi_ctx ctx, uint32_t* flags);
+
+/* ---- the sampled-rollout step ---------------------------------------------- */
+
+/* Sampling and cost of Algorithm 2's inner loop (eqs. (8), (12), (20)): for every
+ * problem b and sample m < K_b, draw eps, clip u = v + eps, integrate f over T_b
+ * steps from x0[b] and write S~ to S[k_off[b]+m] (dtype).
+ * x0: device [B][6] dtype.  V: device control sequences (layout above).
+ * iter: device [B] uint32 iteration counters (noise counter word 3).
+ * eps_out: NULL, or device [sum K][t_max][2] dtype receiving the effective
+ *   noise u - v of every step (debug/test; rows beyond T_b untouched). */
+smppi_status smppi_rollout(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                           const smppi_cost* cost, const smppi_noise* noise, const smppi_track* track,
+                           const void* x0, const void* V, const uint32_t* iter, void* S, void* eps_out,
+                           void* stream);
+
+/* Path-integral weights (eqs. (7), (9), (11)): w_m = exp(-(S_m - min S)/lambda)
+ * / sum, per problem, with non-finite S_m given weight 0.
+ * w: device [sum K] dtype.  stats: device [B][4] dtype = (min S, log sum_m
+ * exp(-(S_m - min S)/lambda), effective sample size 1/sum w^2, number of
+ * non-finite costs); when every cost is non-finite all weights are 0.
+ * lambda > 0. */
+smppi_status smppi_weights(smppi_ctx ctx, const smppi_batch* batch, const void* S, double lambda, void* w,
+                           void* stats, void* stream);
+
+/* Update law (eq. (10) with the per-trajectory weights of eq. (11)):
+ * V+ = V + sum_m w_m (clip(V + eps_m) - V), the noise regenerated from the same
+ * counters as smppi_rollout.  V_plus may equal V (in place). */
+smppi_status smppi_update(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                          const smppi_cost* cost, const smppi_noise* noise, const void* V, const void* w,
+                          const uint32_t* iter, void* V_plus, void* stream);
+
+/* Adjoint rollout: grad_V = sum_m grad_S[m] dL_m/dV for the objective above,
+ * where sample m's trajectory uses the same noise as smppi_rollout.  States are
+ * recomputed from per-sample checkpoints instead of being stored.  grad_V has the
+ * layout of V (dtype).  Gradients pass through the clip where it is inactive and
+ * through the hinge where it is active (one-sided at ties). */
+smppi_status smppi_rollout_backward(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                                    const smppi_cost* cost, const smppi_noise* noise,
+                                    const smppi_track* track, const void* x0, const void* V,
+                                    const uint32_t* iter, const void* grad_S,
+                                    const smppi_objective* objective, void* grad_V, void* stream);
+
+/* Safety shield (Algorithm 1, eq. (22)): V_safe = repair of V_plus from x0 (see
+ * smppi_repair_opts).  V_safe may equal V_plus. */
+smppi_status smppi_shield_repair(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                                 const smppi_cost* cost, const smppi_track* track, const void* x0,
+                                 const void* V_plus, const smppi_repair_opts* opts, void* V_safe,
+                                 void* stream);
+
+/* Execute and warm start (Algorithm 2, last two lines; disturbed plant of eq.
+ * (26)): x[b] <- RK4(x[b], first control of V_exec) + (0,0,0,0,dist_vy,dist_om),
+ * V[b] <- V_plus[b] shifted one step (last step repeated), iter[b] += 1.
+ * dist: NULL or device [n_dist][B][2] dtype; row iter[b] (before the increment)
+ * is used when iter[b] < n_dist, otherwise no disturbance. */
+smppi_status smppi_execute(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                           const void* V_exec, const void* V_plus, const void* dist, int32_t n_dist,
+                           void* x, void* V, uint32_t* iter, void* stream);
+
+/* ---- batched plan: one persistent fused launch, captured in a HIP graph ------ */
+
+typedef struct {
+  double lambda;             /* softmax temperature */
+  int32_t repair;            /* nonzero: run the shield after the update */
+  smppi_repair_opts repair_opts;
+  int32_t execute;           /* nonzero: run smppi_execute after (V_exec = V_safe or V_plus) */
+  const void* dist;          /* as smppi_execute */
+  int32_t n_dist;
+  int32_t block;             /* threads per workgroup (64, 128, 256 or 512); 0 = 256 */
+  int32_t tile;              /* samples per tile (multiple of block); 0 = block */
+  int32_t grid;              /* persistent workgroups; 0 = chosen from occupancy */
+  int32_t use_graph;         /* nonzero: capture into a hipGraph at creation */
+} smppi_plan_opts;
+
+/* Buffers a plan reads and writes on every launch (device pointers, dtype F32):
+ * x0 [B][6] (state; advanced in place when execute is set), V (controls; replaced
+ * by the warm start when execute is set, else read only), iter [B] (incremented
+ * when execute is set), S [sum K] out, V_plus out, stats [B][4] out, V_safe out
+ * (NULL when repair is off). */
+typedef struct {
+  void* x0;
+  void* V;
+  uint32_t* iter;
+  void* S;
+  void* V_plus;
+  void* stats;
+  void* V_safe;
+} smppi_plan_buffers;
+
+/* Build a plan for `batch` (which must stay valid, with its device arrays, for
+ * the plan's life): tile list in longest-first order, per-problem ticket
+ * counters, and (use_graph) the captured graph.  The first launch of a plan
+ * resets nothing the caller owns. */
+smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                               const smppi_cost* cost, const smppi_noise* noise, const smppi_track* track,
+                               const smppi_plan_opts* opts, const smppi_plan_buffers* bufs,
+                               smppi_plan* out);
+/* One MPPI iteration of every problem: rollout, weights and update fused in one
+ * persistent launch, then (optionally) the shield and the execute/warm start. */
+smppi_status smppi_plan_launch(smppi_plan plan, void* stream);
+void smppi_plan_destroy(smppi_plan plan);
+/* Launch geometry the plan uses (any output pointer may be NULL). */
+smppi_status smppi_plan_info(smppi_plan plan, int32_t* grid, int32_t* block, int32_t* tile, int32_t* n_tiles);
+
+/* ---- test hooks: the device generator, evaluated on its own ---------------- */
+
+/* out[4*i + j] = word j of Philox4x32-10(ctr[4*i .. 4*i+3], key = key[0..1]).
+ * ctr: device [n][4] uint32; out: device [n][4] uint32. */
+smppi_status smppi_debug_philox(smppi_ctx ctx, const uint32_t* ctr, const uint32_t* key_host, int64_t n,
+                                uint32_t* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMPPI_H */

@@ -31,7 +31,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "smppi_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
-_ABI = 3
+_ABI = 4
 _lock = threading.Lock()
 _lib = None
 
@@ -143,9 +143,14 @@ def lateral_sq(track, px: float, py: float, idx: int = -1):
 
 # --------------------------------------------------------------------------- MPPI step
 def rollout(model, cost, track, x0, V, K: int, seed: int, pid: int, it: int, nominal: bool = False,
-            want_eps: bool = True, n_threads: int = 1):
-    """Per-sample modified costs S~ [K], effective noise eps' [K][T][2], indicator margins [K]."""
+            want_eps: bool = True, n_threads: int = 1, samples=None):
+    """Per-sample modified costs S~ [K], effective noise eps' [K][T][2], indicator margins [K].
+    With `samples` (sample indices), evaluates just those samples (K is ignored)."""
     V = np.ascontiguousarray(V, dtype=np.float64).reshape(-1, 2)
+    ms = None
+    if samples is not None:
+        ms = np.ascontiguousarray(samples, dtype=np.uint32)
+        K = len(ms)
     T = V.shape[0]
     S = np.zeros(K)
     margin = np.zeros(K)
@@ -154,7 +159,8 @@ def rollout(model, cost, track, x0, V, K: int, seed: int, pid: int, it: int, nom
     x0 = np.ascontiguousarray(x0, dtype=np.float64)
     lib().or_rollout(_p(mp), _p(cp), *ta.args(), _p(x0), _p(V), ctypes.c_int(K), ctypes.c_int(T),
                      ctypes.c_uint32(seed), ctypes.c_uint32(pid), ctypes.c_uint32(it), ctypes.c_int(int(nominal)),
-                     _p(S), _p(eps) if want_eps else None, _p(margin), ctypes.c_int(n_threads))
+                     _p(ms, np.uint32) if ms is not None else None, _p(S), _p(eps) if want_eps else None,
+                     _p(margin), ctypes.c_int(n_threads))
     return S, eps, margin
 
 
@@ -244,7 +250,9 @@ def trajectory(model, cost, track, x0, V, eps=None):
 
 
 def execute(model, x, u0, dist=None) -> np.ndarray:
-    """Disturbed plant of eq. (26): x+ = f(x, u0) + w, with w acting on v_y and omega."""
+    """Disturbed plant of eq. (26): x+ = f(x, u0) + w, with w acting on v_y and omega.
+    The executed command is held inside the control box."""
+    u0 = np.clip(np.asarray(u0, dtype=np.float64), model["u_lo"], model["u_hi"])
     xn = rk4(model, x, u0, model["dt"], 1)
     if dist is not None:
         xn[4] += dist[0]

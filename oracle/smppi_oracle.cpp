@@ -420,7 +420,7 @@ void sample_noise(const Cost& C, uint32_t seed, uint32_t pid, uint32_t it, uint3
 // ===========================================================================
 extern "C" {
 
-int or_abi_version(void) { return 3; }
+int or_abi_version(void) { return 4; }
 
 void or_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { philox4x32_10(ctr, key, out); }
 
@@ -455,18 +455,21 @@ double or_lateral_sq(int kind, const double* circle, const double* poly, int n_p
 }
 
 // Rollout of K samples of one problem (Algorithm 2, inner loop).
-//   V: [T][2]; S: [K]; eps_eff: [K][T][2] or null; margin: [K] or null.
+//   V: [T][2]; S: [K]; eps_eff: [K][T][2] or null; margin: [K] or null;
+//   ms: null (samples 0..K-1) or the K sample indices to evaluate.
 void or_rollout(const double* mp, const double* cp, int kind, const double* circle, const double* poly,
                 int n_poly, double half_width, const double* obs, int n_obs, int window,
                 const double* x0, const double* V, int K, int T, uint32_t seed, uint32_t pid,
-                uint32_t it, int nominal, double* S, double* eps_eff, double* margin, int n_threads) {
+                uint32_t it, int nominal, const uint32_t* ms, double* S, double* eps_eff, double* margin,
+                int n_threads) {
   Model M = model_from(mp);
   Cost C = cost_from(cp);
   Track tr = track_from(kind, circle, poly, n_poly, half_width, obs, n_obs, window);
   auto work = [&](int m0, int m1) {
     std::vector<double> eps(2 * T);
     for (int m = m0; m < m1; ++m) {
-      sample_noise(C, seed, pid, it, (uint32_t)m, T, nominal, eps.data());
+      // output slot m holds sample ms[m] when a sample list is given
+      sample_noise(C, seed, pid, it, ms ? ms[m] : (uint32_t)m, T, nominal, eps.data());
       SampleOut so;
       rollout_one<double>(M, C, tr, x0, V, T, eps.data(), eps_eff ? eps_eff + (size_t)2 * T * m : nullptr,
                           nullptr, nullptr, &so);

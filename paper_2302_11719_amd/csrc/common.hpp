@@ -1,0 +1,61 @@
+// Host-side declarations shared by the translation units of libsmppi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/smppi.h"
+#include "kernels.hpp"
+
+struct smppi_ctx_s {
+  int device = 0;
+  int n_cu = 0;
+  int max_lds = 65536;
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  uint32_t* tickets = nullptr;
+  int n_tickets = 0;
+  uint32_t* err = nullptr;
+  std::vector<void*> retired;
+  std::string last;
+};
+
+extern "C" smppi_status smppi_device_errors(smppi_ctx ctx, uint32_t* flags);
+
+namespace smppi {
+
+constexpr int kMaxT = 4096;
+constexpr int kMaxPoly = 4096;
+constexpr int kMaxObs = 64;
+constexpr int kMaxStageLds = 65536;
+
+smppi_status fail(smppi_ctx ctx, smppi_status s, const char* fmt, ...);
+smppi_status hip_fail(smppi_ctx ctx, hipError_t e, const char* what);
+smppi_status ensure_scratch(smppi_ctx ctx, size_t bytes);
+smppi_status ensure_tickets(smppi_ctx ctx, int n);
+smppi_status check_launch(smppi_ctx ctx, const char* what);
+smppi_status validate_batch(smppi_ctx ctx, const smppi_batch* b);
+smppi_status validate_model(smppi_ctx ctx, const smppi_model* m);
+smppi_status validate_cost(smppi_ctx ctx, const smppi_cost* c);
+smppi_status validate_track(smppi_ctx ctx, const smppi_track* t, smppi_dtype dt, int t_max);
+smppi_status validate_objective(smppi_ctx ctx, const smppi_objective* o);
+smppi_status validate_repair(smppi_ctx ctx, const smppi_repair_opts* o);
+int adj_seg_len(int t_max);
+
+template <class R> DevModel<R> dev_model(const smppi_model* m);
+template <class R> DevCost<R> dev_cost(const smppi_cost* c);
+template <class R> DevObjective<R> dev_objective(const smppi_objective* o);
+template <class R>
+ProblemArgs<R> problem_args(smppi_ctx ctx, const smppi_batch* b, const smppi_track* t, const smppi_noise* n,
+                            const void* x0, const uint32_t* iter);
+template <class R>
+smppi_status repair_t(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const smppi_cost* c,
+                      const smppi_track* t, const void* x0, const void* Vp, const smppi_repair_opts* o, void* Vs,
+                      hipStream_t s);
+template <class R>
+smppi_status execute_t(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const void* Ve, const void* Vp,
+                       const void* dist, int32_t n_dist, void* x, void* V, uint32_t* iter, hipStream_t s);
+
+}  // namespace smppi

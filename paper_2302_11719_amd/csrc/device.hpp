@@ -1,0 +1,538 @@
+// Device building blocks of the Shield-MPPI sampled-rollout step for gfx950.
+//
+// Everything here runs per lane with the state in registers: the counter-based
+// noise generator, the vehicle model and its RK4 step, the track/obstacle
+// barriers, the trajectory cost of Algorithm 2 (eqs. (8), (12), (17)-(20),
+// (23)-(25)) and the reverse (adjoint) sweep that differentiates it.
+// Templates take the arithmetic type R (float or double) and NOBS, the
+// compile-time bound on obstacles per problem (0 or 64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smppi {
+
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------- parameters
+template <class R>
+struct DevModel {
+  R lf, lr, Cf, Cr, a_max, c_v, v_min, dt, inv_m, lr_Iz, lf_Iz;
+  R u_lo[2], u_hi[2];
+};
+
+template <class R>
+struct DevCost {
+  R v_g, q_v, q_ey, C_obs, phi_w;
+  R ctrl_w[2];  // lambda_u / sigma_d^2
+  R sigma[2];
+  R C_cbf, alpha;
+};
+
+template <class R>
+struct DevObjective {
+  R w_S, w_sq, w_lin;
+  int n_lin;
+};
+
+// ---------------------------------------------------------------- math shims
+__device__ __forceinline__ void sincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ float rcp_r(float x) { return 1.0f / x; }
+__device__ __forceinline__ double rcp_r(double x) { return 1.0 / x; }
+__device__ __forceinline__ float sqrt_r(float x) { return sqrtf(x); }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+template <class R> __device__ __forceinline__ R clamp_r(R x, R lo, R hi) { return fmin(fmax(x, lo), hi); }
+
+// ---------------------------------------------------------------- noise
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32 -> 64-bit products with a Weyl-sequence key schedule.
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                              uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// Uniform in (0, 1] from the top 24 bits (exact in FP32), then Box-Muller.
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1) {
+  const float ua = (float)((a >> 8) + 1u) * 0x1p-24f;
+  const float ub = (float)((b >> 8) + 1u) * 0x1p-24f;
+  const float r = sqrtf(-2.0f * logf(ua));
+  float s, c;
+  sincospif(2.0f * ub, &s, &c);
+  z0 = r * c;
+  z1 = r * s;
+}
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& z0, double& z1) {
+  const double ua = (double)((a >> 8) + 1u) * 0x1p-24;
+  const double ub = (double)((b >> 8) + 1u) * 0x1p-24;
+  const double r = sqrt(-2.0 * log(ua));
+  double s, c;
+  sincospi(2.0 * ub, &s, &c);
+  z0 = r * c;
+  z1 = r * s;
+}
+
+// Four standard normals for steps 2j and 2j+1 of sample m: counter
+// (j, m, pid, it), key (seed, 0).
+template <class R>
+__device__ __forceinline__ void normals4(uint32_t seed, uint32_t j, uint32_t m, uint32_t pid, uint32_t it,
+                                         R z[4]) {
+  uint32_t c0 = j, c1 = m, c2 = pid, c3 = it;
+  philox4x32_10(c0, c1, c2, c3, seed, 0u);
+  box_muller(c0, c1, z[0], z[1]);
+  box_muller(c2, c3, z[2], z[3]);
+}
+
+// Per-step noise of one sample: one Philox call covers the pair of steps
+// (2j, 2j+1).  gen(t) regenerates the pair containing t; get(t) reads it.
+template <class R>
+struct NoiseStream {
+  uint32_t seed, m, pid, it;
+  bool nominal;
+  R z[4];
+  __device__ __forceinline__ void gen(int t) {
+    if (!nominal) normals4<R>(seed, (uint32_t)(t >> 1), m, pid, it, z);
+  }
+  __device__ __forceinline__ void get(int t, R sig0, R sig1, R& e0, R& e1) const {
+    if (nominal) {
+      e0 = R(0);
+      e1 = R(0);
+      return;
+    }
+    const int o = (t & 1) * 2;
+    e0 = sig0 * z[o];
+    e1 = sig1 * z[o + 1];
+  }
+  // Sequential access (t = 0, 1, 2, ...): regenerates on even steps.
+  __device__ __forceinline__ void at(int t, R sig0, R sig1, R& e0, R& e1) {
+    if ((t & 1) == 0) gen(t);
+    get(t, sig0, sig1, e0, e1);
+  }
+};
+
+// ---------------------------------------------------------------- dynamics
+// Per-step constants of the held control (steer delta, throttle tau).
+template <class R>
+struct StepCtl {
+  R delta, sd_m, cd_m, lfcd_Iz, a_tau, sd, cd;
+};
+
+template <class R>
+__device__ __forceinline__ StepCtl<R> step_ctl(const DevModel<R>& M, R delta, R tau) {
+  StepCtl<R> c;
+  R sd, cd;
+  sincos_r(delta, &sd, &cd);
+  c.delta = delta;
+  c.sd = sd;
+  c.cd = cd;
+  c.sd_m = sd * M.inv_m;
+  c.cd_m = cd * M.inv_m;
+  c.lfcd_Iz = cd * M.lf_Iz;
+  c.a_tau = M.a_max * tau;
+  return c;
+}
+
+// f of the six-state single-track model; (p_x, p_y) do not feed back, so only
+// (psi, v_x, v_y, omega) are inputs.
+template <class R>
+__device__ __forceinline__ void deriv(const DevModel<R>& M, const StepCtl<R>& c, R psi, R vx, R vy, R om,
+                                      R& dpx, R& dpy, R& dvx, R& dvy, R& dom) {
+  const R vt = fmax(vx, M.v_min);
+  const R inv = rcp_r(vt);
+  const R Ff = M.Cf * (c.delta - (vy + M.lf * om) * inv);
+  const R Fr = M.Cr * ((M.lr * om - vy) * inv);
+  R sp, cp;
+  sincos_r(psi, &sp, &cp);
+  dpx = vx * cp - vy * sp;
+  dpy = vx * sp + vy * cp;
+  dvx = c.a_tau - M.c_v * vx - Ff * c.sd_m + vy * om;
+  dvy = Ff * c.cd_m + Fr * M.inv_m - vx * om;
+  dom = Ff * c.lfcd_Iz - Fr * M.lr_Iz;
+}
+
+template <class R>
+struct State {
+  R px, py, psi, vx, vy, om;
+};
+
+// Classic RK4 over dt with the control held.
+template <class R>
+__device__ __forceinline__ void rk4(const DevModel<R>& M, const StepCtl<R>& c, State<R>& x) {
+  const R h = M.dt, h2 = R(0.5) * M.dt, h6 = M.dt * R(1.0 / 6.0);
+  R a0, a1, a3, a4, a5;  // k1
+  R b0, b1, b3, b4, b5;  // k2
+  R c0, c1, c3, c4, c5;  // k3
+  R d0, d1, d3, d4, d5;  // k4
+  deriv(M, c, x.psi, x.vx, x.vy, x.om, a0, a1, a3, a4, a5);
+  const R a2 = x.om;
+  deriv(M, c, x.psi + h2 * a2, x.vx + h2 * a3, x.vy + h2 * a4, x.om + h2 * a5, b0, b1, b3, b4, b5);
+  const R b2 = x.om + h2 * a5;
+  deriv(M, c, x.psi + h2 * b2, x.vx + h2 * b3, x.vy + h2 * b4, x.om + h2 * b5, c0, c1, c3, c4, c5);
+  const R c2 = x.om + h2 * b5;
+  deriv(M, c, x.psi + h * c2, x.vx + h * c3, x.vy + h * c4, x.om + h * c5, d0, d1, d3, d4, d5);
+  const R d2 = x.om + h * c5;
+  x.px += h6 * (a0 + R(2) * (b0 + c0) + d0);
+  x.py += h6 * (a1 + R(2) * (b1 + c1) + d1);
+  x.psi += h6 * (a2 + R(2) * (b2 + c2) + d2);
+  x.vx += h6 * (a3 + R(2) * (b3 + c3) + d3);
+  x.vy += h6 * (a4 + R(2) * (b4 + c4) + d4);
+  x.om += h6 * (a5 + R(2) * (b5 + c5) + d5);
+}
+
+// ---------------------------------------------------------------- track
+// Polyline segments are staged in LDS as (a_x, a_y, d_x, d_y) plus 1/|d|^2.
+template <class R> struct Vec4 { R x, y, z, w; };
+template <> struct Vec4<float> { float4 v; };
+
+template <class R>
+struct TrackView {
+  int n;                  // polyline segments (0: circle)
+  int window;
+  const R* seg;           // LDS [n][4]
+  const R* il2;           // LDS [n]
+  R cx, cy, rad;          // circle
+  R w2;                   // half width squared
+  const R* obs;           // global [n_obs][4] (uniform reads)
+  int n_obs;
+};
+
+template <class R>
+__device__ __forceinline__ R seg_dist2(const TrackView<R>& tr, int i, R px, R py, R* rx_o = nullptr,
+                                       R* ry_o = nullptr) {
+  const R ax = tr.seg[4 * i + 0], ay = tr.seg[4 * i + 1], dx = tr.seg[4 * i + 2], dy = tr.seg[4 * i + 3];
+  const R rx = px - ax, ry = py - ay;
+  R lam = (rx * dx + ry * dy) * tr.il2[i];
+  lam = clamp_r(lam, R(0), R(1));
+  const R ex = rx - lam * dx, ey = ry - lam * dy;
+  if (rx_o) {
+    *rx_o = ex;
+    *ry_o = ey;
+  }
+  return ex * ex + ey * ey;
+}
+
+// Global nearest segment (first strict minimum: lowest index on ties).
+template <class R>
+__device__ int global_argmin(const TrackView<R>& tr, R px, R py) {
+  int best = 0;
+  R bd = seg_dist2(tr, 0, px, py);
+  for (int i = 1; i < tr.n; ++i) {
+    const R d = seg_dist2(tr, i, px, py);
+    if (d < bd) {
+      bd = d;
+      best = i;
+    }
+  }
+  return best;
+}
+
+// Window rule around `c`: offsets 0, -1, +1, -2, +2, ... (first strict minimum wins).
+template <class R>
+__device__ __forceinline__ R window_min(const TrackView<R>& tr, int& c, R px, R py) {
+  int best = c;
+  R bd = seg_dist2(tr, c, px, py);
+  for (int k = 1; k <= tr.window; ++k) {
+    int i = c - k;
+    if (i < 0) i += tr.n;
+    int j = c + k;
+    if (j >= tr.n) j -= tr.n;
+    const R di = seg_dist2(tr, i, px, py);
+    if (di < bd) {
+      bd = di;
+      best = i;
+    }
+    const R dj = seg_dist2(tr, j, px, py);
+    if (dj < bd) {
+      bd = dj;
+      best = j;
+    }
+  }
+  c = best;
+  return bd;
+}
+
+// e_y^2 at (px, py); for the polyline `idx` is the window centre in/out
+// (negative: global search).
+template <class R>
+__device__ __forceinline__ R lateral_sq(const TrackView<R>& tr, R px, R py, int& idx) {
+  if (tr.n == 0) {
+    const R dx = px - tr.cx, dy = py - tr.cy;
+    const R e = sqrt_r(dx * dx + dy * dy) - tr.rad;
+    return e * e;
+  }
+  if (idx < 0) idx = global_argmin(tr, px, py);
+  return window_min(tr, idx, px, py);
+}
+
+// Gradient of e_y^2 with respect to (px, py) at a fixed segment (envelope of
+// the projection) or for the circle.
+template <class R>
+__device__ __forceinline__ void lateral_sq_grad(const TrackView<R>& tr, R px, R py, int idx, R& gx, R& gy) {
+  if (tr.n == 0) {
+    const R dx = px - tr.cx, dy = py - tr.cy;
+    const R rho = sqrt_r(dx * dx + dy * dy);
+    const R f = R(2) * (rho - tr.rad) / rho;
+    gx = f * dx;
+    gy = f * dy;
+    return;
+  }
+  R ex, ey;
+  seg_dist2(tr, idx, px, py, &ex, &ey);
+  gx = R(2) * ex;
+  gy = R(2) * ey;
+}
+
+// ---------------------------------------------------------------- one sample
+// Modified trajectory cost S~ of one sample (Algorithm 2 inner loop):
+//   S~ = sum_{t<T} [q(x_t) + lambda_u v_t^T Sigma^-1 u_t] + phi_w q(x_T) + sum_{t=0}^{T} C_cbf(z_t).
+// V is [2][T] (steer row, throttle row), read from LDS or global.
+template <class R, int NOBS>
+__device__ R rollout_sample(const DevModel<R>& M, const DevCost<R>& C, const TrackView<R>& tr, const State<R>& x0,
+                            const R* __restrict__ V, int T, NoiseStream<R>& ns, R* eps_out) {
+  State<R> x = x0;
+  int idx = -1;
+  R ey2 = lateral_sq(tr, x.px, x.py, idx);
+  R h0 = tr.w2 - ey2;
+  bool outside = h0 < R(0);
+  R hob[NOBS > 0 ? NOBS : 1];
+  // z_0 = (x_0, x_0): C max((alpha - 1) h(x_0), 0) per barrier.
+  R S = C.C_cbf * fmax((C.alpha - R(1)) * h0, R(0));
+#pragma unroll
+  for (int i = 0; i < NOBS; ++i) {
+    if (i < tr.n_obs) {
+      const R ox = x.px - tr.obs[4 * i], oy = x.py - tr.obs[4 * i + 1];
+      const R d2 = ox * ox + oy * oy;
+      hob[i] = d2 - tr.obs[4 * i + 2];
+      outside = outside || (d2 < tr.obs[4 * i + 3]);
+      S += C.C_cbf * fmax((C.alpha - R(1)) * hob[i], R(0));
+    }
+  }
+  for (int t = 0; t < T; ++t) {
+    const R v0 = V[t], v1 = V[T + t];
+    R e0, e1;
+    ns.at(t, C.sigma[0], C.sigma[1], e0, e1);
+    const R u0 = clamp_r(v0 + e0, M.u_lo[0], M.u_hi[0]);
+    const R u1 = clamp_r(v1 + e1, M.u_lo[1], M.u_hi[1]);
+    if (eps_out) {
+      eps_out[2 * t] = u0 - v0;
+      eps_out[2 * t + 1] = u1 - v1;
+    }
+    const R dv = x.vx - C.v_g;
+    R q = C.q_v * dv * dv + C.q_ey * ey2;
+    if (outside) q += C.C_obs;
+    S += q + (C.ctrl_w[0] * v0 * u0 + C.ctrl_w[1] * v1 * u1);
+    const StepCtl<R> sc = step_ctl(M, u0, u1);
+    rk4(M, sc, x);
+    ey2 = lateral_sq(tr, x.px, x.py, idx);
+    const R h1 = tr.w2 - ey2;
+    R pen = fmax(C.alpha * h0 - h1, R(0));
+    h0 = h1;
+    outside = h1 < R(0);
+#pragma unroll
+    for (int i = 0; i < NOBS; ++i) {
+      if (i < tr.n_obs) {
+        const R ox = x.px - tr.obs[4 * i], oy = x.py - tr.obs[4 * i + 1];
+        const R d2 = ox * ox + oy * oy;
+        const R hi = d2 - tr.obs[4 * i + 2];
+        pen += fmax(C.alpha * hob[i] - hi, R(0));
+        hob[i] = hi;
+        outside = outside || (d2 < tr.obs[4 * i + 3]);
+      }
+    }
+    S += C.C_cbf * pen;
+  }
+  const R dv = x.vx - C.v_g;
+  R q = C.q_v * dv * dv + C.q_ey * ey2;
+  if (outside) q += C.C_obs;
+  S += C.phi_w * q;
+  return S;
+}
+
+// ---------------------------------------------------------------- adjoint
+// Vector-Jacobian product of one derivative evaluation: given the cotangent
+// (gpx, gpy, gpsi, gvx, gvy, gom) of f's output at (psi, vx, vy, om) with the
+// step control, accumulate d/d(psi, vx, vy, om) into o* and d/d(delta, tau)
+// into gd, gt.
+template <class R>
+__device__ __forceinline__ void deriv_vjp(const DevModel<R>& M, const StepCtl<R>& c, R psi, R vx, R vy, R om,
+                                          R gpx, R gpy, R gpsi, R gvx, R gvy, R gom, R& opsi, R& ovx, R& ovy,
+                                          R& oom, R& gd, R& gt) {
+  const bool above = vx >= M.v_min;
+  const R vt = fmax(vx, M.v_min);
+  const R inv = rcp_r(vt);
+  const R Ff = M.Cf * (c.delta - (vy + M.lf * om) * inv);
+  const R Fr = M.Cr * ((M.lr * om - vy) * inv);
+  R sp, cp;
+  sincos_r(psi, &sp, &cp);
+  // kinematics
+  const R dpx = vx * cp - vy * sp, dpy = vx * sp + vy * cp;
+  opsi += gpy * dpx - gpx * dpy;
+  ovx += gpx * cp + gpy * sp;
+  ovy += gpy * cp - gpx * sp;
+  oom += gpsi;
+  // v_x equation
+  ovx += -M.c_v * gvx - om * gvy;
+  ovy += om * gvx;
+  oom += vy * gvx - vx * gvy;
+  gt += M.a_max * gvx;
+  // tyre forces
+  const R gFf = -c.sd_m * gvx + c.cd_m * gvy + c.lfcd_Iz * gom;
+  const R gFr = M.inv_m * gvy - M.lr_Iz * gom;
+  gd += -Ff * c.cd * M.inv_m * gvx - Ff * c.sd * M.inv_m * gvy - Ff * c.sd * M.lf_Iz * gom;
+  const R gaf = M.Cf * gFf, gar = M.Cr * gFr;
+  gd += gaf;
+  ovy += -inv * (gaf + gar);
+  oom += inv * (M.lr * gar - M.lf * gaf);
+  const R ginv = -(vy + M.lf * om) * gaf + (M.lr * om - vy) * gar;
+  if (above) ovx += -inv * inv * ginv;
+}
+
+// Reverse of one RK4 step from x (stage states recomputed): given lam =
+// dL/dx_{t+1}, returns dL/dx_t in lam and accumulates dL/du into gd, gt.
+template <class R>
+__device__ __forceinline__ void rk4_vjp(const DevModel<R>& M, const StepCtl<R>& c, const State<R>& x, R lam[6],
+                                        R& gd, R& gt) {
+  const R h = M.dt, h2 = R(0.5) * M.dt, h6 = M.dt * R(1.0 / 6.0);
+  R a0, a1, a3, a4, a5, b0, b1, b3, b4, b5, c0, c1, c3, c4, c5;
+  deriv(M, c, x.psi, x.vx, x.vy, x.om, a0, a1, a3, a4, a5);
+  const R a2 = x.om;
+  const R X2psi = x.psi + h2 * a2, X2vx = x.vx + h2 * a3, X2vy = x.vy + h2 * a4, X2om = x.om + h2 * a5;
+  deriv(M, c, X2psi, X2vx, X2vy, X2om, b0, b1, b3, b4, b5);
+  const R b2 = X2om;
+  const R X3psi = x.psi + h2 * b2, X3vx = x.vx + h2 * b3, X3vy = x.vy + h2 * b4, X3om = x.om + h2 * b5;
+  deriv(M, c, X3psi, X3vx, X3vy, X3om, c0, c1, c3, c4, c5);
+  const R c2 = X3om;
+  const R X4psi = x.psi + h * c2, X4vx = x.vx + h * c3, X4vy = x.vy + h * c4, X4om = x.om + h * c5;
+  // cotangents of the stage derivatives k1..k4: (h/6, h/3, h/3, h/6) * lam
+  R gk4[6], gk3[6], gk2[6], gk1[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    gk4[i] = h6 * lam[i];
+    gk3[i] = R(2) * h6 * lam[i];
+    gk2[i] = R(2) * h6 * lam[i];
+    gk1[i] = h6 * lam[i];
+  }
+  // k4 = f(X4): X4 = x + h k3 (p components of k feed only the output)
+  R o[4] = {R(0), R(0), R(0), R(0)};
+  deriv_vjp(M, c, X4psi, X4vx, X4vy, X4om, gk4[0], gk4[1], gk4[2], gk4[3], gk4[4], gk4[5], o[0], o[1], o[2],
+            o[3], gd, gt);
+  // psi component of k is omega of the stage state: dpsi_dot/dom = 1 (inside deriv_vjp via gpsi)
+  lam[2] += o[0];
+  lam[3] += o[1];
+  lam[4] += o[2];
+  lam[5] += o[3];
+  gk3[2] += h * o[0];
+  gk3[3] += h * o[1];
+  gk3[4] += h * o[2];
+  gk3[5] += h * o[3];
+  o[0] = o[1] = o[2] = o[3] = R(0);
+  deriv_vjp(M, c, X3psi, X3vx, X3vy, X3om, gk3[0], gk3[1], gk3[2], gk3[3], gk3[4], gk3[5], o[0], o[1], o[2],
+            o[3], gd, gt);
+  lam[2] += o[0];
+  lam[3] += o[1];
+  lam[4] += o[2];
+  lam[5] += o[3];
+  gk2[2] += h2 * o[0];
+  gk2[3] += h2 * o[1];
+  gk2[4] += h2 * o[2];
+  gk2[5] += h2 * o[3];
+  o[0] = o[1] = o[2] = o[3] = R(0);
+  deriv_vjp(M, c, X2psi, X2vx, X2vy, X2om, gk2[0], gk2[1], gk2[2], gk2[3], gk2[4], gk2[5], o[0], o[1], o[2],
+            o[3], gd, gt);
+  lam[2] += o[0];
+  lam[3] += o[1];
+  lam[4] += o[2];
+  lam[5] += o[3];
+  gk1[2] += h2 * o[0];
+  gk1[3] += h2 * o[1];
+  gk1[4] += h2 * o[2];
+  gk1[5] += h2 * o[3];
+  o[0] = o[1] = o[2] = o[3] = R(0);
+  deriv_vjp(M, c, x.psi, x.vx, x.vy, x.om, gk1[0], gk1[1], gk1[2], gk1[3], gk1[4], gk1[5], o[0], o[1], o[2],
+            o[3], gd, gt);
+  lam[2] += o[0];
+  lam[3] += o[1];
+  lam[4] += o[2];
+  lam[5] += o[3];
+  (void)a0; (void)a1; (void)b0; (void)b1; (void)c0; (void)c1;
+}
+
+// Barrier values at a state, given the segment index at that state.
+template <class R, int NOBS>
+__device__ __forceinline__ R track_h_at(const TrackView<R>& tr, const State<R>& x, int idx) {
+  R e2;
+  if (tr.n == 0) {
+    int dummy = 0;
+    e2 = lateral_sq(tr, x.px, x.py, dummy);
+  } else {
+    e2 = seg_dist2(tr, idx, x.px, x.py);
+  }
+  return tr.w2 - e2;
+}
+
+// Adds dP/dx for the transition penalty between x_t (prev) and x_{t+1} (next):
+// r_j = alpha h_j(x_t) - h_j(x_{t+1}); dL/dr_j = w_S C + 2 w_sq r_j + w_lin [t < n_lin]
+// when r_j > 0.  lam_next gets the x_{t+1} part, g_prev the x_t part (p only).
+template <class R, int NOBS>
+__device__ __forceinline__ void penalty_grad(const DevCost<R>& C, const DevObjective<R>& ob, const TrackView<R>& tr,
+                                             const State<R>& xp, int ip, const State<R>& xn, int in_, int t,
+                                             R lam_next[6], R& gpx_prev, R& gpy_prev) {
+  const R lin = (t < ob.n_lin) ? ob.w_lin : R(0);
+  {
+    const R hp = track_h_at<R, NOBS>(tr, xp, ip), hn = track_h_at<R, NOBS>(tr, xn, in_);
+    const R r = C.alpha * hp - hn;
+    if (r > R(0)) {
+      const R g = ob.w_S * C.C_cbf + R(2) * ob.w_sq * r + lin;
+      R gx, gy;
+      // dh/dp = -d(e^2)/dp
+      lateral_sq_grad(tr, xn.px, xn.py, in_, gx, gy);
+      lam_next[0] += g * gx;
+      lam_next[1] += g * gy;
+      lateral_sq_grad(tr, xp.px, xp.py, ip, gx, gy);
+      gpx_prev -= g * C.alpha * gx;
+      gpy_prev -= g * C.alpha * gy;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NOBS; ++i) {
+    if (i < tr.n_obs) {
+      const R cx = tr.obs[4 * i], cy = tr.obs[4 * i + 1], re2 = tr.obs[4 * i + 2];
+      const R pxp = xp.px - cx, pyp = xp.py - cy, pxn = xn.px - cx, pyn = xn.py - cy;
+      const R hp = pxp * pxp + pyp * pyp - re2, hn = pxn * pxn + pyn * pyn - re2;
+      const R r = C.alpha * hp - hn;
+      if (r > R(0)) {
+        const R g = ob.w_S * C.C_cbf + R(2) * ob.w_sq * r + lin;
+        lam_next[0] -= g * R(2) * pxn;
+        lam_next[1] -= g * R(2) * pyn;
+        gpx_prev += g * C.alpha * R(2) * pxp;
+        gpy_prev += g * C.alpha * R(2) * pyp;
+      }
+    }
+  }
+}
+
+// d q'(x)/dx (q' = q without the indicator): speed term and lateral term.
+template <class R>
+__device__ __forceinline__ void stage_grad(const DevCost<R>& C, const TrackView<R>& tr, const State<R>& x, int idx,
+                                           R scale, R lam[6]) {
+  lam[3] += scale * R(2) * C.q_v * (x.vx - C.v_g);
+  R gx, gy;
+  lateral_sq_grad(tr, x.px, x.py, idx, gx, gy);
+  lam[0] += scale * C.q_ey * gx;
+  lam[1] += scale * C.q_ey * gy;
+}
+
+}  // namespace smppi

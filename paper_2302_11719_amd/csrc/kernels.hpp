@@ -1,0 +1,636 @@
+// gfx950 kernels of the plain (one call per stage) sampled-rollout path.
+#pragma once
+
+#include "device.hpp"
+
+namespace smppi {
+
+// Device-side input errors (bounds a kernel relies on); OR-ed into ctx->err.
+enum : uint32_t {
+  DERR_T = 1u,        // T_b outside [1, t_max]
+  DERR_K = 2u,        // K_b outside [0, k_max]
+  DERR_POLY = 4u,     // N_b > poly_max or window too wide for N_b
+  DERR_OBS = 8u,      // O_b > obs_max
+};
+
+template <class R>
+struct ProblemArgs {
+  const int64_t* k_off;
+  const int32_t* t_off;
+  const int32_t* poly_off;
+  const R* poly;
+  const R* circle;
+  const R* half_width;
+  const int32_t* obs_off;
+  const R* obs;
+  const R* x0;
+  const uint32_t* iter;
+  int32_t k_max, t_max, poly_max, obs_max, window, pid_base;
+  uint32_t seed;
+  int32_t nominal;
+  uint32_t* err;
+};
+
+struct ProblemDims {
+  int64_t k0;
+  int K, t0, T, p0, np, o0, no;
+};
+
+template <class R>
+__device__ __forceinline__ bool load_dims(const ProblemArgs<R>& a, int b, ProblemDims& d) {
+  d.k0 = a.k_off[b];
+  const int64_t K = a.k_off[b + 1] - d.k0;
+  d.t0 = a.t_off[b];
+  d.T = a.t_off[b + 1] - d.t0;
+  d.p0 = a.poly_off ? a.poly_off[b] : 0;
+  d.np = a.poly_off ? a.poly_off[b + 1] - d.p0 : 0;
+  d.o0 = a.obs_off ? a.obs_off[b] : 0;
+  d.no = a.obs_off ? a.obs_off[b + 1] - d.o0 : 0;
+  uint32_t e = 0;
+  if (d.T < 1 || d.T > a.t_max) e |= DERR_T;
+  if (K < 0 || K > a.k_max) e |= DERR_K;
+  if (d.np < 0 || d.np > a.poly_max || (d.np > 0 && 2 * a.window + 1 > d.np)) e |= DERR_POLY;
+  if (d.no < 0 || d.no > a.obs_max) e |= DERR_OBS;
+  d.K = (int)K;
+  if (e) {
+    if (threadIdx.x == 0) atomicOr(a.err, e);
+    return false;
+  }
+  return true;
+}
+
+// Stages problem b's polyline and control sequence in LDS; returns the track view.
+// LDS layout: seg [poly_max][4] | il2 [poly_max] | V [2][t_max].
+template <class R>
+__device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const ProblemDims& d, const R* __restrict__ Vg,
+                                      unsigned char* smem, R** Vs_out) {
+  R* seg = reinterpret_cast<R*>(smem);
+  R* il2 = seg + 4 * a.poly_max;
+  R* Vs = il2 + a.poly_max;
+  for (int i = threadIdx.x; i < d.np; i += blockDim.x) {
+    const R* s = a.poly + 5 * (size_t)(d.p0 + i);
+    seg[4 * i + 0] = s[0];
+    seg[4 * i + 1] = s[1];
+    seg[4 * i + 2] = s[2];
+    seg[4 * i + 3] = s[3];
+    il2[i] = s[4];
+  }
+  for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) Vs[i] = Vg[2 * (size_t)d.t0 + i];
+  TrackView<R> tr;
+  tr.n = d.np;
+  tr.window = a.window;
+  tr.seg = seg;
+  tr.il2 = il2;
+  tr.cx = a.circle[3 * b + 0];
+  tr.cy = a.circle[3 * b + 1];
+  tr.rad = a.circle[3 * b + 2];
+  const R w = a.half_width[b];
+  tr.w2 = w * w;
+  tr.obs = a.obs ? a.obs + 4 * (size_t)d.o0 : nullptr;
+  tr.n_obs = d.no;
+  *Vs_out = Vs;
+  return tr;
+}
+
+template <class R>
+__host__ __device__ inline size_t stage_lds_bytes(int poly_max, int t_max) {
+  return sizeof(R) * (5 * (size_t)poly_max + 2 * (size_t)t_max);
+}
+
+template <class R>
+__device__ __forceinline__ State<R> load_state(const R* x) {
+  State<R> s;
+  s.px = x[0];
+  s.py = x[1];
+  s.psi = x[2];
+  s.vx = x[3];
+  s.vy = x[4];
+  s.om = x[5];
+  return s;
+}
+
+template <class R>
+__device__ __forceinline__ R wave_sum(R v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+template <class R>
+__device__ __forceinline__ R wave_min(R v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+
+// Block-wide reductions in a fixed order (lane tree, then waves in index order).
+template <class R>
+__device__ R block_sum(R v, R* red) {
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  R s = R(0);
+  for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+template <class R>
+__device__ R block_min(R v, R* red) {
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  v = wave_min(v);
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  R s = red[0];
+  for (int i = 1; i < nw; ++i) s = fmin(s, red[i]);
+  return s;
+}
+
+// ============================================================== rollout
+template <class R>
+struct RolloutArgs {
+  ProblemArgs<R> p;
+  DevModel<R> M;
+  DevCost<R> C;
+  const R* V;
+  R* S;
+  R* eps_out;
+};
+
+template <class R, int NOBS>
+__global__ __launch_bounds__(256) void k_rollout(RolloutArgs<R> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.y;
+  ProblemDims d;
+  if (!load_dims(a.p, b, d)) return;
+  const int m_base = blockIdx.x * blockDim.x;
+  if (m_base >= d.K) return;
+  R* Vs;
+  const TrackView<R> tr = stage_problem(a.p, b, d, a.V, smem, &Vs);
+  __syncthreads();
+  const int m = m_base + threadIdx.x;
+  if (m >= d.K) return;
+  NoiseStream<R> ns;
+  ns.seed = a.p.seed;
+  ns.m = (uint32_t)m;
+  ns.pid = (uint32_t)(a.p.pid_base + b);
+  ns.it = a.p.iter[b];
+  ns.nominal = a.p.nominal != 0;
+  const State<R> x0 = load_state(a.p.x0 + 6 * (size_t)b);
+  R* eo = a.eps_out ? a.eps_out + (size_t)(d.k0 + m) * a.p.t_max * 2 : nullptr;
+  a.S[d.k0 + m] = rollout_sample<R, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, eo);
+}
+
+// ============================================================== weights
+template <class R>
+__global__ __launch_bounds__(256) void k_weights(const int64_t* __restrict__ k_off, const R* __restrict__ S,
+                                                 R inv_lambda, R* __restrict__ w, R* __restrict__ stats) {
+  __shared__ R red[256 / WAVE];
+  const int b = blockIdx.x;
+  const int64_t k0 = k_off[b];
+  const int K = (int)(k_off[b + 1] - k0);
+  R mn = R(INFINITY), nf = R(0);
+  for (int m = threadIdx.x; m < K; m += blockDim.x) {
+    const R s = S[k0 + m];
+    if (isfinite(s)) mn = fmin(mn, s);
+    else nf += R(1);
+  }
+  mn = block_min(mn, red);
+  nf = block_sum(nf, red);
+  R z = R(0), q = R(0);
+  for (int m = threadIdx.x; m < K; m += blockDim.x) {
+    const R s = S[k0 + m];
+    const R om = isfinite(s) ? exp(-(s - mn) * inv_lambda) : R(0);
+    z += om;
+    q += om * om;
+  }
+  z = block_sum(z, red);
+  q = block_sum(q, red);
+  const R iz = z > R(0) ? R(1) / z : R(0);
+  for (int m = threadIdx.x; m < K; m += blockDim.x) {
+    const R s = S[k0 + m];
+    const R om = isfinite(s) ? exp(-(s - mn) * inv_lambda) : R(0);
+    w[k0 + m] = om * iz;
+  }
+  if (threadIdx.x == 0) {
+    stats[4 * b + 0] = mn;
+    stats[4 * b + 1] = log(z);
+    stats[4 * b + 2] = q > R(0) ? z * z / q : R(0);
+    stats[4 * b + 3] = nf;
+  }
+}
+
+// ============================================================== update
+// Per-step reduction of sum_m w_m eps'_{m,t} over a block's samples, written as
+// block partials; the last block of each problem (ticket) sums the partials in
+// block order and writes V+ = V + sum.
+template <class R>
+struct UpdateArgs {
+  ProblemArgs<R> p;
+  DevModel<R> M;
+  DevCost<R> C;
+  const R* V;
+  const R* w;
+  R* V_plus;
+  R* part;            // [B][nblk_max][2][t_max]
+  uint32_t* tickets;  // [B], zero between calls
+  int nblk_max;
+};
+
+constexpr int UPD_BLOCK = 256;
+constexpr int UPD_TCHUNK = 64;
+
+template <class R>
+__global__ __launch_bounds__(UPD_BLOCK) void k_update(UpdateArgs<R> a) {
+  __shared__ R wpart[UPD_BLOCK / WAVE][2][UPD_TCHUNK];
+  __shared__ uint32_t s_ticket;
+  const int b = blockIdx.y;
+  ProblemDims d;
+  if (!load_dims(a.p, b, d)) return;
+  const R* Vb = a.V + 2 * (size_t)d.t0;
+  R* Vpb = a.V_plus + 2 * (size_t)d.t0;
+  if (d.K == 0) {
+    if (blockIdx.x == 0)
+      for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) Vpb[i] = Vb[i];
+    return;
+  }
+  const int nblk = (d.K + UPD_BLOCK - 1) / UPD_BLOCK;
+  if ((int)blockIdx.x >= nblk) return;
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  const int m = blockIdx.x * UPD_BLOCK + threadIdx.x;
+  const R wm = (m < d.K) ? a.w[d.k0 + m] : R(0);
+  NoiseStream<R> ns;
+  ns.seed = a.p.seed;
+  ns.m = (uint32_t)m;
+  ns.pid = (uint32_t)(a.p.pid_base + b);
+  ns.it = a.p.iter[b];
+  ns.nominal = a.p.nominal != 0;
+  R* gp = a.part + ((size_t)b * a.nblk_max + blockIdx.x) * 2 * a.p.t_max;
+  for (int tc = 0; tc < d.T; tc += UPD_TCHUNK) {
+    const int tn = min(UPD_TCHUNK, d.T - tc);
+    for (int tt = 0; tt < tn; ++tt) {
+      const int t = tc + tt;
+      R p0 = R(0), p1 = R(0);
+      if (wm != R(0)) {
+        R e0, e1;
+        ns.at(t, a.C.sigma[0], a.C.sigma[1], e0, e1);
+        const R v0 = Vb[t], v1 = Vb[d.T + t];
+        p0 = wm * (clamp_r(v0 + e0, a.M.u_lo[0], a.M.u_hi[0]) - v0);
+        p1 = wm * (clamp_r(v1 + e1, a.M.u_lo[1], a.M.u_hi[1]) - v1);
+      }
+      p0 = wave_sum(p0);
+      p1 = wave_sum(p1);
+      if (lane == 0) {
+        wpart[wv][0][tt] = p0;
+        wpart[wv][1][tt] = p1;
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < 2 * tn) {
+      const int dd = threadIdx.x / tn, tt = threadIdx.x % tn;
+      R s = R(0);
+      for (int i = 0; i < UPD_BLOCK / WAVE; ++i) s += wpart[i][dd][tt];
+      gp[dd * d.T + tc + tt] = s;
+    }
+    __syncthreads();
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) s_ticket = atomicAdd(&a.tickets[b], 1u);
+  __syncthreads();
+  if (s_ticket == (uint32_t)(nblk - 1)) {
+    __threadfence();
+    const R* g0 = a.part + (size_t)b * a.nblk_max * 2 * a.p.t_max;
+    for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) {
+      R acc = R(0);
+      for (int k = 0; k < nblk; ++k) acc += __builtin_nontemporal_load(g0 + (size_t)k * 2 * a.p.t_max + i);
+      Vpb[i] = Vb[i] + acc;
+    }
+    if (threadIdx.x == 0) a.tickets[b] = 0u;
+  }
+}
+
+// ============================================================== adjoint
+// Per-lane reverse sweep with checkpoints every `seg_len` steps kept in LDS and
+// the states of one segment recomputed into LDS (layout [slot][component][lane]).
+template <class R>
+struct AdjLds {
+  R* ck;      // [n_ck][6][64]
+  int* cki;   // [n_ck][64]
+  R* sx;      // [seg_len+1][6][64]
+  int* sxi;   // [seg_len+1][64]
+};
+
+template <class R>
+__device__ __forceinline__ void adj_store(R* base, int* ibase, int slot, int lane, const State<R>& x, int idx) {
+  R* p = base + (size_t)slot * 6 * WAVE + lane;
+  p[0 * WAVE] = x.px;
+  p[1 * WAVE] = x.py;
+  p[2 * WAVE] = x.psi;
+  p[3 * WAVE] = x.vx;
+  p[4 * WAVE] = x.vy;
+  p[5 * WAVE] = x.om;
+  ibase[slot * WAVE + lane] = idx;
+}
+template <class R>
+__device__ __forceinline__ State<R> adj_load(const R* base, const int* ibase, int slot, int lane, int& idx) {
+  const R* p = base + (size_t)slot * 6 * WAVE + lane;
+  State<R> x;
+  x.px = p[0 * WAVE];
+  x.py = p[1 * WAVE];
+  x.psi = p[2 * WAVE];
+  x.vx = p[3 * WAVE];
+  x.vy = p[4 * WAVE];
+  x.om = p[5 * WAVE];
+  idx = ibase[slot * WAVE + lane];
+  return x;
+}
+
+template <class R>
+__host__ __device__ inline size_t adj_lds_bytes(int t_max, int seg_len) {
+  const int n_ck = (t_max + seg_len - 1) / seg_len;
+  return (size_t)(n_ck + seg_len + 1) * WAVE * (6 * sizeof(R) + sizeof(int));
+}
+
+// Reverse sweep of one lane's trajectory.  `V` is [2][T] in LDS.  For every t
+// (descending) calls sink(t, dL/dv_{t,0}, dL/dv_{t,1}); the sink may modify V[t]
+// (the repair does), which is safe because V[t'] for t' >= t is never read again.
+template <class R, int NOBS, class Sink>
+__device__ void adjoint_lane(const DevModel<R>& M, const DevCost<R>& C, const DevObjective<R>& ob,
+                             const TrackView<R>& tr, const State<R>& x0, R* V, int T, NoiseStream<R>& ns,
+                             const AdjLds<R>& L, int seg_len, int lane, Sink& sink) {
+  // forward with checkpoints
+  State<R> x = x0;
+  int idx = -1;
+  (void)lateral_sq(tr, x.px, x.py, idx);
+  for (int t = 0; t < T; ++t) {
+    if (t % seg_len == 0) adj_store(L.ck, L.cki, t / seg_len, lane, x, idx);
+    R e0, e1;
+    ns.at(t, C.sigma[0], C.sigma[1], e0, e1);
+    const R u0 = clamp_r(V[t] + e0, M.u_lo[0], M.u_hi[0]);
+    const R u1 = clamp_r(V[T + t] + e1, M.u_lo[1], M.u_hi[1]);
+    rk4(M, step_ctl(M, u0, u1), x);
+    (void)lateral_sq(tr, x.px, x.py, idx);
+  }
+  // terminal cost gradient
+  R lam[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+  stage_grad(C, tr, x, idx, ob.w_S * C.phi_w, lam);
+  const int n_seg = (T + seg_len - 1) / seg_len;
+  for (int c = n_seg - 1; c >= 0; --c) {
+    const int t0 = c * seg_len, t1 = min(T, t0 + seg_len);
+    int ci;
+    State<R> xs = adj_load(L.ck, L.cki, c, lane, ci);
+    adj_store(L.sx, L.sxi, 0, lane, xs, ci);
+    for (int t = t0; t < t1; ++t) {
+      R e0, e1;
+      if (t == t0 || (t & 1) == 0) ns.gen(t);
+      ns.get(t, C.sigma[0], C.sigma[1], e0, e1);
+      const R u0 = clamp_r(V[t] + e0, M.u_lo[0], M.u_hi[0]);
+      const R u1 = clamp_r(V[T + t] + e1, M.u_lo[1], M.u_hi[1]);
+      rk4(M, step_ctl(M, u0, u1), xs);
+      (void)lateral_sq(tr, xs.px, xs.py, ci);
+      adj_store(L.sx, L.sxi, t - t0 + 1, lane, xs, ci);
+    }
+    for (int t = t1 - 1; t >= t0; --t) {
+      int ip, in_;
+      const State<R> xp = adj_load(L.sx, L.sxi, t - t0, lane, ip);
+      const State<R> xn = adj_load(L.sx, L.sxi, t - t0 + 1, lane, in_);
+      R gpx = R(0), gpy = R(0);
+      penalty_grad<R, NOBS>(C, ob, tr, xp, ip, xn, in_, t, lam, gpx, gpy);
+      R e0, e1;
+      // descending: the pair (t-1, t) is regenerated at odd t or at the segment's last step
+      if ((t & 1) == 1 || t == t1 - 1) ns.gen(t);
+      ns.get(t, C.sigma[0], C.sigma[1], e0, e1);
+      const R v0 = V[t], v1 = V[T + t];
+      const R r0 = v0 + e0, r1 = v1 + e1;
+      const R u0 = clamp_r(r0, M.u_lo[0], M.u_hi[0]);
+      const R u1 = clamp_r(r1, M.u_lo[1], M.u_hi[1]);
+      const bool pass0 = (r0 >= M.u_lo[0]) && (r0 <= M.u_hi[0]);
+      const bool pass1 = (r1 >= M.u_lo[1]) && (r1 <= M.u_hi[1]);
+      R gd = R(0), gt = R(0);
+      rk4_vjp(M, step_ctl(M, u0, u1), xp, lam, gd, gt);
+      lam[0] += gpx;
+      lam[1] += gpy;
+      stage_grad(C, tr, xp, ip, ob.w_S, lam);
+      // control term w_S * lambda_u * v^T Sigma^-1 u: direct in v, and through u
+      const R gu0 = gd + ob.w_S * C.ctrl_w[0] * v0;
+      const R gu1 = gt + ob.w_S * C.ctrl_w[1] * v1;
+      const R gv0 = (pass0 ? gu0 : R(0)) + ob.w_S * C.ctrl_w[0] * u0;
+      const R gv1 = (pass1 ? gu1 : R(0)) + ob.w_S * C.ctrl_w[1] * u1;
+      sink(t, gv0, gv1);
+    }
+  }
+}
+
+template <class R>
+struct BackwardArgs {
+  ProblemArgs<R> p;
+  DevModel<R> M;
+  DevCost<R> C;
+  DevObjective<R> ob;
+  const R* V;
+  const R* grad_S;
+  R* grad_V;
+  R* part;            // [B][nblk_max][2][t_max]
+  uint32_t* tickets;  // [B]
+  int nblk_max;
+  int seg_len;
+};
+
+template <class R>
+struct ReduceSink {
+  R g;
+  R* gp;  // this block's partial [2][T]
+  int T;
+  int lane;
+  __device__ __forceinline__ void operator()(int t, R gv0, R gv1) {
+    const R s0 = wave_sum(g * gv0);
+    const R s1 = wave_sum(g * gv1);
+    if (lane == 0) {
+      gp[t] = s0;
+      gp[T + t] = s1;
+    }
+  }
+};
+
+template <class R, int NOBS>
+__global__ __launch_bounds__(WAVE) void k_backward(BackwardArgs<R> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t s_ticket;
+  const int b = blockIdx.y;
+  ProblemDims d;
+  if (!load_dims(a.p, b, d)) return;
+  R* gVb = a.grad_V + 2 * (size_t)d.t0;
+  if (d.K == 0) {
+    if (blockIdx.x == 0)
+      for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) gVb[i] = R(0);
+    return;
+  }
+  const int nblk = (d.K + WAVE - 1) / WAVE;
+  if ((int)blockIdx.x >= nblk) return;
+  R* Vs;
+  const TrackView<R> tr = stage_problem(a.p, b, d, a.V, smem, &Vs);
+  unsigned char* rest = smem + stage_lds_bytes<R>(a.p.poly_max, a.p.t_max);
+  const int n_ck = (a.p.t_max + a.seg_len - 1) / a.seg_len;
+  AdjLds<R> L;
+  L.ck = reinterpret_cast<R*>(rest);
+  L.sx = L.ck + (size_t)n_ck * 6 * WAVE;
+  L.cki = reinterpret_cast<int*>(L.sx + (size_t)(a.seg_len + 1) * 6 * WAVE);
+  L.sxi = L.cki + n_ck * WAVE;
+  __syncthreads();
+  const int lane = threadIdx.x;
+  const int m = blockIdx.x * WAVE + lane;
+  NoiseStream<R> ns;
+  ns.seed = a.p.seed;
+  ns.m = (uint32_t)m;
+  ns.pid = (uint32_t)(a.p.pid_base + b);
+  ns.it = a.p.iter[b];
+  ns.nominal = a.p.nominal != 0;
+  ReduceSink<R> sink;
+  sink.g = (m < d.K) ? a.grad_S[d.k0 + m] : R(0);
+  sink.gp = a.part + ((size_t)b * a.nblk_max + blockIdx.x) * 2 * a.p.t_max;
+  sink.T = d.T;
+  sink.lane = lane;
+  const State<R> x0 = load_state(a.p.x0 + 6 * (size_t)b);
+  adjoint_lane<R, NOBS>(a.M, a.C, a.ob, tr, x0, Vs, d.T, ns, L, a.seg_len, lane, sink);
+  __threadfence();
+  __syncthreads();
+  if (lane == 0) s_ticket = atomicAdd(&a.tickets[b], 1u);
+  __syncthreads();
+  if (s_ticket == (uint32_t)(nblk - 1)) {
+    __threadfence();
+    const R* g0 = a.part + (size_t)b * a.nblk_max * 2 * a.p.t_max;
+    for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) {
+      R acc = R(0);
+      for (int k = 0; k < nblk; ++k) acc += __builtin_nontemporal_load(g0 + (size_t)k * 2 * a.p.t_max + i);
+      gVb[i] = acc;
+    }
+    if (lane == 0) a.tickets[b] = 0u;
+  }
+}
+
+// ============================================================== repair
+template <class R>
+struct RepairArgs {
+  ProblemArgs<R> p;
+  DevModel<R> M;
+  DevCost<R> C;
+  DevObjective<R> ob;
+  const R* V_plus;
+  R* V_safe;
+  int n_steps;
+  R step;
+  int seg_len;
+};
+
+template <class R>
+struct RepairSink {
+  R* V;
+  int T;
+  R step;
+  R lo0, hi0, lo1, hi1;
+  __device__ __forceinline__ void operator()(int t, R gv0, R gv1) {
+    V[t] = clamp_r(V[t] - step * gv0, lo0, hi0);
+    V[T + t] = clamp_r(V[T + t] - step * gv1, lo1, hi1);
+  }
+};
+
+// One workgroup (one wave) per problem; lane 0 runs Algorithm 1's projected
+// gradient steps on the nominal trajectory.
+template <class R, int NOBS>
+__global__ __launch_bounds__(WAVE) void k_repair(RepairArgs<R> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.x;
+  ProblemDims d;
+  if (!load_dims(a.p, b, d)) return;
+  R* Vs;
+  const TrackView<R> tr = stage_problem(a.p, b, d, a.V_plus, smem, &Vs);
+  unsigned char* rest = smem + stage_lds_bytes<R>(a.p.poly_max, a.p.t_max);
+  const int n_ck = (a.p.t_max + a.seg_len - 1) / a.seg_len;
+  AdjLds<R> L;
+  L.ck = reinterpret_cast<R*>(rest);
+  L.sx = L.ck + (size_t)n_ck * 6 * WAVE;
+  L.cki = reinterpret_cast<int*>(L.sx + (size_t)(a.seg_len + 1) * 6 * WAVE);
+  L.sxi = L.cki + n_ck * WAVE;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    NoiseStream<R> ns;
+    ns.seed = 0;
+    ns.m = 0;
+    ns.pid = 0;
+    ns.it = 0;
+    ns.nominal = true;
+    RepairSink<R> sink;
+    sink.V = Vs;
+    sink.T = d.T;
+    sink.step = a.step;
+    sink.lo0 = a.M.u_lo[0];
+    sink.hi0 = a.M.u_hi[0];
+    sink.lo1 = a.M.u_lo[1];
+    sink.hi1 = a.M.u_hi[1];
+    const State<R> x0 = load_state(a.p.x0 + 6 * (size_t)b);
+    for (int s = 0; s < a.n_steps; ++s)
+      adjoint_lane<R, NOBS>(a.M, a.C, a.ob, tr, x0, Vs, d.T, ns, L, a.seg_len, 0, sink);
+  }
+  __syncthreads();
+  R* out = a.V_safe + 2 * (size_t)d.t0;
+  for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) out[i] = Vs[i];
+}
+
+// ============================================================== execute / warm start
+template <class R>
+struct ExecuteArgs {
+  const int32_t* t_off;
+  int32_t B, t_max;
+  DevModel<R> M;
+  const R* V_exec;
+  const R* V_plus;
+  const R* dist;
+  int32_t n_dist;
+  R* x;
+  R* V;
+  uint32_t* iter;
+  uint32_t* err;
+};
+
+template <class R>
+__global__ __launch_bounds__(WAVE) void k_execute(ExecuteArgs<R> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  R* buf = reinterpret_cast<R*>(smem);
+  const int b = blockIdx.x;
+  const int t0 = a.t_off[b], T = a.t_off[b + 1] - t0;
+  if (T < 1 || T > a.t_max) {
+    if (threadIdx.x == 0) atomicOr(a.err, DERR_T);
+    return;
+  }
+  const R* Vp = a.V_plus + 2 * (size_t)t0;
+  for (int i = threadIdx.x; i < 2 * T; i += blockDim.x) buf[i] = Vp[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const R* Ve = a.V_exec + 2 * (size_t)t0;
+    const R u0 = clamp_r(Ve[0], a.M.u_lo[0], a.M.u_hi[0]);
+    const R u1 = clamp_r(Ve[T], a.M.u_lo[1], a.M.u_hi[1]);
+    State<R> x = load_state(a.x + 6 * (size_t)b);
+    rk4(a.M, step_ctl(a.M, u0, u1), x);
+    const uint32_t it = a.iter[b];
+    if (a.dist && (int64_t)it < (int64_t)a.n_dist) {
+      x.vy += a.dist[(2 * ((size_t)it * a.B + b))];
+      x.om += a.dist[(2 * ((size_t)it * a.B + b)) + 1];
+    }
+    R* xo = a.x + 6 * (size_t)b;
+    xo[0] = x.px;
+    xo[1] = x.py;
+    xo[2] = x.psi;
+    xo[3] = x.vx;
+    xo[4] = x.vy;
+    xo[5] = x.om;
+    a.iter[b] = it + 1u;
+  }
+  R* Vo = a.V + 2 * (size_t)t0;
+  for (int i = threadIdx.x; i < 2 * T; i += blockDim.x) {
+    const int dd = i / T, t = i % T;
+    Vo[i] = buf[dd * T + min(t + 1, T - 1)];
+  }
+}
+
+}  // namespace smppi

@@ -1,0 +1,463 @@
+// Batched plan: hundreds of independent MPPI problems of uneven K and T in one
+// persistent launch.  Workgroups pop (problem, sample-tile) items from a queue
+// ordered longest-horizon first; each tile runs its rollouts, reduces them to a
+// split softmax partial (tile min cost, sum of weights, sum of squared weights,
+// weighted noise sums per step) and takes a ticket on its problem; the tile
+// that takes the last ticket combines the partials in tile order (streaming
+// log-sum-exp rescale) and writes V+ and the weight statistics.  The shield
+// (repair) and the execute/warm-start kernels follow on the same stream; the
+// whole sequence is captured once into a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "common.hpp"
+
+using namespace smppi;
+
+namespace {
+
+constexpr int PART_HDR = 4;  // tile min, sum w, sum w^2, non-finite count
+
+struct FusedArgs {
+  ProblemArgs<float> p;
+  DevModel<float> M;
+  DevCost<float> C;
+  const float* V;
+  float* S;
+  float* V_plus;
+  float* stats;
+  float inv_lambda;
+  const int2* tiles;         // [n_tiles] (problem, tile index within problem)
+  const int32_t* tile_off;   // [B+1] first tile of each problem
+  int n_tiles;
+  int tile;                  // samples per tile
+  float* part;               // [n_tiles][PART_HDR + 2 t_max]
+  uint32_t* queue;           // [1]
+  uint32_t* tickets;         // [B]
+};
+
+template <int NOBS, int BLK, int SPT>
+__global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ float red[BLK / WAVE];
+  __shared__ float wpart[BLK / WAVE][2][UPD_TCHUNK];
+  __shared__ int s_tile;
+  __shared__ uint32_t s_ticket;
+  constexpr int NW = BLK / WAVE;
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  const int pstride = PART_HDR + 2 * a.p.t_max;
+  int staged_b = -1;
+  float* Vs = nullptr;
+  TrackView<float> tr;
+  ProblemDims d;
+  for (;;) {
+    if (tid == 0) s_tile = (int)atomicAdd(a.queue, 1u);
+    __syncthreads();
+    const int tile = s_tile;
+    __syncthreads();
+    if (tile >= a.n_tiles) break;
+    const int2 tk = a.tiles[tile];
+    const int b = __builtin_amdgcn_readfirstlane(tk.x);
+    const int kb = __builtin_amdgcn_readfirstlane(tk.y);
+    if (!load_dims(a.p, b, d)) continue;
+    if (b != staged_b) {
+      tr = stage_problem(a.p, b, d, a.V, smem, &Vs);
+      staged_b = b;
+      __syncthreads();
+    }
+    const uint32_t pid = (uint32_t)(a.p.pid_base + b), it = a.p.iter[b];
+    const State<float> x0 = load_state(a.p.x0 + 6 * (size_t)b);
+    // ---- rollouts
+    float s[SPT];
+    float mn = INFINITY;
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+      const int m = kb * a.tile + j * BLK + tid;
+      s[j] = INFINITY;
+      if (m < d.K) {
+        NoiseStream<float> ns;
+        ns.seed = a.p.seed;
+        ns.m = (uint32_t)m;
+        ns.pid = pid;
+        ns.it = it;
+        ns.nominal = a.p.nominal != 0;
+        s[j] = rollout_sample<float, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, nullptr);
+        a.S[d.k0 + m] = s[j];
+      }
+      if (isfinite(s[j])) mn = fminf(mn, s[j]);
+    }
+    // ---- tile-local softmax partial
+    mn = block_min(mn, red);
+    float om[SPT], z = 0.f, q = 0.f, nf = 0.f;
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+      const int m = kb * a.tile + j * BLK + tid;
+      om[j] = isfinite(s[j]) ? expf(-(s[j] - mn) * a.inv_lambda) : 0.f;
+      z += om[j];
+      q += om[j] * om[j];
+      if (m < d.K && !isfinite(s[j])) nf += 1.f;
+    }
+    z = block_sum(z, red);
+    q = block_sum(q, red);
+    nf = block_sum(nf, red);
+    float* P = a.part + (size_t)(a.tile_off[b] + kb) * pstride;
+    NoiseStream<float> ns[SPT];
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+      ns[j].seed = a.p.seed;
+      ns[j].m = (uint32_t)(kb * a.tile + j * BLK + tid);
+      ns[j].pid = pid;
+      ns[j].it = it;
+      ns[j].nominal = a.p.nominal != 0;
+    }
+    for (int tc = 0; tc < d.T; tc += UPD_TCHUNK) {
+      const int tn = min(UPD_TCHUNK, d.T - tc);
+      for (int tt = 0; tt < tn; ++tt) {
+        const int t = tc + tt;
+        const float v0 = Vs[t], v1 = Vs[d.T + t];
+        float p0 = 0.f, p1 = 0.f;
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) {
+          if (om[j] != 0.f) {
+            float e0, e1;
+            ns[j].at(t, a.C.sigma[0], a.C.sigma[1], e0, e1);
+            p0 += om[j] * (clamp_r(v0 + e0, a.M.u_lo[0], a.M.u_hi[0]) - v0);
+            p1 += om[j] * (clamp_r(v1 + e1, a.M.u_lo[1], a.M.u_hi[1]) - v1);
+          }
+        }
+        p0 = wave_sum(p0);
+        p1 = wave_sum(p1);
+        if (lane == 0) {
+          wpart[wv][0][tt] = p0;
+          wpart[wv][1][tt] = p1;
+        }
+      }
+      __syncthreads();
+      if (tid < 2 * tn) {
+        const int dd = tid / tn, tt = tid % tn;
+        float acc = 0.f;
+        for (int i = 0; i < NW; ++i) acc += wpart[i][dd][tt];
+        P[PART_HDR + dd * d.T + tc + tt] = acc;
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      P[0] = mn;
+      P[1] = z;
+      P[2] = q;
+      P[3] = nf;
+    }
+    // ---- ticket; the last tile of problem b combines
+    __threadfence();
+    __syncthreads();
+    const int ntb = (d.K + a.tile - 1) / a.tile;
+    if (tid == 0) s_ticket = atomicAdd(&a.tickets[b], 1u);
+    __syncthreads();
+    if (s_ticket == (uint32_t)(ntb - 1)) {
+      __threadfence();
+      const float* P0 = a.part + (size_t)a.tile_off[b] * pstride;
+      float gmin = INFINITY;
+      for (int k = 0; k < ntb; ++k) gmin = fminf(gmin, __builtin_nontemporal_load(P0 + (size_t)k * pstride));
+      float Z = 0.f, Q = 0.f, NF = 0.f;
+      for (int k = 0; k < ntb; ++k) {
+        const float* Pk = P0 + (size_t)k * pstride;
+        const float mk = __builtin_nontemporal_load(Pk);
+        const float sc = isfinite(mk) ? expf(-(mk - gmin) * a.inv_lambda) : 0.f;
+        Z += sc * __builtin_nontemporal_load(Pk + 1);
+        Q += sc * sc * __builtin_nontemporal_load(Pk + 2);
+        NF += __builtin_nontemporal_load(Pk + 3);
+      }
+      const float iZ = Z > 0.f ? 1.f / Z : 0.f;
+      const float* Vb = a.V + 2 * (size_t)d.t0;
+      float* Vpb = a.V_plus + 2 * (size_t)d.t0;
+      for (int i = tid; i < 2 * d.T; i += BLK) {
+        float acc = 0.f;
+        for (int k = 0; k < ntb; ++k) {
+          const float* Pk = P0 + (size_t)k * pstride;
+          const float mk = __builtin_nontemporal_load(Pk);
+          const float sc = isfinite(mk) ? expf(-(mk - gmin) * a.inv_lambda) : 0.f;
+          acc += sc * __builtin_nontemporal_load(Pk + PART_HDR + i);
+        }
+        Vpb[i] = Vb[i] + acc * iZ;
+      }
+      if (tid == 0) {
+        a.stats[4 * b + 0] = gmin;
+        a.stats[4 * b + 1] = logf(Z);
+        a.stats[4 * b + 2] = Q > 0.f ? Z * Z / Q : 0.f;
+        a.stats[4 * b + 3] = NF;
+        a.tickets[b] = 0u;
+      }
+    }
+  }
+}
+
+// Problems with K_b = 0 still need V+ = V.
+__global__ void k_copy_empty(const int64_t* k_off, const int32_t* t_off, const float* V, float* V_plus,
+                             float* stats) {
+  const int b = blockIdx.x;
+  if (k_off[b + 1] != k_off[b]) return;
+  const int t0 = t_off[b], T = t_off[b + 1] - t0;
+  for (int i = threadIdx.x; i < 2 * T; i += blockDim.x) V_plus[2 * (size_t)t0 + i] = V[2 * (size_t)t0 + i];
+  if (threadIdx.x == 0) {
+    stats[4 * b + 0] = INFINITY;
+    stats[4 * b + 1] = -INFINITY;
+    stats[4 * b + 2] = 0.f;
+    stats[4 * b + 3] = 0.f;
+  }
+}
+
+// Zeroes the work-queue head and the per-problem tickets (a kernel rather than
+// a memset node, so the sequence can be captured and replayed).
+__global__ void k_reset(uint32_t* queue, uint32_t* tickets, int B) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *queue = 0u;
+  if (i < B) tickets[i] = 0u;
+}
+
+using FusedFn = void (*)(FusedArgs);
+
+template <int NOBS>
+FusedFn pick_fused(int blk, int spt) {
+#define SMPPI_CASE(BL, SP) \
+  if (blk == BL && spt == SP) return k_fused<NOBS, BL, SP>;
+  SMPPI_CASE(64, 1) SMPPI_CASE(64, 2) SMPPI_CASE(64, 4)
+  SMPPI_CASE(128, 1) SMPPI_CASE(128, 2) SMPPI_CASE(128, 4)
+  SMPPI_CASE(256, 1) SMPPI_CASE(256, 2) SMPPI_CASE(256, 4)
+  SMPPI_CASE(512, 1) SMPPI_CASE(512, 2)
+#undef SMPPI_CASE
+  return nullptr;
+}
+
+}  // namespace
+
+struct smppi_plan_s {
+  smppi_ctx ctx = nullptr;
+  smppi_batch batch{};
+  smppi_model model{};
+  smppi_cost cost{};
+  smppi_noise noise{};
+  smppi_track track{};
+  smppi_plan_opts opts{};
+  smppi_plan_buffers bufs{};
+  FusedArgs fa{};
+  FusedFn fn = nullptr;
+  int grid = 0, block = 256, lds = 0;
+  bool any_empty = false;
+  // device allocations owned by the plan
+  int2* tiles = nullptr;
+  int32_t* tile_off = nullptr;
+  float* part = nullptr;
+  uint32_t* counters = nullptr;  // [0] queue, [1..B] tickets
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static smppi_status plan_enqueue(smppi_plan p, hipStream_t s) {
+  smppi_ctx ctx = p->ctx;
+  const int B = p->batch.n_problems;
+  hipLaunchKernelGGL(k_reset, dim3((B + 1 + 255) / 256), dim3(256), 0, s, p->counters, p->counters + 1, B);
+  smppi_status st = check_launch(ctx, "k_reset");
+  if (st) return st;
+  if (p->any_empty) {
+    hipLaunchKernelGGL(k_copy_empty, dim3(B), dim3(64), 0, s, p->batch.k_off, p->batch.t_off,
+                       static_cast<const float*>(p->bufs.V), static_cast<float*>(p->bufs.V_plus),
+                       static_cast<float*>(p->bufs.stats));
+    if ((st = check_launch(ctx, "k_copy_empty"))) return st;
+  }
+  if (p->fa.n_tiles > 0) {
+    hipLaunchKernelGGL(p->fn, dim3(p->grid), dim3(p->block), p->lds, s, p->fa);
+    if ((st = check_launch(ctx, "k_fused"))) return st;
+  }
+  const void* V_exec = p->bufs.V_plus;
+  if (p->opts.repair) {
+    if ((st = repair_t<float>(ctx, &p->batch, &p->model, &p->cost, &p->track, p->bufs.x0, p->bufs.V_plus,
+                              &p->opts.repair_opts, p->bufs.V_safe, s)))
+      return st;
+    V_exec = p->bufs.V_safe;
+  }
+  if (p->opts.execute) {
+    if ((st = execute_t<float>(ctx, &p->batch, &p->model, V_exec, p->bufs.V_plus, p->opts.dist, p->opts.n_dist,
+                               p->bufs.x0, p->bufs.V, p->bufs.iter, s)))
+      return st;
+  }
+  return SMPPI_OK;
+}
+
+extern "C" void smppi_plan_destroy(smppi_plan p) {
+  if (!p) return;
+  (void)hipSetDevice(p->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->tiles) (void)hipFree(p->tiles);
+  if (p->tile_off) (void)hipFree(p->tile_off);
+  if (p->part) (void)hipFree(p->part);
+  if (p->counters) (void)hipFree(p->counters);
+  delete p;
+}
+
+extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                                          const smppi_cost* cost, const smppi_noise* noise,
+                                          const smppi_track* track, const smppi_plan_opts* opts,
+                                          const smppi_plan_buffers* bufs, smppi_plan* out) {
+  if (!ctx || !out) return SMPPI_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  smppi_status st;
+  if ((st = validate_batch(ctx, batch)) || (st = validate_model(ctx, model)) || (st = validate_cost(ctx, cost)) ||
+      (st = validate_track(ctx, track, batch->dtype, batch->t_max)))
+    return st;
+  if (batch->dtype != SMPPI_F32) return fail(ctx, SMPPI_ERR_DTYPE, "plans run in FP32 only");
+  if (!noise || !opts || !bufs) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "noise, opts, bufs are required");
+  if (!(opts->lambda > 0.0) || !std::isfinite(opts->lambda))
+    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "opts.lambda must be > 0");
+  if (!bufs->x0 || !bufs->V || !bufs->iter || !bufs->S || !bufs->V_plus || !bufs->stats)
+    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "plan buffers x0, V, iter, S, V_plus, stats are required");
+  if (opts->repair && ((st = validate_repair(ctx, &opts->repair_opts)))) return st;
+  if (opts->repair && !bufs->V_safe) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "V_safe required with repair");
+  if (opts->execute && opts->dist && opts->n_dist < 0)
+    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "n_dist must be >= 0");
+  const int block = opts->block ? opts->block : 256;
+  const int tile = opts->tile ? opts->tile : block;
+  if (block != 64 && block != 128 && block != 256 && block != 512)
+    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "block must be 64, 128, 256 or 512");
+  if (tile % block != 0) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "tile must be a multiple of block");
+  const int spt = tile / block;
+  FusedFn fn = track->obs_max > 0 ? pick_fused<kMaxObs>(block, spt) : pick_fused<0>(block, spt);
+  if (!fn) return fail(ctx, SMPPI_ERR_UNSUPPORTED, "no fused kernel for block %d, tile %d", block, tile);
+  (void)hipSetDevice(ctx->device);
+  const int B = batch->n_problems;
+
+  // Host copies of the CSR offsets for the tile list (creation-time only).
+  std::vector<int64_t> koff(B + 1);
+  std::vector<int32_t> toff(B + 1);
+  hipError_t e = hipMemcpy(koff.data(), batch->k_off, sizeof(int64_t) * (B + 1), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(k_off)");
+  e = hipMemcpy(toff.data(), batch->t_off, sizeof(int32_t) * (B + 1), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(t_off)");
+  std::vector<int32_t> ntile(B), tile_off(B + 1, 0);
+  bool any_empty = false;
+  for (int b = 0; b < B; ++b) {
+    const int64_t K = koff[b + 1] - koff[b];
+    const int T = toff[b + 1] - toff[b];
+    if (K < 0 || K > batch->k_max || T < 1 || T > batch->t_max)
+      return fail(ctx, SMPPI_ERR_SHAPE, "problem %d: K=%lld T=%d outside k_max/t_max", b, (long long)K, T);
+    ntile[b] = (int)((K + tile - 1) / tile);
+    tile_off[b + 1] = tile_off[b] + ntile[b];
+    any_empty = any_empty || K == 0;
+  }
+  const int n_tiles = tile_off[B];
+  // Longest-processing-time order: problems by T (tile cost ~ tile * T), descending.
+  std::vector<int> order(B);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (toff[x + 1] - toff[x]) > (toff[y + 1] - toff[y]);
+  });
+  std::vector<int2> tl;
+  tl.reserve(n_tiles);
+  for (int b : order)
+    for (int k = 0; k < ntile[b]; ++k) tl.push_back(make_int2(b, k));
+
+  smppi_plan p = new smppi_plan_s();
+  p->ctx = ctx;
+  p->batch = *batch;
+  p->model = *model;
+  p->cost = *cost;
+  p->noise = *noise;
+  p->track = *track;
+  p->opts = *opts;
+  p->bufs = *bufs;
+  p->block = block;
+  p->fn = fn;
+  p->any_empty = any_empty;
+  auto bail = [&](smppi_status s2) {
+    smppi_plan_destroy(p);
+    return s2;
+  };
+  const int pstride = PART_HDR + 2 * batch->t_max;
+  if ((e = hipMalloc(&p->tiles, sizeof(int2) * std::max(1, n_tiles))) != hipSuccess ||
+      (e = hipMalloc(&p->tile_off, sizeof(int32_t) * (B + 1))) != hipSuccess ||
+      (e = hipMalloc(&p->part, sizeof(float) * (size_t)std::max(1, n_tiles) * pstride)) != hipSuccess ||
+      (e = hipMalloc(&p->counters, sizeof(uint32_t) * (B + 1))) != hipSuccess)
+    return bail(hip_fail(ctx, e, "hipMalloc(plan)"));
+  if (n_tiles > 0 && (e = hipMemcpy(p->tiles, tl.data(), sizeof(int2) * n_tiles, hipMemcpyHostToDevice)) != hipSuccess)
+    return bail(hip_fail(ctx, e, "hipMemcpy(tiles)"));
+  if ((e = hipMemcpy(p->tile_off, tile_off.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice)) != hipSuccess)
+    return bail(hip_fail(ctx, e, "hipMemcpy(tile_off)"));
+  if ((e = hipMemset(p->counters, 0, sizeof(uint32_t) * (B + 1))) != hipSuccess)
+    return bail(hip_fail(ctx, e, "hipMemset(counters)"));
+
+  FusedArgs& a = p->fa;
+  a.p = problem_args<float>(ctx, &p->batch, &p->track, &p->noise, bufs->x0, bufs->iter);
+  a.M = dev_model<float>(model);
+  a.C = dev_cost<float>(cost);
+  a.V = static_cast<const float*>(bufs->V);
+  a.S = static_cast<float*>(bufs->S);
+  a.V_plus = static_cast<float*>(bufs->V_plus);
+  a.stats = static_cast<float*>(bufs->stats);
+  a.inv_lambda = (float)(1.0 / opts->lambda);
+  a.tiles = p->tiles;
+  a.tile_off = p->tile_off;
+  a.n_tiles = n_tiles;
+  a.tile = tile;
+  a.part = p->part;
+  a.queue = p->counters;
+  a.tickets = p->counters + 1;
+  p->lds = (int)stage_lds_bytes<float>(track->poly_max, batch->t_max);
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, p->lds);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  int grid = opts->grid > 0 ? opts->grid : ctx->n_cu * per_cu;
+  grid = std::max(1, std::min(grid, std::max(1, n_tiles)));
+  p->grid = grid;
+  if (opts->repair || opts->execute) {
+    // the shield and execute kernels need their own validation-time state only
+  }
+  if (opts->use_graph) {
+    if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+      return bail(hip_fail(ctx, e, "hipStreamCreate"));
+    if ((e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return bail(hip_fail(ctx, e, "hipStreamBeginCapture"));
+    st = plan_enqueue(p, p->cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->cap_stream, &g);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      return bail(st);
+    }
+    if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipStreamEndCapture"));
+    p->graph = g;
+    if ((e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0)) != hipSuccess)
+      return bail(hip_fail(ctx, e, "hipGraphInstantiate"));
+  }
+  *out = p;
+  return SMPPI_OK;
+}
+
+extern "C" smppi_status smppi_plan_launch(smppi_plan p, void* stream) {
+  if (!p) return SMPPI_ERR_INVALID_ARGUMENT;
+  (void)hipSetDevice(p->ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->exec) {
+    hipError_t e = hipGraphLaunch(p->exec, s);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "hipGraphLaunch");
+    return SMPPI_OK;
+  }
+  return plan_enqueue(p, s);
+}
+
+// Launch geometry actually used by a plan: grid, block, tile, tiles.
+extern "C" smppi_status smppi_plan_info(smppi_plan p, int32_t* grid, int32_t* block, int32_t* tile,
+                                        int32_t* n_tiles) {
+  if (!p) return SMPPI_ERR_INVALID_ARGUMENT;
+  if (grid) *grid = p->grid;
+  if (block) *block = p->block;
+  if (tile) *tile = p->fa.tile;
+  if (n_tiles) *n_tiles = p->fa.n_tiles;
+  return SMPPI_OK;
+}

@@ -1,0 +1,162 @@
+"""GPU parity of the batched persistent plan (fused rollout + split softmax +
+update, shield, execute; HIP graph) against the plain path and the oracle,
+including sampled parity at the full workload sizes."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2302_11719_amd import core
+from paper_2302_11719_amd import workloads as W
+
+from gpu_helpers import ctx, oracle_iteration, params, prep, ragged_problems, rel_err, say
+
+pytestmark = pytest.mark.gpu
+F32 = torch.float32
+BAND = 1e-3
+
+
+def _plain(db, M, C, seed, lam):
+    c = ctx()
+    S = core.rollout(c, db, M, C, seed)
+    w, stats = core.weights(c, db, S, lam)
+    Vp = core.update(c, db, M, C, seed, w)
+    return S, w, stats, Vp
+
+
+@pytest.mark.parametrize("block,tile", [(256, 256), (64, 128), (128, 512), (512, 512)])
+def test_plan_matches_plain_path(block, tile):
+    probs = prep(ragged_problems(), F32)
+    M, C = params(F32)
+    db = core.DeviceBatch(probs, dtype=F32)
+    say(f"plan vs plain block={block} tile={tile}")
+    S, w, stats, Vp = _plain(db, M, C, 5, W.LAMBDA)
+    plan = core.Plan(ctx(), db, M, C, 5, W.LAMBDA, block=block, tile=tile, use_graph=False)
+    plan.launch()
+    torch.cuda.synchronize()
+    assert ctx().device_errors() == 0
+    assert rel_err(plan.S.cpu().numpy(), S.cpu().numpy().astype(np.float64)).max() <= 1e-6
+    assert np.abs(plan.V_plus.cpu().numpy() - Vp.cpu().numpy()).max() <= 2e-5
+    ps, st = plan.stats.cpu().numpy().reshape(-1, 4), stats.cpu().numpy()
+    assert np.allclose(ps[:, 0], st[:, 0], rtol=1e-6)
+    assert np.allclose(ps[:, 2], st[:, 2], rtol=1e-3)
+    assert np.array_equal(ps[:, 3], st[:, 3])
+    # and the oracle, problem by problem (V+ given the device costs)
+    Ss = db.per_problem(plan.S)
+    Vps = db.controls(plan.V_plus)
+    for b, p in enumerate(probs):
+        r = oracle_iteration(p, M, C, 5, W.LAMBDA)
+        ok = r["margin"] > BAND
+        assert rel_err(Ss[b], r["S"])[ok].max() <= 1e-4
+        w_ref, _ = oracle.weights(Ss[b].astype(np.float64), W.LAMBDA)
+        assert np.abs(Vps[b] - oracle.update(p.V, w_ref, r["eps"])).max() <= 1e-5
+
+
+def test_plan_graph_replays_match_eager_plan():
+    """Closed loop on the device: 4 graph replays (with eager work and synchronisations
+    in between) equal 4 launches of the same plan without a graph."""
+    probs = prep(ragged_problems(), F32)
+    M, C = params(F32)
+    dist = torch.as_tensor(W.disturbances(1, 8 * len(probs)).reshape(-1), dtype=F32, device="cuda")
+    rep = dict(n_steps=3, step=0.05, objective=W.OBJ_SHIELD)
+    dbs = [core.DeviceBatch(probs, dtype=F32) for _ in range(2)]
+    plans = [core.Plan(ctx(), dbs[i], M, C, 9, W.LAMBDA, repair=rep, execute=True, dist=dist.view(8, -1),
+                       use_graph=(i == 0)) for i in range(2)]
+    for step in range(4):
+        say(f"graph replay {step}")
+        for pl in plans:
+            pl.launch()
+            torch.cuda.synchronize()
+            _ = torch.zeros(1000, device="cuda").sum().item()  # eager work between replays
+        for name in ("x0", "V", "iter"):
+            assert torch.equal(getattr(dbs[0], name), getattr(dbs[1], name)), (step, name)
+        assert torch.equal(plans[0].V_safe, plans[1].V_safe)
+        assert torch.equal(plans[0].S, plans[1].S)
+    assert ctx().device_errors() == 0
+    assert np.array_equal(dbs[0].iter.cpu().numpy(), np.arange(1, 6) + 4)
+
+
+def test_closed_loop_teacher_forced_c1():
+    """Config-1 shape (K=4096, T=50): 4 receding-horizon steps through the graph plan with
+    the shield and the disturbed plant; every step checked against the oracle from the
+    device's own state (teacher forcing)."""
+    p = prep([W.config1()], F32)[0]
+    M, C = params(F32)
+    db = core.DeviceBatch([p], dtype=F32)
+    dist_np = W.disturbances(0, 8).astype(np.float32)
+    dist = torch.as_tensor(dist_np.reshape(-1), device="cuda")
+    rep = dict(n_steps=10, step=0.05, objective=W.OBJ_SHIELD)
+    plan = core.Plan(ctx(), db, M, C, 0, W.LAMBDA, repair=rep, execute=True, dist=dist.view(8, 1, 2),
+                     use_graph=True)
+    for k in range(4):
+        x_b = db.x0.cpu().numpy().astype(np.float64)
+        V_b = db.controls(db.V)[0].astype(np.float64)
+        it_b = int(db.iter.item())
+        say(f"closed loop step {k} it={it_b}")
+        plan.launch()
+        torch.cuda.synchronize()
+        S = plan.S.cpu().numpy().astype(np.float64)
+        S_ref, eps, margin = oracle.rollout(M, C, p.track, x_b, V_b, p.K, 0, 0, it_b)
+        ok = margin > BAND
+        assert rel_err(S, S_ref)[ok].max() <= 1e-4
+        w_ref, _ = oracle.weights(S, W.LAMBDA)
+        Vp = db.controls(plan.V_plus)[0].astype(np.float64)
+        assert np.abs(Vp - oracle.update(V_b, w_ref, eps)).max() <= 1e-5
+        Vs = db.controls(plan.V_safe)[0].astype(np.float64)
+        Vs_ref = oracle.repair(M, C, p.track, x_b, Vp, 10, 0.05, W.OBJ_SHIELD)
+        assert np.abs(Vs - Vs_ref).max() <= 1e-3 * max(1.0, np.linalg.norm(Vp))
+        x_ref = oracle.execute(M, x_b, Vs[0], dist_np[it_b])
+        assert np.abs(db.x0.cpu().numpy() - x_ref).max() <= 1e-5
+        assert np.array_equal(db.controls(db.V)[0], oracle.shift(Vp).astype(np.float32))
+    assert ctx().device_errors() == 0
+
+
+def _sampled(p, S_dev, M, C, seed, n, rng):
+    ms = np.sort(rng.choice(p.K, size=min(n, p.K), replace=False))
+    S_ref, _, margin = oracle.rollout(M, C, p.track, p.x0, p.V, 0, seed, p.pid, p.it, want_eps=False,
+                                      samples=ms)
+    ok = margin > BAND
+    return rel_err(S_dev[ms], S_ref)[ok], (~ok).sum()
+
+
+def test_full_size_config2_sampled():
+    """512 ragged problems (K log-uniform in [256, 16384], T in [20, 100]) in the plan's
+    launch configuration: sampled per-sample costs vs the oracle, and V+ vs the plain
+    weights + update kernels applied to the plan's own costs."""
+    probs = prep(W.config2(), F32)
+    M, C = params(F32)
+    db = core.DeviceBatch(probs, dtype=F32)
+    say(f"config2 full: B={db.B} sum K={db.sum_K}")
+    plan = core.Plan(ctx(), db, M, C, 0, W.LAMBDA, use_graph=True)
+    plan.launch()
+    torch.cuda.synchronize()
+    assert ctx().device_errors() == 0
+    Ss = db.per_problem(plan.S)
+    rng = np.random.default_rng(0)
+    for b in rng.choice(db.B, size=12, replace=False):
+        e, n_ex = _sampled(probs[b], Ss[b].astype(np.float64), M, C, 0, 16, rng)
+        assert e.max() <= 1e-4, (b, e.max())
+    w, stats = core.weights(ctx(), db, plan.S, W.LAMBDA)
+    Vp = core.update(ctx(), db, M, C, 0, w)
+    torch.cuda.synchronize()
+    assert np.abs(plan.V_plus.cpu().numpy() - Vp.cpu().numpy()).max() <= 2e-5
+    assert np.all(np.isfinite(plan.stats.cpu().numpy()))
+
+
+def test_full_size_config4_sampled():
+    """K=65536, T=100 with 64 obstacles: sampled costs of the plain rollout and of the
+    plan vs the oracle; plan V+ vs the plain path."""
+    p = prep([W.config4()], F32)[0]
+    M, C = params(F32)
+    db = core.DeviceBatch([p], dtype=F32)
+    say("config4 full: K=65536 T=100 obstacles=64")
+    S, w, stats, Vp = _plain(db, M, C, 0, W.LAMBDA)
+    plan = core.Plan(ctx(), db, M, C, 0, W.LAMBDA, use_graph=True)
+    plan.launch()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    e, n_ex = _sampled(p, S.cpu().numpy().astype(np.float64), M, C, 0, 48, rng)
+    assert e.max() <= 1e-4
+    assert rel_err(plan.S.cpu().numpy(), S.cpu().numpy().astype(np.float64)).max() <= 1e-6
+    assert np.abs(plan.V_plus.cpu().numpy() - Vp.cpu().numpy()).max() <= 2e-5
+    assert ctx().device_errors() == 0
