@@ -1,0 +1,291 @@
+"""Benchmark of the Shield-MPPI sampled-rollout step on one MI355X.
+
+Headline workload: the closed-loop configuration, K = 4096 samples, T = 50 steps,
+one problem on a seeded spline track (12 control points, radius 15 +- 4 m,
+half width 0.9 m), disturbance sigma = 0.3 on v_y and omega.  One timed step is
+one receding-horizon Shield-MPPI iteration run by the batched plan in a HIP
+graph: fused rollout + softmax weights + update, the shield (10 projected
+gradient steps of the hand-written adjoint, step 0.05), and execute + warm
+start on the device.  value = rollout-steps/s = K*T*steps / elapsed.
+
+Also measured in the same run (reported beside the headline): the plain
+per-call form (rollout, weights, update, execute launches, no shield), the
+batched plan on B identical-shape problems vs the plain per-problem loop, the
+512-problem ragged batch, the K=65536/T=100/64-obstacle rollout, per-stage
+durations (HIP events), the dominant kernel's roofline, and the FP64 CPU oracle
+on a bounded sample of the headline workload.
+
+usage: python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--skip-cpu] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic FP32 operation counts per rollout-step (FMA = 2, transcendental = 1,
+# compares/selects not counted); derivation in DESIGN.md, section "Roofline".
+FLOP_STEP_POLY = 345      # noise, clip, cost, RK4 (4 derivative evaluations), 9-segment window, DCBF
+FLOP_STEP_PER_OBS = 9     # one circular obstacle barrier + penalty + indicator test
+FLOP_UPDATE_STEP = 4      # w * eps' accumulated for two controls
+PEAK_FP32 = 157.3e12      # MI355X FP32 vector peak (packed FMA on every lane)
+PEAK_HBM = 8.0e12
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="headline only (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2302_11719_amd import core
+    from paper_2302_11719_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(1)
+    ctx = core.Context(0)
+    M, C = W.params_f32(W.MODEL, W.COST)
+    lam = W.LAMBDA
+    rep = dict(n_steps=10, step=0.05, objective=W.OBJ_SHIELD)
+    K, T = 4096, 50
+    steps, warm = args.steps, args.warmup
+    seed = 0
+
+    def sync():
+        torch.cuda.synchronize()
+
+    # ------------------------------------------------------------------ headline
+    prob = W.round_to_f32(W.config1(K=K, T=T))
+    n_dist = warm + steps + 8
+    dist = torch.as_tensor(W.disturbances(0, n_dist).astype(np.float32).reshape(n_dist, 1, 2), device="cuda")
+    db = core.DeviceBatch([prob], dtype=torch.float32)
+    plan = core.Plan(ctx, db, M, C, seed, lam, repair=rep, execute=True, dist=dist, use_graph=True)
+    _log(f"headline: K={K} T={T} plan={plan.info()} warmup={warm} steps={steps}")
+    for _ in range(warm):
+        plan.launch()
+    sync()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        plan.launch()
+    ev1.record()
+    sync()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    assert ctx.device_errors() == 0
+    ms_per_step = 1e3 * wall / steps
+    value = K * T * steps / wall
+    _log(f"  {ms_per_step:.4f} ms/iter (events {ev_ms / steps:.4f}), {value:.4g} rollout-steps/s")
+
+    # per-stage durations of the same work (HIP events between the stages)
+    db_p = core.DeviceBatch([prob], dtype=torch.float32)
+    plan_p = core.Plan(ctx, db_p, M, C, seed, lam, repair=rep, execute=True, dist=dist, use_graph=False)
+    n_prof = min(steps, 100)
+    fused, repair_t, exec_t = [], [], []
+    for i in range(warm + n_prof):
+        plan_p.launch_profiled()
+        f, r, e = plan_p.stage_ms()
+        if i >= warm:
+            fused.append(f)
+            repair_t.append(r)
+            exec_t.append(e)
+    stage = dict(fused_rollout_weights_update_ms=float(np.mean(fused)), shield_repair_ms=float(np.mean(repair_t)),
+                 execute_ms=float(np.mean(exec_t)))
+    _log(f"  stages: {stage}")
+
+    flop_step = FLOP_STEP_POLY + FLOP_UPDATE_STEP
+    dominant = "k_fused" if stage["fused_rollout_weights_update_ms"] >= stage["shield_repair_ms"] else "k_repair"
+    if dominant == "k_fused":
+        flops = K * T * flop_step
+        dur = stage["fused_rollout_weights_update_ms"] * 1e-3
+    else:
+        # one problem: n_s x (forward T steps + reverse T steps with recompute ~ 3x forward)
+        flops = rep["n_steps"] * T * FLOP_STEP_POLY * 4
+        dur = stage["shield_repair_ms"] * 1e-3
+    achieved = flops / dur
+    roofline = {"bound": "alu", "kernel": dominant, "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                "flop_per_launch": flops, "avg_launch_ms": dur * 1e3}
+
+    result = {
+        "metric": "rollout-steps/s and ms/MPPI iter (K=4096,T=50); batched+adjoint vs plain",
+        "value": value, "unit": "rollout-steps/s", "n_gpus": 1, "steps": steps, "warmup": warm,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "closed-loop Shield-MPPI iteration (batched+adjoint plan, HIP graph): "
+                               "K=4096, T=50, 1 problem, spline track, shield 10x0.05, plant disturbance 0.3",
+                   "K": K, "T": T, "problems": 1, "repair_steps": 10, "parallelism": "single-gpu"},
+        "stages_ms": stage,
+        "roofline": roofline,
+    }
+
+    if not args.quick:
+        result["forms"] = extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync)
+    if not args.skip_cpu:
+        result["cpu_baseline"] = cpu_baseline(W, K, T, lam, rep)
+    print(json.dumps(result), flush=True)
+
+
+def _time(fn, n, warm, sync):
+    for _ in range(warm):
+        fn()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        fn()
+    sync()
+    return (time.perf_counter() - t0) / n
+
+
+def extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync):
+    import torch
+
+    out = {}
+    seed = 0
+    # plain per-call form on the headline problem: rollout, weights, update, execute (no shield)
+    prob = W.round_to_f32(W.config1(K=K, T=T))
+    db = core.DeviceBatch([prob], dtype=torch.float32)
+
+    def plain_iter():
+        S = core.rollout(ctx, db, M, C, seed)
+        w, _ = core.weights(ctx, db, S, lam)
+        Vp = core.update(ctx, db, M, C, seed, w)
+        core.execute(ctx, db, M, Vp, Vp)
+
+    dt = _time(plain_iter, 200, 20, sync)
+    out["plain_single"] = {"ms_per_iter": dt * 1e3, "rollout_steps_per_s": K * T / dt, "shield": False}
+
+    # batched plan without the shield on the same problem (isolates fusion + graph)
+    db2 = core.DeviceBatch([prob], dtype=torch.float32)
+    pl = core.Plan(ctx, db2, M, C, seed, lam, execute=True, use_graph=True)
+    dt = _time(pl.launch, 200, 20, sync)
+    out["batched_single_noshield"] = {"ms_per_iter": dt * 1e3, "rollout_steps_per_s": K * T / dt}
+    pl.close()
+    _log(f"  plain single {out['plain_single']}, batched no-shield {out['batched_single_noshield']}")
+
+    # B identical-shape problems: plain per-problem loop vs the batched+adjoint plan
+    for B in (8, 64, 512):
+        probs = [W.round_to_f32(p) for p in W.identical_batch(B, K, T)]
+        dbs = [core.DeviceBatch([p], dtype=torch.float32, pid_base=b) for b, p in enumerate(probs)]
+
+        def loop():
+            for d in dbs:
+                S = core.rollout(ctx, d, M, C, seed)
+                w, _ = core.weights(ctx, d, S, lam)
+                core.update(ctx, d, M, C, seed, w)
+
+        n_it = 3 if B == 512 else 10
+        t_plain = _time(loop, n_it, 1, sync)
+        dbB = core.DeviceBatch(probs, dtype=torch.float32)
+        plB = core.Plan(ctx, dbB, M, C, seed, lam, repair=rep, use_graph=True)
+        t_b = _time(plB.launch, n_it, 2, sync)
+        out[f"identical_B{B}"] = {"plain_loop_ms": t_plain * 1e3, "batched_adjoint_ms": t_b * 1e3,
+                                  "plain_rollout_steps_per_s": B * K * T / t_plain,
+                                  "batched_rollout_steps_per_s": B * K * T / t_b, "speedup": t_plain / t_b}
+        _log(f"  B={B}: {out[f'identical_B{B}']}")
+        plB.close()
+        del dbs, dbB
+
+    # the 512-problem ragged batch (K log-uniform [256, 16384], T uniform [20, 100])
+    probs = [W.round_to_f32(p) for p in W.config2()]
+    steps_total = sum(p.K * p.T for p in probs)
+    dbR = core.DeviceBatch(probs, dtype=torch.float32)
+    plR = core.Plan(ctx, dbR, M, C, seed, lam, use_graph=True)
+    t_r = _time(plR.launch, 5, 2, sync)
+    dbs = [core.DeviceBatch([p], dtype=torch.float32, pid_base=b) for b, p in enumerate(probs)]
+
+    def loopR():
+        for d in dbs:
+            S = core.rollout(ctx, d, M, C, seed)
+            w, _ = core.weights(ctx, d, S, lam)
+            core.update(ctx, d, M, C, seed, w)
+
+    t_rp = _time(loopR, 2, 1, sync)
+    out["ragged_B512"] = {"rollout_steps": steps_total, "batched_ms": t_r * 1e3,
+                          "batched_rollout_steps_per_s": steps_total / t_r, "plain_loop_ms": t_rp * 1e3,
+                          "plain_rollout_steps_per_s": steps_total / t_rp, "plan": plR.info()}
+    _log(f"  ragged: {out['ragged_B512']}")
+    plR.close()
+    del dbs
+
+    # large single problem: K=65536, T=100, 64 obstacles (rollout kernel alone and the plan)
+    p4 = W.round_to_f32(W.config4())
+    db4 = core.DeviceBatch([p4], dtype=torch.float32)
+    S4 = db4.new_S()
+    t4 = _time(lambda: core.rollout(ctx, db4, M, C, seed, S=S4), 20, 3, sync)
+    fl4 = (FLOP_STEP_POLY + 64 * FLOP_STEP_PER_OBS) * p4.K * p4.T
+    pl4 = core.Plan(ctx, db4, M, C, seed, lam, use_graph=True)
+    t4p = _time(pl4.launch, 20, 3, sync)
+    out["large_K65536_T100_obs64"] = {
+        "rollout_ms": t4 * 1e3, "rollout_steps_per_s": p4.K * p4.T / t4,
+        "rollout_achieved_TFLOPs": fl4 / t4 / 1e12, "rollout_frac_fp32_peak": fl4 / t4 / PEAK_FP32,
+        "plan_ms": t4p * 1e3, "plan_rollout_steps_per_s": p4.K * p4.T / t4p}
+    _log(f"  large: {out['large_K65536_T100_obs64']}")
+    pl4.close()
+
+    # config 3: 64 problems x (K=2048, T=50), batched plan with and without the shield
+    p3 = [W.round_to_f32(p) for p in W.config3()]
+    db3 = core.DeviceBatch(p3, dtype=torch.float32)
+    pa = core.Plan(ctx, db3, M, C, seed, lam, repair=rep, use_graph=True)
+    pb = core.Plan(ctx, db3, M, C, seed, lam, use_graph=True)
+    ta = _time(pa.launch, 20, 3, sync)
+    tb = _time(pb.launch, 20, 3, sync)
+    out["c3_B64_K2048_T50"] = {"with_shield_ms": ta * 1e3, "without_shield_ms": tb * 1e3}
+    _log(f"  c3: {out['c3_B64_K2048_T50']}")
+    pa.close()
+    pb.close()
+    return out
+
+
+def cpu_baseline(W, K, T, lam, rep):
+    """The FP64 oracle, as it stands, on a bounded sample of the headline workload:
+    a few closed-loop iterations (rollout of all K samples, weights, update, shield,
+    plant) with the rollout threaded over the host's cores."""
+    import oracle
+
+    cores = min(os.cpu_count() or 1, 16)
+    p = W.config1(K=K, T=T)
+    x, V = p.x0.copy(), p.V.copy()
+    dist = W.disturbances(0, 64)
+    n_it = 0
+    t0 = time.perf_counter()
+    while True:
+        r = oracle.mppi_iteration(W.MODEL, W.COST, p.track, x, V, K, 0, 0, n_it, lam, n_threads=cores)
+        Vs = oracle.repair(W.MODEL, W.COST, p.track, x, r["V_plus"], rep["n_steps"], rep["step"], rep["objective"])
+        x = oracle.execute(W.MODEL, x, Vs[0], dist[n_it])
+        V = oracle.shift(r["V_plus"])
+        n_it += 1
+        el = time.perf_counter() - t0
+        if el > 10.0 or n_it >= 60:
+            break
+    return {"value": K * T * n_it / el, "unit": "rollout-steps/s", "cores": cores, "kind": "oracle",
+            "ms_per_iter": 1e3 * el / n_it,
+            "sample": f"{n_it} closed-loop iterations of the headline workload (K={K}, T={T}, shield on), "
+                      f"FP64 oracle, rollout threaded over {cores} host threads"}
+
+
+if __name__ == "__main__":
+    main()

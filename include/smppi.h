@@ -261,6 +261,12 @@ smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batch, const sm
  * persistent launch, then (optionally) the shield and the execute/warm start. */
 smppi_status smppi_plan_launch(smppi_plan plan, void* stream);
 void smppi_plan_destroy(smppi_plan plan);
+/* Profiling: the same work as smppi_plan_launch, enqueued without the graph and
+ * with HIP events recorded between the stages on `stream`; smppi_plan_stage_ms
+ * waits for the last profiled launch and returns its stage durations (ms):
+ * reset + fused rollout/weights/update, shield repair, execute/warm start. */
+smppi_status smppi_plan_launch_profiled(smppi_plan plan, void* stream);
+smppi_status smppi_plan_stage_ms(smppi_plan plan, float* fused_ms, float* repair_ms, float* execute_ms);
 /* Launch geometry the plan uses (any output pointer may be NULL). */
 smppi_status smppi_plan_info(smppi_plan plan, int32_t* grid, int32_t* block, int32_t* tile, int32_t* n_tiles);
 

@@ -244,6 +244,17 @@ class Plan:
     def launch(self):
         self.ctx.check(L.lib().smppi_plan_launch(self.h, ctypes.c_void_p(_stream())), "smppi_plan_launch")
 
+    def launch_profiled(self):
+        self.ctx.check(L.lib().smppi_plan_launch_profiled(self.h, ctypes.c_void_p(_stream())),
+                       "smppi_plan_launch_profiled")
+
+    def stage_ms(self):
+        """(fused, repair, execute) durations in ms of the last profiled launch."""
+        f, r, e = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+        self.ctx.check(L.lib().smppi_plan_stage_ms(self.h, ctypes.byref(f), ctypes.byref(r), ctypes.byref(e)),
+                       "smppi_plan_stage_ms")
+        return f.value, r.value, e.value
+
     def info(self):
         g, b, t, n = (ctypes.c_int32() for _ in range(4))
         self.ctx.check(L.lib().smppi_plan_info(self.h, ctypes.byref(g), ctypes.byref(b), ctypes.byref(t),

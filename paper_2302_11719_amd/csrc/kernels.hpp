@@ -286,8 +286,8 @@ __global__ __launch_bounds__(UPD_BLOCK) void k_update(UpdateArgs<R> a) {
       }
     }
     __syncthreads();
-    if ((int)threadIdx.x < 2 * tn) {
-      const int dd = threadIdx.x / tn, tt = threadIdx.x % tn;
+    for (int e = threadIdx.x; e < 2 * tn; e += UPD_BLOCK) {
+      const int dd = e / tn, tt = e % tn;
       R s = R(0);
       for (int i = 0; i < UPD_BLOCK / WAVE; ++i) s += wpart[i][dd][tt];
       gp[dd * d.T + tc + tt] = s;

@@ -137,8 +137,8 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
         }
       }
       __syncthreads();
-      if (tid < 2 * tn) {
-        const int dd = tid / tn, tt = tid % tn;
+      for (int e = tid; e < 2 * tn; e += BLK) {
+        const int dd = e / tn, tt = e % tn;
         float acc = 0.f;
         for (int i = 0; i < NW; ++i) acc += wpart[i][dd][tt];
         P[PART_HDR + dd * d.T + tc + tt] = acc;
@@ -255,11 +255,28 @@ struct smppi_plan_s {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
-static smppi_status plan_enqueue(smppi_plan p, hipStream_t s) {
+static smppi_status mark(smppi_plan p, hipStream_t s, int i, bool profiled) {
+  if (!profiled) return SMPPI_OK;
+  if (!p->ev[i]) {
+    hipError_t e = hipEventCreate(&p->ev[i]);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "hipEventCreate");
+  }
+  hipError_t e = hipEventRecord(p->ev[i], s);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "hipEventRecord");
+  return SMPPI_OK;
+}
+
+// Records event i of a profiled launch (no-op for ordinary launches).
+static smppi_status mark(smppi_plan p, hipStream_t s, int i, bool profiled);
+
+static smppi_status plan_enqueue(smppi_plan p, hipStream_t s, bool profiled = false) {
   smppi_ctx ctx = p->ctx;
   const int B = p->batch.n_problems;
+  smppi_status st0 = mark(p, s, 0, profiled);
+  if (st0) return st0;
   hipLaunchKernelGGL(k_reset, dim3((B + 1 + 255) / 256), dim3(256), 0, s, p->counters, p->counters + 1, B);
   smppi_status st = check_launch(ctx, "k_reset");
   if (st) return st;
@@ -273,6 +290,7 @@ static smppi_status plan_enqueue(smppi_plan p, hipStream_t s) {
     hipLaunchKernelGGL(p->fn, dim3(p->grid), dim3(p->block), p->lds, s, p->fa);
     if ((st = check_launch(ctx, "k_fused"))) return st;
   }
+  if ((st = mark(p, s, 1, profiled))) return st;
   const void* V_exec = p->bufs.V_plus;
   if (p->opts.repair) {
     if ((st = repair_t<float>(ctx, &p->batch, &p->model, &p->cost, &p->track, p->bufs.x0, p->bufs.V_plus,
@@ -280,12 +298,13 @@ static smppi_status plan_enqueue(smppi_plan p, hipStream_t s) {
       return st;
     V_exec = p->bufs.V_safe;
   }
+  if ((st = mark(p, s, 2, profiled))) return st;
   if (p->opts.execute) {
     if ((st = execute_t<float>(ctx, &p->batch, &p->model, V_exec, p->bufs.V_plus, p->opts.dist, p->opts.n_dist,
                                p->bufs.x0, p->bufs.V, p->bufs.iter, s)))
       return st;
   }
-  return SMPPI_OK;
+  return mark(p, s, 3, profiled);
 }
 
 extern "C" void smppi_plan_destroy(smppi_plan p) {
@@ -295,6 +314,8 @@ extern "C" void smppi_plan_destroy(smppi_plan p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  for (hipEvent_t e : p->ev)
+    if (e) (void)hipEventDestroy(e);
   if (p->tiles) (void)hipFree(p->tiles);
   if (p->tile_off) (void)hipFree(p->tile_off);
   if (p->part) (void)hipFree(p->part);
@@ -449,6 +470,28 @@ extern "C" smppi_status smppi_plan_launch(smppi_plan p, void* stream) {
     return SMPPI_OK;
   }
   return plan_enqueue(p, s);
+}
+
+extern "C" smppi_status smppi_plan_launch_profiled(smppi_plan p, void* stream) {
+  if (!p) return SMPPI_ERR_INVALID_ARGUMENT;
+  (void)hipSetDevice(p->ctx->device);
+  return plan_enqueue(p, static_cast<hipStream_t>(stream), true);
+}
+
+extern "C" smppi_status smppi_plan_stage_ms(smppi_plan p, float* fused_ms, float* repair_ms, float* execute_ms) {
+  if (!p || !p->ev[3]) return p ? smppi::fail(p->ctx, SMPPI_ERR_INVALID_ARGUMENT, "no profiled launch yet")
+                                : SMPPI_ERR_INVALID_ARGUMENT;
+  hipError_t e = hipEventSynchronize(p->ev[3]);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "hipEventSynchronize");
+  float t[3] = {0.f, 0.f, 0.f};
+  for (int i = 0; i < 3; ++i) {
+    e = hipEventElapsedTime(&t[i], p->ev[i], p->ev[i + 1]);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "hipEventElapsedTime");
+  }
+  if (fused_ms) *fused_ms = t[0];
+  if (repair_ms) *repair_ms = t[1];
+  if (execute_ms) *execute_ms = t[2];
+  return SMPPI_OK;
 }
 
 // Launch geometry actually used by a plan: grid, block, tile, tiles.
