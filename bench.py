@@ -104,7 +104,7 @@ def main():
     db_p = core.DeviceBatch([prob], dtype=torch.float32)
     plan_p = core.Plan(ctx, db_p, M, C, seed, lam, repair=rep, execute=True, dist=dist, use_graph=False)
     n_prof = min(steps, 100)
-    fused, repair_t, exec_t = [], [], []
+    fused, repair_t, exec_t, active = [], [], [], []
     for i in range(warm + n_prof):
         plan_p.launch_profiled()
         f, r, e = plan_p.stage_ms()
@@ -112,8 +112,14 @@ def main():
             fused.append(f)
             repair_t.append(r)
             exec_t.append(e)
-    stage = dict(fused_rollout_weights_update_ms=float(np.mean(fused)), shield_repair_ms=float(np.mean(repair_t)),
-                 execute_ms=float(np.mean(exec_t)))
+            # the shield changed the MPPI output (some DCBF condition was violated)
+            active.append(not torch.equal(plan_p.V_safe, plan_p.V_plus))
+    act = np.array(active)
+    rt = np.array(repair_t)
+    stage = dict(fused_rollout_weights_update_ms=float(np.mean(fused)), shield_repair_ms=float(np.mean(rt)),
+                 execute_ms=float(np.mean(exec_t)), shield_active_fraction=float(act.mean()),
+                 shield_ms_when_active=float(rt[act].mean()) if act.any() else None,
+                 shield_ms_when_idle=float(rt[~act].mean()) if (~act).any() else None)
     _log(f"  stages: {stage}")
 
     flop_step = FLOP_STEP_POLY + FLOP_UPDATE_STEP

@@ -37,12 +37,22 @@ struct DevObjective {
 };
 
 // ---------------------------------------------------------------- math shims
-__device__ __forceinline__ void sincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
+// FP32 uses the hardware transcendental units directly: v_sin/v_cos take their
+// argument in revolutions, so an angle is first scaled by 1/(2 pi) and reduced
+// to [0, 1) with v_fract (exact), v_rcp/v_sqrt/v_log are the single-instruction
+// approximations (about 1 ulp).  FP64 uses the correctly rounded library calls.
+__device__ __forceinline__ void sincos_r(float x, float* s, float* c) {
+  const float r = __builtin_amdgcn_fractf(x * 0.15915494309189535f);
+  *s = __builtin_amdgcn_sinf(r);
+  *c = __builtin_amdgcn_cosf(r);
+}
 __device__ __forceinline__ void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
-__device__ __forceinline__ float rcp_r(float x) { return 1.0f / x; }
+__device__ __forceinline__ float rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp_r(double x) { return 1.0 / x; }
-__device__ __forceinline__ float sqrt_r(float x) { return sqrtf(x); }
+__device__ __forceinline__ float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+__device__ __forceinline__ float exp_r(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+__device__ __forceinline__ double exp_r(double x) { return exp(x); }
 template <class R> __device__ __forceinline__ R clamp_r(R x, R lo, R hi) { return fmin(fmax(x, lo), hi); }
 
 // ---------------------------------------------------------------- noise
@@ -69,11 +79,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1) {
   const float ua = (float)((a >> 8) + 1u) * 0x1p-24f;
   const float ub = (float)((b >> 8) + 1u) * 0x1p-24f;
-  const float r = sqrtf(-2.0f * logf(ua));
-  float s, c;
-  sincospif(2.0f * ub, &s, &c);
-  z0 = r * c;
-  z1 = r * s;
+  // -2 ln u = -2 ln 2 * log2 u; v_sin/v_cos of ub in revolutions give sin/cos(2 pi ub)
+  const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ua));
+  z0 = r * __builtin_amdgcn_cosf(ub);
+  z1 = r * __builtin_amdgcn_sinf(ub);
 }
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& z0, double& z1) {
   const double ua = (double)((a >> 8) + 1u) * 0x1p-24;
@@ -112,9 +121,10 @@ struct NoiseStream {
       e1 = R(0);
       return;
     }
-    const int o = (t & 1) * 2;
-    e0 = sig0 * z[o];
-    e1 = sig1 * z[o + 1];
+    // selects rather than a computed index keep z in registers
+    const bool odd = (t & 1) != 0;
+    e0 = sig0 * (odd ? z[2] : z[0]);
+    e1 = sig1 * (odd ? z[3] : z[1]);
   }
   // Sequential access (t = 0, 1, 2, ...): regenerates on even steps.
   __device__ __forceinline__ void at(int t, R sig0, R sig1, R& e0, R& e1) {

@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void k_weights(const int64_t* __restrict__ k_o
   R z = R(0), q = R(0);
   for (int m = threadIdx.x; m < K; m += blockDim.x) {
     const R s = S[k0 + m];
-    const R om = isfinite(s) ? exp(-(s - mn) * inv_lambda) : R(0);
+    const R om = isfinite(s) ? exp_r(-(s - mn) * inv_lambda) : R(0);
     z += om;
     q += om * om;
   }
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(256) void k_weights(const int64_t* __restrict__ k_o
   const R iz = z > R(0) ? R(1) / z : R(0);
   for (int m = threadIdx.x; m < K; m += blockDim.x) {
     const R s = S[k0 + m];
-    const R om = isfinite(s) ? exp(-(s - mn) * inv_lambda) : R(0);
+    const R om = isfinite(s) ? exp_r(-(s - mn) * inv_lambda) : R(0);
     w[k0 + m] = om * iz;
   }
   if (threadIdx.x == 0) {
@@ -524,19 +524,99 @@ struct RepairArgs {
 };
 
 template <class R>
-struct RepairSink {
-  R* V;
-  int T;
-  R step;
-  R lo0, hi0, lo1, hi1;
-  __device__ __forceinline__ void operator()(int t, R gv0, R gv1) {
-    V[t] = clamp_r(V[t] - step * gv0, lo0, hi0);
-    V[T + t] = clamp_r(V[T + t] - step * gv1, lo1, hi1);
-  }
-};
+__host__ __device__ inline size_t repair_lds_bytes(int t_max) {
+  return (size_t)(t_max + 1) * (6 * sizeof(R) + sizeof(int));
+}
 
-// One workgroup (one wave) per problem; lane 0 runs Algorithm 1's projected
-// gradient steps on the nominal trajectory.
+// Algorithm 1 for one problem on one lane.  The nominal trajectory is short
+// (T+1 states), so every state is kept in LDS and the reverse sweep reads it
+// back instead of recomputing it.  The sweep starts at the last transition
+// whose term in the objective has a non-zero derivative (everything later has
+// a zero gradient, so those controls only get the box projection), and the
+// iteration stops as soon as no such transition is left: the gradient is then
+// exactly zero and every remaining step would be the identity after the
+// projection already applied.
+template <class R, int NOBS>
+__device__ void repair_lane(const DevModel<R>& M, const DevCost<R>& C, const DevObjective<R>& ob,
+                            const TrackView<R>& tr, const State<R>& x0, R* V, int T, int n_steps, R step, R* xs,
+                            int* is) {
+  const bool cost_terms = ob.w_S != R(0);
+  for (int s = 0; s < n_steps; ++s) {
+    // ---- forward: states, segment indices, last transition with a live hinge
+    State<R> x = x0;
+    int idx = -1;
+    R e2 = lateral_sq(tr, x.px, x.py, idx);
+    R hp = tr.w2 - e2;
+    R hob[NOBS > 0 ? NOBS : 1];
+#pragma unroll
+    for (int i = 0; i < NOBS; ++i)
+      if (i < tr.n_obs) {
+        const R ox = x.px - tr.obs[4 * i], oy = x.py - tr.obs[4 * i + 1];
+        hob[i] = ox * ox + oy * oy - tr.obs[4 * i + 2];
+      }
+    xs[0] = x.px; xs[1] = x.py; xs[2] = x.psi; xs[3] = x.vx; xs[4] = x.vy; xs[5] = x.om;
+    is[0] = idx;
+    int last = -1;
+    for (int t = 0; t < T; ++t) {
+      const R u0 = clamp_r(V[t], M.u_lo[0], M.u_hi[0]);
+      const R u1 = clamp_r(V[T + t], M.u_lo[1], M.u_hi[1]);
+      rk4(M, step_ctl(M, u0, u1), x);
+      e2 = lateral_sq(tr, x.px, x.py, idx);
+      R* o = xs + 6 * (t + 1);
+      o[0] = x.px; o[1] = x.py; o[2] = x.psi; o[3] = x.vx; o[4] = x.vy; o[5] = x.om;
+      is[t + 1] = idx;
+      const R h = tr.w2 - e2;
+      bool act = C.alpha * hp - h > R(0);
+      hp = h;
+#pragma unroll
+      for (int i = 0; i < NOBS; ++i)
+        if (i < tr.n_obs) {
+          const R ox = x.px - tr.obs[4 * i], oy = x.py - tr.obs[4 * i + 1];
+          const R hi = ox * ox + oy * oy - tr.obs[4 * i + 2];
+          act = act || (C.alpha * hob[i] - hi > R(0));
+          hob[i] = hi;
+        }
+      if (act && (ob.w_sq != R(0) || (ob.w_lin != R(0) && t < ob.n_lin))) last = t;
+    }
+    const int t_end = cost_terms ? T - 1 : last;
+    for (int t = t_end + 1; t < T; ++t) {
+      V[t] = clamp_r(V[t], M.u_lo[0], M.u_hi[0]);
+      V[T + t] = clamp_r(V[T + t], M.u_lo[1], M.u_hi[1]);
+    }
+    if (t_end < 0) break;
+    // ---- reverse sweep with the in-place projected step
+    R lam[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    if (cost_terms) stage_grad(C, tr, x, idx, ob.w_S * C.phi_w, lam);
+    for (int t = t_end; t >= 0; --t) {
+      const R* pp = xs + 6 * t;
+      const R* pn = pp + 6;
+      State<R> xp, xn;
+      xp.px = pp[0]; xp.py = pp[1]; xp.psi = pp[2]; xp.vx = pp[3]; xp.vy = pp[4]; xp.om = pp[5];
+      xn.px = pn[0]; xn.py = pn[1]; xn.psi = pn[2]; xn.vx = pn[3]; xn.vy = pn[4]; xn.om = pn[5];
+      const int ip = is[t], in_ = is[t + 1];
+      R gpx = R(0), gpy = R(0);
+      penalty_grad<R, NOBS>(C, ob, tr, xp, ip, xn, in_, t, lam, gpx, gpy);
+      const R v0 = V[t], v1 = V[T + t];
+      const R u0 = clamp_r(v0, M.u_lo[0], M.u_hi[0]);
+      const R u1 = clamp_r(v1, M.u_lo[1], M.u_hi[1]);
+      const bool pass0 = (v0 >= M.u_lo[0]) && (v0 <= M.u_hi[0]);
+      const bool pass1 = (v1 >= M.u_lo[1]) && (v1 <= M.u_hi[1]);
+      R gd = R(0), gt = R(0);
+      rk4_vjp(M, step_ctl(M, u0, u1), xp, lam, gd, gt);
+      lam[0] += gpx;
+      lam[1] += gpy;
+      if (cost_terms) stage_grad(C, tr, xp, ip, ob.w_S, lam);
+      const R gu0 = gd + ob.w_S * C.ctrl_w[0] * v0;
+      const R gu1 = gt + ob.w_S * C.ctrl_w[1] * v1;
+      const R gv0 = (pass0 ? gu0 : R(0)) + ob.w_S * C.ctrl_w[0] * u0;
+      const R gv1 = (pass1 ? gu1 : R(0)) + ob.w_S * C.ctrl_w[1] * u1;
+      V[t] = clamp_r(v0 - step * gv0, M.u_lo[0], M.u_hi[0]);
+      V[T + t] = clamp_r(v1 - step * gv1, M.u_lo[1], M.u_hi[1]);
+    }
+  }
+}
+
+// One workgroup (one wave) per problem; lane 0 runs the shield.
 template <class R, int NOBS>
 __global__ __launch_bounds__(WAVE) void k_repair(RepairArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -545,32 +625,12 @@ __global__ __launch_bounds__(WAVE) void k_repair(RepairArgs<R> a) {
   if (!load_dims(a.p, b, d)) return;
   R* Vs;
   const TrackView<R> tr = stage_problem(a.p, b, d, a.V_plus, smem, &Vs);
-  unsigned char* rest = smem + stage_lds_bytes<R>(a.p.poly_max, a.p.t_max);
-  const int n_ck = (a.p.t_max + a.seg_len - 1) / a.seg_len;
-  AdjLds<R> L;
-  L.ck = reinterpret_cast<R*>(rest);
-  L.sx = L.ck + (size_t)n_ck * 6 * WAVE;
-  L.cki = reinterpret_cast<int*>(L.sx + (size_t)(a.seg_len + 1) * 6 * WAVE);
-  L.sxi = L.cki + n_ck * WAVE;
+  R* xs = reinterpret_cast<R*>(smem + stage_lds_bytes<R>(a.p.poly_max, a.p.t_max));
+  int* is = reinterpret_cast<int*>(xs + 6 * (size_t)(a.p.t_max + 1));
   __syncthreads();
   if (threadIdx.x == 0) {
-    NoiseStream<R> ns;
-    ns.seed = 0;
-    ns.m = 0;
-    ns.pid = 0;
-    ns.it = 0;
-    ns.nominal = true;
-    RepairSink<R> sink;
-    sink.V = Vs;
-    sink.T = d.T;
-    sink.step = a.step;
-    sink.lo0 = a.M.u_lo[0];
-    sink.hi0 = a.M.u_hi[0];
-    sink.lo1 = a.M.u_lo[1];
-    sink.hi1 = a.M.u_hi[1];
     const State<R> x0 = load_state(a.p.x0 + 6 * (size_t)b);
-    for (int s = 0; s < a.n_steps; ++s)
-      adjoint_lane<R, NOBS>(a.M, a.C, a.ob, tr, x0, Vs, d.T, ns, L, a.seg_len, 0, sink);
+    repair_lane<R, NOBS>(a.M, a.C, a.ob, tr, x0, Vs, d.T, a.n_steps, a.step, xs, is);
   }
   __syncthreads();
   R* out = a.V_safe + 2 * (size_t)d.t0;

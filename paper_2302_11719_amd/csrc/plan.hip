@@ -96,7 +96,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
       const int m = kb * a.tile + j * BLK + tid;
-      om[j] = isfinite(s[j]) ? expf(-(s[j] - mn) * a.inv_lambda) : 0.f;
+      om[j] = isfinite(s[j]) ? exp_r(-(s[j] - mn) * a.inv_lambda) : 0.f;
       z += om[j];
       q += om[j] * om[j];
       if (m < d.K && !isfinite(s[j])) nf += 1.f;
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       for (int k = 0; k < ntb; ++k) {
         const float* Pk = P0 + (size_t)k * pstride;
         const float mk = __builtin_nontemporal_load(Pk);
-        const float sc = isfinite(mk) ? expf(-(mk - gmin) * a.inv_lambda) : 0.f;
+        const float sc = isfinite(mk) ? exp_r(-(mk - gmin) * a.inv_lambda) : 0.f;
         Z += sc * __builtin_nontemporal_load(Pk + 1);
         Q += sc * sc * __builtin_nontemporal_load(Pk + 2);
         NF += __builtin_nontemporal_load(Pk + 3);
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
         for (int k = 0; k < ntb; ++k) {
           const float* Pk = P0 + (size_t)k * pstride;
           const float mk = __builtin_nontemporal_load(Pk);
-          const float sc = isfinite(mk) ? expf(-(mk - gmin) * a.inv_lambda) : 0.f;
+          const float sc = isfinite(mk) ? exp_r(-(mk - gmin) * a.inv_lambda) : 0.f;
           acc += sc * __builtin_nontemporal_load(Pk + PART_HDR + i);
         }
         Vpb[i] = Vb[i] + acc * iZ;

@@ -449,7 +449,7 @@ extern "C" smppi_status smppi_rollout_backward(smppi_ctx ctx, const smppi_batch*
 // ------------------------------------------------------------------ repair
 template <class R, int NOBS>
 static smppi_status launch_repair(smppi_ctx ctx, const smppi_batch* b, const RepairArgs<R>& a, hipStream_t s) {
-  const size_t lds = stage_lds_bytes<R>(a.p.poly_max, a.p.t_max) + adj_lds_bytes<R>(a.p.t_max, a.seg_len);
+  const size_t lds = stage_lds_bytes<R>(a.p.poly_max, a.p.t_max) + repair_lds_bytes<R>(a.p.t_max);
   if (lds > (size_t)ctx->max_lds)
     return fail(ctx, SMPPI_ERR_SHAPE, "repair needs %zu B of LDS per workgroup (device max %d)", lds, ctx->max_lds);
   hipLaunchKernelGGL((k_repair<R, NOBS>), dim3(b->n_problems), dim3(WAVE), lds, s, a);
