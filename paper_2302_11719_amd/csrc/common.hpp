@@ -31,6 +31,10 @@ constexpr int kMaxPoly = 4096;
 constexpr int kMaxObs = 64;
 constexpr int kMaxStageLds = 65536;
 
+// Obstacle slots staged per problem: kernels with obstacles run a fixed count
+// of kMaxObs barriers (unused slots hold an inert barrier).
+inline int obs_slots(const smppi_track* t) { return t->obs_max > 0 ? kMaxObs : 0; }
+
 smppi_status fail(smppi_ctx ctx, smppi_status s, const char* fmt, ...);
 smppi_status hip_fail(smppi_ctx ctx, hipError_t e, const char* what);
 smppi_status ensure_scratch(smppi_ctx ctx, size_t bytes);

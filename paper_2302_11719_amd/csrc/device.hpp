@@ -54,6 +54,10 @@ __device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
 __device__ __forceinline__ float exp_r(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
 __device__ __forceinline__ double exp_r(double x) { return exp(x); }
 template <class R> __device__ __forceinline__ R clamp_r(R x, R lo, R hi) { return fmin(fmax(x, lo), hi); }
+// single v_med3_f32 (lo <= hi)
+template <> __device__ __forceinline__ float clamp_r<float>(float x, float lo, float hi) {
+  return __builtin_amdgcn_fmed3f(x, lo, hi);
+}
 
 // ---------------------------------------------------------------- noise
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
@@ -219,6 +223,19 @@ struct TrackView {
   int n_obs;
 };
 
+// One circular obstacle: centre, inflated radius squared (barrier), radius
+// squared (collision indicator).  LDS slots are 16-byte aligned for FP32.
+template <class R> struct Obs { R cx, cy, re2, r2; };
+template <class R>
+__device__ __forceinline__ Obs<R> obs_at(const TrackView<R>& tr, int i) {
+  return Obs<R>{tr.obs[4 * i], tr.obs[4 * i + 1], tr.obs[4 * i + 2], tr.obs[4 * i + 3]};
+}
+template <>
+__device__ __forceinline__ Obs<float> obs_at<float>(const TrackView<float>& tr, int i) {
+  const float4 v = reinterpret_cast<const float4*>(tr.obs)[i];
+  return Obs<float>{v.x, v.y, v.z, v.w};
+}
+
 template <class R>
 __device__ __forceinline__ R seg_dist2(const TrackView<R>& tr, int i, R px, R py, R* rx_o = nullptr,
                                        R* ry_o = nullptr) {
@@ -274,6 +291,44 @@ __device__ __forceinline__ R window_min(const TrackView<R>& tr, int& c, R px, R 
   return bd;
 }
 
+// The same rule with the half width fixed at compile time: all 2W+1 segments
+// are read from LDS first (one latency for the whole window), then compared
+// in the rule's order.
+template <int W, class R>
+__device__ __forceinline__ R window_min_fixed(const TrackView<R>& tr, int& c, R px, R py) {
+  constexpr int NS = 2 * W + 1;
+  R ax[NS], ay[NS], dx[NS], dy[NS], il[NS];
+  int id[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int off = (k == 0) ? 0 : ((k & 1) ? -((k + 1) / 2) : (k / 2));
+    int i = c + off;
+    i += (i < 0) ? tr.n : 0;
+    i -= (i >= tr.n) ? tr.n : 0;
+    id[k] = i;
+    ax[k] = tr.seg[4 * i + 0];
+    ay[k] = tr.seg[4 * i + 1];
+    dx[k] = tr.seg[4 * i + 2];
+    dy[k] = tr.seg[4 * i + 3];
+    il[k] = tr.il2[i];
+  }
+  int best = id[0];
+  R bd = R(0);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const R rx = px - ax[k], ry = py - ay[k];
+    const R lam = clamp_r((rx * dx[k] + ry * dy[k]) * il[k], R(0), R(1));
+    const R ex = rx - lam * dx[k], ey = ry - lam * dy[k];
+    const R d2 = ex * ex + ey * ey;
+    if (k == 0 || d2 < bd) {
+      bd = d2;
+      best = id[k];
+    }
+  }
+  c = best;
+  return bd;
+}
+
 // e_y^2 at (px, py); for the polyline `idx` is the window centre in/out
 // (negative: global search).
 template <class R>
@@ -284,6 +339,7 @@ __device__ __forceinline__ R lateral_sq(const TrackView<R>& tr, R px, R py, int&
     return e * e;
   }
   if (idx < 0) idx = global_argmin(tr, px, py);
+  if (tr.window == 4) return window_min_fixed<4>(tr, idx, px, py);
   return window_min(tr, idx, px, py);
 }
 
@@ -322,13 +378,12 @@ __device__ R rollout_sample(const DevModel<R>& M, const DevCost<R>& C, const Tra
   R S = C.C_cbf * fmax((C.alpha - R(1)) * h0, R(0));
 #pragma unroll
   for (int i = 0; i < NOBS; ++i) {
-    if (i < tr.n_obs) {
-      const R ox = x.px - tr.obs[4 * i], oy = x.py - tr.obs[4 * i + 1];
-      const R d2 = ox * ox + oy * oy;
-      hob[i] = d2 - tr.obs[4 * i + 2];
-      outside = outside || (d2 < tr.obs[4 * i + 3]);
-      S += C.C_cbf * fmax((C.alpha - R(1)) * hob[i], R(0));
-    }
+    const Obs<R> o = obs_at(tr, i);
+    const R ox = x.px - o.cx, oy = x.py - o.cy;
+    const R d2 = ox * ox + oy * oy;
+    hob[i] = d2 - o.re2;
+    outside = outside || (d2 < o.r2);
+    S += C.C_cbf * fmax((C.alpha - R(1)) * hob[i], R(0));
   }
   for (int t = 0; t < T; ++t) {
     const R v0 = V[t], v1 = V[T + t];
@@ -353,14 +408,13 @@ __device__ R rollout_sample(const DevModel<R>& M, const DevCost<R>& C, const Tra
     outside = h1 < R(0);
 #pragma unroll
     for (int i = 0; i < NOBS; ++i) {
-      if (i < tr.n_obs) {
-        const R ox = x.px - tr.obs[4 * i], oy = x.py - tr.obs[4 * i + 1];
-        const R d2 = ox * ox + oy * oy;
-        const R hi = d2 - tr.obs[4 * i + 2];
-        pen += fmax(C.alpha * hob[i] - hi, R(0));
-        hob[i] = hi;
-        outside = outside || (d2 < tr.obs[4 * i + 3]);
-      }
+      const Obs<R> o = obs_at(tr, i);
+      const R ox = x.px - o.cx, oy = x.py - o.cy;
+      const R d2 = ox * ox + oy * oy;
+      const R hi = d2 - o.re2;
+      pen += fmax(C.alpha * hob[i] - hi, R(0));
+      hob[i] = hi;
+      outside = outside || (d2 < o.r2);
     }
     S += C.C_cbf * pen;
   }
@@ -518,19 +572,15 @@ __device__ __forceinline__ void penalty_grad(const DevCost<R>& C, const DevObjec
   }
 #pragma unroll
   for (int i = 0; i < NOBS; ++i) {
-    if (i < tr.n_obs) {
-      const R cx = tr.obs[4 * i], cy = tr.obs[4 * i + 1], re2 = tr.obs[4 * i + 2];
-      const R pxp = xp.px - cx, pyp = xp.py - cy, pxn = xn.px - cx, pyn = xn.py - cy;
-      const R hp = pxp * pxp + pyp * pyp - re2, hn = pxn * pxn + pyn * pyn - re2;
-      const R r = C.alpha * hp - hn;
-      if (r > R(0)) {
-        const R g = ob.w_S * C.C_cbf + R(2) * ob.w_sq * r + lin;
-        lam_next[0] -= g * R(2) * pxn;
-        lam_next[1] -= g * R(2) * pyn;
-        gpx_prev += g * C.alpha * R(2) * pxp;
-        gpy_prev += g * C.alpha * R(2) * pyp;
-      }
-    }
+    const Obs<R> o = obs_at(tr, i);
+    const R pxp = xp.px - o.cx, pyp = xp.py - o.cy, pxn = xn.px - o.cx, pyn = xn.py - o.cy;
+    const R hp = pxp * pxp + pyp * pyp - o.re2, hn = pxn * pxn + pyn * pyn - o.re2;
+    const R r = C.alpha * hp - hn;
+    const R g = r > R(0) ? ob.w_S * C.C_cbf + R(2) * ob.w_sq * r + lin : R(0);
+    lam_next[0] -= g * R(2) * pxn;
+    lam_next[1] -= g * R(2) * pyn;
+    gpx_prev += g * C.alpha * R(2) * pxp;
+    gpy_prev += g * C.alpha * R(2) * pyp;
   }
 }
 

@@ -59,13 +59,15 @@ __device__ __forceinline__ bool load_dims(const ProblemArgs<R>& a, int b, Proble
   return true;
 }
 
-// Stages problem b's polyline and control sequence in LDS; returns the track view.
-// LDS layout: seg [poly_max][4] | il2 [poly_max] | V [2][t_max].
+// Stages problem b's polyline, obstacles and control sequence in LDS; returns
+// the track view.  LDS layout: seg [poly_max][4] | obs [obs_max][4] |
+// il2 [poly_max] | V [2][t_max].
 template <class R>
 __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const ProblemDims& d, const R* __restrict__ Vg,
                                       unsigned char* smem, R** Vs_out) {
   R* seg = reinterpret_cast<R*>(smem);
-  R* il2 = seg + 4 * a.poly_max;
+  R* obs = seg + 4 * a.poly_max;
+  R* il2 = obs + 4 * a.obs_max;
   R* Vs = il2 + a.poly_max;
   for (int i = threadIdx.x; i < d.np; i += blockDim.x) {
     const R* s = a.poly + 5 * (size_t)(d.p0 + i);
@@ -75,6 +77,11 @@ __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const Prob
     seg[4 * i + 3] = s[3];
     il2[i] = s[4];
   }
+  // Obstacle slots beyond the problem's own count hold an inert barrier
+  // (h = |p|^2 + 1e30 > 0 everywhere, never violated, never hit), so the
+  // per-step loops run a fixed count without per-obstacle branches.
+  for (int i = threadIdx.x; i < 4 * a.obs_max; i += blockDim.x)
+    obs[i] = i < 4 * d.no ? a.obs[4 * (size_t)d.o0 + i] : ((i & 3) >= 2 ? R(-1e30) : R(0));
   for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) Vs[i] = Vg[2 * (size_t)d.t0 + i];
   TrackView<R> tr;
   tr.n = d.np;
@@ -86,15 +93,15 @@ __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const Prob
   tr.rad = a.circle[3 * b + 2];
   const R w = a.half_width[b];
   tr.w2 = w * w;
-  tr.obs = a.obs ? a.obs + 4 * (size_t)d.o0 : nullptr;
+  tr.obs = obs;
   tr.n_obs = d.no;
   *Vs_out = Vs;
   return tr;
 }
 
 template <class R>
-__host__ __device__ inline size_t stage_lds_bytes(int poly_max, int t_max) {
-  return sizeof(R) * (5 * (size_t)poly_max + 2 * (size_t)t_max);
+__host__ __device__ inline size_t stage_lds_bytes(int poly_max, int t_max, int obs_max) {
+  return sizeof(R) * (5 * (size_t)poly_max + 2 * (size_t)t_max + 4 * (size_t)obs_max);
 }
 
 template <class R>
@@ -470,7 +477,7 @@ __global__ __launch_bounds__(WAVE) void k_backward(BackwardArgs<R> a) {
   if ((int)blockIdx.x >= nblk) return;
   R* Vs;
   const TrackView<R> tr = stage_problem(a.p, b, d, a.V, smem, &Vs);
-  unsigned char* rest = smem + stage_lds_bytes<R>(a.p.poly_max, a.p.t_max);
+  unsigned char* rest = smem + stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max);
   const int n_ck = (a.p.t_max + a.seg_len - 1) / a.seg_len;
   AdjLds<R> L;
   L.ck = reinterpret_cast<R*>(rest);
@@ -549,11 +556,11 @@ __device__ void repair_lane(const DevModel<R>& M, const DevCost<R>& C, const Dev
     R hp = tr.w2 - e2;
     R hob[NOBS > 0 ? NOBS : 1];
 #pragma unroll
-    for (int i = 0; i < NOBS; ++i)
-      if (i < tr.n_obs) {
-        const R ox = x.px - tr.obs[4 * i], oy = x.py - tr.obs[4 * i + 1];
-        hob[i] = ox * ox + oy * oy - tr.obs[4 * i + 2];
-      }
+    for (int i = 0; i < NOBS; ++i) {
+      const Obs<R> o = obs_at(tr, i);
+      const R ox = x.px - o.cx, oy = x.py - o.cy;
+      hob[i] = ox * ox + oy * oy - o.re2;
+    }
     xs[0] = x.px; xs[1] = x.py; xs[2] = x.psi; xs[3] = x.vx; xs[4] = x.vy; xs[5] = x.om;
     is[0] = idx;
     int last = -1;
@@ -569,13 +576,13 @@ __device__ void repair_lane(const DevModel<R>& M, const DevCost<R>& C, const Dev
       bool act = C.alpha * hp - h > R(0);
       hp = h;
 #pragma unroll
-      for (int i = 0; i < NOBS; ++i)
-        if (i < tr.n_obs) {
-          const R ox = x.px - tr.obs[4 * i], oy = x.py - tr.obs[4 * i + 1];
-          const R hi = ox * ox + oy * oy - tr.obs[4 * i + 2];
-          act = act || (C.alpha * hob[i] - hi > R(0));
-          hob[i] = hi;
-        }
+      for (int i = 0; i < NOBS; ++i) {
+        const Obs<R> ob_i = obs_at(tr, i);
+        const R ox = x.px - ob_i.cx, oy = x.py - ob_i.cy;
+        const R hi = ox * ox + oy * oy - ob_i.re2;
+        act = act || (C.alpha * hob[i] - hi > R(0));
+        hob[i] = hi;
+      }
       if (act && (ob.w_sq != R(0) || (ob.w_lin != R(0) && t < ob.n_lin))) last = t;
     }
     const int t_end = cost_terms ? T - 1 : last;
@@ -625,7 +632,7 @@ __global__ __launch_bounds__(WAVE) void k_repair(RepairArgs<R> a) {
   if (!load_dims(a.p, b, d)) return;
   R* Vs;
   const TrackView<R> tr = stage_problem(a.p, b, d, a.V_plus, smem, &Vs);
-  R* xs = reinterpret_cast<R*>(smem + stage_lds_bytes<R>(a.p.poly_max, a.p.t_max));
+  R* xs = reinterpret_cast<R*>(smem + stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max));
   int* is = reinterpret_cast<int*>(xs + 6 * (size_t)(a.p.t_max + 1));
   __syncthreads();
   if (threadIdx.x == 0) {

@@ -429,7 +429,7 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   a.part = p->part;
   a.queue = p->counters;
   a.tickets = p->counters + 1;
-  p->lds = (int)stage_lds_bytes<float>(track->poly_max, batch->t_max);
+  p->lds = (int)stage_lds_bytes<float>(track->poly_max, batch->t_max, obs_slots(track));
   int per_cu = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, p->lds);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;

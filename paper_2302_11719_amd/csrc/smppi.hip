@@ -115,8 +115,9 @@ smppi_status smppi::validate_track(smppi_ctx ctx, const smppi_track* t, smppi_dt
     return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "track: obs/obs_off are NULL with obs_max > 0");
   if (t->poly_max > 0 && (t->window < 1 || 2 * t->window + 1 > t->poly_max))
     return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "track: window must satisfy 1 <= window, 2*window+1 <= poly_max");
-  const size_t lds = dt == SMPPI_F32 ? stage_lds_bytes<float>(t->poly_max, t_max)
-                                     : stage_lds_bytes<double>(t->poly_max, t_max);
+  const int slots = obs_slots(t);
+  const size_t lds = dt == SMPPI_F32 ? stage_lds_bytes<float>(t->poly_max, t_max, slots)
+                                     : stage_lds_bytes<double>(t->poly_max, t_max, slots);
   if (lds > (size_t)kMaxStageLds)
     return fail(ctx, SMPPI_ERR_SHAPE, "track: polyline + control staging needs %zu B of LDS (max %d)", lds,
                 kMaxStageLds);
@@ -192,7 +193,7 @@ ProblemArgs<R> smppi::problem_args(smppi_ctx ctx, const smppi_batch* b, const sm
   p.k_max = b->k_max;
   p.t_max = b->t_max;
   p.poly_max = t ? t->poly_max : 0;
-  p.obs_max = t ? t->obs_max : 0;
+  p.obs_max = t ? obs_slots(t) : 0;
   p.window = t ? t->window : 1;
   p.pid_base = b->pid_base;
   p.seed = n ? n->seed : 0u;
@@ -289,7 +290,7 @@ static smppi_status launch_rollout(smppi_ctx ctx, const smppi_batch* b, const Ro
   const int blk = 256;
   const int gx = b->k_max > 0 ? (b->k_max + blk - 1) / blk : 0;
   if (gx == 0) return SMPPI_OK;
-  const size_t lds = stage_lds_bytes<R>(a.p.poly_max, a.p.t_max);
+  const size_t lds = stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max);
   hipLaunchKernelGGL((k_rollout<R, NOBS>), dim3(gx, b->n_problems), dim3(blk), lds, s, a);
   return check_launch(ctx, "k_rollout");
 }
@@ -388,7 +389,7 @@ extern "C" smppi_status smppi_update(smppi_ctx ctx, const smppi_batch* batch, co
 // ------------------------------------------------------------------ adjoint
 template <class R, int NOBS>
 static smppi_status launch_backward(smppi_ctx ctx, const smppi_batch* b, const BackwardArgs<R>& a, hipStream_t s) {
-  const size_t lds = stage_lds_bytes<R>(a.p.poly_max, a.p.t_max) + adj_lds_bytes<R>(a.p.t_max, a.seg_len);
+  const size_t lds = stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max) + adj_lds_bytes<R>(a.p.t_max, a.seg_len);
   if (lds > (size_t)ctx->max_lds)
     return fail(ctx, SMPPI_ERR_SHAPE, "adjoint needs %zu B of LDS per workgroup (device max %d)", lds, ctx->max_lds);
   hipLaunchKernelGGL((k_backward<R, NOBS>), dim3(a.nblk_max, b->n_problems), dim3(WAVE), lds, s, a);
@@ -449,7 +450,7 @@ extern "C" smppi_status smppi_rollout_backward(smppi_ctx ctx, const smppi_batch*
 // ------------------------------------------------------------------ repair
 template <class R, int NOBS>
 static smppi_status launch_repair(smppi_ctx ctx, const smppi_batch* b, const RepairArgs<R>& a, hipStream_t s) {
-  const size_t lds = stage_lds_bytes<R>(a.p.poly_max, a.p.t_max) + repair_lds_bytes<R>(a.p.t_max);
+  const size_t lds = stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max) + repair_lds_bytes<R>(a.p.t_max);
   if (lds > (size_t)ctx->max_lds)
     return fail(ctx, SMPPI_ERR_SHAPE, "repair needs %zu B of LDS per workgroup (device max %d)", lds, ctx->max_lds);
   hipLaunchKernelGGL((k_repair<R, NOBS>), dim3(b->n_problems), dim3(WAVE), lds, s, a);
