@@ -247,9 +247,117 @@ struct UpdateArgs {
 constexpr int UPD_BLOCK = 256;
 constexpr int UPD_TCHUNK = 64;
 
+template <class R, int BLK, int SPT>
+struct NoiseSumLds {
+  int m[BLK * SPT];
+  R w[BLK * SPT];
+  int cnt[BLK / WAVE];
+  R wpart[BLK / WAVE][2][UPD_TCHUNK];
+};
+
+// Weighted sums of a workgroup's effective noise, P[d*T + t] = sum_m w_m
+// eps'_{m,t,d}, for the SPT samples (ms, ws) each thread holds.  Samples with
+// a zero weight (most of them: exp(-(S - min S)/lambda) underflows) contribute
+// nothing, so they are first compacted in ascending sample order; when few
+// remain, each thread owns a time step and regenerates only the live samples'
+// noise (no cross-lane reduction); otherwise every lane keeps its own sample
+// and the per-step sums go through wave reductions.  Both orders are fixed.
+template <class R, int BLK, int SPT>
+__device__ void block_noise_sums(const DevModel<R>& M, const DevCost<R>& C, uint32_t seed, uint32_t pid, uint32_t it,
+                                 bool nominal, const R* V, int T, const int (&ms)[SPT], const R (&ws)[SPT],
+                                 NoiseSumLds<R, BLK, SPT>& L, R* P) {
+  constexpr int NW = BLK / WAVE;
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  int n_live = 0;
+#pragma unroll
+  for (int j = 0; j < SPT; ++j) {
+    const bool f = ws[j] != R(0);
+    const unsigned long long bal = __ballot(f);
+    if (lane == 0) L.cnt[wv] = __popcll(bal);
+    __syncthreads();
+    int base = n_live, tot = 0;
+    for (int i = 0; i < NW; ++i) {
+      base += (i < wv) ? L.cnt[i] : 0;
+      tot += L.cnt[i];
+    }
+    if (f) {
+      const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
+      L.m[pos] = ms[j];
+      L.w[pos] = ws[j];
+    }
+    n_live += tot;
+    __syncthreads();
+  }
+  const int t_rounds = (T + BLK - 1) / BLK;
+  if (n_live * t_rounds <= 2 * T) {
+    for (int t = tid; t < T; t += BLK) {
+      const R v0 = V[t], v1 = V[T + t];
+      R a0 = R(0), a1 = R(0);
+      for (int i = 0; i < n_live; ++i) {
+        R e0 = R(0), e1 = R(0);
+        if (!nominal) {
+          uint32_t c0 = (uint32_t)(t >> 1), c1 = (uint32_t)L.m[i], c2 = pid, c3 = it;
+          philox4x32_10(c0, c1, c2, c3, seed, 0u);
+          R z0, z1;
+          const bool odd = (t & 1) != 0;
+          box_muller(odd ? c2 : c0, odd ? c3 : c1, z0, z1);
+          e0 = C.sigma[0] * z0;
+          e1 = C.sigma[1] * z1;
+        }
+        const R wi = L.w[i];
+        a0 += wi * (clamp_r(v0 + e0, M.u_lo[0], M.u_hi[0]) - v0);
+        a1 += wi * (clamp_r(v1 + e1, M.u_lo[1], M.u_hi[1]) - v1);
+      }
+      P[t] = a0;
+      P[T + t] = a1;
+    }
+    return;
+  }
+  NoiseStream<R> ns[SPT];
+#pragma unroll
+  for (int j = 0; j < SPT; ++j) {
+    ns[j].seed = seed;
+    ns[j].m = (uint32_t)ms[j];
+    ns[j].pid = pid;
+    ns[j].it = it;
+    ns[j].nominal = nominal;
+  }
+  for (int tc = 0; tc < T; tc += UPD_TCHUNK) {
+    const int tn = min(UPD_TCHUNK, T - tc);
+    for (int tt = 0; tt < tn; ++tt) {
+      const int t = tc + tt;
+      const R v0 = V[t], v1 = V[T + t];
+      R p0 = R(0), p1 = R(0);
+#pragma unroll
+      for (int j = 0; j < SPT; ++j) {
+        if (ws[j] != R(0)) {
+          R e0, e1;
+          ns[j].at(t, C.sigma[0], C.sigma[1], e0, e1);
+          p0 += ws[j] * (clamp_r(v0 + e0, M.u_lo[0], M.u_hi[0]) - v0);
+          p1 += ws[j] * (clamp_r(v1 + e1, M.u_lo[1], M.u_hi[1]) - v1);
+        }
+      }
+      p0 = wave_sum(p0);
+      p1 = wave_sum(p1);
+      if (lane == 0) {
+        L.wpart[wv][0][tt] = p0;
+        L.wpart[wv][1][tt] = p1;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < 2 * tn; e += BLK) {
+      const int dd = e / tn, tt = e % tn;
+      R acc = R(0);
+      for (int i = 0; i < NW; ++i) acc += L.wpart[i][dd][tt];
+      P[dd * T + tc + tt] = acc;
+    }
+    __syncthreads();
+  }
+}
+
 template <class R>
 __global__ __launch_bounds__(UPD_BLOCK) void k_update(UpdateArgs<R> a) {
-  __shared__ R wpart[UPD_BLOCK / WAVE][2][UPD_TCHUNK];
+  __shared__ NoiseSumLds<R, UPD_BLOCK, 1> L;
   __shared__ uint32_t s_ticket;
   const int b = blockIdx.y;
   ProblemDims d;
@@ -263,44 +371,12 @@ __global__ __launch_bounds__(UPD_BLOCK) void k_update(UpdateArgs<R> a) {
   }
   const int nblk = (d.K + UPD_BLOCK - 1) / UPD_BLOCK;
   if ((int)blockIdx.x >= nblk) return;
-  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
   const int m = blockIdx.x * UPD_BLOCK + threadIdx.x;
-  const R wm = (m < d.K) ? a.w[d.k0 + m] : R(0);
-  NoiseStream<R> ns;
-  ns.seed = a.p.seed;
-  ns.m = (uint32_t)m;
-  ns.pid = (uint32_t)(a.p.pid_base + b);
-  ns.it = a.p.iter[b];
-  ns.nominal = a.p.nominal != 0;
+  const int ms[1] = {m};
+  const R ws[1] = {(m < d.K) ? a.w[d.k0 + m] : R(0)};
   R* gp = a.part + ((size_t)b * a.nblk_max + blockIdx.x) * 2 * a.p.t_max;
-  for (int tc = 0; tc < d.T; tc += UPD_TCHUNK) {
-    const int tn = min(UPD_TCHUNK, d.T - tc);
-    for (int tt = 0; tt < tn; ++tt) {
-      const int t = tc + tt;
-      R p0 = R(0), p1 = R(0);
-      if (wm != R(0)) {
-        R e0, e1;
-        ns.at(t, a.C.sigma[0], a.C.sigma[1], e0, e1);
-        const R v0 = Vb[t], v1 = Vb[d.T + t];
-        p0 = wm * (clamp_r(v0 + e0, a.M.u_lo[0], a.M.u_hi[0]) - v0);
-        p1 = wm * (clamp_r(v1 + e1, a.M.u_lo[1], a.M.u_hi[1]) - v1);
-      }
-      p0 = wave_sum(p0);
-      p1 = wave_sum(p1);
-      if (lane == 0) {
-        wpart[wv][0][tt] = p0;
-        wpart[wv][1][tt] = p1;
-      }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 2 * tn; e += UPD_BLOCK) {
-      const int dd = e / tn, tt = e % tn;
-      R s = R(0);
-      for (int i = 0; i < UPD_BLOCK / WAVE; ++i) s += wpart[i][dd][tt];
-      gp[dd * d.T + tc + tt] = s;
-    }
-    __syncthreads();
-  }
+  block_noise_sums<R, UPD_BLOCK, 1>(a.M, a.C, a.p.seed, (uint32_t)(a.p.pid_base + b), a.p.iter[b],
+                                    a.p.nominal != 0, Vb, d.T, ms, ws, L, gp);
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) s_ticket = atomicAdd(&a.tickets[b], 1u);

@@ -44,11 +44,10 @@ template <int NOBS, int BLK, int SPT>
 __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float red[BLK / WAVE];
-  __shared__ float wpart[BLK / WAVE][2][UPD_TCHUNK];
+  __shared__ NoiseSumLds<float, BLK, SPT> L;
   __shared__ int s_tile;
   __shared__ uint32_t s_ticket;
-  constexpr int NW = BLK / WAVE;
-  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  const int tid = threadIdx.x;
   const int pstride = PART_HDR + 2 * a.p.t_max;
   int staged_b = -1;
   float* Vs = nullptr;
@@ -105,46 +104,11 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
     q = block_sum(q, red);
     nf = block_sum(nf, red);
     float* P = a.part + (size_t)(a.tile_off[b] + kb) * pstride;
-    NoiseStream<float> ns[SPT];
+    int ms[SPT];
 #pragma unroll
-    for (int j = 0; j < SPT; ++j) {
-      ns[j].seed = a.p.seed;
-      ns[j].m = (uint32_t)(kb * a.tile + j * BLK + tid);
-      ns[j].pid = pid;
-      ns[j].it = it;
-      ns[j].nominal = a.p.nominal != 0;
-    }
-    for (int tc = 0; tc < d.T; tc += UPD_TCHUNK) {
-      const int tn = min(UPD_TCHUNK, d.T - tc);
-      for (int tt = 0; tt < tn; ++tt) {
-        const int t = tc + tt;
-        const float v0 = Vs[t], v1 = Vs[d.T + t];
-        float p0 = 0.f, p1 = 0.f;
-#pragma unroll
-        for (int j = 0; j < SPT; ++j) {
-          if (om[j] != 0.f) {
-            float e0, e1;
-            ns[j].at(t, a.C.sigma[0], a.C.sigma[1], e0, e1);
-            p0 += om[j] * (clamp_r(v0 + e0, a.M.u_lo[0], a.M.u_hi[0]) - v0);
-            p1 += om[j] * (clamp_r(v1 + e1, a.M.u_lo[1], a.M.u_hi[1]) - v1);
-          }
-        }
-        p0 = wave_sum(p0);
-        p1 = wave_sum(p1);
-        if (lane == 0) {
-          wpart[wv][0][tt] = p0;
-          wpart[wv][1][tt] = p1;
-        }
-      }
-      __syncthreads();
-      for (int e = tid; e < 2 * tn; e += BLK) {
-        const int dd = e / tn, tt = e % tn;
-        float acc = 0.f;
-        for (int i = 0; i < NW; ++i) acc += wpart[i][dd][tt];
-        P[PART_HDR + dd * d.T + tc + tt] = acc;
-      }
-      __syncthreads();
-    }
+    for (int j = 0; j < SPT; ++j) ms[j] = kb * a.tile + j * BLK + tid;
+    block_noise_sums<float, BLK, SPT>(a.M, a.C, a.p.seed, pid, it, a.p.nominal != 0, Vs, d.T, ms, om, L,
+                                      P + PART_HDR);
     if (tid == 0) {
       P[0] = mn;
       P[1] = z;
