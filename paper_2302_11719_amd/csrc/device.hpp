@@ -66,8 +66,11 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
                                               uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    // one 32x32 -> 64-bit product per multiplier (v_mad_u64_u32)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
     const uint32_t n0 = hi1 ^ c1 ^ k0;
     const uint32_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
@@ -211,12 +214,16 @@ __device__ __forceinline__ void rk4(const DevModel<R>& M, const StepCtl<R>& c, S
 template <class R> struct Vec4 { R x, y, z, w; };
 template <> struct Vec4<float> { float4 v; };
 
+// Wrapped copies kept on each side of the staged polyline (bounds the window
+// half width of the unwrapped search).
+constexpr int SEG_PAD = 8;
+
 template <class R>
 struct TrackView {
   int n;                  // polyline segments (0: circle)
   int window;
-  const R* seg;           // LDS [n][4]
-  const R* il2;           // LDS [n]
+  const R* seg;           // LDS [n][4], valid for indices -SEG_PAD .. n+SEG_PAD-1
+  const R* il2;           // LDS [n], same index range
   R cx, cy, rad;          // circle
   R w2;                   // half width squared
   const R* obs;           // global [n_obs][4] (uniform reads)
@@ -296,36 +303,39 @@ __device__ __forceinline__ R window_min(const TrackView<R>& tr, int& c, R px, R 
 // in the rule's order.
 template <int W, class R>
 __device__ __forceinline__ R window_min_fixed(const TrackView<R>& tr, int& c, R px, R py) {
+  static_assert(W <= SEG_PAD, "window wider than the staged wrap-around");
   constexpr int NS = 2 * W + 1;
-  R ax[NS], ay[NS], dx[NS], dy[NS], il[NS];
-  int id[NS];
+  // slots c-W .. c+W are consecutive in the padded copy: one base address,
+  // immediate offsets, no index wrapping
+  const R* sg = tr.seg + 4 * (c - W);
+  const R* il = tr.il2 + (c - W);
+  R d2[NS];
 #pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    const int off = (k == 0) ? 0 : ((k & 1) ? -((k + 1) / 2) : (k / 2));
-    int i = c + off;
-    i += (i < 0) ? tr.n : 0;
-    i -= (i >= tr.n) ? tr.n : 0;
-    id[k] = i;
-    ax[k] = tr.seg[4 * i + 0];
-    ay[k] = tr.seg[4 * i + 1];
-    dx[k] = tr.seg[4 * i + 2];
-    dy[k] = tr.seg[4 * i + 3];
-    il[k] = tr.il2[i];
+  for (int s = 0; s < NS; ++s) {
+    const R rx = px - sg[4 * s + 0], ry = py - sg[4 * s + 1];
+    const R dx = sg[4 * s + 2], dy = sg[4 * s + 3];
+    const R lam = clamp_r((rx * dx + ry * dy) * il[s], R(0), R(1));
+    const R ex = rx - lam * dx, ey = ry - lam * dy;
+    d2[s] = ex * ex + ey * ey;
   }
-  int best = id[0];
-  R bd = R(0);
+  // the rule's order: offsets 0, -1, +1, -2, +2, ...; first strict minimum wins
+  R bd = d2[W];
+  int off = 0;
 #pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    const R rx = px - ax[k], ry = py - ay[k];
-    const R lam = clamp_r((rx * dx[k] + ry * dy[k]) * il[k], R(0), R(1));
-    const R ex = rx - lam * dx[k], ey = ry - lam * dy[k];
-    const R d2 = ex * ex + ey * ey;
-    if (k == 0 || d2 < bd) {
-      bd = d2;
-      best = id[k];
+  for (int k = 1; k <= W; ++k) {
+    if (d2[W - k] < bd) {
+      bd = d2[W - k];
+      off = -k;
+    }
+    if (d2[W + k] < bd) {
+      bd = d2[W + k];
+      off = k;
     }
   }
-  c = best;
+  int i = c + off;
+  i += (i < 0) ? tr.n : 0;
+  i -= (i >= tr.n) ? tr.n : 0;
+  c = i;
   return bd;
 }
 

@@ -65,18 +65,23 @@ __device__ __forceinline__ bool load_dims(const ProblemArgs<R>& a, int b, Proble
 template <class R>
 __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const ProblemDims& d, const R* __restrict__ Vg,
                                       unsigned char* smem, R** Vs_out) {
+  // The closed polyline is stored with SEG_PAD wrapped copies on each side, so
+  // a window around any segment reads consecutive slots without index wrapping.
+  const int ns = a.poly_max + 2 * SEG_PAD;
   R* seg = reinterpret_cast<R*>(smem);
-  R* obs = seg + 4 * a.poly_max;
+  R* obs = seg + 4 * ns;
   R* il2 = obs + 4 * a.obs_max;
-  R* Vs = il2 + a.poly_max;
-  for (int i = threadIdx.x; i < d.np; i += blockDim.x) {
-    const R* s = a.poly + 5 * (size_t)(d.p0 + i);
-    seg[4 * i + 0] = s[0];
-    seg[4 * i + 1] = s[1];
-    seg[4 * i + 2] = s[2];
-    seg[4 * i + 3] = s[3];
-    il2[i] = s[4];
-  }
+  R* Vs = il2 + ns;
+  if (d.np > 0)
+    for (int i = threadIdx.x; i < d.np + 2 * SEG_PAD; i += blockDim.x) {
+      const int src = ((i - SEG_PAD) % d.np + d.np) % d.np;
+      const R* s = a.poly + 5 * (size_t)(d.p0 + src);
+      seg[4 * i + 0] = s[0];
+      seg[4 * i + 1] = s[1];
+      seg[4 * i + 2] = s[2];
+      seg[4 * i + 3] = s[3];
+      il2[i] = s[4];
+    }
   // Obstacle slots beyond the problem's own count hold an inert barrier
   // (h = |p|^2 + 1e30 > 0 everywhere, never violated, never hit), so the
   // per-step loops run a fixed count without per-obstacle branches.
@@ -86,8 +91,8 @@ __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const Prob
   TrackView<R> tr;
   tr.n = d.np;
   tr.window = a.window;
-  tr.seg = seg;
-  tr.il2 = il2;
+  tr.seg = seg + 4 * SEG_PAD;
+  tr.il2 = il2 + SEG_PAD;
   tr.cx = a.circle[3 * b + 0];
   tr.cy = a.circle[3 * b + 1];
   tr.rad = a.circle[3 * b + 2];
@@ -101,7 +106,7 @@ __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const Prob
 
 template <class R>
 __host__ __device__ inline size_t stage_lds_bytes(int poly_max, int t_max, int obs_max) {
-  return sizeof(R) * (5 * (size_t)poly_max + 2 * (size_t)t_max + 4 * (size_t)obs_max);
+  return sizeof(R) * (5 * ((size_t)poly_max + 2 * SEG_PAD) + 2 * (size_t)t_max + 4 * (size_t)obs_max);
 }
 
 template <class R>

@@ -160,3 +160,25 @@ def test_full_size_config4_sampled():
     assert rel_err(plan.S.cpu().numpy(), S.cpu().numpy().astype(np.float64)).max() <= 1e-6
     assert np.abs(plan.V_plus.cpu().numpy() - Vp.cpu().numpy()).max() <= 2e-5
     assert ctx().device_errors() == 0
+
+
+@pytest.mark.parametrize("lam", [1.0, 30.0, 1e4])
+def test_update_sparse_and_dense_paths(lam):
+    """The update takes its sparse path when few weights are non-zero (lambda = 1) and its
+    dense path when all are (large lambda); both agree with the oracle given the weights."""
+    probs = prep(ragged_problems(), F32)
+    M, C = params(F32)
+    db = core.DeviceBatch(probs, dtype=F32)
+    say(f"update paths lambda={lam}")
+    S, w, stats, Vp = _plain(db, M, C, 3, lam)
+    plan = core.Plan(ctx(), db, M, C, 3, lam, use_graph=False)
+    plan.launch()
+    torch.cuda.synchronize()
+    ws = db.per_problem(w)
+    Vps = db.controls(Vp)
+    for b, p in enumerate(probs):
+        r = oracle_iteration(p, M, C, 3, lam)
+        err = float(np.abs(Vps[b] - oracle.update(p.V, ws[b].astype(np.float64), r["eps"])).max())
+        assert err <= 1e-5, (b, err)
+    err = float(np.abs(plan.V_plus.cpu().numpy() - Vp.cpu().numpy()).max())
+    assert err <= 2e-5, err
