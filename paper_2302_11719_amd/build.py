@@ -39,10 +39,11 @@ def build(jobs: int = 2, verbose: bool = False) -> str:
             failed.append((src, text))
         elif verbose and text.strip():
             print(text)
-    if failed:
+    missing = [o for o in objs if not os.path.exists(o)]
+    if failed or missing:
         for src, text in failed:
             print(f"---- {src}\n{text}", file=sys.stderr)
-        raise RuntimeError("hipcc failed: " + ", ".join(s for s, _ in failed))
+        raise RuntimeError("hipcc failed: " + ", ".join([s for s, _ in failed] + missing))
     tmp = LIB + ".tmp"
     subprocess.check_call([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)

@@ -391,7 +391,8 @@ __global__ __launch_bounds__(UPD_BLOCK) void k_update(UpdateArgs<R> a) {
     const R* g0 = a.part + (size_t)b * a.nblk_max * 2 * a.p.t_max;
     for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) {
       R acc = R(0);
-      for (int k = 0; k < nblk; ++k) acc += __builtin_nontemporal_load(g0 + (size_t)k * 2 * a.p.t_max + i);
+#pragma unroll 8
+      for (int k = 0; k < nblk; ++k) acc += g0[(size_t)k * 2 * a.p.t_max + i];
       Vpb[i] = Vb[i] + acc;
     }
     if (threadIdx.x == 0) a.tickets[b] = 0u;
@@ -590,7 +591,8 @@ __global__ __launch_bounds__(WAVE) void k_backward(BackwardArgs<R> a) {
     const R* g0 = a.part + (size_t)b * a.nblk_max * 2 * a.p.t_max;
     for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) {
       R acc = R(0);
-      for (int k = 0; k < nblk; ++k) acc += __builtin_nontemporal_load(g0 + (size_t)k * 2 * a.p.t_max + i);
+#pragma unroll 8
+      for (int k = 0; k < nblk; ++k) acc += g0[(size_t)k * 2 * a.p.t_max + i];
       gVb[i] = acc;
     }
     if (lane == 0) a.tickets[b] = 0u;

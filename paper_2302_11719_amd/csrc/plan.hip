@@ -123,31 +123,48 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
     __syncthreads();
     if (s_ticket == (uint32_t)(ntb - 1)) {
       __threadfence();
+      // Streaming log-sum-exp combine: tile k's sums are rescaled by
+      // exp(-(min_k - min)/lambda); the scales of a chunk of tiles go through LDS.
       const float* P0 = a.part + (size_t)a.tile_off[b] * pstride;
-      float gmin = INFINITY;
-      for (int k = 0; k < ntb; ++k) gmin = fminf(gmin, __builtin_nontemporal_load(P0 + (size_t)k * pstride));
-      float Z = 0.f, Q = 0.f, NF = 0.f;
-      for (int k = 0; k < ntb; ++k) {
+      float mn_l = INFINITY;
+      for (int k = tid; k < ntb; k += BLK) mn_l = fminf(mn_l, P0[(size_t)k * pstride]);
+      const float gmin = block_min(mn_l, red);
+      float z_l = 0.f, q_l = 0.f, nf_l = 0.f;
+      for (int k = tid; k < ntb; k += BLK) {
         const float* Pk = P0 + (size_t)k * pstride;
-        const float mk = __builtin_nontemporal_load(Pk);
+        const float mk = Pk[0];
         const float sc = isfinite(mk) ? exp_r(-(mk - gmin) * a.inv_lambda) : 0.f;
-        Z += sc * __builtin_nontemporal_load(Pk + 1);
-        Q += sc * sc * __builtin_nontemporal_load(Pk + 2);
-        NF += __builtin_nontemporal_load(Pk + 3);
+        z_l += sc * Pk[1];
+        q_l += sc * sc * Pk[2];
+        nf_l += Pk[3];
       }
+      const float Z = block_sum(z_l, red);
+      const float Q = block_sum(q_l, red);
+      const float NF = block_sum(nf_l, red);
       const float iZ = Z > 0.f ? 1.f / Z : 0.f;
       const float* Vb = a.V + 2 * (size_t)d.t0;
       float* Vpb = a.V_plus + 2 * (size_t)d.t0;
-      for (int i = tid; i < 2 * d.T; i += BLK) {
+      float* s_sc = L.w;
+      for (int i0 = 0; i0 < 2 * d.T; i0 += BLK) {
+        const int i = i0 + tid;
         float acc = 0.f;
-        for (int k = 0; k < ntb; ++k) {
-          const float* Pk = P0 + (size_t)k * pstride;
-          const float mk = __builtin_nontemporal_load(Pk);
-          const float sc = isfinite(mk) ? exp_r(-(mk - gmin) * a.inv_lambda) : 0.f;
-          acc += sc * __builtin_nontemporal_load(Pk + PART_HDR + i);
+        for (int k0 = 0; k0 < ntb; k0 += BLK) {
+          __syncthreads();
+          if (k0 + tid < ntb) {
+            const float mk = P0[(size_t)(k0 + tid) * pstride];
+            s_sc[tid] = isfinite(mk) ? exp_r(-(mk - gmin) * a.inv_lambda) : 0.f;
+          }
+          __syncthreads();
+          const int kn = min(BLK, ntb - k0);
+          if (i < 2 * d.T) {
+            const float* Pi = P0 + (size_t)k0 * pstride + PART_HDR + i;
+#pragma unroll 8
+            for (int kk = 0; kk < kn; ++kk) acc += s_sc[kk] * Pi[(size_t)kk * pstride];
+          }
         }
-        Vpb[i] = Vb[i] + acc * iZ;
+        if (i < 2 * d.T) Vpb[i] = Vb[i] + acc * iZ;
       }
+      __syncthreads();
       if (tid == 0) {
         a.stats[4 * b + 0] = gmin;
         a.stats[4 * b + 1] = logf(Z);
