@@ -232,6 +232,9 @@ typedef struct {
   int32_t tile;              /* samples per tile (multiple of block); 0 = block */
   int32_t grid;              /* persistent workgroups; 0 = chosen from occupancy */
   int32_t use_graph;         /* nonzero: capture into a hipGraph at creation */
+  int32_t pipeline;          /* 1: latency mode (64-sample tiles, three specialised waves
+                                pipelining noise, dynamics and cost); -1: off; 0: on when
+                                the batch has at most 2*64 samples per compute unit */
 } smppi_plan_opts;
 
 /* Buffers a plan reads and writes on every launch (device pointers, dtype F32):

@@ -65,7 +65,7 @@ class RepairOpts(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("lambda_", c_f64), ("repair", c_i32), ("repair_opts", RepairOpts), ("execute", c_i32),
                 ("dist", c_vp), ("n_dist", c_i32), ("block", c_i32), ("tile", c_i32), ("grid", c_i32),
-                ("use_graph", c_i32)]
+                ("use_graph", c_i32), ("pipeline", c_i32)]
 
 
 class PlanBuffers(ctypes.Structure):

@@ -40,7 +40,144 @@ struct FusedArgs {
   uint32_t* tickets;         // [B]
 };
 
-template <int NOBS, int BLK, int SPT>
+// ---------------------------------------------------------------------------
+// Latency mode: one tile = 64 samples handled by three specialised waves that
+// run the same trajectories as a pipeline over chunks of PIPE_C steps.
+//   wave 1: noise, clipped controls, control cost, per-step control constants
+//           (chunk s),
+//   wave 0: the RK4 chain only (chunk s-1), reading the constants from LDS and
+//           writing (p_x, p_y, v_x) of every new state,
+//   wave 2: lateral offset window, running cost, DCBF penalties, obstacles,
+//           collision indicator (chunk s-2).
+// A workgroup barrier separates the stages; each wave's per-step chain is a
+// third of the one-lane-per-sample loop, which is what bounds a launch with
+// fewer waves than SIMDs.  Same arithmetic as rollout_sample, summed in three
+// partial sums (control terms, state terms) instead of one.
+constexpr int PIPE_C = 8;
+constexpr int PIPE_BLK = 3 * WAVE;
+
+struct PipeLds {
+  float ctl[2][PIPE_C][6][WAVE];  // u0, u1, sin(u0)/m, cos(u0)/m, l_f cos(u0)/I_z, a_max u1
+  float pos[2][PIPE_C][3][WAVE];  // p_x, p_y, v_x of x_{t+1}
+  float part[2][WAVE];
+};
+
+template <int NOBS>
+__device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, const State<float>& x0,
+                              const float* Vs, const ProblemDims& d, int m, uint32_t pid, uint32_t it,
+                              PipeLds& P) {
+  const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int T = d.T, nch = (T + PIPE_C - 1) / PIPE_C;
+  const DevModel<float>& M = a.M;
+  const DevCost<float>& C = a.C;
+  // wave 1
+  NoiseStream<float> ns;
+  ns.seed = a.p.seed;
+  ns.m = (uint32_t)m;
+  ns.pid = pid;
+  ns.it = it;
+  ns.nominal = a.p.nominal != 0;
+  float Sc = 0.f;
+  // wave 0
+  State<float> x = x0;
+  // wave 2
+  int idx = -1;
+  float ey2 = 0.f, hp = 0.f, vxp = x0.vx, S2 = 0.f;
+  bool outside = false;
+  float hob[NOBS > 0 ? NOBS : 1];
+  if (w == 2) {
+    ey2 = lateral_sq(tr, x0.px, x0.py, idx);
+    hp = tr.w2 - ey2;
+    outside = hp < 0.f;
+    S2 = C.C_cbf * fmaxf((C.alpha - 1.f) * hp, 0.f);
+#pragma unroll
+    for (int i = 0; i < NOBS; ++i) {
+      const Obs<float> o = obs_at(tr, i);
+      const float ox = x0.px - o.cx, oy = x0.py - o.cy;
+      const float d2 = ox * ox + oy * oy;
+      hob[i] = d2 - o.re2;
+      outside = outside || (d2 < o.r2);
+      S2 += C.C_cbf * fmaxf((C.alpha - 1.f) * hob[i], 0.f);
+    }
+  }
+  for (int s = 0; s < nch + 2; ++s) {
+    if (w == 1 && s < nch) {
+      const int t0 = s * PIPE_C, t1 = min(T, t0 + PIPE_C);
+      for (int t = t0; t < t1; ++t) {
+        const float v0 = Vs[t], v1 = Vs[T + t];
+        float e0, e1;
+        ns.at(t, C.sigma[0], C.sigma[1], e0, e1);
+        const float u0 = clamp_r(v0 + e0, M.u_lo[0], M.u_hi[0]);
+        const float u1 = clamp_r(v1 + e1, M.u_lo[1], M.u_hi[1]);
+        Sc += C.ctrl_w[0] * v0 * u0 + C.ctrl_w[1] * v1 * u1;
+        const StepCtl<float> sc = step_ctl(M, u0, u1);
+        float(*c)[WAVE] = P.ctl[s & 1][t - t0];
+        c[0][lane] = u0;
+        c[1][lane] = u1;
+        c[2][lane] = sc.sd_m;
+        c[3][lane] = sc.cd_m;
+        c[4][lane] = sc.lfcd_Iz;
+        c[5][lane] = sc.a_tau;
+      }
+    } else if (w == 0 && s >= 1 && s <= nch) {
+      const int cc = s - 1, t0 = cc * PIPE_C, t1 = min(T, t0 + PIPE_C);
+      for (int t = t0; t < t1; ++t) {
+        const float(*c)[WAVE] = P.ctl[cc & 1][t - t0];
+        StepCtl<float> sc;
+        sc.delta = c[0][lane];
+        sc.sd_m = c[2][lane];
+        sc.cd_m = c[3][lane];
+        sc.lfcd_Iz = c[4][lane];
+        sc.a_tau = c[5][lane];
+        sc.sd = sc.cd = 0.f;  // used by the reverse sweep only
+        rk4(M, sc, x);
+        float(*q)[WAVE] = P.pos[cc & 1][t - t0];
+        q[0][lane] = x.px;
+        q[1][lane] = x.py;
+        q[2][lane] = x.vx;
+      }
+    } else if (w == 2 && s >= 2) {
+      const int cc = s - 2, t0 = cc * PIPE_C, t1 = min(T, t0 + PIPE_C);
+      for (int t = t0; t < t1; ++t) {
+        const float dv = vxp - C.v_g;
+        float q = C.q_v * dv * dv + C.q_ey * ey2;
+        if (outside) q += C.C_obs;
+        S2 += q;
+        const float(*qp)[WAVE] = P.pos[cc & 1][t - t0];
+        const float px = qp[0][lane], py = qp[1][lane];
+        vxp = qp[2][lane];
+        ey2 = lateral_sq(tr, px, py, idx);
+        const float h1 = tr.w2 - ey2;
+        float pen = fmaxf(C.alpha * hp - h1, 0.f);
+        hp = h1;
+        outside = h1 < 0.f;
+#pragma unroll
+        for (int i = 0; i < NOBS; ++i) {
+          const Obs<float> o = obs_at(tr, i);
+          const float ox = px - o.cx, oy = py - o.cy;
+          const float d2 = ox * ox + oy * oy;
+          const float hi = d2 - o.re2;
+          pen += fmaxf(C.alpha * hob[i] - hi, 0.f);
+          hob[i] = hi;
+          outside = outside || (d2 < o.r2);
+        }
+        S2 += C.C_cbf * pen;
+      }
+    }
+    __syncthreads();
+  }
+  if (w == 2) {
+    const float dv = vxp - C.v_g;
+    float q = C.q_v * dv * dv + C.q_ey * ey2;
+    if (outside) q += C.C_obs;
+    P.part[1][lane] = S2 + C.phi_w * q;
+  }
+  if (w == 1) P.part[0][lane] = Sc;
+  __syncthreads();
+  return P.part[0][lane] + P.part[1][lane];
+}
+
+template <int NOBS, int BLK, int SPT, bool PIPE>
 __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float red[BLK / WAVE];
@@ -70,43 +207,52 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
     }
     const uint32_t pid = (uint32_t)(a.p.pid_base + b), it = a.p.iter[b];
     const State<float> x0 = load_state(a.p.x0 + 6 * (size_t)b);
-    // ---- rollouts
+    // ---- rollouts: sample ms[j] of this tile, owned by this thread when own[j]
     float s[SPT];
+    int ms[SPT];
+    bool own[SPT];
     float mn = INFINITY;
+    if constexpr (PIPE) {
+      __shared__ PipeLds PL;
+      ms[0] = kb * a.tile + tid % WAVE;
+      own[0] = tid < WAVE && ms[0] < d.K;
+      const float sv = rollout_pipe<NOBS>(a, tr, x0, Vs, d, ms[0], pid, it, PL);
+      s[0] = own[0] ? sv : INFINITY;
+      if (own[0]) a.S[d.k0 + ms[0]] = sv;
+      if (isfinite(s[0])) mn = s[0];
+    } else {
 #pragma unroll
-    for (int j = 0; j < SPT; ++j) {
-      const int m = kb * a.tile + j * BLK + tid;
-      s[j] = INFINITY;
-      if (m < d.K) {
-        NoiseStream<float> ns;
-        ns.seed = a.p.seed;
-        ns.m = (uint32_t)m;
-        ns.pid = pid;
-        ns.it = it;
-        ns.nominal = a.p.nominal != 0;
-        s[j] = rollout_sample<float, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, nullptr);
-        a.S[d.k0 + m] = s[j];
+      for (int j = 0; j < SPT; ++j) {
+        ms[j] = kb * a.tile + j * BLK + tid;
+        own[j] = ms[j] < d.K;
+        s[j] = INFINITY;
+        if (own[j]) {
+          NoiseStream<float> ns;
+          ns.seed = a.p.seed;
+          ns.m = (uint32_t)ms[j];
+          ns.pid = pid;
+          ns.it = it;
+          ns.nominal = a.p.nominal != 0;
+          s[j] = rollout_sample<float, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, nullptr);
+          a.S[d.k0 + ms[j]] = s[j];
+        }
+        if (isfinite(s[j])) mn = fminf(mn, s[j]);
       }
-      if (isfinite(s[j])) mn = fminf(mn, s[j]);
     }
     // ---- tile-local softmax partial
     mn = block_min(mn, red);
     float om[SPT], z = 0.f, q = 0.f, nf = 0.f;
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
-      const int m = kb * a.tile + j * BLK + tid;
       om[j] = isfinite(s[j]) ? exp_r(-(s[j] - mn) * a.inv_lambda) : 0.f;
       z += om[j];
       q += om[j] * om[j];
-      if (m < d.K && !isfinite(s[j])) nf += 1.f;
+      if (own[j] && !isfinite(s[j])) nf += 1.f;
     }
     z = block_sum(z, red);
     q = block_sum(q, red);
     nf = block_sum(nf, red);
     float* P = a.part + (size_t)(a.tile_off[b] + kb) * pstride;
-    int ms[SPT];
-#pragma unroll
-    for (int j = 0; j < SPT; ++j) ms[j] = kb * a.tile + j * BLK + tid;
     block_noise_sums<float, BLK, SPT>(a.M, a.C, a.p.seed, pid, it, a.p.nominal != 0, Vs, d.T, ms, om, L,
                                       P + PART_HDR);
     if (tid == 0) {
@@ -204,7 +350,7 @@ using FusedFn = void (*)(FusedArgs);
 template <int NOBS>
 FusedFn pick_fused(int blk, int spt) {
 #define SMPPI_CASE(BL, SP) \
-  if (blk == BL && spt == SP) return k_fused<NOBS, BL, SP>;
+  if (blk == BL && spt == SP) return k_fused<NOBS, BL, SP, false>;
   SMPPI_CASE(64, 1) SMPPI_CASE(64, 2) SMPPI_CASE(64, 4)
   SMPPI_CASE(128, 1) SMPPI_CASE(128, 2) SMPPI_CASE(128, 4)
   SMPPI_CASE(256, 1) SMPPI_CASE(256, 2) SMPPI_CASE(256, 4)
@@ -324,14 +470,8 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   if (opts->repair && !bufs->V_safe) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "V_safe required with repair");
   if (opts->execute && opts->dist && opts->n_dist < 0)
     return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "n_dist must be >= 0");
-  const int block = opts->block ? opts->block : 256;
-  const int tile = opts->tile ? opts->tile : block;
-  if (block != 64 && block != 128 && block != 256 && block != 512)
-    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "block must be 64, 128, 256 or 512");
-  if (tile % block != 0) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "tile must be a multiple of block");
-  const int spt = tile / block;
-  FusedFn fn = track->obs_max > 0 ? pick_fused<kMaxObs>(block, spt) : pick_fused<0>(block, spt);
-  if (!fn) return fail(ctx, SMPPI_ERR_UNSUPPORTED, "no fused kernel for block %d, tile %d", block, tile);
+  if (opts->pipeline < -1 || opts->pipeline > 1)
+    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "pipeline must be -1, 0 or 1");
   (void)hipSetDevice(ctx->device);
   const int B = batch->n_problems;
 
@@ -342,6 +482,21 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(k_off)");
   e = hipMemcpy(toff.data(), batch->t_off, sizeof(int32_t) * (B + 1), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(t_off)");
+  // Latency mode when the whole batch gives at most two sample-waves per CU:
+  // then each wave's per-step chain, not the VALU throughput, bounds the launch.
+  const bool pipe = opts->pipeline == 1 ||
+                    (opts->pipeline == 0 && koff[B] <= (int64_t)2 * WAVE * std::max(ctx->n_cu, 1));
+  const int block = pipe ? PIPE_BLK : (opts->block ? opts->block : 256);
+  const int tile = pipe ? WAVE : (opts->tile ? opts->tile : block);
+  if (!pipe && block != 64 && block != 128 && block != 256 && block != 512)
+    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "block must be 64, 128, 256 or 512");
+  if (!pipe && tile % block != 0)
+    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "tile must be a multiple of block");
+  const int spt = tile / block;
+  FusedFn fn = pipe ? (track->obs_max > 0 ? (FusedFn)k_fused<kMaxObs, PIPE_BLK, 1, true>
+                                          : (FusedFn)k_fused<0, PIPE_BLK, 1, true>)
+                    : (track->obs_max > 0 ? pick_fused<kMaxObs>(block, spt) : pick_fused<0>(block, spt));
+  if (!fn) return fail(ctx, SMPPI_ERR_UNSUPPORTED, "no fused kernel for block %d, tile %d", block, tile);
   std::vector<int32_t> ntile(B), tile_off(B + 1, 0);
   bool any_empty = false;
   for (int b = 0; b < B; ++b) {

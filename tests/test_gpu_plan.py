@@ -24,21 +24,27 @@ def _plain(db, M, C, seed, lam):
     return S, w, stats, Vp
 
 
-@pytest.mark.parametrize("block,tile", [(256, 256), (64, 128), (128, 512), (512, 512)])
-def test_plan_matches_plain_path(block, tile):
+@pytest.mark.parametrize("block,tile,pipeline", [(256, 256, -1), (64, 128, -1), (128, 512, -1), (512, 512, -1),
+                                                 (0, 0, 1)])
+def test_plan_matches_plain_path(block, tile, pipeline):
+    """Plan (fused persistent kernel; pipeline = 1 is the three-wave latency mode) against
+    the plain per-call kernels and the oracle.  Costs agree to 1e-5 relative with the plain
+    rollout: the same arithmetic, summed in a different order in the latency mode."""
     probs = prep(ragged_problems(), F32)
     M, C = params(F32)
     db = core.DeviceBatch(probs, dtype=F32)
-    say(f"plan vs plain block={block} tile={tile}")
+    say(f"plan vs plain block={block} tile={tile} pipeline={pipeline}")
     S, w, stats, Vp = _plain(db, M, C, 5, W.LAMBDA)
-    plan = core.Plan(ctx(), db, M, C, 5, W.LAMBDA, block=block, tile=tile, use_graph=False)
+    plan = core.Plan(ctx(), db, M, C, 5, W.LAMBDA, block=block, tile=tile, use_graph=False, pipeline=pipeline)
     plan.launch()
     torch.cuda.synchronize()
     assert ctx().device_errors() == 0
-    assert rel_err(plan.S.cpu().numpy(), S.cpu().numpy().astype(np.float64)).max() <= 1e-6
-    assert np.abs(plan.V_plus.cpu().numpy() - Vp.cpu().numpy()).max() <= 2e-5
+    err = float(rel_err(plan.S.cpu().numpy(), S.cpu().numpy().astype(np.float64)).max())
+    assert err <= (1e-6 if pipeline < 0 else 1e-5), err
     ps, st = plan.stats.cpu().numpy().reshape(-1, 4), stats.cpu().numpy()
-    assert np.allclose(ps[:, 0], st[:, 0], rtol=1e-6)
+    if pipeline < 0:  # identical costs: V+ and the minimum agree to reduction order
+        assert np.abs(plan.V_plus.cpu().numpy() - Vp.cpu().numpy()).max() <= 2e-5
+        assert np.allclose(ps[:, 0], st[:, 0], rtol=1e-6)
     assert np.allclose(ps[:, 2], st[:, 2], rtol=1e-3)
     assert np.array_equal(ps[:, 3], st[:, 3])
     # and the oracle, problem by problem (V+ given the device costs)
