@@ -258,6 +258,7 @@ struct NoiseSumLds {
   R w[BLK * SPT];
   int cnt[BLK / WAVE];
   R wpart[BLK / WAVE][2][UPD_TCHUNK];
+  R red4[4][BLK];
 };
 
 // Weighted sums of a workgroup's effective noise, P[d*T + t] = sum_m w_m
@@ -293,28 +294,41 @@ __device__ void block_noise_sums(const DevModel<R>& M, const DevCost<R>& C, uint
     n_live += tot;
     __syncthreads();
   }
-  const int t_rounds = (T + BLK - 1) / BLK;
-  if (n_live * t_rounds <= 2 * T) {
-    for (int t = tid; t < T; t += BLK) {
-      const R v0 = V[t], v1 = V[T + t];
-      R a0 = R(0), a1 = R(0);
-      for (int i = 0; i < n_live; ++i) {
-        R e0 = R(0), e1 = R(0);
-        if (!nominal) {
-          uint32_t c0 = (uint32_t)(t >> 1), c1 = (uint32_t)L.m[i], c2 = pid, c3 = it;
-          philox4x32_10(c0, c1, c2, c3, seed, 0u);
-          R z0, z1;
-          const bool odd = (t & 1) != 0;
-          box_muller(odd ? c2 : c0, odd ? c3 : c1, z0, z1);
-          e0 = C.sigma[0] * z0;
-          e1 = C.sigma[1] * z1;
+  // Sparse path: thread (g, j) owns the step pair (2j, 2j+1) (one Philox call
+  // per live sample gives both steps) for the live samples i = g, g+G, ...;
+  // the G partial sums of a pair are then added in g order.
+  const int npairs = (T + 1) / 2;
+  const int G = npairs >= BLK ? 1 : BLK / npairs;
+  if (n_live <= G * T) {
+    for (int j0 = 0; j0 < npairs; j0 += BLK / G) {
+      const int j = j0 + tid % (BLK / G), g = tid / (BLK / G);
+      R acc[4] = {R(0), R(0), R(0), R(0)};
+      if (g < G && j < npairs) {
+        const int ta = 2 * j, tb = min(2 * j + 1, T - 1);
+        const R va0 = V[ta], va1 = V[T + ta], vb0 = V[tb], vb1 = V[T + tb];
+        for (int i = g; i < n_live; i += G) {
+          R z[4] = {R(0), R(0), R(0), R(0)};
+          if (!nominal) normals4<R>(seed, (uint32_t)j, (uint32_t)L.m[i], pid, it, z);
+          const R wi = L.w[i];
+          acc[0] += wi * (clamp_r(va0 + C.sigma[0] * z[0], M.u_lo[0], M.u_hi[0]) - va0);
+          acc[1] += wi * (clamp_r(va1 + C.sigma[1] * z[1], M.u_lo[1], M.u_hi[1]) - va1);
+          acc[2] += wi * (clamp_r(vb0 + C.sigma[0] * z[2], M.u_lo[0], M.u_hi[0]) - vb0);
+          acc[3] += wi * (clamp_r(vb1 + C.sigma[1] * z[3], M.u_lo[1], M.u_hi[1]) - vb1);
         }
-        const R wi = L.w[i];
-        a0 += wi * (clamp_r(v0 + e0, M.u_lo[0], M.u_hi[0]) - v0);
-        a1 += wi * (clamp_r(v1 + e1, M.u_lo[1], M.u_hi[1]) - v1);
       }
-      P[t] = a0;
-      P[T + t] = a1;
+      const int per = BLK / G, jn = min(per, npairs - j0);
+      if (g < G && j < npairs)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) L.red4[q][g * per + tid % per] = acc[q];
+      __syncthreads();
+      for (int e = tid; e < 4 * jn; e += BLK) {
+        const int q = e / jn, jj = e % jn;
+        R s = R(0);
+        for (int gg = 0; gg < G; ++gg) s += L.red4[q][gg * per + jj];
+        const int t = 2 * (j0 + jj) + (q >> 1);
+        if (t < T) P[(q & 1) * T + t] = s;
+      }
+      __syncthreads();
     }
     return;
   }
@@ -618,98 +632,126 @@ __host__ __device__ inline size_t repair_lds_bytes(int t_max) {
   return (size_t)(t_max + 1) * (6 * sizeof(R) + sizeof(int));
 }
 
-// Algorithm 1 for one problem on one lane.  The nominal trajectory is short
-// (T+1 states), so every state is kept in LDS and the reverse sweep reads it
-// back instead of recomputing it.  The sweep starts at the last transition
-// whose term in the objective has a non-zero derivative (everything later has
-// a zero gradient, so those controls only get the box projection), and the
+// Algorithm 1 for one problem on one workgroup of two waves.  The nominal
+// trajectory is short (T+1 states), so every state is kept in LDS and the
+// reverse sweep reads it back instead of recomputing it.  The forward pass is
+// pipelined over chunks of REP_C steps: lane 0 of wave 0 runs the RK4 chain
+// (chunk s), wave 1 follows one chunk behind with the lateral-offset window
+// (one segment per lane, the rule's first minimum picked by ballot) and the
+// obstacle barriers (one obstacle per lane), recording the segment indices and
+// the last transition whose objective term has a non-zero derivative.  The
+// reverse sweep (lane 0) starts at that transition (everything later has a
+// zero gradient, so those controls only get the box projection), and the
 // iteration stops as soon as no such transition is left: the gradient is then
 // exactly zero and every remaining step would be the identity after the
 // projection already applied.
+constexpr int REP_C = 8;
+constexpr int REP_BLK = 2 * WAVE;
+
+// Global nearest segment computed by one wave: lanes scan strided segments,
+// then (distance, index) is reduced with the lowest index winning ties.
+template <class R>
+__device__ int wave_global_argmin(const TrackView<R>& tr, R px, R py) {
+  const int lane = threadIdx.x % WAVE;
+  R bd = R(INFINITY);
+  int bi = 0x7fffffff;
+  for (int i = lane; i < tr.n; i += WAVE) {
+    const R dd = seg_dist2(tr, i, px, py);
+    if (dd < bd) {
+      bd = dd;
+      bi = i;
+    }
+  }
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const R od = __shfl_xor(bd, o, WAVE);
+    const int oi = __shfl_xor(bi, o, WAVE);
+    if (od < bd || (od == bd && oi < bi)) {
+      bd = od;
+      bi = oi;
+    }
+  }
+  return bi == 0x7fffffff ? 0 : bi;
+}
+
+// The window rule evaluated by one wave: lane r holds the r-th offset of the
+// rule's order (0, -1, +1, -2, ...); the first offset in that order attaining
+// the minimum is the lowest set bit of the ballot.  c (uniform) in/out.
+template <class R>
+__device__ R wave_window(const TrackView<R>& tr, int& c, R px, R py) {
+  const int lane = threadIdx.x % WAVE;
+  R dd = R(INFINITY);
+  int off = 0;
+  if (lane < 2 * tr.window + 1) {
+    off = (lane == 0) ? 0 : ((lane & 1) ? -((lane + 1) / 2) : (lane / 2));
+    int i = c + off;
+    i += (i < 0) ? tr.n : 0;
+    i -= (i >= tr.n) ? tr.n : 0;
+    dd = seg_dist2(tr, i, px, py);
+  }
+  const R m = wave_min(dd);
+  const unsigned long long bal = __ballot(dd == m);
+  const int r = bal ? __ffsll((long long)bal) - 1 : 0;
+  int i = c + __shfl(off, r, WAVE);
+  i += (i < 0) ? tr.n : 0;
+  i -= (i >= tr.n) ? tr.n : 0;
+  c = i;
+  return m;
+}
+
+template <class R>
+__device__ __forceinline__ R circle_e2(const TrackView<R>& tr, R px, R py) {
+  const R dx = px - tr.cx, dy = py - tr.cy;
+  const R e = sqrt_r(dx * dx + dy * dy) - tr.rad;
+  return e * e;
+}
+
+// Reverse sweep of the shield objective on the stored nominal trajectory,
+// t = t_end .. 0, applying the projected step to V in place.
 template <class R, int NOBS>
-__device__ void repair_lane(const DevModel<R>& M, const DevCost<R>& C, const DevObjective<R>& ob,
-                            const TrackView<R>& tr, const State<R>& x0, R* V, int T, int n_steps, R step, R* xs,
-                            int* is) {
+__device__ void repair_reverse(const DevModel<R>& M, const DevCost<R>& C, const DevObjective<R>& ob,
+                               const TrackView<R>& tr, R* V, int T, int t_end, R step, const R* xs, const int* is) {
   const bool cost_terms = ob.w_S != R(0);
-  for (int s = 0; s < n_steps; ++s) {
-    // ---- forward: states, segment indices, last transition with a live hinge
-    State<R> x = x0;
-    int idx = -1;
-    R e2 = lateral_sq(tr, x.px, x.py, idx);
-    R hp = tr.w2 - e2;
-    R hob[NOBS > 0 ? NOBS : 1];
-#pragma unroll
-    for (int i = 0; i < NOBS; ++i) {
-      const Obs<R> o = obs_at(tr, i);
-      const R ox = x.px - o.cx, oy = x.py - o.cy;
-      hob[i] = ox * ox + oy * oy - o.re2;
-    }
-    xs[0] = x.px; xs[1] = x.py; xs[2] = x.psi; xs[3] = x.vx; xs[4] = x.vy; xs[5] = x.om;
-    is[0] = idx;
-    int last = -1;
-    for (int t = 0; t < T; ++t) {
-      const R u0 = clamp_r(V[t], M.u_lo[0], M.u_hi[0]);
-      const R u1 = clamp_r(V[T + t], M.u_lo[1], M.u_hi[1]);
-      rk4(M, step_ctl(M, u0, u1), x);
-      e2 = lateral_sq(tr, x.px, x.py, idx);
-      R* o = xs + 6 * (t + 1);
-      o[0] = x.px; o[1] = x.py; o[2] = x.psi; o[3] = x.vx; o[4] = x.vy; o[5] = x.om;
-      is[t + 1] = idx;
-      const R h = tr.w2 - e2;
-      bool act = C.alpha * hp - h > R(0);
-      hp = h;
-#pragma unroll
-      for (int i = 0; i < NOBS; ++i) {
-        const Obs<R> ob_i = obs_at(tr, i);
-        const R ox = x.px - ob_i.cx, oy = x.py - ob_i.cy;
-        const R hi = ox * ox + oy * oy - ob_i.re2;
-        act = act || (C.alpha * hob[i] - hi > R(0));
-        hob[i] = hi;
-      }
-      if (act && (ob.w_sq != R(0) || (ob.w_lin != R(0) && t < ob.n_lin))) last = t;
-    }
-    const int t_end = cost_terms ? T - 1 : last;
-    for (int t = t_end + 1; t < T; ++t) {
-      V[t] = clamp_r(V[t], M.u_lo[0], M.u_hi[0]);
-      V[T + t] = clamp_r(V[T + t], M.u_lo[1], M.u_hi[1]);
-    }
-    if (t_end < 0) break;
-    // ---- reverse sweep with the in-place projected step
-    R lam[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-    if (cost_terms) stage_grad(C, tr, x, idx, ob.w_S * C.phi_w, lam);
-    for (int t = t_end; t >= 0; --t) {
-      const R* pp = xs + 6 * t;
-      const R* pn = pp + 6;
-      State<R> xp, xn;
-      xp.px = pp[0]; xp.py = pp[1]; xp.psi = pp[2]; xp.vx = pp[3]; xp.vy = pp[4]; xp.om = pp[5];
-      xn.px = pn[0]; xn.py = pn[1]; xn.psi = pn[2]; xn.vx = pn[3]; xn.vy = pn[4]; xn.om = pn[5];
-      const int ip = is[t], in_ = is[t + 1];
-      R gpx = R(0), gpy = R(0);
-      penalty_grad<R, NOBS>(C, ob, tr, xp, ip, xn, in_, t, lam, gpx, gpy);
-      const R v0 = V[t], v1 = V[T + t];
-      const R u0 = clamp_r(v0, M.u_lo[0], M.u_hi[0]);
-      const R u1 = clamp_r(v1, M.u_lo[1], M.u_hi[1]);
-      const bool pass0 = (v0 >= M.u_lo[0]) && (v0 <= M.u_hi[0]);
-      const bool pass1 = (v1 >= M.u_lo[1]) && (v1 <= M.u_hi[1]);
-      R gd = R(0), gt = R(0);
-      rk4_vjp(M, step_ctl(M, u0, u1), xp, lam, gd, gt);
-      lam[0] += gpx;
-      lam[1] += gpy;
-      if (cost_terms) stage_grad(C, tr, xp, ip, ob.w_S, lam);
-      const R gu0 = gd + ob.w_S * C.ctrl_w[0] * v0;
-      const R gu1 = gt + ob.w_S * C.ctrl_w[1] * v1;
-      const R gv0 = (pass0 ? gu0 : R(0)) + ob.w_S * C.ctrl_w[0] * u0;
-      const R gv1 = (pass1 ? gu1 : R(0)) + ob.w_S * C.ctrl_w[1] * u1;
-      V[t] = clamp_r(v0 - step * gv0, M.u_lo[0], M.u_hi[0]);
-      V[T + t] = clamp_r(v1 - step * gv1, M.u_lo[1], M.u_hi[1]);
-    }
+  R lam[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+  if (cost_terms) {
+    State<R> xT;
+    const R* pT = xs + 6 * T;
+    xT.px = pT[0]; xT.py = pT[1]; xT.psi = pT[2]; xT.vx = pT[3]; xT.vy = pT[4]; xT.om = pT[5];
+    stage_grad(C, tr, xT, is[T], ob.w_S * C.phi_w, lam);
+  }
+  for (int t = t_end; t >= 0; --t) {
+    const R* pp = xs + 6 * t;
+    const R* pn = pp + 6;
+    State<R> xp, xn;
+    xp.px = pp[0]; xp.py = pp[1]; xp.psi = pp[2]; xp.vx = pp[3]; xp.vy = pp[4]; xp.om = pp[5];
+    xn.px = pn[0]; xn.py = pn[1]; xn.psi = pn[2]; xn.vx = pn[3]; xn.vy = pn[4]; xn.om = pn[5];
+    const int ip = is[t], in_ = is[t + 1];
+    R gpx = R(0), gpy = R(0);
+    penalty_grad<R, NOBS>(C, ob, tr, xp, ip, xn, in_, t, lam, gpx, gpy);
+    const R v0 = V[t], v1 = V[T + t];
+    const R u0 = clamp_r(v0, M.u_lo[0], M.u_hi[0]);
+    const R u1 = clamp_r(v1, M.u_lo[1], M.u_hi[1]);
+    const bool pass0 = (v0 >= M.u_lo[0]) && (v0 <= M.u_hi[0]);
+    const bool pass1 = (v1 >= M.u_lo[1]) && (v1 <= M.u_hi[1]);
+    R gd = R(0), gt = R(0);
+    rk4_vjp(M, step_ctl(M, u0, u1), xp, lam, gd, gt);
+    lam[0] += gpx;
+    lam[1] += gpy;
+    if (cost_terms) stage_grad(C, tr, xp, ip, ob.w_S, lam);
+    const R gu0 = gd + ob.w_S * C.ctrl_w[0] * v0;
+    const R gu1 = gt + ob.w_S * C.ctrl_w[1] * v1;
+    const R gv0 = (pass0 ? gu0 : R(0)) + ob.w_S * C.ctrl_w[0] * u0;
+    const R gv1 = (pass1 ? gu1 : R(0)) + ob.w_S * C.ctrl_w[1] * u1;
+    V[t] = clamp_r(v0 - step * gv0, M.u_lo[0], M.u_hi[0]);
+    V[T + t] = clamp_r(v1 - step * gv1, M.u_lo[1], M.u_hi[1]);
   }
 }
 
-// One workgroup (one wave) per problem; lane 0 runs the shield.
+// One workgroup (two waves) per problem.
 template <class R, int NOBS>
-__global__ __launch_bounds__(WAVE) void k_repair(RepairArgs<R> a) {
+__global__ __launch_bounds__(REP_BLK) void k_repair(RepairArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_last;
   const int b = blockIdx.x;
   ProblemDims d;
   if (!load_dims(a.p, b, d)) return;
@@ -718,11 +760,87 @@ __global__ __launch_bounds__(WAVE) void k_repair(RepairArgs<R> a) {
   R* xs = reinterpret_cast<R*>(smem + stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max));
   int* is = reinterpret_cast<int*>(xs + 6 * (size_t)(a.p.t_max + 1));
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const State<R> x0 = load_state(a.p.x0 + 6 * (size_t)b);
-    repair_lane<R, NOBS>(a.M, a.C, a.ob, tr, x0, Vs, d.T, a.n_steps, a.step, xs, is);
+  const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const DevModel<R>& M = a.M;
+  const DevCost<R>& C = a.C;
+  const DevObjective<R>& ob = a.ob;
+  const bool cost_terms = ob.w_S != R(0);
+  const int T = d.T, nch = (T + REP_C - 1) / REP_C;
+  const State<R> x0 = load_state(a.p.x0 + 6 * (size_t)b);
+  // segment and offset at x0 do not change over the iterations
+  int idx0 = 0;
+  R e20 = R(0);
+  if (w == 1) {
+    if (tr.n > 0) {
+      idx0 = wave_global_argmin(tr, x0.px, x0.py);
+      e20 = seg_dist2(tr, idx0, x0.px, x0.py);
+    } else {
+      e20 = circle_e2(tr, x0.px, x0.py);
+    }
   }
-  __syncthreads();
+  for (int s = 0; s < a.n_steps; ++s) {
+    State<R> x = x0;
+    int idx = idx0, last = -1;
+    R hp = tr.w2 - e20, hob = R(0);
+    if (w == 1) {
+      if (lane < NOBS) {
+        const Obs<R> o = obs_at(tr, lane);
+        const R ox = x0.px - o.cx, oy = x0.py - o.cy;
+        hob = ox * ox + oy * oy - o.re2;
+      }
+      if (lane == 0) {
+        xs[0] = x0.px; xs[1] = x0.py; xs[2] = x0.psi; xs[3] = x0.vx; xs[4] = x0.vy; xs[5] = x0.om;
+        is[0] = idx0;
+      }
+    }
+    for (int st = 0; st <= nch; ++st) {
+      if (w == 0 && lane == 0 && st < nch) {
+        const int t0 = st * REP_C, t1 = min(T, t0 + REP_C);
+        for (int t = t0; t < t1; ++t) {
+          const R u0 = clamp_r(Vs[t], M.u_lo[0], M.u_hi[0]);
+          const R u1 = clamp_r(Vs[T + t], M.u_lo[1], M.u_hi[1]);
+          rk4(M, step_ctl(M, u0, u1), x);
+          R* o = xs + 6 * (t + 1);
+          o[0] = x.px; o[1] = x.py; o[2] = x.psi; o[3] = x.vx; o[4] = x.vy; o[5] = x.om;
+        }
+      } else if (w == 1 && st >= 1) {
+        const int t0 = (st - 1) * REP_C, t1 = min(T, t0 + REP_C);
+        for (int t = t0; t < t1; ++t) {
+          const R px = xs[6 * (t + 1)], py = xs[6 * (t + 1) + 1];
+          const R e2 = tr.n > 0 ? wave_window(tr, idx, px, py) : circle_e2(tr, px, py);
+          if (lane == 0) is[t + 1] = idx;
+          const R h = tr.w2 - e2;
+          bool act = C.alpha * hp - h > R(0);
+          hp = h;
+          if (NOBS > 0) {
+            bool ao = false;
+            if (lane < NOBS) {
+              const Obs<R> o = obs_at(tr, lane);
+              const R ox = px - o.cx, oy = py - o.cy;
+              const R hi = ox * ox + oy * oy - o.re2;
+              ao = C.alpha * hob - hi > R(0);
+              hob = hi;
+            }
+            act = act || (__ballot(ao) != 0ull);
+          }
+          if (act && (ob.w_sq != R(0) || (ob.w_lin != R(0) && t < ob.n_lin))) last = t;
+        }
+      }
+      __syncthreads();
+    }
+    if (w == 1 && lane == 0) s_last = last;
+    __syncthreads();
+    const int t_end = cost_terms ? T - 1 : s_last;
+    if (w == 0 && lane == 0) {
+      for (int t = t_end + 1; t < T; ++t) {
+        Vs[t] = clamp_r(Vs[t], M.u_lo[0], M.u_hi[0]);
+        Vs[T + t] = clamp_r(Vs[T + t], M.u_lo[1], M.u_hi[1]);
+      }
+      if (t_end >= 0) repair_reverse<R, NOBS>(M, C, ob, tr, Vs, T, t_end, a.step, xs, is);
+    }
+    __syncthreads();
+    if (t_end < 0) break;
+  }
   R* out = a.V_safe + 2 * (size_t)d.t0;
   for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) out[i] = Vs[i];
 }

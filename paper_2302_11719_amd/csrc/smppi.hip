@@ -453,7 +453,7 @@ static smppi_status launch_repair(smppi_ctx ctx, const smppi_batch* b, const Rep
   const size_t lds = stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max) + repair_lds_bytes<R>(a.p.t_max);
   if (lds > (size_t)ctx->max_lds)
     return fail(ctx, SMPPI_ERR_SHAPE, "repair needs %zu B of LDS per workgroup (device max %d)", lds, ctx->max_lds);
-  hipLaunchKernelGGL((k_repair<R, NOBS>), dim3(b->n_problems), dim3(WAVE), lds, s, a);
+  hipLaunchKernelGGL((k_repair<R, NOBS>), dim3(b->n_problems), dim3(REP_BLK), lds, s, a);
   return check_launch(ctx, "k_repair");
 }
 
