@@ -226,8 +226,9 @@ struct TrackView {
   const R* il2;           // LDS [n], same index range
   R cx, cy, rad;          // circle
   R w2;                   // half width squared
-  const R* obs;           // global [n_obs][4] (uniform reads)
+  const R* obs;           // LDS [obstacle slots][4]
   int n_obs;
+  int idx0;               // nearest segment to the problem's start state
 };
 
 // One circular obstacle: centre, inflated radius squared (barrier), radius
@@ -379,7 +380,8 @@ template <class R, int NOBS>
 __device__ R rollout_sample(const DevModel<R>& M, const DevCost<R>& C, const TrackView<R>& tr, const State<R>& x0,
                             const R* __restrict__ V, int T, NoiseStream<R>& ns, R* eps_out) {
   State<R> x = x0;
-  int idx = -1;
+  // the window around the global nearest segment of x0 returns that segment
+  int idx = tr.idx0;
   R ey2 = lateral_sq(tr, x.px, x.py, idx);
   R h0 = tr.w2 - ey2;
   bool outside = h0 < R(0);

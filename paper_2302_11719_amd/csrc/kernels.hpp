@@ -100,7 +100,48 @@ __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const Prob
   tr.w2 = w * w;
   tr.obs = obs;
   tr.n_obs = d.no;
+  tr.idx0 = 0;
   *Vs_out = Vs;
+  // Nearest segment to the problem's start state (global search; lowest index
+  // on ties), shared by every sample: computed once by the whole workgroup.
+  __syncthreads();
+  if (d.np > 0) {
+    __shared__ R s_bd[32];
+    __shared__ int s_bi[32];
+    const R px = a.x0[6 * (size_t)b], py = a.x0[6 * (size_t)b + 1];
+    R bd = R(INFINITY);
+    int bi = 0x7fffffff;
+    for (int i = threadIdx.x; i < d.np; i += blockDim.x) {
+      const R dd = seg_dist2(tr, i, px, py);
+      if (dd < bd) {
+        bd = dd;
+        bi = i;
+      }
+    }
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+      const R od = __shfl_xor(bd, o, WAVE);
+      const int oi = __shfl_xor(bi, o, WAVE);
+      if (od < bd || (od == bd && oi < bi)) {
+        bd = od;
+        bi = oi;
+      }
+    }
+    if (threadIdx.x % WAVE == 0) {
+      s_bd[threadIdx.x / WAVE] = bd;
+      s_bi[threadIdx.x / WAVE] = bi;
+    }
+    __syncthreads();
+    bd = s_bd[0];
+    bi = s_bi[0];
+    for (int k = 1; k < (int)(blockDim.x / WAVE); ++k)
+      if (s_bd[k] < bd || (s_bd[k] == bd && s_bi[k] < bi)) {
+        bd = s_bd[k];
+        bi = s_bi[k];
+      }
+    tr.idx0 = bi == 0x7fffffff ? 0 : bi;
+    __syncthreads();
+  }
   return tr;
 }
 
@@ -464,7 +505,7 @@ __device__ void adjoint_lane(const DevModel<R>& M, const DevCost<R>& C, const De
                              const AdjLds<R>& L, int seg_len, int lane, Sink& sink) {
   // forward with checkpoints
   State<R> x = x0;
-  int idx = -1;
+  int idx = tr.idx0;
   (void)lateral_sq(tr, x.px, x.py, idx);
   for (int t = 0; t < T; ++t) {
     if (t % seg_len == 0) adj_store(L.ck, L.cki, t / seg_len, lane, x, idx);
@@ -648,32 +689,6 @@ __host__ __device__ inline size_t repair_lds_bytes(int t_max) {
 constexpr int REP_C = 8;
 constexpr int REP_BLK = 2 * WAVE;
 
-// Global nearest segment computed by one wave: lanes scan strided segments,
-// then (distance, index) is reduced with the lowest index winning ties.
-template <class R>
-__device__ int wave_global_argmin(const TrackView<R>& tr, R px, R py) {
-  const int lane = threadIdx.x % WAVE;
-  R bd = R(INFINITY);
-  int bi = 0x7fffffff;
-  for (int i = lane; i < tr.n; i += WAVE) {
-    const R dd = seg_dist2(tr, i, px, py);
-    if (dd < bd) {
-      bd = dd;
-      bi = i;
-    }
-  }
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) {
-    const R od = __shfl_xor(bd, o, WAVE);
-    const int oi = __shfl_xor(bi, o, WAVE);
-    if (od < bd || (od == bd && oi < bi)) {
-      bd = od;
-      bi = oi;
-    }
-  }
-  return bi == 0x7fffffff ? 0 : bi;
-}
-
 // The window rule evaluated by one wave: lane r holds the r-th offset of the
 // rule's order (0, -1, +1, -2, ...); the first offset in that order attaining
 // the minimum is the lowest set bit of the ballot.  c (uniform) in/out.
@@ -768,16 +783,8 @@ __global__ __launch_bounds__(REP_BLK) void k_repair(RepairArgs<R> a) {
   const int T = d.T, nch = (T + REP_C - 1) / REP_C;
   const State<R> x0 = load_state(a.p.x0 + 6 * (size_t)b);
   // segment and offset at x0 do not change over the iterations
-  int idx0 = 0;
-  R e20 = R(0);
-  if (w == 1) {
-    if (tr.n > 0) {
-      idx0 = wave_global_argmin(tr, x0.px, x0.py);
-      e20 = seg_dist2(tr, idx0, x0.px, x0.py);
-    } else {
-      e20 = circle_e2(tr, x0.px, x0.py);
-    }
-  }
+  const int idx0 = tr.idx0;
+  const R e20 = tr.n > 0 ? seg_dist2(tr, idx0, x0.px, x0.py) : circle_e2(tr, x0.px, x0.py);
   for (int s = 0; s < a.n_steps; ++s) {
     State<R> x = x0;
     int idx = idx0, last = -1;

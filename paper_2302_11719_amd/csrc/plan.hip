@@ -81,7 +81,7 @@ __device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, co
   // wave 0
   State<float> x = x0;
   // wave 2
-  int idx = -1;
+  int idx = tr.idx0;
   float ey2 = 0.f, hp = 0.f, vxp = x0.vx, S2 = 0.f;
   bool outside = false;
   float hob[NOBS > 0 ? NOBS : 1];
