@@ -16,6 +16,7 @@ durations (HIP events), the dominant kernel's roofline, and the FP64 CPU oracle
 on a bounded sample of the headline workload.
 
 usage: python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--skip-cpu] [--quick]
+                       [--forms plain,identical,ragged,large,c3] [--copy-calibration-mib N]
 """
 from __future__ import annotations
 
@@ -38,6 +39,8 @@ FLOP_STEP_PER_OBS = 9     # one circular obstacle barrier + penalty + indicator 
 FLOP_UPDATE_STEP = 4      # w * eps' accumulated for two controls
 PEAK_FP32 = 157.3e12      # MI355X FP32 vector peak (packed FMA on every lane)
 PEAK_HBM = 8.0e12
+FORMS = ("plain", "identical", "ragged", "large", "c3")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_K4096_T50_hbm_traffic.md")
 
 
 def _log(msg):
@@ -50,8 +53,16 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--quick", action="store_true", help="headline only (for profiler runs)")
+    ap.add_argument("--quick", action="store_true", help="headline only (same as --forms none)")
+    ap.add_argument("--forms", default="all",
+                    help="comma list of the extra forms to run: plain, identical, ragged, large, c3 (or all/none)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
+    forms = set() if args.quick or args.forms == "none" else (
+        set(FORMS) if args.forms == "all" else set(args.forms.split(",")))
+    if forms - set(FORMS):
+        ap.error(f"unknown forms {sorted(forms - set(FORMS))}")
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
@@ -76,6 +87,16 @@ def main():
     def sync():
         torch.cuda.synchronize()
 
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        sync()
+        dst.copy_(src)
+        sync()
+        _log(f"copy calibration: {n} bytes read + {n} bytes written")
+        del src, dst
+
     # ------------------------------------------------------------------ headline
     prob = W.round_to_f32(W.config1(K=K, T=T))
     n_dist = warm + steps + 8
@@ -86,32 +107,36 @@ def main():
     for _ in range(warm):
         plan.launch()
     sync()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    ev0.record()
-    for _ in range(steps):
+    evs[0].record()
+    for i in range(steps):
         plan.launch()
-    ev1.record()
+        evs[i + 1].record()
     sync()
     wall = time.perf_counter() - t0
-    ev_ms = ev0.elapsed_time(ev1)
+    per_iter = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(steps)])
     assert ctx.device_errors() == 0
     ms_per_step = 1e3 * wall / steps
     value = K * T * steps / wall
-    _log(f"  {ms_per_step:.4f} ms/iter (events {ev_ms / steps:.4f}), {value:.4g} rollout-steps/s")
+    _log(f"  {ms_per_step:.4f} ms/iter (events: mean {per_iter.mean():.4f}, median {np.median(per_iter):.4f}), "
+         f"{value:.4g} rollout-steps/s")
 
     # per-stage durations of the same work (HIP events between the stages)
     db_p = core.DeviceBatch([prob], dtype=torch.float32)
     plan_p = core.Plan(ctx, db_p, M, C, seed, lam, repair=rep, execute=True, dist=dist, use_graph=False)
     n_prof = min(steps, 100)
-    fused, repair_t, exec_t, active = [], [], [], []
+    fused, repair_t, exec_t, active, kf, kr = [], [], [], [], [], []
     for i in range(warm + n_prof):
         plan_p.launch_profiled()
         f, r, e = plan_p.stage_ms()
+        k1, k2 = plan_p.kernel_ms()
         if i >= warm:
             fused.append(f)
             repair_t.append(r)
             exec_t.append(e)
+            kf.append(k1)
+            kr.append(k2)
             # the shield changed the MPPI output (some DCBF condition was violated)
             active.append(not torch.equal(plan_p.V_safe, plan_p.V_plus))
     act = np.array(active)
@@ -119,27 +144,33 @@ def main():
     stage = dict(fused_rollout_weights_update_ms=float(np.mean(fused)), shield_repair_ms=float(np.mean(rt)),
                  execute_ms=float(np.mean(exec_t)), shield_active_fraction=float(act.mean()),
                  shield_ms_when_active=float(rt[act].mean()) if act.any() else None,
-                 shield_ms_when_idle=float(rt[~act].mean()) if (~act).any() else None)
+                 shield_ms_when_idle=float(rt[~act].mean()) if (~act).any() else None,
+                 k_fused_kernel_ms=float(np.mean(kf)), k_repair_kernel_ms=float(np.mean(kr)))
     _log(f"  stages: {stage}")
 
     flop_step = FLOP_STEP_POLY + FLOP_UPDATE_STEP
-    dominant = "k_fused" if stage["fused_rollout_weights_update_ms"] >= stage["shield_repair_ms"] else "k_repair"
+    dominant = "k_fused" if stage["k_fused_kernel_ms"] >= stage["k_repair_kernel_ms"] else "k_repair"
     if dominant == "k_fused":
         flops = K * T * flop_step
-        dur = stage["fused_rollout_weights_update_ms"] * 1e-3
+        dur = stage["k_fused_kernel_ms"] * 1e-3
     else:
         # one problem: n_s x (forward T steps + reverse T steps with recompute ~ 3x forward)
         flops = rep["n_steps"] * T * FLOP_STEP_POLY * 4
-        dur = stage["shield_repair_ms"] * 1e-3
+        dur = stage["k_repair_kernel_ms"] * 1e-3
     achieved = flops / dur
+    from paper_2302_11719_amd.profile_summary import load_traffic
+
+    traffic, why = load_traffic(TRAFFIC_SUMMARY, dominant) if dominant == "k_fused" else (None, "no summary")
     roofline = {"bound": "alu", "kernel": dominant, "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
-                "flop_per_launch": flops, "avg_launch_ms": dur * 1e3}
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": traffic,
+                "traffic_unit": "bytes/launch", "flop_per_launch": flops, "avg_launch_ms": dur * 1e3}
+    if traffic is None:
+        roofline["traffic_note"] = why
 
     result = {
         "metric": "rollout-steps/s and ms/MPPI iter (K=4096,T=50); batched+adjoint vs plain",
         "value": value, "unit": "rollout-steps/s", "n_gpus": 1, "steps": steps, "warmup": warm,
-        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "ms_per_step": ms_per_step, "ms_per_step_median": float(np.median(per_iter)), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "closed-loop Shield-MPPI iteration (batched+adjoint plan, HIP graph): "
                                "K=4096, T=50, 1 problem, spline track, shield 10x0.05, plant disturbance 0.3",
@@ -148,8 +179,8 @@ def main():
         "roofline": roofline,
     }
 
-    if not args.quick:
-        result["forms"] = extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync)
+    if forms:
+        result["forms"] = extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync, forms)
     if not args.skip_cpu:
         result["cpu_baseline"] = cpu_baseline(W, K, T, lam, rep)
     print(json.dumps(result), flush=True)
@@ -166,11 +197,25 @@ def _time(fn, n, warm, sync):
     return (time.perf_counter() - t0) / n
 
 
-def extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync):
-    import torch
-
+def extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync, forms):
     out = {}
     seed = 0
+    if "plain" in forms:
+        _form_plain(ctx, core, W, M, C, lam, K, T, sync, out, seed)
+    if "identical" in forms:
+        _form_identical(ctx, core, W, M, C, lam, rep, K, T, sync, out, seed)
+    if "ragged" in forms:
+        _form_ragged(ctx, core, W, M, C, lam, sync, out, seed)
+    if "large" in forms:
+        _form_large(ctx, core, W, M, C, lam, sync, out, seed)
+    if "c3" in forms:
+        _form_c3(ctx, core, W, M, C, lam, rep, sync, out, seed)
+    return out
+
+
+def _form_plain(ctx, core, W, M, C, lam, K, T, sync, out, seed):
+    import torch
+
     # plain per-call form on the headline problem: rollout, weights, update, execute (no shield)
     prob = W.round_to_f32(W.config1(K=K, T=T))
     db = core.DeviceBatch([prob], dtype=torch.float32)
@@ -191,6 +236,10 @@ def extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync):
     out["batched_single_noshield"] = {"ms_per_iter": dt * 1e3, "rollout_steps_per_s": K * T / dt}
     pl.close()
     _log(f"  plain single {out['plain_single']}, batched no-shield {out['batched_single_noshield']}")
+
+
+def _form_identical(ctx, core, W, M, C, lam, rep, K, T, sync, out, seed):
+    import torch
 
     # B identical-shape problems: plain per-problem loop vs the batched+adjoint plan
     for B in (8, 64, 512):
@@ -215,6 +264,10 @@ def extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync):
         plB.close()
         del dbs, dbB
 
+
+def _form_ragged(ctx, core, W, M, C, lam, sync, out, seed):
+    import torch
+
     # the 512-problem ragged batch (K log-uniform [256, 16384], T uniform [20, 100])
     probs = [W.round_to_f32(p) for p in W.config2()]
     steps_total = sum(p.K * p.T for p in probs)
@@ -237,6 +290,10 @@ def extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync):
     plR.close()
     del dbs
 
+
+def _form_large(ctx, core, W, M, C, lam, sync, out, seed):
+    import torch
+
     # large single problem: K=65536, T=100, 64 obstacles (rollout kernel alone and the plan)
     p4 = W.round_to_f32(W.config4())
     db4 = core.DeviceBatch([p4], dtype=torch.float32)
@@ -252,6 +309,10 @@ def extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync):
     _log(f"  large: {out['large_K65536_T100_obs64']}")
     pl4.close()
 
+
+def _form_c3(ctx, core, W, M, C, lam, rep, sync, out, seed):
+    import torch
+
     # config 3: 64 problems x (K=2048, T=50), batched plan with and without the shield
     p3 = [W.round_to_f32(p) for p in W.config3()]
     db3 = core.DeviceBatch(p3, dtype=torch.float32)
@@ -263,34 +324,51 @@ def extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync):
     _log(f"  c3: {out['c3_B64_K2048_T50']}")
     pa.close()
     pb.close()
-    return out
 
 
-def cpu_baseline(W, K, T, lam, rep):
-    """The FP64 oracle, as it stands, on a bounded sample of the headline workload:
-    a few closed-loop iterations (rollout of all K samples, weights, update, shield,
-    plant) with the rollout threaded over the host's cores."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_closed_loop(W, K, T, lam, rep, threads, budget_s, max_it):
     import oracle
 
-    cores = min(os.cpu_count() or 1, 16)
     p = W.config1(K=K, T=T)
     x, V = p.x0.copy(), p.V.copy()
-    dist = W.disturbances(0, 64)
+    dist = W.disturbances(0, max_it)
     n_it = 0
     t0 = time.perf_counter()
     while True:
-        r = oracle.mppi_iteration(W.MODEL, W.COST, p.track, x, V, K, 0, 0, n_it, lam, n_threads=cores)
+        r = oracle.mppi_iteration(W.MODEL, W.COST, p.track, x, V, K, 0, 0, n_it, lam, n_threads=threads)
         Vs = oracle.repair(W.MODEL, W.COST, p.track, x, r["V_plus"], rep["n_steps"], rep["step"], rep["objective"])
         x = oracle.execute(W.MODEL, x, Vs[0], dist[n_it])
         V = oracle.shift(r["V_plus"])
         n_it += 1
         el = time.perf_counter() - t0
-        if el > 10.0 or n_it >= 60:
-            break
+        if el > budget_s or n_it >= max_it:
+            return n_it, el
+
+
+def cpu_baseline(W, K, T, lam, rep):
+    """The FP64 oracle, as it stands, on a bounded sample of the headline workload:
+    a few closed-loop iterations (rollout of all K samples, weights, update, shield,
+    plant), with the rollout threaded over the host's cores, and the same again on
+    one thread."""
+    cores = min(os.cpu_count() or 1, 16)
+    n_it, el = _oracle_closed_loop(W, K, T, lam, rep, cores, 10.0, 60)
+    n1, el1 = _oracle_closed_loop(W, K, T, lam, rep, 1, 5.0, 60)
     return {"value": K * T * n_it / el, "unit": "rollout-steps/s", "cores": cores, "kind": "oracle",
             "ms_per_iter": 1e3 * el / n_it,
+            "single_thread": {"value": K * T * n1 / el1, "ms_per_iter": 1e3 * el1 / n1, "iterations": n1},
+            "cpu": _cpu_model(),
             "sample": f"{n_it} closed-loop iterations of the headline workload (K={K}, T={T}, shield on), "
-                      f"FP64 oracle, rollout threaded over {cores} host threads"}
+                      f"FP64 oracle, rollout threaded over {cores} host threads; {n1} more on one thread"}
 
 
 if __name__ == "__main__":

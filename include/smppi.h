@@ -270,6 +270,11 @@ void smppi_plan_destroy(smppi_plan plan);
  * reset + fused rollout/weights/update, shield repair, execute/warm start. */
 smppi_status smppi_plan_launch_profiled(smppi_plan plan, void* stream);
 smppi_status smppi_plan_stage_ms(smppi_plan plan, float* fused_ms, float* repair_ms, float* execute_ms);
+/* Kernel-only durations (ms) of the last profiled launch: the fused
+ * rollout/weights/update kernel and the shield kernel, from events stamped with
+ * each kernel's own start and end (no launch gaps); 0 for a stage the plan does
+ * not run.  Waits for the last profiled launch; INVALID_ARGUMENT before one. */
+smppi_status smppi_plan_kernel_ms(smppi_plan plan, float* fused_ms, float* repair_ms);
 /* Launch geometry the plan uses (any output pointer may be NULL). */
 smppi_status smppi_plan_info(smppi_plan plan, int32_t* grid, int32_t* block, int32_t* tile, int32_t* n_tiles);
 

@@ -26,7 +26,7 @@ EXPORTS = ("smppi_create", "smppi_destroy", "smppi_last_error", "smppi_status_st
            "smppi_reserve", "smppi_device_errors", "smppi_rollout", "smppi_weights", "smppi_update",
            "smppi_rollout_backward", "smppi_shield_repair", "smppi_execute", "smppi_plan_create",
            "smppi_plan_launch", "smppi_plan_destroy", "smppi_plan_info", "smppi_plan_launch_profiled",
-           "smppi_plan_stage_ms", "smppi_debug_philox")
+           "smppi_plan_stage_ms", "smppi_plan_kernel_ms", "smppi_debug_philox")
 
 
 class Model(ctypes.Structure):
@@ -99,6 +99,7 @@ _SIGS = {
     "smppi_plan_info": (c_i32, [c_vp, P(c_i32), P(c_i32), P(c_i32), P(c_i32)]),
     "smppi_plan_launch_profiled": (c_i32, [c_vp, c_vp]),
     "smppi_plan_stage_ms": (c_i32, [c_vp, P(ctypes.c_float), P(ctypes.c_float), P(ctypes.c_float)]),
+    "smppi_plan_kernel_ms": (c_i32, [c_vp, P(ctypes.c_float), P(ctypes.c_float)]),
     "smppi_debug_philox": (c_i32, [c_vp, c_vp, P(c_u32), c_i64, c_vp, c_vp]),
 }
 

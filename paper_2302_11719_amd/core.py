@@ -256,6 +256,14 @@ class Plan:
                        "smppi_plan_stage_ms")
         return f.value, r.value, e.value
 
+    def kernel_ms(self):
+        """(fused kernel, shield kernel) durations in ms of the last profiled launch,
+        from events stamped with the kernels' own start and end."""
+        f, r = ctypes.c_float(), ctypes.c_float()
+        self.ctx.check(L.lib().smppi_plan_kernel_ms(self.h, ctypes.byref(f), ctypes.byref(r)),
+                       "smppi_plan_kernel_ms")
+        return f.value, r.value
+
     def info(self):
         g, b, t, n = (ctypes.c_int32() for _ in range(4))
         self.ctx.check(L.lib().smppi_plan_info(self.h, ctypes.byref(g), ctypes.byref(b), ctypes.byref(t),

@@ -57,7 +57,7 @@ ProblemArgs<R> problem_args(smppi_ctx ctx, const smppi_batch* b, const smppi_tra
 template <class R>
 smppi_status repair_t(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const smppi_cost* c,
                       const smppi_track* t, const void* x0, const void* Vp, const smppi_repair_opts* o, void* Vs,
-                      hipStream_t s);
+                      hipStream_t s, hipEvent_t kernel_start = nullptr, hipEvent_t kernel_stop = nullptr);
 template <class R>
 smppi_status execute_t(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const void* Ve, const void* Vp,
                        const void* dist, int32_t n_dist, void* x, void* V, uint32_t* iter, hipStream_t s);

@@ -7,6 +7,7 @@
 // log-sum-exp rescale) and writes V+ and the weight statistics.  The shield
 // (repair) and the execute/warm-start kernels follow on the same stream; the
 // whole sequence is captured once into a HIP graph.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -383,14 +384,22 @@ struct smppi_plan_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ek[4] = {nullptr, nullptr, nullptr, nullptr};  // k_fused, k_repair start/stop
 };
+
+static smppi_status ensure_events(smppi_plan p, hipEvent_t* e, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!e[i]) {
+      hipError_t r = hipEventCreate(&e[i]);
+      if (r != hipSuccess) return hip_fail(p->ctx, r, "hipEventCreate");
+    }
+  return SMPPI_OK;
+}
 
 static smppi_status mark(smppi_plan p, hipStream_t s, int i, bool profiled) {
   if (!profiled) return SMPPI_OK;
-  if (!p->ev[i]) {
-    hipError_t e = hipEventCreate(&p->ev[i]);
-    if (e != hipSuccess) return hip_fail(p->ctx, e, "hipEventCreate");
-  }
+  smppi_status st = ensure_events(p, p->ev + i, 1);
+  if (st) return st;
   hipError_t e = hipEventRecord(p->ev[i], s);
   if (e != hipSuccess) return hip_fail(p->ctx, e, "hipEventRecord");
   return SMPPI_OK;
@@ -404,6 +413,7 @@ static smppi_status plan_enqueue(smppi_plan p, hipStream_t s, bool profiled = fa
   const int B = p->batch.n_problems;
   smppi_status st0 = mark(p, s, 0, profiled);
   if (st0) return st0;
+  if (profiled && (st0 = ensure_events(p, p->ek, 4))) return st0;
   hipLaunchKernelGGL(k_reset, dim3((B + 1 + 255) / 256), dim3(256), 0, s, p->counters, p->counters + 1, B);
   smppi_status st = check_launch(ctx, "k_reset");
   if (st) return st;
@@ -414,14 +424,18 @@ static smppi_status plan_enqueue(smppi_plan p, hipStream_t s, bool profiled = fa
     if ((st = check_launch(ctx, "k_copy_empty"))) return st;
   }
   if (p->fa.n_tiles > 0) {
-    hipLaunchKernelGGL(p->fn, dim3(p->grid), dim3(p->block), p->lds, s, p->fa);
+    if (profiled)  // events stamped with the kernel's own start and end
+      hipExtLaunchKernelGGL(p->fn, dim3(p->grid), dim3(p->block), (uint32_t)p->lds, s, p->ek[0], p->ek[1], 0u, p->fa);
+    else
+      hipLaunchKernelGGL(p->fn, dim3(p->grid), dim3(p->block), p->lds, s, p->fa);
     if ((st = check_launch(ctx, "k_fused"))) return st;
   }
   if ((st = mark(p, s, 1, profiled))) return st;
   const void* V_exec = p->bufs.V_plus;
   if (p->opts.repair) {
     if ((st = repair_t<float>(ctx, &p->batch, &p->model, &p->cost, &p->track, p->bufs.x0, p->bufs.V_plus,
-                              &p->opts.repair_opts, p->bufs.V_safe, s)))
+                              &p->opts.repair_opts, p->bufs.V_safe, s, profiled ? p->ek[2] : nullptr,
+                              profiled ? p->ek[3] : nullptr)))
       return st;
     V_exec = p->bufs.V_safe;
   }
@@ -442,6 +456,8 @@ extern "C" void smppi_plan_destroy(smppi_plan p) {
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (hipEvent_t e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : p->ek)
     if (e) (void)hipEventDestroy(e);
   if (p->tiles) (void)hipFree(p->tiles);
   if (p->tile_off) (void)hipFree(p->tile_off);
@@ -627,6 +643,21 @@ extern "C" smppi_status smppi_plan_stage_ms(smppi_plan p, float* fused_ms, float
   if (fused_ms) *fused_ms = t[0];
   if (repair_ms) *repair_ms = t[1];
   if (execute_ms) *execute_ms = t[2];
+  return SMPPI_OK;
+}
+
+extern "C" smppi_status smppi_plan_kernel_ms(smppi_plan p, float* fused_ms, float* repair_ms) {
+  if (!p || !p->ev[3]) return p ? smppi::fail(p->ctx, SMPPI_ERR_INVALID_ARGUMENT, "no profiled launch yet")
+                                : SMPPI_ERR_INVALID_ARGUMENT;
+  hipError_t e = hipEventSynchronize(p->ev[3]);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "hipEventSynchronize");
+  float f = 0.f, r = 0.f;
+  if (p->fa.n_tiles > 0 && (e = hipEventElapsedTime(&f, p->ek[0], p->ek[1])) != hipSuccess)
+    return hip_fail(p->ctx, e, "hipEventElapsedTime");
+  if (p->opts.repair && (e = hipEventElapsedTime(&r, p->ek[2], p->ek[3])) != hipSuccess)
+    return hip_fail(p->ctx, e, "hipEventElapsedTime");
+  if (fused_ms) *fused_ms = f;
+  if (repair_ms) *repair_ms = r;
   return SMPPI_OK;
 }
 

@@ -1,5 +1,6 @@
 // Host side of the C ABI: context, validation, scratch, dispatch of the plain
 // (one call per stage) path.  The batched persistent plan lives in plan.hip.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -449,18 +450,22 @@ extern "C" smppi_status smppi_rollout_backward(smppi_ctx ctx, const smppi_batch*
 
 // ------------------------------------------------------------------ repair
 template <class R, int NOBS>
-static smppi_status launch_repair(smppi_ctx ctx, const smppi_batch* b, const RepairArgs<R>& a, hipStream_t s) {
+static smppi_status launch_repair(smppi_ctx ctx, const smppi_batch* b, const RepairArgs<R>& a, hipStream_t s,
+                                  hipEvent_t e0, hipEvent_t e1) {
   const size_t lds = stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max) + repair_lds_bytes<R>(a.p.t_max);
   if (lds > (size_t)ctx->max_lds)
     return fail(ctx, SMPPI_ERR_SHAPE, "repair needs %zu B of LDS per workgroup (device max %d)", lds, ctx->max_lds);
-  hipLaunchKernelGGL((k_repair<R, NOBS>), dim3(b->n_problems), dim3(REP_BLK), lds, s, a);
+  if (e0 && e1)  // events stamped with the kernel's own start and end
+    hipExtLaunchKernelGGL((k_repair<R, NOBS>), dim3(b->n_problems), dim3(REP_BLK), (uint32_t)lds, s, e0, e1, 0u, a);
+  else
+    hipLaunchKernelGGL((k_repair<R, NOBS>), dim3(b->n_problems), dim3(REP_BLK), lds, s, a);
   return check_launch(ctx, "k_repair");
 }
 
 template <class R>
 smppi_status smppi::repair_t(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const smppi_cost* c,
                              const smppi_track* t, const void* x0, const void* Vp, const smppi_repair_opts* o,
-                             void* Vs, hipStream_t s) {
+                             void* Vs, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   RepairArgs<R> a;
   a.p = problem_args<R>(ctx, b, t, nullptr, x0, nullptr);
   a.M = dev_model<R>(m);
@@ -471,12 +476,12 @@ smppi_status smppi::repair_t(smppi_ctx ctx, const smppi_batch* b, const smppi_mo
   a.n_steps = o->n_steps;
   a.step = (R)o->step;
   a.seg_len = adj_seg_len(b->t_max);
-  if (t->obs_max > 0) return launch_repair<R, kMaxObs>(ctx, b, a, s);
-  return launch_repair<R, 0>(ctx, b, a, s);
+  if (t->obs_max > 0) return launch_repair<R, kMaxObs>(ctx, b, a, s, e0, e1);
+  return launch_repair<R, 0>(ctx, b, a, s, e0, e1);
 }
 template smppi_status smppi::repair_t<float>(smppi_ctx, const smppi_batch*, const smppi_model*, const smppi_cost*,
                                              const smppi_track*, const void*, const void*, const smppi_repair_opts*,
-                                             void*, hipStream_t);
+                                             void*, hipStream_t, hipEvent_t, hipEvent_t);
 
 smppi_status smppi::validate_repair(smppi_ctx ctx, const smppi_repair_opts* o) {
   if (!o) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "repair opts are NULL");

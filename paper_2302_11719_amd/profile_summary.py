@@ -1,0 +1,237 @@
+"""Summaries of rocprofv3 output for this library's kernels.
+
+rocprofv3 writes one CSV row per (dispatch, counter) for ``--pmc`` runs and one
+row per dispatch for ``--kernel-trace``.  This module reduces them to per-kernel
+means, scales the HBM byte counters by a plain copy kernel of known size, and
+writes/reads the short text summaries kept beside the benchmark.
+
+  python -m paper_2302_11719_amd.profile_summary traffic \\
+      --fetch DIR --write DIR --kernel k_fused --copy-bytes N --out FILE --command "..."
+  python -m paper_2302_11719_amd.profile_summary counters --pmc DIR [DIR ...] --trace DIR \\
+      --kernel NAME [--kernel NAME ...] --out FILE --command "..."
+  python -m paper_2302_11719_amd.profile_summary stats --trace DIR --out FILE --command "..."
+
+A traffic summary carries a digest of the kernel sources; ``load_traffic``
+returns None once the sources have changed since the counters were taken.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+COPY_KERNELS = ("__amd_rocclr_copyBuffer", "copyBuffer")
+
+
+def kernel_sources_digest() -> str:
+    """sha256 over the HIP sources (sorted by name), first 16 hex digits."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(CSRC, "*"))):
+        if f.endswith((".hip", ".hpp", ".h")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(kernel: str) -> str:
+    """'void ns::k_fused<0, 192, 1, true>(ns::FusedArgs) [clone .kd]' -> 'k_fused<0, 192, 1, true>'
+    (namespaces and the parameter list dropped)."""
+    k = re.sub(r"^void\s+", "", kernel.strip())
+    k = re.sub(r"\s*\[clone.*$", "", k)
+    k = k.replace("(anonymous namespace)::", "")
+    k = re.sub(r"^(\w+::)+", "", k)
+    depth = 0
+    for i, ch in enumerate(k):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return k[:i]
+    return k
+
+
+def _csvs(d: str, suffix: str):
+    return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+
+
+def read_counters(d: str):
+    """{kernel short name: {counter: [value per dispatch]}} from a --pmc run."""
+    per = defaultdict(lambda: defaultdict(dict))
+    for f in _csvs(d, "counter_collection.csv"):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                k = short_name(r["Kernel_Name"])
+                disp = (f, r["Dispatch_Id"])
+                c = r["Counter_Name"]
+                per[k][c][disp] = per[k][c].get(disp, 0.0) + float(r["Counter_Value"])
+    return {k: {c: list(v.values()) for c, v in cs.items()} for k, cs in per.items()}
+
+
+def read_trace(d: str):
+    """{kernel short name: [duration ns per dispatch]} from a --kernel-trace run."""
+    out = defaultdict(list)
+    for f in _csvs(d, "kernel_trace.csv"):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                out[short_name(r["Kernel_Name"])].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return dict(out)
+
+
+def read_stats(d: str):
+    rows = []
+    for f in _csvs(d, "kernel_stats.csv"):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _match(names, pattern):
+    return [k for k in names if k == pattern or k.startswith(pattern + "<") or k.startswith(pattern + "(")]
+
+
+def _mean(v):
+    return sum(v) / len(v) if v else float("nan")
+
+
+def _copy_factor(counters, counter, copy_bytes):
+    """Known bytes / counter bytes for the plain copy kernel (largest dispatch)."""
+    for k in counters:
+        if any(c in k for c in COPY_KERNELS) and counter in counters[k]:
+            kib = max(counters[k][counter])
+            if kib > 0:
+                return copy_bytes / (kib * 1024.0), kib
+    return None, None
+
+
+def traffic_summary(fetch_dir, write_dir, kernel, copy_bytes):
+    fc, wc = read_counters(fetch_dir), read_counters(write_dir)
+    ff, fcopy = _copy_factor(fc, "FETCH_SIZE", copy_bytes)
+    wf, wcopy = _copy_factor(wc, "WRITE_SIZE", copy_bytes)
+    out = {"digest": kernel_sources_digest(), "copy_bytes": copy_bytes,
+           "copy_fetch_kib": fcopy, "copy_write_kib": wcopy, "fetch_factor": ff, "write_factor": wf,
+           "kernels": {}}
+    names = sorted(set(_match(fc, kernel)) | set(_match(wc, kernel)))
+    for k in names:
+        fk = fc.get(k, {}).get("FETCH_SIZE", [])
+        wk = wc.get(k, {}).get("WRITE_SIZE", [])
+        fb = _mean(fk) * 1024.0 * (ff or float("nan"))
+        wb = _mean(wk) * 1024.0 * (wf or float("nan"))
+        out["kernels"][k] = {"dispatches": [len(fk), len(wk)], "fetch_kib": _mean(fk), "write_kib": _mean(wk),
+                             "fetch_bytes": fb, "write_bytes": wb, "traffic_bytes": fb + wb}
+    return out
+
+
+def _md_table(head, rows):
+    s = "| " + " | ".join(head) + " |\n|" + "---|" * len(head) + "\n"
+    for r in rows:
+        s += "| " + " | ".join(str(x) for x in r) + " |\n"
+    return s
+
+
+def write_md(path, title, command, body, payload):
+    with open(path, "w") as fh:
+        fh.write(f"# {title}\n\nCommand (from the repository root on the GPU host):\n\n```\n{command}\n```\n\n")
+        fh.write(body)
+        fh.write("\n```json\n" + json.dumps(payload, indent=1, sort_keys=True) + "\n```\n")
+
+
+def load_payload(path):
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"```json\n(.*?)\n```", txt, re.S)
+    return json.loads(m.group(1)) if m else None
+
+
+def load_traffic(path, kernel_prefix):
+    """(bytes per launch, summary) for the first kernel matching the prefix, or
+    (None, reason) when the summary is missing or the sources have changed."""
+    p = load_payload(path)
+    if p is None:
+        return None, "no traffic summary"
+    if p.get("digest") != kernel_sources_digest():
+        return None, "kernel sources changed since the counters were taken"
+    for k, v in p.get("kernels", {}).items():
+        if k.startswith(kernel_prefix):
+            return v["traffic_bytes"], p
+    return None, "kernel not in summary"
+
+
+def _cmd_traffic(a):
+    s = traffic_summary(a.fetch, a.write, a.kernel, a.copy_bytes)
+    rows = [[k, v["dispatches"], f"{v['fetch_kib']:.1f}", f"{v['write_kib']:.1f}", f"{v['traffic_bytes']:.0f}"]
+            for k, v in s["kernels"].items()]
+    body = (f"Plain copy of {a.copy_bytes} bytes (read + write) reads FETCH_SIZE {s['copy_fetch_kib']} KiB and "
+            f"WRITE_SIZE {s['copy_write_kib']} KiB; factors (known / counted) fetch {s['fetch_factor']}, "
+            f"write {s['write_factor']}.\n\n"
+            + _md_table(["kernel", "dispatches (fetch, write run)", "FETCH_SIZE KiB/dispatch",
+                         "WRITE_SIZE KiB/dispatch", "scaled HBM bytes/dispatch"], rows))
+    write_md(a.out, a.title or f"HBM traffic of {a.kernel}", a.command, body, s)
+
+
+def _cmd_counters(a):
+    merged = defaultdict(dict)
+    for d in a.pmc:
+        for k, cs in read_counters(d).items():
+            for c, v in cs.items():
+                merged[k][c] = v
+    tr = read_trace(a.trace) if a.trace else {}
+    payload = {"digest": kernel_sources_digest(), "kernels": {}}
+    rows = []
+    for pat in a.kernel:
+        for k in _match(merged, pat):
+            cs = {c: _mean(v) for c, v in merged[k].items()}
+            dur = _mean(tr.get(k, [])) if tr else float("nan")
+            cs["duration_ns"] = dur
+            payload["kernels"][k] = cs
+            for c in sorted(cs):
+                rows.append([k, c, f"{cs[c]:.6g}"])
+    write_md(a.out, a.title or "Counters", a.command,
+             _md_table(["kernel", "counter (mean per dispatch)", "value"], rows), payload)
+
+
+def _cmd_stats(a):
+    rows = read_stats(a.trace)
+    keep = ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs"]
+    rows = sorted(rows, key=lambda r: -float(r.get("TotalDurationNs", 0)))[: a.top]
+    body = _md_table(keep, [[short_name(r["Name"]) if c == "Name" else r.get(c, "") for c in keep] for r in rows])
+    payload = {"digest": kernel_sources_digest(),
+               "kernels": {short_name(r["Name"]): {"calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"])}
+                           for r in rows}}
+    write_md(a.out, a.title or "Kernel statistics", a.command, body, payload)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("--pmc", nargs="+", required=True)
+    c.add_argument("--trace")
+    c.add_argument("--kernel", action="append", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("--trace", required=True)
+    s.add_argument("--top", type=int, default=20)
+    for p in (t, c, s):
+        p.add_argument("--out", required=True)
+        p.add_argument("--command", required=True)
+        p.add_argument("--title")
+    a = ap.parse_args(argv)
+    {"traffic": _cmd_traffic, "counters": _cmd_counters, "stats": _cmd_stats}[a.cmd](a)
+
+
+if __name__ == "__main__":
+    main()

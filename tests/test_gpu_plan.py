@@ -82,6 +82,30 @@ def test_plan_graph_replays_match_eager_plan():
     assert np.array_equal(dbs[0].iter.cpu().numpy(), np.arange(1, 6) + 4)
 
 
+def test_profiled_launch_matches_and_times():
+    """The profiled launch (events between the stages, kernel-stamped events on the
+    fused and shield kernels) computes exactly what the ordinary launch computes, and
+    its kernel-only durations are positive and within the stage durations."""
+    probs = prep(ragged_problems(), F32)
+    M, C = params(F32)
+    rep = dict(n_steps=3, step=0.05, objective=W.OBJ_SHIELD)
+    dbs = [core.DeviceBatch(probs, dtype=F32) for _ in range(2)]
+    plans = [core.Plan(ctx(), dbs[i], M, C, 4, W.LAMBDA, repair=rep, execute=True, use_graph=False)
+             for i in range(2)]
+    for step in range(3):
+        say(f"profiled launch {step}")
+        plans[0].launch()
+        plans[1].launch_profiled()
+        torch.cuda.synchronize()
+        f, r, _ = plans[1].stage_ms()
+        kf, kr = plans[1].kernel_ms()
+        assert 0.0 < kf <= f + 1e-3 and 0.0 < kr <= r + 1e-3, (f, r, kf, kr)
+        for name in ("x0", "V", "iter"):
+            assert torch.equal(getattr(dbs[0], name), getattr(dbs[1], name)), (step, name)
+        assert torch.equal(plans[0].V_safe, plans[1].V_safe)
+    assert ctx().device_errors() == 0
+
+
 def test_closed_loop_teacher_forced_c1():
     """Config-1 shape (K=4096, T=50): 4 receding-horizon steps through the graph plan with
     the shield and the disturbed plant; every step checked against the oracle from the
