@@ -16,7 +16,7 @@ durations (HIP events), the dominant kernel's roofline, and the FP64 CPU oracle
 on a bounded sample of the headline workload.
 
 usage: python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--skip-cpu] [--quick]
-                       [--forms plain,identical,ragged,large,c3] [--copy-calibration-mib N]
+                       [--forms plain,identical,ragged,large,c3,autotune] [--copy-calibration-mib N]
 """
 from __future__ import annotations
 
@@ -39,7 +39,7 @@ FLOP_STEP_PER_OBS = 9     # one circular obstacle barrier + penalty + indicator 
 FLOP_UPDATE_STEP = 4      # w * eps' accumulated for two controls
 PEAK_FP32 = 157.3e12      # MI355X FP32 vector peak (packed FMA on every lane)
 PEAK_HBM = 8.0e12
-FORMS = ("plain", "identical", "ragged", "large", "c3")
+FORMS = ("plain", "identical", "ragged", "large", "c3", "autotune")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_K4096_T50_hbm_traffic.md")
 
 
@@ -55,7 +55,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline only (same as --forms none)")
     ap.add_argument("--forms", default="all",
-                    help="comma list of the extra forms to run: plain, identical, ragged, large, c3 (or all/none)")
+                    help="comma list of the extra forms to run: plain, identical, ragged, large, c3, "
+                         "autotune (or all/none)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -210,6 +211,8 @@ def extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync, forms):
         _form_large(ctx, core, W, M, C, lam, sync, out, seed)
     if "c3" in forms:
         _form_c3(ctx, core, W, M, C, lam, rep, sync, out, seed)
+    if "autotune" in forms:
+        _form_autotune(ctx, core, W, M, C, lam, sync, out, seed)
     return out
 
 
@@ -324,6 +327,32 @@ def _form_c3(ctx, core, W, M, C, lam, rep, sync, out, seed):
     _log(f"  c3: {out['c3_B64_K2048_T50']}")
     pa.close()
     pb.close()
+
+
+def _form_autotune(ctx, core, W, M, C, lam, sync, out, seed):
+    """Autotuner table on the 512-problem ragged batch and on the headline shape
+    (fused kernel alone, kernel-stamped events; no cache file)."""
+    import torch
+
+    from paper_2302_11719_amd import autotune
+
+    for name, probs in (("ragged_B512", [W.round_to_f32(p) for p in W.config2()]),
+                        ("headline_K4096_T50", [W.round_to_f32(W.config1(K=4096, T=50))])):
+        db = core.DeviceBatch(probs, dtype=torch.float32)
+        r = autotune.tune(ctx, db, M, C, seed, lam, reps=5, warmup=2, cache=None)
+        default = core.Plan(ctx, db, M, C, seed, lam, use_graph=False)
+        info = default.info()
+        dms = []
+        for i in range(7):
+            default.launch_profiled()
+            if i >= 2:
+                dms.append(default.kernel_ms()[0])
+        default.close()
+        out[f"autotune_{name}"] = {"best": r.best, "best_kernel_ms": r.best_ms,
+                                   "default": info, "default_kernel_ms": float(np.median(dms)),
+                                   "candidates": len(r.table), "top5": r.table[:5], "worst": r.table[-1]}
+        _log(f"  autotune {name}: best {r.best} {r.best_ms:.4f} ms; default {info} {np.median(dms):.4f} ms; "
+             f"worst {r.table[-1]['kernel_ms']:.4f} ms over {len(r.table)} candidates")
 
 
 def _cpu_model():

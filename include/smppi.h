@@ -229,7 +229,8 @@ typedef struct {
   const void* dist;          /* as smppi_execute */
   int32_t n_dist;
   int32_t block;             /* threads per workgroup (64, 128, 256 or 512); 0 = 256 */
-  int32_t tile;              /* samples per tile (multiple of block); 0 = block */
+  int32_t tile;              /* samples per tile (multiple of block); 0 = 2 block when the
+                                batch has at least 16 block samples per CU, else block */
   int32_t grid;              /* persistent workgroups; 0 = chosen from occupancy */
   int32_t use_graph;         /* nonzero: capture into a hipGraph at creation */
   int32_t pipeline;          /* 1: latency mode (64-sample tiles, three specialised waves

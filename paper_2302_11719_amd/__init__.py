@@ -2,8 +2,8 @@
 
 The compute path is libsmppi.so (hand-written HIP kernels behind the C ABI of
 include/smppi.h); this package binds it (``core``), adds the autograd face of
-the adjoint kernel (``autograd``), the closed-loop controller (``controller``),
-the plan autotuner (``autotune``) and the seeded workload generator
+the adjoint kernel (``autograd``), the plan autotuner (``autotune``), rocprofv3
+summaries (``profile_summary``) and the seeded workload generator
 (``workloads``)."""
 from . import workloads  # noqa: F401
 
@@ -12,7 +12,7 @@ __all__ = ["workloads", "core", "autograd"]
 
 def __getattr__(name):
     # torch-dependent modules load lazily so that the generator imports cheaply
-    if name in ("core", "autograd", "controller", "autotune"):
+    if name in ("core", "autograd", "autotune"):
         import importlib
 
         return importlib.import_module(f".{name}", __name__)

@@ -503,7 +503,11 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   const bool pipe = opts->pipeline == 1 ||
                     (opts->pipeline == 0 && koff[B] <= (int64_t)2 * WAVE * std::max(ctx->n_cu, 1));
   const int block = pipe ? PIPE_BLK : (opts->block ? opts->block : 256);
-  const int tile = pipe ? WAVE : (opts->tile ? opts->tile : block);
+  // Two samples per thread once the batch has at least 8 two-sample tiles per CU
+  // (halves the tile partials the combine reads; measured faster on large ragged
+  // batches); one otherwise, so that smaller batches still fill every CU.
+  const bool two = koff[B] >= (int64_t)16 * block * std::max(ctx->n_cu, 1);
+  const int tile = pipe ? WAVE : (opts->tile ? opts->tile : (two ? 2 * block : block));
   if (!pipe && block != 64 && block != 128 && block != 256 && block != 512)
     return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "block must be 64, 128, 256 or 512");
   if (!pipe && tile % block != 0)
@@ -588,9 +592,6 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   int grid = opts->grid > 0 ? opts->grid : ctx->n_cu * per_cu;
   grid = std::max(1, std::min(grid, std::max(1, n_tiles)));
   p->grid = grid;
-  if (opts->repair || opts->execute) {
-    // the shield and execute kernels need their own validation-time state only
-  }
   if (opts->use_graph) {
     if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess)
       return bail(hip_fail(ctx, e, "hipStreamCreate"));

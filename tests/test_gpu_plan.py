@@ -212,3 +212,32 @@ def test_update_sparse_and_dense_paths(lam):
         assert err <= 1e-5, (b, err)
     err = float(np.abs(plan.V_plus.cpu().numpy() - Vp.cpu().numpy()).max())
     assert err <= 2e-5, err
+
+
+def test_autotune_picks_a_timed_candidate_and_caches(tmp_path):
+    """The autotuner times the candidates it is given, returns the fastest, stores it
+    under the batch's shape key and returns the stored entry on the next call; a plan
+    with the tuned geometry computes the same costs as another one-sample-per-lane plan."""
+    from paper_2302_11719_amd import autotune
+
+    probs = prep(ragged_problems(), F32)
+    M, C = params(F32)
+    db = core.DeviceBatch(probs, dtype=F32)
+    cache = str(tmp_path / "tune.json")
+    cands = [dict(pipeline=-1, block=64, tile=128, grid=0), dict(pipeline=-1, block=256, tile=256, grid=0),
+             dict(pipeline=-1, block=128, tile=128, grid=256)]
+    say("autotune 3 candidates")
+    r = autotune.tune(ctx(), db, M, C, 3, W.LAMBDA, cands=cands, reps=3, warmup=1, cache=cache)
+    assert not r.cached and len(r.table) == 3
+    assert r.best in [{k: c[k] for k in ("pipeline", "block", "tile", "grid")} for c in cands]
+    assert r.best_ms == min(row["kernel_ms"] for row in r.table) > 0.0
+    r2 = autotune.tune(ctx(), db, M, C, 3, W.LAMBDA, cands=cands, cache=cache)
+    assert r2.cached and r2.best == r.best and r2.key == r.key
+    tp = autotune.tuned_plan(ctx(), db, M, C, 3, W.LAMBDA, cache=cache, use_graph=False)
+    # one sample per lane in every candidate: per-sample costs are bit-identical across geometries
+    ref = core.Plan(ctx(), db, M, C, 3, W.LAMBDA, use_graph=False, pipeline=-1, block=256, tile=256)
+    tp.launch()
+    ref.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(tp.S, ref.S)
+    assert ctx().device_errors() == 0
