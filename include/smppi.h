@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define SMPPI_ABI_VERSION 1
+#define SMPPI_ABI_VERSION 2
 
 typedef enum {
   SMPPI_OK = 0,
@@ -232,10 +232,15 @@ typedef struct {
   int32_t tile;              /* samples per tile (multiple of block); 0 = 2 block when the
                                 batch has at least 16 block samples per CU, else block */
   int32_t grid;              /* persistent workgroups; 0 = chosen from occupancy */
-  int32_t use_graph;         /* nonzero: capture into a hipGraph at creation */
+  int32_t use_graph;         /* nonzero: capture into a hipGraph at creation when a launch
+                                has more than one kernel (one kernel is launched directly) */
   int32_t pipeline;          /* 1: latency mode (64-sample tiles, three specialised waves
                                 pipelining noise, dynamics and cost); -1: off; 0: on when
                                 the batch has at most 2*64 samples per compute unit */
+  int32_t fuse_shield;       /* 0: run the shield (and execute) of each problem inside the
+                                fused launch, in the workgroup that combines the problem,
+                                when its workgroups have at least two waves and the LDS
+                                fits; -1: always a separate shield kernel */
 } smppi_plan_opts;
 
 /* Buffers a plan reads and writes on every launch (device pointers, dtype F32):

@@ -22,6 +22,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "shape", 3: "dtype", 4: "no device"
 ERR_NO_DEVICE = 4
 
 # Symbols declared in include/smppi.h (checked by the CPU test suite).
+ABI_VERSION = 2  # SMPPI_ABI_VERSION of include/smppi.h this binding matches
 EXPORTS = ("smppi_create", "smppi_destroy", "smppi_last_error", "smppi_status_string", "smppi_abi_version",
            "smppi_reserve", "smppi_device_errors", "smppi_rollout", "smppi_weights", "smppi_update",
            "smppi_rollout_backward", "smppi_shield_repair", "smppi_execute", "smppi_plan_create",
@@ -65,7 +66,7 @@ class RepairOpts(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("lambda_", c_f64), ("repair", c_i32), ("repair_opts", RepairOpts), ("execute", c_i32),
                 ("dist", c_vp), ("n_dist", c_i32), ("block", c_i32), ("tile", c_i32), ("grid", c_i32),
-                ("use_graph", c_i32), ("pipeline", c_i32)]
+                ("use_graph", c_i32), ("pipeline", c_i32), ("fuse_shield", c_i32)]
 
 
 class PlanBuffers(ctypes.Structure):
@@ -126,8 +127,9 @@ def lib():
                 f = getattr(L, name)
                 f.restype = res
                 f.argtypes = args
-            if L.smppi_abi_version() != 1:
-                raise ImportError("libsmppi ABI version mismatch")
+            if L.smppi_abi_version() != ABI_VERSION:
+                raise ImportError(f"libsmppi ABI version {L.smppi_abi_version()}, binding expects {ABI_VERSION}: "
+                                  "rebuild the library")
             _lib = L
     return _lib
 

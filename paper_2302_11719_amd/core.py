@@ -213,7 +213,7 @@ class Plan:
     def __init__(self, ctx: Context, db: DeviceBatch, model: dict, cost: dict, seed: int, lam: float,
                  repair: Optional[dict] = None, execute: bool = False, dist: Optional[torch.Tensor] = None,
                  block: int = 0, tile: int = 0, grid: int = 0, use_graph: bool = True, nominal: bool = False,
-                 pipeline: int = 0):
+                 pipeline: int = 0, fuse_shield: int = 0):
         if db.dtype != torch.float32:
             raise ValueError("plans run in FP32")
         self.ctx, self.db = ctx, db
@@ -228,7 +228,7 @@ class Plan:
         opts = L.PlanOpts(float(lam), 1 if repair else 0, ro, 1 if execute else 0,
                           dist.data_ptr() if dist is not None else None,
                           int(dist.shape[0]) if dist is not None else 0, int(block), int(tile), int(grid),
-                          1 if use_graph else 0, int(pipeline))
+                          1 if use_graph else 0, int(pipeline), int(fuse_shield))
         bufs = L.PlanBuffers(db.x0.data_ptr(), db.V.data_ptr(), db.iter.data_ptr(), self.S.data_ptr(),
                              self.V_plus.data_ptr(), self.stats.data_ptr(),
                              self.V_safe.data_ptr() if self.V_safe is not None else None)

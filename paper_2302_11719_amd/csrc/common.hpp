@@ -54,10 +54,24 @@ template <class R> DevObjective<R> dev_objective(const smppi_objective* o);
 template <class R>
 ProblemArgs<R> problem_args(smppi_ctx ctx, const smppi_batch* b, const smppi_track* t, const smppi_noise* n,
                             const void* x0, const uint32_t* iter);
+// Plant step + warm start fused into the shield kernel (plans with both).
+struct ExecFuse {
+  const void* dist;
+  int32_t n_dist;
+  void* x;
+  void* V;
+  uint32_t* iter;
+};
+
+template <class R>
+RepairArgs<R> repair_args(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const smppi_cost* c,
+                          const smppi_track* t, const void* x0, const void* Vp, const smppi_repair_opts* o, void* Vs,
+                          const ExecFuse* ex);
 template <class R>
 smppi_status repair_t(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const smppi_cost* c,
                       const smppi_track* t, const void* x0, const void* Vp, const smppi_repair_opts* o, void* Vs,
-                      hipStream_t s, hipEvent_t kernel_start = nullptr, hipEvent_t kernel_stop = nullptr);
+                      hipStream_t s, hipEvent_t kernel_start = nullptr, hipEvent_t kernel_stop = nullptr,
+                      const ExecFuse* ex = nullptr);
 template <class R>
 smppi_status execute_t(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const void* Ve, const void* Vp,
                        const void* dist, int32_t n_dist, void* x, void* V, uint32_t* iter, hipStream_t s);

@@ -655,6 +655,57 @@ __global__ __launch_bounds__(WAVE) void k_backward(BackwardArgs<R> a) {
 }
 
 // ============================================================== repair
+// ============================================================== execute / warm start
+template <class R>
+struct ExecuteArgs {
+  const int32_t* t_off;
+  int32_t B, t_max;
+  DevModel<R> M;
+  const R* V_exec;
+  const R* V_plus;
+  const R* dist;
+  int32_t n_dist;
+  R* x;
+  R* V;
+  uint32_t* iter;
+  uint32_t* err;
+};
+
+// Plant step and warm start of problem b by one workgroup (Alg. 2, last two
+// lines): x <- RK4(x, clip(v_0)) + disturbance on (v_y, omega); V <- V+ shifted
+// by one step, last step repeated.  Vexec points at the problem's executed
+// sequence (global or LDS); buf is 2T values of LDS.
+template <class R>
+__device__ void execute_problem(const ExecuteArgs<R>& a, int b, int t0, int T, const R* Vexec, R* buf) {
+  const R* Vp = a.V_plus + 2 * (size_t)t0;
+  for (int i = threadIdx.x; i < 2 * T; i += blockDim.x) buf[i] = Vp[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const R u0 = clamp_r(Vexec[0], a.M.u_lo[0], a.M.u_hi[0]);
+    const R u1 = clamp_r(Vexec[T], a.M.u_lo[1], a.M.u_hi[1]);
+    State<R> x = load_state(a.x + 6 * (size_t)b);
+    rk4(a.M, step_ctl(a.M, u0, u1), x);
+    const uint32_t it = a.iter[b];
+    if (a.dist && (int64_t)it < (int64_t)a.n_dist) {
+      x.vy += a.dist[(2 * ((size_t)it * a.B + b))];
+      x.om += a.dist[(2 * ((size_t)it * a.B + b)) + 1];
+    }
+    R* xo = a.x + 6 * (size_t)b;
+    xo[0] = x.px;
+    xo[1] = x.py;
+    xo[2] = x.psi;
+    xo[3] = x.vx;
+    xo[4] = x.vy;
+    xo[5] = x.om;
+    a.iter[b] = it + 1u;
+  }
+  R* Vo = a.V + 2 * (size_t)t0;
+  for (int i = threadIdx.x; i < 2 * T; i += blockDim.x) {
+    const int dd = i / T, t = i % T;
+    Vo[i] = buf[dd * T + min(t + 1, T - 1)];
+  }
+}
+
 template <class R>
 struct RepairArgs {
   ProblemArgs<R> p;
@@ -666,11 +717,15 @@ struct RepairArgs {
   int n_steps;
   R step;
   int seg_len;
+  int exec;             // nonzero: also run the plant step and warm start (ex)
+  ExecuteArgs<R> ex;
 };
 
+// LDS of the shield beyond the staged problem: states x_0..x_T, segment
+// indices, and the per-step control constants (5 per step).
 template <class R>
 __host__ __device__ inline size_t repair_lds_bytes(int t_max) {
-  return (size_t)(t_max + 1) * (6 * sizeof(R) + sizeof(int));
+  return (size_t)(t_max + 1) * (6 * sizeof(R) + sizeof(int)) + (size_t)5 * t_max * sizeof(R);
 }
 
 // Algorithm 1 for one problem on one workgroup of two waves.  The nominal
@@ -762,19 +817,21 @@ __device__ void repair_reverse(const DevModel<R>& M, const DevCost<R>& C, const 
   }
 }
 
-// One workgroup (two waves) per problem.
+// Algorithm 1 for problem b by one workgroup of at least two waves (threads
+// beyond the first two waves only join the barriers).  Vs (LDS) holds V+ on
+// entry and V_safe on exit; tr is the staged problem; xs/is/ctl is
+// repair_lds_bytes of LDS.  Per iteration: every thread computes the control
+// constants of its share of the steps; wave 0 runs the RK4 chain on one lane
+// and wave 1 follows one chunk behind with the window (one segment per lane),
+// the obstacles (one per lane) and the barrier activity; the reverse sweep
+// starts at the last active transition, and the iteration loop stops when no
+// transition is active (zero gradient).
 template <class R, int NOBS>
-__global__ __launch_bounds__(REP_BLK) void k_repair(RepairArgs<R> a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_last;
-  const int b = blockIdx.x;
-  ProblemDims d;
-  if (!load_dims(a.p, b, d)) return;
-  R* Vs;
-  const TrackView<R> tr = stage_problem(a.p, b, d, a.V_plus, smem, &Vs);
-  R* xs = reinterpret_cast<R*>(smem + stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max));
+__device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims& d, const TrackView<R>& tr, R* Vs,
+                               unsigned char* lds, int* s_last) {
+  R* xs = reinterpret_cast<R*>(lds);
   int* is = reinterpret_cast<int*>(xs + 6 * (size_t)(a.p.t_max + 1));
-  __syncthreads();
+  R* ctl = reinterpret_cast<R*>(is + (a.p.t_max + 1));
   const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   const DevModel<R>& M = a.M;
   const DevCost<R>& C = a.C;
@@ -786,6 +843,15 @@ __global__ __launch_bounds__(REP_BLK) void k_repair(RepairArgs<R> a) {
   const int idx0 = tr.idx0;
   const R e20 = tr.n > 0 ? seg_dist2(tr, idx0, x0.px, x0.py) : circle_e2(tr, x0.px, x0.py);
   for (int s = 0; s < a.n_steps; ++s) {
+    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+      const StepCtl<R> sc =
+          step_ctl(M, clamp_r(Vs[t], M.u_lo[0], M.u_hi[0]), clamp_r(Vs[T + t], M.u_lo[1], M.u_hi[1]));
+      ctl[t] = sc.delta;
+      ctl[T + t] = sc.sd_m;
+      ctl[2 * T + t] = sc.cd_m;
+      ctl[3 * T + t] = sc.lfcd_Iz;
+      ctl[4 * T + t] = sc.a_tau;
+    }
     State<R> x = x0;
     int idx = idx0, last = -1;
     R hp = tr.w2 - e20, hob = R(0);
@@ -800,13 +866,19 @@ __global__ __launch_bounds__(REP_BLK) void k_repair(RepairArgs<R> a) {
         is[0] = idx0;
       }
     }
+    __syncthreads();
     for (int st = 0; st <= nch; ++st) {
       if (w == 0 && lane == 0 && st < nch) {
         const int t0 = st * REP_C, t1 = min(T, t0 + REP_C);
         for (int t = t0; t < t1; ++t) {
-          const R u0 = clamp_r(Vs[t], M.u_lo[0], M.u_hi[0]);
-          const R u1 = clamp_r(Vs[T + t], M.u_lo[1], M.u_hi[1]);
-          rk4(M, step_ctl(M, u0, u1), x);
+          StepCtl<R> sc;
+          sc.delta = ctl[t];
+          sc.sd_m = ctl[T + t];
+          sc.cd_m = ctl[2 * T + t];
+          sc.lfcd_Iz = ctl[3 * T + t];
+          sc.a_tau = ctl[4 * T + t];
+          sc.sd = sc.cd = R(0);  // used by the reverse sweep only
+          rk4(M, sc, x);
           R* o = xs + 6 * (t + 1);
           o[0] = x.px; o[1] = x.py; o[2] = x.psi; o[3] = x.vx; o[4] = x.vy; o[5] = x.om;
         }
@@ -835,77 +907,49 @@ __global__ __launch_bounds__(REP_BLK) void k_repair(RepairArgs<R> a) {
       }
       __syncthreads();
     }
-    if (w == 1 && lane == 0) s_last = last;
+    if (w == 1 && lane == 0) *s_last = last;
     __syncthreads();
-    const int t_end = cost_terms ? T - 1 : s_last;
-    if (w == 0 && lane == 0) {
-      for (int t = t_end + 1; t < T; ++t) {
-        Vs[t] = clamp_r(Vs[t], M.u_lo[0], M.u_hi[0]);
-        Vs[T + t] = clamp_r(Vs[T + t], M.u_lo[1], M.u_hi[1]);
-      }
-      if (t_end >= 0) repair_reverse<R, NOBS>(M, C, ob, tr, Vs, T, t_end, a.step, xs, is);
+    const int t_end = cost_terms ? T - 1 : *s_last;
+    // steps after the last active transition have zero gradient: projection only
+    for (int t = t_end + 1 + (int)threadIdx.x; t < T; t += blockDim.x) {
+      Vs[t] = clamp_r(Vs[t], M.u_lo[0], M.u_hi[0]);
+      Vs[T + t] = clamp_r(Vs[T + t], M.u_lo[1], M.u_hi[1]);
     }
+    if (w == 0 && lane == 0 && t_end >= 0) repair_reverse<R, NOBS>(M, C, ob, tr, Vs, T, t_end, a.step, xs, is);
     __syncthreads();
     if (t_end < 0) break;
   }
-  R* out = a.V_safe + 2 * (size_t)d.t0;
-  for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) out[i] = Vs[i];
 }
 
-// ============================================================== execute / warm start
-template <class R>
-struct ExecuteArgs {
-  const int32_t* t_off;
-  int32_t B, t_max;
-  DevModel<R> M;
-  const R* V_exec;
-  const R* V_plus;
-  const R* dist;
-  int32_t n_dist;
-  R* x;
-  R* V;
-  uint32_t* iter;
-  uint32_t* err;
-};
+// One workgroup (two waves) per problem.
+template <class R, int NOBS>
+__global__ __launch_bounds__(REP_BLK) void k_repair(RepairArgs<R> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_last;
+  const int b = blockIdx.x;
+  ProblemDims d;
+  if (!load_dims(a.p, b, d)) return;
+  R* Vs;
+  const TrackView<R> tr = stage_problem(a.p, b, d, a.V_plus, smem, &Vs);
+  unsigned char* lds = smem + stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max);
+  __syncthreads();
+  repair_problem<R, NOBS>(a, b, d, tr, Vs, lds, &s_last);
+  R* out = a.V_safe + 2 * (size_t)d.t0;
+  for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) out[i] = Vs[i];
+  if (a.exec) execute_problem(a.ex, b, d.t0, d.T, Vs, reinterpret_cast<R*>(lds));
+}
 
+// The plant step and warm start as a kernel of their own.
 template <class R>
 __global__ __launch_bounds__(WAVE) void k_execute(ExecuteArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  R* buf = reinterpret_cast<R*>(smem);
   const int b = blockIdx.x;
   const int t0 = a.t_off[b], T = a.t_off[b + 1] - t0;
   if (T < 1 || T > a.t_max) {
     if (threadIdx.x == 0) atomicOr(a.err, DERR_T);
     return;
   }
-  const R* Vp = a.V_plus + 2 * (size_t)t0;
-  for (int i = threadIdx.x; i < 2 * T; i += blockDim.x) buf[i] = Vp[i];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const R* Ve = a.V_exec + 2 * (size_t)t0;
-    const R u0 = clamp_r(Ve[0], a.M.u_lo[0], a.M.u_hi[0]);
-    const R u1 = clamp_r(Ve[T], a.M.u_lo[1], a.M.u_hi[1]);
-    State<R> x = load_state(a.x + 6 * (size_t)b);
-    rk4(a.M, step_ctl(a.M, u0, u1), x);
-    const uint32_t it = a.iter[b];
-    if (a.dist && (int64_t)it < (int64_t)a.n_dist) {
-      x.vy += a.dist[(2 * ((size_t)it * a.B + b))];
-      x.om += a.dist[(2 * ((size_t)it * a.B + b)) + 1];
-    }
-    R* xo = a.x + 6 * (size_t)b;
-    xo[0] = x.px;
-    xo[1] = x.py;
-    xo[2] = x.psi;
-    xo[3] = x.vx;
-    xo[4] = x.vy;
-    xo[5] = x.om;
-    a.iter[b] = it + 1u;
-  }
-  R* Vo = a.V + 2 * (size_t)t0;
-  for (int i = threadIdx.x; i < 2 * T; i += blockDim.x) {
-    const int dd = i / T, t = i % T;
-    Vo[i] = buf[dd * T + min(t + 1, T - 1)];
-  }
+  execute_problem(a, b, t0, T, a.V_exec + 2 * (size_t)t0, reinterpret_cast<R*>(smem));
 }
 
 }  // namespace smppi

@@ -4,9 +4,11 @@
 // split softmax partial (tile min cost, sum of weights, sum of squared weights,
 // weighted noise sums per step) and takes a ticket on its problem; the tile
 // that takes the last ticket combines the partials in tile order (streaming
-// log-sum-exp rescale) and writes V+ and the weight statistics.  The shield
-// (repair) and the execute/warm-start kernels follow on the same stream; the
-// whole sequence is captured once into a HIP graph.
+// log-sum-exp rescale) and writes V+ and the weight statistics; the last
+// workgroup to leave re-arms the queue.  The shield (repair) kernel follows on
+// the same stream and, when the plan executes, also runs the plant step and
+// warm start (a separate execute kernel when the shield is off); the sequence
+// is captured once into a HIP graph.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -37,8 +39,11 @@ struct FusedArgs {
   int n_tiles;
   int tile;                  // samples per tile
   float* part;               // [n_tiles][PART_HDR + 2 t_max]
-  uint32_t* queue;           // [1]
-  uint32_t* tickets;         // [B]
+  uint32_t* queue;           // [1] next tile
+  uint32_t* tickets;         // [B] finished tiles per problem
+  uint32_t* exits;           // [1] workgroups that have left the tile loop
+  int repair;                // nonzero: the combining workgroup also runs the shield (and execute)
+  RepairArgs<float> rep;
 };
 
 // ---------------------------------------------------------------------------
@@ -185,6 +190,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
   __shared__ NoiseSumLds<float, BLK, SPT> L;
   __shared__ int s_tile;
   __shared__ uint32_t s_ticket;
+  __shared__ int s_last;
   const int tid = threadIdx.x;
   const int pstride = PART_HDR + 2 * a.p.t_max;
   int staged_b = -1;
@@ -271,45 +277,98 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
     if (s_ticket == (uint32_t)(ntb - 1)) {
       __threadfence();
       // Streaming log-sum-exp combine: tile k's sums are rescaled by
-      // exp(-(min_k - min)/lambda); the scales of a chunk of tiles go through LDS.
+      // exp(-(min_k - min)/lambda).  The partials were written by other
+      // workgroups (other XCDs), so every pass is a round trip to memory: the
+      // tile headers are read once into registers and the scales kept in LDS
+      // when the problem has at most BLK*SPT tiles; the V+ pass keeps 16 loads
+      // in flight per thread.
       const float* P0 = a.part + (size_t)a.tile_off[b] * pstride;
-      float mn_l = INFINITY;
-      for (int k = tid; k < ntb; k += BLK) mn_l = fminf(mn_l, P0[(size_t)k * pstride]);
-      const float gmin = block_min(mn_l, red);
-      float z_l = 0.f, q_l = 0.f, nf_l = 0.f;
-      for (int k = tid; k < ntb; k += BLK) {
-        const float* Pk = P0 + (size_t)k * pstride;
-        const float mk = Pk[0];
-        const float sc = isfinite(mk) ? exp_r(-(mk - gmin) * a.inv_lambda) : 0.f;
-        z_l += sc * Pk[1];
-        q_l += sc * sc * Pk[2];
-        nf_l += Pk[3];
+      float* s_sc = L.w;
+      float gmin, Z, Q, NF;
+      const bool one_pass = ntb <= BLK * SPT;
+      if (one_pass) {
+        float mk[SPT], zk[SPT], qk[SPT];
+        float mn_l = INFINITY, nf_l = 0.f;
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) {
+          const int k = tid + j * BLK;
+          mk[j] = INFINITY;
+          zk[j] = qk[j] = 0.f;
+          if (k < ntb) {
+            const float* Pk = P0 + (size_t)k * pstride;
+            mk[j] = Pk[0];
+            zk[j] = Pk[1];
+            qk[j] = Pk[2];
+            nf_l += Pk[3];
+            mn_l = fminf(mn_l, mk[j]);
+          }
+        }
+        gmin = block_min(mn_l, red);
+        float z_l = 0.f, q_l = 0.f;
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) {
+          const int k = tid + j * BLK;
+          if (k < ntb) {
+            const float sc = isfinite(mk[j]) ? exp_r(-(mk[j] - gmin) * a.inv_lambda) : 0.f;
+            s_sc[k] = sc;
+            z_l += sc * zk[j];
+            q_l += sc * sc * qk[j];
+          }
+        }
+        Z = block_sum(z_l, red);
+        Q = block_sum(q_l, red);
+        NF = block_sum(nf_l, red);
+      } else {
+        float mn_l = INFINITY;
+        for (int k = tid; k < ntb; k += BLK) mn_l = fminf(mn_l, P0[(size_t)k * pstride]);
+        gmin = block_min(mn_l, red);
+        float z_l = 0.f, q_l = 0.f, nf_l = 0.f;
+        for (int k = tid; k < ntb; k += BLK) {
+          const float* Pk = P0 + (size_t)k * pstride;
+          const float mk = Pk[0];
+          const float sc = isfinite(mk) ? exp_r(-(mk - gmin) * a.inv_lambda) : 0.f;
+          z_l += sc * Pk[1];
+          q_l += sc * sc * Pk[2];
+          nf_l += Pk[3];
+        }
+        Z = block_sum(z_l, red);
+        Q = block_sum(q_l, red);
+        NF = block_sum(nf_l, red);
       }
-      const float Z = block_sum(z_l, red);
-      const float Q = block_sum(q_l, red);
-      const float NF = block_sum(nf_l, red);
       const float iZ = Z > 0.f ? 1.f / Z : 0.f;
       const float* Vb = a.V + 2 * (size_t)d.t0;
       float* Vpb = a.V_plus + 2 * (size_t)d.t0;
-      float* s_sc = L.w;
       for (int i0 = 0; i0 < 2 * d.T; i0 += BLK) {
         const int i = i0 + tid;
         float acc = 0.f;
-        for (int k0 = 0; k0 < ntb; k0 += BLK) {
-          __syncthreads();
-          if (k0 + tid < ntb) {
-            const float mk = P0[(size_t)(k0 + tid) * pstride];
-            s_sc[tid] = isfinite(mk) ? exp_r(-(mk - gmin) * a.inv_lambda) : 0.f;
-          }
-          __syncthreads();
-          const int kn = min(BLK, ntb - k0);
+        if (one_pass) {
           if (i < 2 * d.T) {
-            const float* Pi = P0 + (size_t)k0 * pstride + PART_HDR + i;
+            const float* Pi = P0 + PART_HDR + i;
+#pragma unroll 16
+            for (int kk = 0; kk < ntb; ++kk) acc += s_sc[kk] * Pi[(size_t)kk * pstride];
+          }
+        } else {
+          for (int k0 = 0; k0 < ntb; k0 += BLK) {
+            __syncthreads();
+            if (k0 + tid < ntb) {
+              const float mk = P0[(size_t)(k0 + tid) * pstride];
+              s_sc[tid] = isfinite(mk) ? exp_r(-(mk - gmin) * a.inv_lambda) : 0.f;
+            }
+            __syncthreads();
+            const int kn = min(BLK, ntb - k0);
+            if (i < 2 * d.T) {
+              const float* Pi = P0 + (size_t)k0 * pstride + PART_HDR + i;
 #pragma unroll 8
-            for (int kk = 0; kk < kn; ++kk) acc += s_sc[kk] * Pi[(size_t)kk * pstride];
+              for (int kk = 0; kk < kn; ++kk) acc += s_sc[kk] * Pi[(size_t)kk * pstride];
+            }
           }
         }
-        if (i < 2 * d.T) Vpb[i] = Vb[i] + acc * iZ;
+        if (i < 2 * d.T) {
+          const float vp = Vb[i] + acc * iZ;
+          Vpb[i] = vp;
+          // no tile of problem b is left: its staged V becomes the shield's V+
+          if (BLK >= 2 * WAVE && a.repair) Vs[i] = vp;
+        }
       }
       __syncthreads();
       if (tid == 0) {
@@ -319,7 +378,25 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
         a.stats[4 * b + 3] = NF;
         a.tickets[b] = 0u;
       }
+      if constexpr (BLK >= 2 * WAVE) {
+        if (a.repair) {
+          __syncthreads();
+          unsigned char* rl = smem + stage_lds_bytes<float>(a.p.poly_max, a.p.t_max, a.p.obs_max);
+          repair_problem<float, NOBS>(a.rep, b, d, tr, Vs, rl, &s_last);
+          float* out = a.rep.V_safe + 2 * (size_t)d.t0;
+          for (int i = tid; i < 2 * d.T; i += BLK) out[i] = Vs[i];
+          if (a.rep.exec) execute_problem(a.rep.ex, b, d.t0, d.T, Vs, reinterpret_cast<float*>(rl));
+          __syncthreads();
+          staged_b = -1;  // Vs no longer holds problem b's V
+        }
+      }
     }
+  }
+  // The last workgroup to leave re-arms the queue for the next launch (every
+  // other workgroup has taken its final, out-of-range, tile by then).
+  if (tid == 0 && atomicAdd(a.exits, 1u) == gridDim.x - 1) {
+    atomicExch(a.queue, 0u);
+    atomicExch(a.exits, 0u);
   }
 }
 
@@ -338,13 +415,6 @@ __global__ void k_copy_empty(const int64_t* k_off, const int32_t* t_off, const f
   }
 }
 
-// Zeroes the work-queue head and the per-problem tickets (a kernel rather than
-// a memset node, so the sequence can be captured and replayed).
-__global__ void k_reset(uint32_t* queue, uint32_t* tickets, int B) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) *queue = 0u;
-  if (i < B) tickets[i] = 0u;
-}
 
 using FusedFn = void (*)(FusedArgs);
 
@@ -375,11 +445,12 @@ struct smppi_plan_s {
   FusedFn fn = nullptr;
   int grid = 0, block = 256, lds = 0;
   bool any_empty = false;
+  bool fused_shield = false;  // shield (+ execute) run inside k_fused
   // device allocations owned by the plan
   int2* tiles = nullptr;
   int32_t* tile_off = nullptr;
   float* part = nullptr;
-  uint32_t* counters = nullptr;  // [0] queue, [1..B] tickets
+  uint32_t* counters = nullptr;  // [0] queue, [1..B] tickets, [B+1] exits
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -414,9 +485,7 @@ static smppi_status plan_enqueue(smppi_plan p, hipStream_t s, bool profiled = fa
   smppi_status st0 = mark(p, s, 0, profiled);
   if (st0) return st0;
   if (profiled && (st0 = ensure_events(p, p->ek, 4))) return st0;
-  hipLaunchKernelGGL(k_reset, dim3((B + 1 + 255) / 256), dim3(256), 0, s, p->counters, p->counters + 1, B);
-  smppi_status st = check_launch(ctx, "k_reset");
-  if (st) return st;
+  smppi_status st = SMPPI_OK;
   if (p->any_empty) {
     hipLaunchKernelGGL(k_copy_empty, dim3(B), dim3(64), 0, s, p->batch.k_off, p->batch.t_off,
                        static_cast<const float*>(p->bufs.V), static_cast<float*>(p->bufs.V_plus),
@@ -431,16 +500,17 @@ static smppi_status plan_enqueue(smppi_plan p, hipStream_t s, bool profiled = fa
     if ((st = check_launch(ctx, "k_fused"))) return st;
   }
   if ((st = mark(p, s, 1, profiled))) return st;
-  const void* V_exec = p->bufs.V_plus;
-  if (p->opts.repair) {
+  if (p->opts.repair && !p->fused_shield) {
+    // with execute on, the shield kernel also runs the plant step and warm start
+    const ExecFuse ef{p->opts.dist, p->opts.n_dist, p->bufs.x0, p->bufs.V, p->bufs.iter};
     if ((st = repair_t<float>(ctx, &p->batch, &p->model, &p->cost, &p->track, p->bufs.x0, p->bufs.V_plus,
                               &p->opts.repair_opts, p->bufs.V_safe, s, profiled ? p->ek[2] : nullptr,
-                              profiled ? p->ek[3] : nullptr)))
+                              profiled ? p->ek[3] : nullptr, p->opts.execute ? &ef : nullptr)))
       return st;
-    V_exec = p->bufs.V_safe;
   }
   if ((st = mark(p, s, 2, profiled))) return st;
-  if (p->opts.execute) {
+  if (p->opts.execute && !p->opts.repair) {  // (with the shield, it runs the plant step)
+    const void* V_exec = p->bufs.V_plus;
     if ((st = execute_t<float>(ctx, &p->batch, &p->model, V_exec, p->bufs.V_plus, p->opts.dist, p->opts.n_dist,
                                p->bufs.x0, p->bufs.V, p->bufs.iter, s)))
       return st;
@@ -486,6 +556,8 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   if (opts->repair && !bufs->V_safe) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "V_safe required with repair");
   if (opts->execute && opts->dist && opts->n_dist < 0)
     return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "n_dist must be >= 0");
+  if (opts->fuse_shield < -1 || opts->fuse_shield > 0)
+    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "fuse_shield must be -1 or 0");
   if (opts->pipeline < -1 || opts->pipeline > 1)
     return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "pipeline must be -1, 0 or 1");
   (void)hipSetDevice(ctx->device);
@@ -560,13 +632,13 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   if ((e = hipMalloc(&p->tiles, sizeof(int2) * std::max(1, n_tiles))) != hipSuccess ||
       (e = hipMalloc(&p->tile_off, sizeof(int32_t) * (B + 1))) != hipSuccess ||
       (e = hipMalloc(&p->part, sizeof(float) * (size_t)std::max(1, n_tiles) * pstride)) != hipSuccess ||
-      (e = hipMalloc(&p->counters, sizeof(uint32_t) * (B + 1))) != hipSuccess)
+      (e = hipMalloc(&p->counters, sizeof(uint32_t) * (B + 2))) != hipSuccess)
     return bail(hip_fail(ctx, e, "hipMalloc(plan)"));
   if (n_tiles > 0 && (e = hipMemcpy(p->tiles, tl.data(), sizeof(int2) * n_tiles, hipMemcpyHostToDevice)) != hipSuccess)
     return bail(hip_fail(ctx, e, "hipMemcpy(tiles)"));
   if ((e = hipMemcpy(p->tile_off, tile_off.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice)) != hipSuccess)
     return bail(hip_fail(ctx, e, "hipMemcpy(tile_off)"));
-  if ((e = hipMemset(p->counters, 0, sizeof(uint32_t) * (B + 1))) != hipSuccess)
+  if ((e = hipMemset(p->counters, 0, sizeof(uint32_t) * (B + 2))) != hipSuccess)
     return bail(hip_fail(ctx, e, "hipMemset(counters)"));
 
   FusedArgs& a = p->fa;
@@ -585,14 +657,39 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   a.part = p->part;
   a.queue = p->counters;
   a.tickets = p->counters + 1;
+  a.exits = p->counters + 1 + B;
   p->lds = (int)stage_lds_bytes<float>(track->poly_max, batch->t_max, obs_slots(track));
+  hipFuncAttributes fattr{};
+  if ((e = hipFuncGetAttributes(&fattr, reinterpret_cast<const void*>(fn))) != hipSuccess)
+    return bail(hip_fail(ctx, e, "hipFuncGetAttributes"));
+  const size_t lds_static = fattr.sharedSizeBytes;
+  if (lds_static + p->lds > (size_t)ctx->max_lds)
+    return bail(fail(ctx, SMPPI_ERR_SHAPE, "fused kernel needs %zu B of LDS per workgroup (device max %d)",
+                     lds_static + p->lds, ctx->max_lds));
+  // The shield (and execute) inside the fused launch: the workgroup that
+  // combines a problem runs Algorithm 1 on it right away.
+  a.repair = 0;
+  a.rep = RepairArgs<float>{};
+  if (opts->repair && opts->fuse_shield == 0 && block >= 2 * WAVE &&
+      lds_static + p->lds + repair_lds_bytes<float>(batch->t_max) <= (size_t)ctx->max_lds) {
+    const ExecFuse ef{opts->dist, opts->n_dist, bufs->x0, bufs->V, bufs->iter};
+    a.repair = 1;
+    a.rep = repair_args<float>(ctx, &p->batch, model, cost, &p->track, bufs->x0, bufs->V_plus, &opts->repair_opts,
+                               bufs->V_safe, opts->execute ? &ef : nullptr);
+    p->lds += (int)repair_lds_bytes<float>(batch->t_max);
+  }
+  p->fused_shield = a.repair != 0;
   int per_cu = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, p->lds);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   int grid = opts->grid > 0 ? opts->grid : ctx->n_cu * per_cu;
   grid = std::max(1, std::min(grid, std::max(1, n_tiles)));
   p->grid = grid;
-  if (opts->use_graph) {
+  // A graph only pays when the launch has several kernels; a single kernel is
+  // launched directly (measured: the one-node graph adds about 4 us per launch).
+  const int n_kernels = (any_empty ? 1 : 0) + (n_tiles > 0 ? 1 : 0) + (opts->repair && !p->fused_shield ? 1 : 0) +
+                        (opts->execute && !opts->repair ? 1 : 0);
+  if (opts->use_graph && n_kernels > 1) {
     if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess)
       return bail(hip_fail(ctx, e, "hipStreamCreate"));
     if ((e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
@@ -655,7 +752,7 @@ extern "C" smppi_status smppi_plan_kernel_ms(smppi_plan p, float* fused_ms, floa
   float f = 0.f, r = 0.f;
   if (p->fa.n_tiles > 0 && (e = hipEventElapsedTime(&f, p->ek[0], p->ek[1])) != hipSuccess)
     return hip_fail(p->ctx, e, "hipEventElapsedTime");
-  if (p->opts.repair && (e = hipEventElapsedTime(&r, p->ek[2], p->ek[3])) != hipSuccess)
+  if (p->opts.repair && !p->fused_shield && (e = hipEventElapsedTime(&r, p->ek[2], p->ek[3])) != hipSuccess)
     return hip_fail(p->ctx, e, "hipEventElapsedTime");
   if (fused_ms) *fused_ms = f;
   if (repair_ms) *repair_ms = r;

@@ -463,9 +463,9 @@ static smppi_status launch_repair(smppi_ctx ctx, const smppi_batch* b, const Rep
 }
 
 template <class R>
-smppi_status smppi::repair_t(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const smppi_cost* c,
-                             const smppi_track* t, const void* x0, const void* Vp, const smppi_repair_opts* o,
-                             void* Vs, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+RepairArgs<R> smppi::repair_args(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const smppi_cost* c,
+                                 const smppi_track* t, const void* x0, const void* Vp, const smppi_repair_opts* o,
+                                 void* Vs, const ExecFuse* ex) {
   RepairArgs<R> a;
   a.p = problem_args<R>(ctx, b, t, nullptr, x0, nullptr);
   a.M = dev_model<R>(m);
@@ -476,12 +476,39 @@ smppi_status smppi::repair_t(smppi_ctx ctx, const smppi_batch* b, const smppi_mo
   a.n_steps = o->n_steps;
   a.step = (R)o->step;
   a.seg_len = adj_seg_len(b->t_max);
+  a.exec = ex != nullptr;
+  a.ex = ExecuteArgs<R>{};
+  if (ex) {
+    a.ex.t_off = b->t_off;
+    a.ex.B = b->n_problems;
+    a.ex.t_max = b->t_max;
+    a.ex.M = a.M;
+    a.ex.V_exec = static_cast<const R*>(Vs);
+    a.ex.V_plus = static_cast<const R*>(Vp);
+    a.ex.dist = static_cast<const R*>(ex->dist);
+    a.ex.n_dist = ex->n_dist;
+    a.ex.x = static_cast<R*>(ex->x);
+    a.ex.V = static_cast<R*>(ex->V);
+    a.ex.iter = ex->iter;
+    a.ex.err = ctx->err;
+  }
+  return a;
+}
+template RepairArgs<float> smppi::repair_args<float>(smppi_ctx, const smppi_batch*, const smppi_model*,
+                                                     const smppi_cost*, const smppi_track*, const void*, const void*,
+                                                     const smppi_repair_opts*, void*, const ExecFuse*);
+
+template <class R>
+smppi_status smppi::repair_t(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const smppi_cost* c,
+                             const smppi_track* t, const void* x0, const void* Vp, const smppi_repair_opts* o,
+                             void* Vs, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const ExecFuse* ex) {
+  const RepairArgs<R> a = repair_args<R>(ctx, b, m, c, t, x0, Vp, o, Vs, ex);
   if (t->obs_max > 0) return launch_repair<R, kMaxObs>(ctx, b, a, s, e0, e1);
   return launch_repair<R, 0>(ctx, b, a, s, e0, e1);
 }
 template smppi_status smppi::repair_t<float>(smppi_ctx, const smppi_batch*, const smppi_model*, const smppi_cost*,
                                              const smppi_track*, const void*, const void*, const smppi_repair_opts*,
-                                             void*, hipStream_t, hipEvent_t, hipEvent_t);
+                                             void*, hipStream_t, hipEvent_t, hipEvent_t, const ExecFuse*);
 
 smppi_status smppi::validate_repair(smppi_ctx ctx, const smppi_repair_opts* o) {
   if (!o) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "repair opts are NULL");

@@ -39,7 +39,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = L.lib()
-    assert lib.smppi_abi_version() == 1
+    hdr = open(os.path.join(ROOT, "include", "smppi.h")).read()
+    ver = int(re.search(r"#define SMPPI_ABI_VERSION (\d+)", hdr).group(1))
+    assert lib.smppi_abi_version() == ver == L.ABI_VERSION
     assert lib.smppi_status_string(0) == b"ok"
     assert lib.smppi_status_string(4) == b"no device"
 

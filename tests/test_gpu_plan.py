@@ -66,8 +66,9 @@ def test_plan_graph_replays_match_eager_plan():
     dist = torch.as_tensor(W.disturbances(1, 8 * len(probs)).reshape(-1), dtype=F32, device="cuda")
     rep = dict(n_steps=3, step=0.05, objective=W.OBJ_SHIELD)
     dbs = [core.DeviceBatch(probs, dtype=F32) for _ in range(2)]
+    # separate shield kernel: the launch has two kernels, so the first plan is a graph
     plans = [core.Plan(ctx(), dbs[i], M, C, 9, W.LAMBDA, repair=rep, execute=True, dist=dist.view(8, -1),
-                       use_graph=(i == 0)) for i in range(2)]
+                       use_graph=(i == 0), fuse_shield=-1) for i in range(2)]
     for step in range(4):
         say(f"graph replay {step}")
         for pl in plans:
@@ -82,16 +83,18 @@ def test_plan_graph_replays_match_eager_plan():
     assert np.array_equal(dbs[0].iter.cpu().numpy(), np.arange(1, 6) + 4)
 
 
-def test_profiled_launch_matches_and_times():
+@pytest.mark.parametrize("fuse", [-1, 0])
+def test_profiled_launch_matches_and_times(fuse):
     """The profiled launch (events between the stages, kernel-stamped events on the
     fused and shield kernels) computes exactly what the ordinary launch computes, and
-    its kernel-only durations are positive and within the stage durations."""
+    its kernel-only durations are positive and within the stage durations (the shield's
+    is 0 when it runs inside the fused launch)."""
     probs = prep(ragged_problems(), F32)
     M, C = params(F32)
     rep = dict(n_steps=3, step=0.05, objective=W.OBJ_SHIELD)
     dbs = [core.DeviceBatch(probs, dtype=F32) for _ in range(2)]
-    plans = [core.Plan(ctx(), dbs[i], M, C, 4, W.LAMBDA, repair=rep, execute=True, use_graph=False)
-             for i in range(2)]
+    plans = [core.Plan(ctx(), dbs[i], M, C, 4, W.LAMBDA, repair=rep, execute=True, use_graph=False,
+                       fuse_shield=fuse) for i in range(2)]
     for step in range(3):
         say(f"profiled launch {step}")
         plans[0].launch()
@@ -99,10 +102,36 @@ def test_profiled_launch_matches_and_times():
         torch.cuda.synchronize()
         f, r, _ = plans[1].stage_ms()
         kf, kr = plans[1].kernel_ms()
-        assert 0.0 < kf <= f + 1e-3 and 0.0 < kr <= r + 1e-3, (f, r, kf, kr)
+        assert 0.0 < kf <= f + 1e-3, (f, kf)
+        assert (0.0 < kr <= r + 1e-3) if fuse == -1 else kr == 0.0, (r, kr)
         for name in ("x0", "V", "iter"):
             assert torch.equal(getattr(dbs[0], name), getattr(dbs[1], name)), (step, name)
         assert torch.equal(plans[0].V_safe, plans[1].V_safe)
+    assert ctx().device_errors() == 0
+
+
+@pytest.mark.parametrize("pipeline,block", [(1, 0), (-1, 256), (-1, 64)])
+def test_fused_shield_matches_separate_shield_kernel(pipeline, block):
+    """Shield and execute run by the combining workgroup inside the fused launch equal
+    the separate shield kernel bit for bit, over three closed-loop launches (block 64
+    has one wave, so it always uses the separate kernel)."""
+    probs = prep(ragged_problems(), F32)
+    M, C = params(F32)
+    dist = torch.as_tensor(W.disturbances(2, 8 * len(probs)).reshape(-1), dtype=F32, device="cuda")
+    rep = dict(n_steps=4, step=0.05, objective=W.OBJ_SHIELD)
+    dbs = [core.DeviceBatch(probs, dtype=F32) for _ in range(2)]
+    plans = [core.Plan(ctx(), dbs[i], M, C, 11, W.LAMBDA, repair=rep, execute=True, dist=dist.view(8, -1),
+                       use_graph=False, pipeline=pipeline, block=block, fuse_shield=(0 if i == 0 else -1))
+             for i in range(2)]
+    for step in range(3):
+        say(f"fused shield pipeline={pipeline} block={block} step {step}")
+        for pl in plans:
+            pl.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(plans[0].V_plus, plans[1].V_plus), step
+        assert torch.equal(plans[0].V_safe, plans[1].V_safe), step
+        for name in ("x0", "V", "iter"):
+            assert torch.equal(getattr(dbs[0], name), getattr(dbs[1], name)), (step, name)
     assert ctx().device_errors() == 0
 
 
