@@ -239,7 +239,7 @@ typedef struct {
                                 the batch has at most 2*64 samples per compute unit */
   int32_t fuse_shield;       /* 0: run the shield (and execute) of each problem inside the
                                 fused launch, in the workgroup that combines the problem,
-                                when its workgroups have at least two waves and the LDS
+                                when its workgroups have at least three waves and the LDS
                                 fits; -1: always a separate shield kernel */
 } smppi_plan_opts;
 

@@ -162,22 +162,35 @@ __device__ __forceinline__ StepCtl<R> step_ctl(const DevModel<R>& M, R delta, R 
   return c;
 }
 
-// f of the six-state single-track model; (p_x, p_y) do not feed back, so only
-// (psi, v_x, v_y, omega) are inputs.
+// f of the six-state single-track model.  The velocities (v_x, v_y, omega)
+// evolve on their own (body-frame forces depend on neither position nor
+// heading); (p_x, p_y, psi) integrate them.  The two parts are separate
+// functions so that a step can be split across waves with the same arithmetic.
 template <class R>
-__device__ __forceinline__ void deriv(const DevModel<R>& M, const StepCtl<R>& c, R psi, R vx, R vy, R om,
-                                      R& dpx, R& dpy, R& dvx, R& dvy, R& dom) {
+__device__ __forceinline__ void vel_deriv(const DevModel<R>& M, const StepCtl<R>& c, R vx, R vy, R om, R& dvx,
+                                          R& dvy, R& dom) {
   const R vt = fmax(vx, M.v_min);
   const R inv = rcp_r(vt);
   const R Ff = M.Cf * (c.delta - (vy + M.lf * om) * inv);
   const R Fr = M.Cr * ((M.lr * om - vy) * inv);
+  dvx = c.a_tau - M.c_v * vx - Ff * c.sd_m + vy * om;
+  dvy = Ff * c.cd_m + Fr * M.inv_m - vx * om;
+  dom = Ff * c.lfcd_Iz - Fr * M.lr_Iz;
+}
+
+template <class R>
+__device__ __forceinline__ void pose_deriv(R psi, R vx, R vy, R& dpx, R& dpy) {
   R sp, cp;
   sincos_r(psi, &sp, &cp);
   dpx = vx * cp - vy * sp;
   dpy = vx * sp + vy * cp;
-  dvx = c.a_tau - M.c_v * vx - Ff * c.sd_m + vy * om;
-  dvy = Ff * c.cd_m + Fr * M.inv_m - vx * om;
-  dom = Ff * c.lfcd_Iz - Fr * M.lr_Iz;
+}
+
+template <class R>
+__device__ __forceinline__ void deriv(const DevModel<R>& M, const StepCtl<R>& c, R psi, R vx, R vy, R om,
+                                      R& dpx, R& dpy, R& dvx, R& dvy, R& dom) {
+  vel_deriv(M, c, vx, vy, om, dvx, dvy, dom);
+  pose_deriv(psi, vx, vy, dpx, dpy);
 }
 
 template <class R>
@@ -185,28 +198,60 @@ struct State {
   R px, py, psi, vx, vy, om;
 };
 
+// Velocities at the four RK4 stages of one step (stage 1 = the step's start).
+template <class R>
+struct VelStages {
+  R vx[4], vy[4], om[4];
+};
+
+// Velocity part of a classic RK4 step over dt with the control held: advances
+// (v_x, v_y, omega) and returns the stage velocities the pose part needs.
+template <class R>
+__device__ __forceinline__ void rk4_vel(const DevModel<R>& M, const StepCtl<R>& c, R& vx, R& vy, R& om,
+                                        VelStages<R>& g) {
+  const R h = M.dt, h2 = R(0.5) * M.dt, h6 = M.dt * R(1.0 / 6.0);
+  R a3, a4, a5, b3, b4, b5, c3, c4, c5, d3, d4, d5;
+  g.vx[0] = vx;
+  g.vy[0] = vy;
+  g.om[0] = om;
+  vel_deriv(M, c, vx, vy, om, a3, a4, a5);
+  g.vx[1] = vx + h2 * a3;
+  g.vy[1] = vy + h2 * a4;
+  g.om[1] = om + h2 * a5;
+  vel_deriv(M, c, g.vx[1], g.vy[1], g.om[1], b3, b4, b5);
+  g.vx[2] = vx + h2 * b3;
+  g.vy[2] = vy + h2 * b4;
+  g.om[2] = om + h2 * b5;
+  vel_deriv(M, c, g.vx[2], g.vy[2], g.om[2], c3, c4, c5);
+  g.vx[3] = vx + h * c3;
+  g.vy[3] = vy + h * c4;
+  g.om[3] = om + h * c5;
+  vel_deriv(M, c, g.vx[3], g.vy[3], g.om[3], d3, d4, d5);
+  vx += h6 * (a3 + R(2) * (b3 + c3) + d3);
+  vy += h6 * (a4 + R(2) * (b4 + c4) + d4);
+  om += h6 * (a5 + R(2) * (b5 + c5) + d5);
+}
+
+// Pose part of the same step from the stage velocities.
+template <class R>
+__device__ __forceinline__ void rk4_pose(const DevModel<R>& M, const VelStages<R>& g, R& px, R& py, R& psi) {
+  const R h = M.dt, h2 = R(0.5) * M.dt, h6 = M.dt * R(1.0 / 6.0);
+  R a0, a1, b0, b1, c0, c1, d0, d1;
+  pose_deriv(psi, g.vx[0], g.vy[0], a0, a1);
+  pose_deriv(psi + h2 * g.om[0], g.vx[1], g.vy[1], b0, b1);
+  pose_deriv(psi + h2 * g.om[1], g.vx[2], g.vy[2], c0, c1);
+  pose_deriv(psi + h * g.om[2], g.vx[3], g.vy[3], d0, d1);
+  px += h6 * (a0 + R(2) * (b0 + c0) + d0);
+  py += h6 * (a1 + R(2) * (b1 + c1) + d1);
+  psi += h6 * (g.om[0] + R(2) * (g.om[1] + g.om[2]) + g.om[3]);
+}
+
 // Classic RK4 over dt with the control held.
 template <class R>
 __device__ __forceinline__ void rk4(const DevModel<R>& M, const StepCtl<R>& c, State<R>& x) {
-  const R h = M.dt, h2 = R(0.5) * M.dt, h6 = M.dt * R(1.0 / 6.0);
-  R a0, a1, a3, a4, a5;  // k1
-  R b0, b1, b3, b4, b5;  // k2
-  R c0, c1, c3, c4, c5;  // k3
-  R d0, d1, d3, d4, d5;  // k4
-  deriv(M, c, x.psi, x.vx, x.vy, x.om, a0, a1, a3, a4, a5);
-  const R a2 = x.om;
-  deriv(M, c, x.psi + h2 * a2, x.vx + h2 * a3, x.vy + h2 * a4, x.om + h2 * a5, b0, b1, b3, b4, b5);
-  const R b2 = x.om + h2 * a5;
-  deriv(M, c, x.psi + h2 * b2, x.vx + h2 * b3, x.vy + h2 * b4, x.om + h2 * b5, c0, c1, c3, c4, c5);
-  const R c2 = x.om + h2 * b5;
-  deriv(M, c, x.psi + h * c2, x.vx + h * c3, x.vy + h * c4, x.om + h * c5, d0, d1, d3, d4, d5);
-  const R d2 = x.om + h * c5;
-  x.px += h6 * (a0 + R(2) * (b0 + c0) + d0);
-  x.py += h6 * (a1 + R(2) * (b1 + c1) + d1);
-  x.psi += h6 * (a2 + R(2) * (b2 + c2) + d2);
-  x.vx += h6 * (a3 + R(2) * (b3 + c3) + d3);
-  x.vy += h6 * (a4 + R(2) * (b4 + c4) + d4);
-  x.om += h6 * (a5 + R(2) * (b5 + c5) + d5);
+  VelStages<R> g;
+  rk4_vel(M, c, x.vx, x.vy, x.om, g);
+  rk4_pose(M, g, x.px, x.py, x.psi);
 }
 
 // ---------------------------------------------------------------- track

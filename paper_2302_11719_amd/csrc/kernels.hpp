@@ -721,11 +721,15 @@ struct RepairArgs {
   ExecuteArgs<R> ex;
 };
 
+constexpr int REP_C = 8;  // steps per shield pipeline chunk
+
 // LDS of the shield beyond the staged problem: states x_0..x_T, segment
-// indices, and the per-step control constants (5 per step).
+// indices, the per-step control constants (5 per step) and two chunks of RK4
+// stage velocities (12 per step) passed from the velocity wave to the pose wave.
 template <class R>
 __host__ __device__ inline size_t repair_lds_bytes(int t_max) {
-  return (size_t)(t_max + 1) * (6 * sizeof(R) + sizeof(int)) + (size_t)5 * t_max * sizeof(R);
+  return (size_t)(t_max + 1) * (6 * sizeof(R) + sizeof(int)) + (size_t)5 * t_max * sizeof(R) +
+         (size_t)2 * REP_C * 12 * sizeof(R);
 }
 
 // Algorithm 1 for one problem on one workgroup of two waves.  The nominal
@@ -741,28 +745,43 @@ __host__ __device__ inline size_t repair_lds_bytes(int t_max) {
 // iteration stops as soon as no such transition is left: the gradient is then
 // exactly zero and every remaining step would be the identity after the
 // projection already applied.
-constexpr int REP_C = 8;
-constexpr int REP_BLK = 2 * WAVE;
+constexpr int REP_BLK = 3 * WAVE;
 
-// The window rule evaluated by one wave: lane r holds the r-th offset of the
-// rule's order (0, -1, +1, -2, ...); the first offset in that order attaining
-// the minimum is the lowest set bit of the ballot.  c (uniform) in/out.
+// Row-rotate of a value across the 16 lanes of each row (DPP row_ror:N).
+template <int N>
+__device__ __forceinline__ float row_ror(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 + N, 0xF, 0xF, false));
+}
+template <int N>
+__device__ __forceinline__ double row_ror(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, 0x120 + N, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), 0x120 + N, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// The window rule on the lanes of a row (half width <= 7; the whole wave must
+// be active and c, px, py uniform): lane r of each row holds the r-th offset of
+// the rule's order (0, -1, +1, -2, ...), the row minimum comes from four DPP
+// rotations, and the first offset in the rule's order attaining it is the
+// lowest set bit of the ballot.  Returns e_y^2; c (uniform) in/out.
 template <class R>
-__device__ R wave_window(const TrackView<R>& tr, int& c, R px, R py) {
-  const int lane = threadIdx.x % WAVE;
+__device__ R row_window(const TrackView<R>& tr, int& c, R px, R py) {
+  const int r = threadIdx.x & 15;
   R dd = R(INFINITY);
-  int off = 0;
-  if (lane < 2 * tr.window + 1) {
-    off = (lane == 0) ? 0 : ((lane & 1) ? -((lane + 1) / 2) : (lane / 2));
-    int i = c + off;
-    i += (i < 0) ? tr.n : 0;
-    i -= (i >= tr.n) ? tr.n : 0;
-    dd = seg_dist2(tr, i, px, py);
+  if (r < 2 * tr.window + 1) {
+    const int off = r == 0 ? 0 : ((r & 1) ? -((r + 1) >> 1) : (r >> 1));
+    dd = seg_dist2(tr, c + off, px, py);  // padded copy: c + off needs no wrap to be read
   }
-  const R m = wave_min(dd);
-  const unsigned long long bal = __ballot(dd == m);
-  const int r = bal ? __ffsll((long long)bal) - 1 : 0;
-  int i = c + __shfl(off, r, WAVE);
+  R m = dd;
+  m = fmin(m, row_ror<8>(m));
+  m = fmin(m, row_ror<4>(m));
+  m = fmin(m, row_ror<2>(m));
+  m = fmin(m, row_ror<1>(m));
+  const unsigned long long bal = __ballot(dd == m) & 0xFFFFull;
+  const int rr = bal ? __ffsll((long long)bal) - 1 : 0;
+  const int off = rr == 0 ? 0 : ((rr & 1) ? -((rr + 1) >> 1) : (rr >> 1));
+  int i = c + off;
   i += (i < 0) ? tr.n : 0;
   i -= (i >= tr.n) ? tr.n : 0;
   c = i;
@@ -817,21 +836,23 @@ __device__ void repair_reverse(const DevModel<R>& M, const DevCost<R>& C, const 
   }
 }
 
-// Algorithm 1 for problem b by one workgroup of at least two waves (threads
-// beyond the first two waves only join the barriers).  Vs (LDS) holds V+ on
-// entry and V_safe on exit; tr is the staged problem; xs/is/ctl is
+// Algorithm 1 for problem b by one workgroup of at least three waves (threads
+// beyond the first three waves only join the barriers).  Vs (LDS) holds V+ on
+// entry and V_safe on exit; tr is the staged problem; `lds` is
 // repair_lds_bytes of LDS.  Per iteration: every thread computes the control
-// constants of its share of the steps; wave 0 runs the RK4 chain on one lane
-// and wave 1 follows one chunk behind with the window (one segment per lane),
-// the obstacles (one per lane) and the barrier activity; the reverse sweep
-// starts at the last active transition, and the iteration loop stops when no
-// transition is active (zero gradient).
+// constants of its share of the steps; then a pipeline over chunks of REP_C
+// steps: wave 0 runs the velocity part of the RK4 chain on one lane, wave 2 the
+// pose part one chunk behind, and wave 1 two chunks behind evaluates the
+// window (one segment per lane), the obstacles (one per lane) and the barrier
+// activity.  The reverse sweep starts at the last active transition, and the
+// iteration loop stops when no transition is active (zero gradient).
 template <class R, int NOBS>
 __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims& d, const TrackView<R>& tr, R* Vs,
                                unsigned char* lds, int* s_last) {
   R* xs = reinterpret_cast<R*>(lds);
   int* is = reinterpret_cast<int*>(xs + 6 * (size_t)(a.p.t_max + 1));
   R* ctl = reinterpret_cast<R*>(is + (a.p.t_max + 1));
+  R* vst = ctl + 5 * (size_t)a.p.t_max;  // [2][REP_C][12]
   const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   const DevModel<R>& M = a.M;
   const DevCost<R>& C = a.C;
@@ -867,9 +888,10 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
       }
     }
     __syncthreads();
-    for (int st = 0; st <= nch; ++st) {
+    for (int st = 0; st <= nch + 1; ++st) {
       if (w == 0 && lane == 0 && st < nch) {
         const int t0 = st * REP_C, t1 = min(T, t0 + REP_C);
+        R* gb = vst + (st & 1) * (REP_C * 12);
         for (int t = t0; t < t1; ++t) {
           StepCtl<R> sc;
           sc.delta = ctl[t];
@@ -878,15 +900,48 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
           sc.lfcd_Iz = ctl[3 * T + t];
           sc.a_tau = ctl[4 * T + t];
           sc.sd = sc.cd = R(0);  // used by the reverse sweep only
-          rk4(M, sc, x);
+          VelStages<R> g;
+          rk4_vel(M, sc, x.vx, x.vy, x.om, g);
+          R* gt = gb + 12 * (t - t0);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            gt[k] = g.vx[k];
+            gt[4 + k] = g.vy[k];
+            gt[8 + k] = g.om[k];
+          }
           R* o = xs + 6 * (t + 1);
-          o[0] = x.px; o[1] = x.py; o[2] = x.psi; o[3] = x.vx; o[4] = x.vy; o[5] = x.om;
+          o[3] = x.vx; o[4] = x.vy; o[5] = x.om;
         }
-      } else if (w == 1 && st >= 1) {
+      } else if (w == 2 && lane == 0 && st >= 1 && st <= nch) {
         const int t0 = (st - 1) * REP_C, t1 = min(T, t0 + REP_C);
+        const R* gb = vst + ((st - 1) & 1) * (REP_C * 12);
+        for (int t = t0; t < t1; ++t) {
+          const R* gt = gb + 12 * (t - t0);
+          VelStages<R> g;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            g.vx[k] = gt[k];
+            g.vy[k] = gt[4 + k];
+            g.om[k] = gt[8 + k];
+          }
+          rk4_pose(M, g, x.px, x.py, x.psi);
+          R* o = xs + 6 * (t + 1);
+          o[0] = x.px; o[1] = x.py; o[2] = x.psi;
+        }
+      } else if (w == 1 && st >= 2) {
+        const int t0 = (st - 2) * REP_C, t1 = min(T, t0 + REP_C);
         for (int t = t0; t < t1; ++t) {
           const R px = xs[6 * (t + 1)], py = xs[6 * (t + 1) + 1];
-          const R e2 = tr.n > 0 ? wave_window(tr, idx, px, py) : circle_e2(tr, px, py);
+          // window segments on the lanes of a row, min by DPP (no LDS round trip
+          // on the chain through idx); wider windows: one lane, sequential rule
+          R e2;
+          if (tr.n == 0) {
+            e2 = circle_e2(tr, px, py);
+          } else if (tr.window <= 7) {
+            e2 = row_window(tr, idx, px, py);
+          } else {
+            e2 = window_min(tr, idx, px, py);
+          }
           if (lane == 0) is[t + 1] = idx;
           const R h = tr.w2 - e2;
           bool act = C.alpha * hp - h > R(0);

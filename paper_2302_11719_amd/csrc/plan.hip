@@ -367,7 +367,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
           const float vp = Vb[i] + acc * iZ;
           Vpb[i] = vp;
           // no tile of problem b is left: its staged V becomes the shield's V+
-          if (BLK >= 2 * WAVE && a.repair) Vs[i] = vp;
+          if (BLK >= 3 * WAVE && a.repair) Vs[i] = vp;
         }
       }
       __syncthreads();
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
         a.stats[4 * b + 3] = NF;
         a.tickets[b] = 0u;
       }
-      if constexpr (BLK >= 2 * WAVE) {
+      if constexpr (BLK >= 3 * WAVE) {
         if (a.repair) {
           __syncthreads();
           unsigned char* rl = smem + stage_lds_bytes<float>(a.p.poly_max, a.p.t_max, a.p.obs_max);
@@ -670,7 +670,7 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   // combines a problem runs Algorithm 1 on it right away.
   a.repair = 0;
   a.rep = RepairArgs<float>{};
-  if (opts->repair && opts->fuse_shield == 0 && block >= 2 * WAVE &&
+  if (opts->repair && opts->fuse_shield == 0 && block >= 3 * WAVE &&
       lds_static + p->lds + repair_lds_bytes<float>(batch->t_max) <= (size_t)ctx->max_lds) {
     const ExecFuse ef{opts->dist, opts->n_dist, bufs->x0, bufs->V, bufs->iter};
     a.repair = 1;

@@ -110,11 +110,12 @@ def test_profiled_launch_matches_and_times(fuse):
     assert ctx().device_errors() == 0
 
 
-@pytest.mark.parametrize("pipeline,block", [(1, 0), (-1, 256), (-1, 64)])
+@pytest.mark.parametrize("pipeline,block", [(1, 0), (-1, 256), (-1, 128), (-1, 64)])
 def test_fused_shield_matches_separate_shield_kernel(pipeline, block):
     """Shield and execute run by the combining workgroup inside the fused launch equal
-    the separate shield kernel bit for bit, over three closed-loop launches (block 64
-    has one wave, so it always uses the separate kernel)."""
+    the separate shield kernel bit for bit, over three closed-loop launches (blocks of
+    64 and 128 threads have fewer than three waves, so they always use the separate
+    kernel)."""
     probs = prep(ragged_problems(), F32)
     M, C = params(F32)
     dist = torch.as_tensor(W.disturbances(2, 8 * len(probs)).reshape(-1), dtype=F32, device="cuda")
