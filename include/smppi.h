@@ -236,7 +236,8 @@ typedef struct {
                                 has more than one kernel (one kernel is launched directly) */
   int32_t pipeline;          /* 1: latency mode (64-sample tiles, three specialised waves
                                 pipelining noise, dynamics and cost); -1: off; 0: on when
-                                the batch has at most 2*64 samples per compute unit */
+                                the batch has at most 2*64 samples per compute unit and
+                                no obstacles */
   int32_t fuse_shield;       /* 0: run the shield (and execute) of each problem inside the
                                 fused launch, in the workgroup that combines the problem,
                                 when its workgroups have at least three waves and the LDS

@@ -47,20 +47,22 @@ struct FusedArgs {
 };
 
 // ---------------------------------------------------------------------------
-// Latency mode: one tile = 64 samples handled by three specialised waves that
-// run the same trajectories as a pipeline over chunks of PIPE_C steps.
-//   wave 1: noise, clipped controls, control cost, per-step control constants
+// Latency mode: one tile = 64 samples handled by four specialised waves (one
+// per SIMD) that run the same trajectories as a pipeline over chunks of PIPE_C
+// steps.
+//   wave 0: noise, clipped controls, control cost, per-step control constants
 //           (chunk s),
-//   wave 0: the RK4 chain only (chunk s-1), reading the constants from LDS and
-//           writing (p_x, p_y, v_x) of every new state,
-//   wave 2: lateral offset window, running cost, DCBF penalties, obstacles,
-//           collision indicator (chunk s-2).
-// A workgroup barrier separates the stages; each wave's per-step chain is a
-// third of the one-lane-per-sample loop, which is what bounds a launch with
-// fewer waves than SIMDs.  Same arithmetic as rollout_sample, summed in three
-// partial sums (control terms, state terms) instead of one.
+//   wave 1: the RK4 chain (chunk s-1), writing (p_x, p_y, v_x) of every new
+//           state,
+//   waves 2-3: two lanes per sample (chunk s-2): the lateral offset window
+//           split between the pair, running cost, DCBF penalties, obstacles
+//           (split between the pair), collision indicator.
+// A workgroup barrier separates the stages.  A launch with fewer waves than
+// SIMDs is bound by each wave's per-step chain; splitting the step four ways
+// shortens it.  Same arithmetic as rollout_sample, summed in partial sums
+// (control terms, state terms of each half) instead of one.
 constexpr int PIPE_C = 8;
-constexpr int PIPE_BLK = 3 * WAVE;
+constexpr int PIPE_BLK = 4 * WAVE;
 
 struct PipeLds {
   float ctl[2][PIPE_C][6][WAVE];  // u0, u1, sin(u0)/m, cos(u0)/m, l_f cos(u0)/I_z, a_max u1
@@ -68,15 +70,62 @@ struct PipeLds {
   float part[2][WAVE];
 };
 
+// Swap with the neighbouring lane (DPP quad_perm [1,0,3,2]).
+__device__ __forceinline__ float pair_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ int pair_swap(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
+
+// The window rule with half width 4 on a pair of lanes.  Half 0 evaluates the
+// offsets 0, -1, +1, -2, +2 (slots c-2..c+2), half 1 the offsets -3, +3, -4,
+// +4 (slots c-4, c-3, c+3, c+4; its fifth slot, c-2, is excluded), each half
+// in the rule's order; all of half 0's offsets precede half 1's in the rule,
+// so the pair keeps half 1's result only when it is strictly smaller.  Both
+// lanes return the same e_y^2 and centre.  The whole wave must be active.
+__device__ __forceinline__ float pair_window4(const TrackView<float>& tr, int& c, float px, float py, int half) {
+  const int bA = half ? -4 : -2, bB = half ? 3 : 1;
+  const float* sa = tr.seg + 4 * (c + bA);
+  const float* la = tr.il2 + (c + bA);
+  const float* sb = tr.seg + 4 * (c + bB);
+  const float* lb = tr.il2 + (c + bB);
+  auto d2 = [&](const float* sg, const float* il, int k) {
+    const float rx = px - sg[4 * k + 0], ry = py - sg[4 * k + 1];
+    const float dx = sg[4 * k + 2], dy = sg[4 * k + 3];
+    const float lam = clamp_r((rx * dx + ry * dy) * il[k], 0.f, 1.f);
+    const float ex = rx - lam * dx, ey = ry - lam * dy;
+    return ex * ex + ey * ey;
+  };
+  const float a0 = d2(sa, la, 0), a1 = d2(sa, la, 1), a2 = d2(sa, la, 2);
+  const float b0 = d2(sb, lb, 0), b1 = d2(sb, lb, 1);
+  const int m1 = 1 + 2 * half, m2 = 2 + 2 * half;
+  float bd = half ? INFINITY : a2;  // offset 0 (half 1: excluded slot)
+  int off = 0;
+  if (a1 < bd) { bd = a1; off = -m1; }
+  if (b0 < bd) { bd = b0; off = m1; }
+  if (a0 < bd) { bd = a0; off = -m2; }
+  if (b1 < bd) { bd = b1; off = m2; }
+  const float obd = pair_swap(bd);
+  const int ooff = pair_swap(off);
+  const float bd0 = half ? obd : bd, bd1 = half ? bd : obd;
+  const int off0 = half ? ooff : off, off1 = half ? off : ooff;
+  const bool take1 = bd1 < bd0;
+  int i = c + (take1 ? off1 : off0);
+  i += (i < 0) ? tr.n : 0;
+  i -= (i >= tr.n) ? tr.n : 0;
+  c = i;
+  return take1 ? bd1 : bd0;
+}
+
 template <int NOBS>
 __device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, const State<float>& x0,
                               const float* Vs, const ProblemDims& d, int m, uint32_t pid, uint32_t it,
                               PipeLds& P) {
+  constexpr int NH = NOBS > 0 ? (NOBS + 1) / 2 : 1;  // obstacles per half
   const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   const int T = d.T, nch = (T + PIPE_C - 1) / PIPE_C;
   const DevModel<float>& M = a.M;
   const DevCost<float>& C = a.C;
-  // wave 1
+  // wave 0
   NoiseStream<float> ns;
   ns.seed = a.p.seed;
   ns.m = (uint32_t)m;
@@ -84,30 +133,43 @@ __device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, co
   ns.it = it;
   ns.nominal = a.p.nominal != 0;
   float Sc = 0.f;
-  // wave 0
+  // wave 1
   State<float> x = x0;
-  // wave 2
+  // waves 2-3: sample j = lane pair, half h
+  const int tt = threadIdx.x - 2 * WAVE, j = tt >> 1, half = tt & 1;
   int idx = tr.idx0;
   float ey2 = 0.f, hp = 0.f, vxp = x0.vx, S2 = 0.f;
   bool outside = false;
-  float hob[NOBS > 0 ? NOBS : 1];
-  if (w == 2) {
-    ey2 = lateral_sq(tr, x0.px, x0.py, idx);
+  float hob[NH];
+  if (w >= 2) {
+    if (tr.n > 0) {
+      ey2 = seg_dist2(tr, idx, x0.px, x0.py);  // the window around the global nearest segment returns it
+    } else {
+      int dummy = 0;
+      ey2 = lateral_sq(tr, x0.px, x0.py, dummy);
+    }
     hp = tr.w2 - ey2;
     outside = hp < 0.f;
-    S2 = C.C_cbf * fmaxf((C.alpha - 1.f) * hp, 0.f);
+    float pen0 = half ? 0.f : fmaxf((C.alpha - 1.f) * hp, 0.f);
+    bool oo = false;
 #pragma unroll
-    for (int i = 0; i < NOBS; ++i) {
-      const Obs<float> o = obs_at(tr, i);
-      const float ox = x0.px - o.cx, oy = x0.py - o.cy;
-      const float d2 = ox * ox + oy * oy;
-      hob[i] = d2 - o.re2;
-      outside = outside || (d2 < o.r2);
-      S2 += C.C_cbf * fmaxf((C.alpha - 1.f) * hob[i], 0.f);
+    for (int k = 0; k < NH; ++k) {
+      const int i = 2 * k + half;
+      hob[k] = 0.f;
+      if (i < NOBS) {
+        const Obs<float> o = obs_at(tr, i);
+        const float ox = x0.px - o.cx, oy = x0.py - o.cy;
+        const float dd = ox * ox + oy * oy;
+        hob[k] = dd - o.re2;
+        oo = oo || (dd < o.r2);
+        pen0 += fmaxf((C.alpha - 1.f) * hob[k], 0.f);
+      }
     }
+    if (NOBS > 0) outside = outside || oo || (pair_swap((int)oo) != 0);
+    S2 = C.C_cbf * pen0;
   }
   for (int s = 0; s < nch + 2; ++s) {
-    if (w == 1 && s < nch) {
+    if (w == 0 && s < nch) {
       const int t0 = s * PIPE_C, t1 = min(T, t0 + PIPE_C);
       for (int t = t0; t < t1; ++t) {
         const float v0 = Vs[t], v1 = Vs[T + t];
@@ -125,7 +187,7 @@ __device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, co
         c[4][lane] = sc.lfcd_Iz;
         c[5][lane] = sc.a_tau;
       }
-    } else if (w == 0 && s >= 1 && s <= nch) {
+    } else if (w == 1 && s >= 1 && s <= nch) {
       const int cc = s - 1, t0 = cc * PIPE_C, t1 = min(T, t0 + PIPE_C);
       for (int t = t0; t < t1; ++t) {
         const float(*c)[WAVE] = P.ctl[cc & 1][t - t0];
@@ -137,48 +199,59 @@ __device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, co
         sc.a_tau = c[5][lane];
         sc.sd = sc.cd = 0.f;  // used by the reverse sweep only
         rk4(M, sc, x);
-        float(*q)[WAVE] = P.pos[cc & 1][t - t0];
-        q[0][lane] = x.px;
-        q[1][lane] = x.py;
-        q[2][lane] = x.vx;
+        float(*o)[WAVE] = P.pos[cc & 1][t - t0];
+        o[0][lane] = x.px;
+        o[1][lane] = x.py;
+        o[2][lane] = x.vx;
       }
-    } else if (w == 2 && s >= 2) {
+    } else if (w >= 2 && s >= 2) {
       const int cc = s - 2, t0 = cc * PIPE_C, t1 = min(T, t0 + PIPE_C);
       for (int t = t0; t < t1; ++t) {
         const float dv = vxp - C.v_g;
         float q = C.q_v * dv * dv + C.q_ey * ey2;
         if (outside) q += C.C_obs;
-        S2 += q;
+        S2 += half ? 0.f : q;
         const float(*qp)[WAVE] = P.pos[cc & 1][t - t0];
-        const float px = qp[0][lane], py = qp[1][lane];
-        vxp = qp[2][lane];
-        ey2 = lateral_sq(tr, px, py, idx);
+        const float px = qp[0][j], py = qp[1][j];
+        vxp = qp[2][j];
+        if (tr.n > 0 && tr.window == 4) {
+          ey2 = pair_window4(tr, idx, px, py, half);
+        } else {
+          ey2 = lateral_sq(tr, px, py, idx);
+        }
         const float h1 = tr.w2 - ey2;
-        float pen = fmaxf(C.alpha * hp - h1, 0.f);
+        float pen = half ? 0.f : fmaxf(C.alpha * hp - h1, 0.f);
         hp = h1;
         outside = h1 < 0.f;
+        bool oo = false;
 #pragma unroll
-        for (int i = 0; i < NOBS; ++i) {
-          const Obs<float> o = obs_at(tr, i);
-          const float ox = px - o.cx, oy = py - o.cy;
-          const float d2 = ox * ox + oy * oy;
-          const float hi = d2 - o.re2;
-          pen += fmaxf(C.alpha * hob[i] - hi, 0.f);
-          hob[i] = hi;
-          outside = outside || (d2 < o.r2);
+        for (int k = 0; k < NH; ++k) {
+          const int i = 2 * k + half;
+          if (i < NOBS) {
+            const Obs<float> o = obs_at(tr, i);
+            const float ox = px - o.cx, oy = py - o.cy;
+            const float dd = ox * ox + oy * oy;
+            const float hi = dd - o.re2;
+            pen += fmaxf(C.alpha * hob[k] - hi, 0.f);
+            hob[k] = hi;
+            oo = oo || (dd < o.r2);
+          }
         }
+        if (NOBS > 0) outside = outside || oo || (pair_swap((int)oo) != 0);
         S2 += C.C_cbf * pen;
       }
     }
     __syncthreads();
   }
-  if (w == 2) {
+  if (w >= 2) {
     const float dv = vxp - C.v_g;
     float q = C.q_v * dv * dv + C.q_ey * ey2;
     if (outside) q += C.C_obs;
-    P.part[1][lane] = S2 + C.phi_w * q;
+    const float mine = S2 + (half ? 0.f : C.phi_w * q);
+    const float other = pair_swap(mine);
+    if (half == 0) P.part[1][j] = mine + other;
   }
-  if (w == 1) P.part[0][lane] = Sc;
+  if (w == 0) P.part[0][lane] = Sc;
   __syncthreads();
   return P.part[0][lane] + P.part[1][lane];
 }
@@ -572,8 +645,11 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(t_off)");
   // Latency mode when the whole batch gives at most two sample-waves per CU:
   // then each wave's per-step chain, not the VALU throughput, bounds the launch.
+  // (Obstacles: the latency-mode kernel with 64 obstacle slots spills
+  // registers, so it is used only when asked for.)
   const bool pipe = opts->pipeline == 1 ||
-                    (opts->pipeline == 0 && koff[B] <= (int64_t)2 * WAVE * std::max(ctx->n_cu, 1));
+                    (opts->pipeline == 0 && track->obs_max == 0 &&
+                     koff[B] <= (int64_t)2 * WAVE * std::max(ctx->n_cu, 1));
   const int block = pipe ? PIPE_BLK : (opts->block ? opts->block : 256);
   // Two samples per thread once the batch has at least 8 two-sample tiles per CU
   // (halves the tile partials the combine reads; measured faster on large ragged
