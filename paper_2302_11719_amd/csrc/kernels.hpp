@@ -293,6 +293,13 @@ struct UpdateArgs {
 constexpr int UPD_BLOCK = 256;
 constexpr int UPD_TCHUNK = 64;
 
+// Release (every writer, before its ticket increment) and acquire (the last
+// ticket holder, before it reads the partials) halves of the ticket protocol,
+// at device scope.  A full __threadfence on the reader side would also write
+// back the reader's L2, which costs microseconds and is not needed there.
+__device__ __forceinline__ void ticket_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void ticket_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
 template <class R, int BLK, int SPT>
 struct NoiseSumLds {
   int m[BLK * SPT];
@@ -437,12 +444,12 @@ __global__ __launch_bounds__(UPD_BLOCK) void k_update(UpdateArgs<R> a) {
   R* gp = a.part + ((size_t)b * a.nblk_max + blockIdx.x) * 2 * a.p.t_max;
   block_noise_sums<R, UPD_BLOCK, 1>(a.M, a.C, a.p.seed, (uint32_t)(a.p.pid_base + b), a.p.iter[b],
                                     a.p.nominal != 0, Vb, d.T, ms, ws, L, gp);
-  __threadfence();
+  ticket_release();
   __syncthreads();
   if (threadIdx.x == 0) s_ticket = atomicAdd(&a.tickets[b], 1u);
   __syncthreads();
   if (s_ticket == (uint32_t)(nblk - 1)) {
-    __threadfence();
+    ticket_acquire();
     const R* g0 = a.part + (size_t)b * a.nblk_max * 2 * a.p.t_max;
     for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) {
       R acc = R(0);
@@ -637,12 +644,12 @@ __global__ __launch_bounds__(WAVE) void k_backward(BackwardArgs<R> a) {
   sink.lane = lane;
   const State<R> x0 = load_state(a.p.x0 + 6 * (size_t)b);
   adjoint_lane<R, NOBS>(a.M, a.C, a.ob, tr, x0, Vs, d.T, ns, L, a.seg_len, lane, sink);
-  __threadfence();
+  ticket_release();
   __syncthreads();
   if (lane == 0) s_ticket = atomicAdd(&a.tickets[b], 1u);
   __syncthreads();
   if (s_ticket == (uint32_t)(nblk - 1)) {
-    __threadfence();
+    ticket_acquire();
     const R* g0 = a.part + (size_t)b * a.nblk_max * 2 * a.p.t_max;
     for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) {
       R acc = R(0);

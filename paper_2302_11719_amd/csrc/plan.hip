@@ -342,13 +342,13 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       P[3] = nf;
     }
     // ---- ticket; the last tile of problem b combines
-    __threadfence();
+    ticket_release();
     __syncthreads();
     const int ntb = (d.K + a.tile - 1) / a.tile;
     if (tid == 0) s_ticket = atomicAdd(&a.tickets[b], 1u);
     __syncthreads();
     if (s_ticket == (uint32_t)(ntb - 1)) {
-      __threadfence();
+      ticket_acquire();
       // Streaming log-sum-exp combine: tile k's sums are rescaled by
       // exp(-(min_k - min)/lambda).  The partials were written by other
       // workgroups (other XCDs), so every pass is a round trip to memory: the
@@ -411,15 +411,39 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       const float iZ = Z > 0.f ? 1.f / Z : 0.f;
       const float* Vb = a.V + 2 * (size_t)d.t0;
       float* Vpb = a.V_plus + 2 * (size_t)d.t0;
-      for (int i0 = 0; i0 < 2 * d.T; i0 += BLK) {
-        const int i = i0 + tid;
+      // V+ pass: thread (g, il) sums tiles g, g+G, ... of output i0 + il (16
+      // loads in flight); the G group sums are then added in group order.
+      const int nI = min(2 * d.T, BLK), G = one_pass ? BLK / nI : 1;
+      const int g = tid / nI, il = tid % nI;
+      float* s_red = &L.red4[0][0];
+      for (int i0 = 0; i0 < 2 * d.T; i0 += (one_pass ? nI : BLK)) {
+        const int i = one_pass ? i0 + il : i0 + tid;
         float acc = 0.f;
         if (one_pass) {
-          if (i < 2 * d.T) {
+          if (g < G && i < 2 * d.T) {
             const float* Pi = P0 + PART_HDR + i;
-#pragma unroll 16
-            for (int kk = 0; kk < ntb; ++kk) acc += s_sc[kk] * Pi[(size_t)kk * pstride];
+            constexpr int NB = 16;  // loads issued before the first is consumed
+            for (int k0 = g; k0 < ntb; k0 += NB * G) {
+              float v[NB], sc[NB];
+#pragma unroll
+              for (int u = 0; u < NB; ++u) {
+                const int kk = k0 + u * G;
+                const bool in = kk < ntb;
+                v[u] = in ? Pi[(size_t)kk * pstride] : 0.f;
+                sc[u] = in ? s_sc[kk] : 0.f;
+              }
+#pragma unroll
+              for (int u = 0; u < NB; ++u) acc += sc[u] * v[u];
+            }
           }
+          if (G > 1) {
+            s_red[tid] = acc;
+            __syncthreads();
+            if (g == 0)
+              for (int gg = 1; gg < G; ++gg) acc += s_red[gg * nI + il];
+            __syncthreads();
+          }
+          if (g != 0) continue;
         } else {
           for (int k0 = 0; k0 < ntb; k0 += BLK) {
             __syncthreads();
