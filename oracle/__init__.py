@@ -31,7 +31,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "smppi_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
-_ABI = 4
+_ABI = 5
 _lock = threading.Lock()
 _lib = None
 
@@ -227,13 +227,34 @@ def gradient_fd(model, cost, track, x0, V, obj, eps=None, h: float = 1e-6):
     return g, valid.astype(bool)
 
 
-def repair(model, cost, track, x0, V_plus, n_steps: int, step: float, obj) -> np.ndarray:
+def repair(model, cost, track, x0, V_plus, n_steps: int, step: float, obj, method: str = "gradient",
+           memory: int = 5) -> np.ndarray:
+    """Safety shield: Algorithm 1 (method "gradient") or the projected L-BFGS
+    variant ("lbfgs", `memory` pairs).  V_plus: [T][2]."""
     V_plus = np.ascontiguousarray(V_plus, dtype=np.float64).reshape(-1, 2)
     out = np.zeros_like(V_plus)
     mp, cp, ta = model_array(model), cost_array(cost), _TrackArgs(track)
-    lib().or_repair(_p(mp), _p(cp), *ta.args(), _p(x0), _p(V_plus), ctypes.c_int(V_plus.shape[0]),
-                    ctypes.c_int(n_steps), ctypes.c_double(step), *_objective_args(obj), _p(out))
+    if method == "gradient":
+        lib().or_repair(_p(mp), _p(cp), *ta.args(), _p(x0), _p(V_plus), ctypes.c_int(V_plus.shape[0]),
+                        ctypes.c_int(n_steps), ctypes.c_double(step), *_objective_args(obj), _p(out))
+    elif method == "lbfgs":
+        lib().or_repair_lbfgs(_p(mp), _p(cp), *ta.args(), _p(x0), _p(V_plus), ctypes.c_int(V_plus.shape[0]),
+                              ctypes.c_int(n_steps), ctypes.c_double(step), *_objective_args(obj),
+                              ctypes.c_int(memory), _p(out))
+    else:
+        raise ValueError(method)
     return out
+
+
+def lbfgs_direction(g, S, Y, gamma: float) -> np.ndarray:
+    """d = -H g by the two-loop recursion; S, Y: [n_pairs][n], oldest first."""
+    g = np.ascontiguousarray(g, dtype=np.float64).ravel()
+    S = np.ascontiguousarray(S, dtype=np.float64).reshape(-1, g.size)
+    Y = np.ascontiguousarray(Y, dtype=np.float64).reshape(-1, g.size)
+    d = np.zeros_like(g)
+    lib().or_lbfgs_direction(_p(g), _p(S) if len(S) else None, _p(Y) if len(Y) else None, ctypes.c_int(len(S)),
+                             ctypes.c_int(g.size), ctypes.c_double(gamma), _p(d))
+    return d
 
 
 def trajectory(model, cost, track, x0, V, eps=None):

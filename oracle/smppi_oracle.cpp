@@ -420,7 +420,7 @@ void sample_noise(const Cost& C, uint32_t seed, uint32_t pid, uint32_t it, uint3
 // ===========================================================================
 extern "C" {
 
-int or_abi_version(void) { return 4; }
+int or_abi_version(void) { return 5; }
 
 void or_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { philox4x32_10(ctr, key, out); }
 
@@ -607,6 +607,107 @@ void or_repair(const double* mp, const double* cp, int kind, const double* circl
         V_safe[2 * t + d] = std::min(std::max(v, M.u_lo[d]), M.u_hi[d]);
       }
   }
+}
+
+// Quasi-Newton direction d = -H g of limited-memory BFGS by the two-loop
+// recursion (Nocedal & Wright, Numerical Optimization, Algorithm 7.4): pairs
+// S[i], Y[i] ([n_pairs][n], oldest first), initial inverse Hessian gamma I.
+void or_lbfgs_direction(const double* g, const double* S, const double* Y, int n_pairs, int n, double gamma,
+                        double* d) {
+  std::vector<double> q(g, g + n), alpha(n_pairs), rho(n_pairs);
+  for (int i = n_pairs - 1; i >= 0; --i) {
+    const double* s = S + (size_t)i * n;
+    const double* y = Y + (size_t)i * n;
+    double sy = 0.0, sq = 0.0;
+    for (int k = 0; k < n; ++k) sy += s[k] * y[k];
+    rho[i] = 1.0 / sy;
+    for (int k = 0; k < n; ++k) sq += s[k] * q[k];
+    alpha[i] = rho[i] * sq;
+    for (int k = 0; k < n; ++k) q[k] -= alpha[i] * y[k];
+  }
+  for (int k = 0; k < n; ++k) q[k] *= gamma;
+  for (int i = 0; i < n_pairs; ++i) {
+    const double* s = S + (size_t)i * n;
+    const double* y = Y + (size_t)i * n;
+    double yr = 0.0;
+    for (int k = 0; k < n; ++k) yr += y[k] * q[k];
+    const double beta = rho[i] * yr;
+    for (int k = 0; k < n; ++k) q[k] += s[k] * (alpha[i] - beta);
+  }
+  for (int k = 0; k < n; ++k) d[k] = -q[k];
+}
+
+// Safety shield with the quasi-Newton optimiser the paper's text names
+// (Sec. IV-B) in place of Algorithm 1's plain gradient step; limited-memory
+// BFGS with projection onto the control box (reading: the paper gives no
+// details).  Per iteration k, with g_k = grad L(V_k) of the objective above:
+//   stop when g_k = 0 (V is then only projected);
+//   for k > 0 the pair s = V_k - V_{k-1}, y = g_k - g_{k-1} is kept (at most
+//   `memory` pairs, oldest dropped) when s.y > 1e-2 |s| |y|;
+//   d = -H g_k by the two-loop recursion with H_0 = gamma I, gamma = s.y / y.y
+//   of the newest kept pair, or delta when none is kept (then the step is
+//   Algorithm 1's);  V_{k+1} = clip(V_k + d).
+// memory = 0 is Algorithm 1 exactly.
+void or_repair_lbfgs(const double* mp, const double* cp, int kind, const double* circle, const double* poly,
+                     int n_poly, double half_width, const double* obs, int n_obs, int window, const double* x0,
+                     const double* V_plus, int T, int n_steps, double delta, double w_S, double w_sq,
+                     double w_lin, int n_lin, int memory, double* V_safe) {
+  Model M = model_from(mp);
+  const int n = 2 * T;
+  std::vector<double> V(V_plus, V_plus + n), g(n), Vp(n), gp(n), d(n), S, Y;
+  int n_pairs = 0;
+  auto clip_all = [&](std::vector<double>& v) {
+    for (int t = 0; t < T; ++t)
+      for (int c = 0; c < 2; ++c) v[2 * t + c] = std::min(std::max(v[2 * t + c], M.u_lo[c]), M.u_hi[c]);
+  };
+  for (int k = 0; k < n_steps; ++k) {
+    or_gradient_dual(mp, cp, kind, circle, poly, n_poly, half_width, obs, n_obs, window, x0, V.data(), T,
+                     nullptr, w_S, w_sq, w_lin, n_lin, g.data());
+    bool zero = true;
+    for (int i = 0; i < n; ++i) zero = zero && g[i] == 0.0;
+    if (zero) {
+      clip_all(V);
+      break;
+    }
+    if (k > 0 && memory > 0) {
+      std::vector<double> s(n), y(n);
+      double sy = 0.0, ss = 0.0, yy = 0.0;
+      for (int i = 0; i < n; ++i) {
+        s[i] = V[i] - Vp[i];
+        y[i] = g[i] - gp[i];
+        sy += s[i] * y[i];
+        ss += s[i] * s[i];
+        yy += y[i] * y[i];
+      }
+      if (sy > 1e-2 * std::sqrt(ss) * std::sqrt(yy)) {
+        if (n_pairs == memory) {
+          S.erase(S.begin(), S.begin() + n);
+          Y.erase(Y.begin(), Y.begin() + n);
+          --n_pairs;
+        }
+        S.insert(S.end(), s.begin(), s.end());
+        Y.insert(Y.end(), y.begin(), y.end());
+        ++n_pairs;
+      }
+    }
+    double gamma = delta;
+    if (n_pairs > 0) {
+      const double* s = S.data() + (size_t)(n_pairs - 1) * n;
+      const double* y = Y.data() + (size_t)(n_pairs - 1) * n;
+      double sy = 0.0, yy = 0.0;
+      for (int i = 0; i < n; ++i) {
+        sy += s[i] * y[i];
+        yy += y[i] * y[i];
+      }
+      gamma = sy / yy;
+    }
+    or_lbfgs_direction(g.data(), S.data(), Y.data(), n_pairs, n, gamma, d.data());
+    Vp = V;
+    gp = g;
+    for (int i = 0; i < n; ++i) V[i] += d[i];
+    clip_all(V);
+  }
+  for (int i = 0; i < n; ++i) V_safe[i] = V[i];
 }
 
 // Nominal trajectory x_0..x_T ([T+1][6]) and barrier values ([T+1][1+n_obs]).
