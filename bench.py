@@ -39,7 +39,7 @@ FLOP_STEP_PER_OBS = 9     # one circular obstacle barrier + penalty + indicator 
 FLOP_UPDATE_STEP = 4      # w * eps' accumulated for two controls
 PEAK_FP32 = 157.3e12      # MI355X FP32 vector peak (packed FMA on every lane)
 PEAK_HBM = 8.0e12
-FORMS = ("plain", "identical", "ragged", "large", "c3", "autotune")
+FORMS = ("plain", "identical", "ragged", "large", "c3", "shield", "autotune")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_K4096_T50_hbm_traffic.md")
 
 
@@ -220,6 +220,8 @@ def extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync, forms):
         _form_large(ctx, core, W, M, C, lam, sync, out, seed)
     if "c3" in forms:
         _form_c3(ctx, core, W, M, C, lam, rep, sync, out, seed)
+    if "shield" in forms:
+        _form_shield(ctx, core, W, M, C, rep, sync, out)
     if "autotune" in forms:
         _form_autotune(ctx, core, W, M, C, lam, sync, out, seed)
     return out
@@ -336,6 +338,36 @@ def _form_c3(ctx, core, W, M, C, lam, rep, sync, out, seed):
     _log(f"  c3: {out['c3_B64_K2048_T50']}")
     pa.close()
     pb.close()
+
+
+def _form_shield(ctx, core, W, M, C, rep, sync, out):
+    """The shield alone on 64 violating problems (T = 50, spline tracks): Algorithm 1
+    vs the projected L-BFGS variant, same steps and delta; time and the summed DCBF
+    violation left (FP64 oracle objective of the device result)."""
+    import torch
+
+    import oracle
+
+    probs = []
+    for b in range(64):
+        tr = W.spline_track(100 + b)
+        V = W.test_sequences(1, 50, seed=300 + b, scale=0.8)[0]
+        probs.append(W.round_to_f32(W.Problem(1, 50, tr, W.start_state(tr, vx=3.0 + (b % 3)), V, b, 0)))
+    db = core.DeviceBatch(probs, dtype=torch.float32)
+    before = np.mean([oracle.objective(W.MODEL, W.COST, p.track, p.x0, p.V, rep["objective"])[0] for p in probs])
+    res = {"problems": 64, "T": 50, "steps": rep["n_steps"], "delta": rep["step"],
+           "violation_before": float(before)}
+    for method in ("gradient", "lbfgs"):
+        def run():
+            return core.shield_repair(ctx, db, M, C, db.V, rep["n_steps"], rep["step"], rep["objective"],
+                                      method=method, memory=5)
+        dt = _time(run, 50, 5, sync)
+        Vs = db.controls(run())
+        after = np.mean([oracle.objective(W.MODEL, W.COST, p.track, p.x0, Vs[b].astype(np.float64),
+                                          rep["objective"])[0] for b, p in enumerate(probs)])
+        res[method] = {"ms": dt * 1e3, "violation_after": float(after)}
+    out["shield_B64_T50"] = res
+    _log(f"  shield: {res}")
 
 
 def _form_autotune(ctx, core, W, M, C, lam, sync, out, seed):

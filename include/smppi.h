@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define SMPPI_ABI_VERSION 2
+#define SMPPI_ABI_VERSION 3
 
 typedef enum {
   SMPPI_OK = 0,
@@ -136,13 +136,20 @@ typedef struct {
   int32_t n_lin;
 } smppi_objective;
 
-/* Safety shield (Algorithm 1) as projected gradient descent on the objective
- * evaluated on the nominal trajectory from x0: n_steps times
- * V <- clip(V - step * dL/dV, u_lo, u_hi). */
+/* Safety shield on the objective evaluated on the nominal trajectory from x0.
+ * method 0 (Algorithm 1): n_steps times V <- clip(V - step * dL/dV, u_lo, u_hi).
+ * method 1 (the quasi-Newton optimiser the text of Sec. IV-B names): projected
+ * limited-memory BFGS, V <- clip(V - H dL/dV), H from the two-loop recursion
+ * over the last `memory` (1..16) pairs (s, y) of iterate and gradient
+ * differences kept when s.y > 0.01 |s| |y|, H_0 = (s.y / y.y) I of the newest
+ * pair, or step * I when none is kept.  Both stop early when the gradient is
+ * zero. */
 typedef struct {
   int32_t n_steps;
   double step;
   smppi_objective objective;
+  int32_t method;
+  int32_t memory;
 } smppi_repair_opts;
 
 /* ---- context ---------------------------------------------------------------- */

@@ -22,7 +22,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "shape", 3: "dtype", 4: "no device"
 ERR_NO_DEVICE = 4
 
 # Symbols declared in include/smppi.h (checked by the CPU test suite).
-ABI_VERSION = 2  # SMPPI_ABI_VERSION of include/smppi.h this binding matches
+ABI_VERSION = 3  # SMPPI_ABI_VERSION of include/smppi.h this binding matches
 EXPORTS = ("smppi_create", "smppi_destroy", "smppi_last_error", "smppi_status_string", "smppi_abi_version",
            "smppi_reserve", "smppi_device_errors", "smppi_rollout", "smppi_weights", "smppi_update",
            "smppi_rollout_backward", "smppi_shield_repair", "smppi_execute", "smppi_plan_create",
@@ -60,7 +60,17 @@ class Objective(ctypes.Structure):
 
 
 class RepairOpts(ctypes.Structure):
-    _fields_ = [("n_steps", c_i32), ("step", c_f64), ("objective", Objective)]
+    _fields_ = [("n_steps", c_i32), ("step", c_f64), ("objective", Objective), ("method", c_i32),
+                ("memory", c_i32)]
+
+
+REPAIR_METHODS = {"gradient": 0, "lbfgs": 1}
+
+
+def repair_opts(n_steps: int, step: float, objective: dict, method: str = "gradient", memory: int = 5) -> RepairOpts:
+    """smppi_repair_opts from Python values (method "gradient" = Algorithm 1, "lbfgs")."""
+    return RepairOpts(int(n_steps), float(step), objective_struct(objective), REPAIR_METHODS[method],
+                      int(memory) if method == "lbfgs" else 0)
 
 
 class PlanOpts(ctypes.Structure):

@@ -181,10 +181,11 @@ def rollout_backward(ctx: Context, db: DeviceBatch, model: dict, cost: dict, see
 
 
 def shield_repair(ctx: Context, db: DeviceBatch, model: dict, cost: dict, V_plus: torch.Tensor, n_steps: int,
-                  step: float, objective: dict, x0=None, out=None):
-    """smppi_shield_repair: V_safe in the library layout."""
+                  step: float, objective: dict, x0=None, out=None, method: str = "gradient", memory: int = 5):
+    """smppi_shield_repair: V_safe in the library layout (method "gradient": Algorithm 1;
+    "lbfgs": projected L-BFGS with `memory` pairs)."""
     out = db.new_V() if out is None else out
-    opts = L.RepairOpts(int(n_steps), float(step), L.objective_struct(objective))
+    opts = L.repair_opts(n_steps, step, objective, method, memory)
     st = L.lib().smppi_shield_repair(ctx.h, ctypes.byref(db.batch), ctypes.byref(L.model_struct(model)),
                                      ctypes.byref(L.cost_struct(cost)), ctypes.byref(db.track),
                                      _p(db.x0 if x0 is None else x0), _p(V_plus), ctypes.byref(opts), _p(out),
@@ -222,9 +223,10 @@ class Plan:
         self.V_safe = db.new_V() if repair else None
         self.stats = torch.empty(4 * db.B, dtype=db.dtype, device=db.device)
         self.dist = dist
-        ro = L.RepairOpts(0, 0.0, L.Objective(0, 0, 0, 0))
+        ro = L.RepairOpts(0, 0.0, L.Objective(0, 0, 0, 0), 0, 0)
         if repair:
-            ro = L.RepairOpts(int(repair["n_steps"]), float(repair["step"]), L.objective_struct(repair["objective"]))
+            ro = L.repair_opts(repair["n_steps"], repair["step"], repair["objective"],
+                               repair.get("method", "gradient"), repair.get("memory", 5))
         opts = L.PlanOpts(float(lam), 1 if repair else 0, ro, 1 if execute else 0,
                           dist.data_ptr() if dist is not None else None,
                           int(dist.shape[0]) if dist is not None else 0, int(block), int(tile), int(grid),

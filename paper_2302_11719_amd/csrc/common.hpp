@@ -29,6 +29,7 @@ namespace smppi {
 constexpr int kMaxT = 4096;
 constexpr int kMaxPoly = 4096;
 constexpr int kMaxObs = 64;
+constexpr int kMaxMemory = 16;  // L-BFGS pairs of the shield
 constexpr int kMaxStageLds = 65536;
 
 // Obstacle slots staged per problem: kernels with obstacles run a fixed count

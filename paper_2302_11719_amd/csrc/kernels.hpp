@@ -724,6 +724,8 @@ struct RepairArgs {
   int n_steps;
   R step;
   int seg_len;
+  int method;           // 0: Algorithm 1; 1: projected L-BFGS
+  int memory;           // L-BFGS pairs (0 with method 0)
   int exec;             // nonzero: also run the plant step and warm start (ex)
   ExecuteArgs<R> ex;
 };
@@ -732,11 +734,16 @@ constexpr int REP_C = 8;  // steps per shield pipeline chunk
 
 // LDS of the shield beyond the staged problem: states x_0..x_T, segment
 // indices, the per-step control constants (5 per step) and two chunks of RK4
-// stage velocities (12 per step) passed from the velocity wave to the pose wave.
+// stage velocities (12 per step) passed from the velocity wave to the pose wave;
+// with L-BFGS (memory > 0) also the gradient, the previous iterate and
+// gradient, the two-loop vector, memory + 1 pair slots (s, y) of 2 t_max
+// values, four scalars per slot and a reduction buffer.
 template <class R>
-__host__ __device__ inline size_t repair_lds_bytes(int t_max) {
-  return (size_t)(t_max + 1) * (6 * sizeof(R) + sizeof(int)) + (size_t)5 * t_max * sizeof(R) +
-         (size_t)2 * REP_C * 12 * sizeof(R);
+__host__ __device__ inline size_t repair_lds_bytes(int t_max, int memory) {
+  size_t n = (size_t)(t_max + 1) * (6 * sizeof(R) + sizeof(int)) + (size_t)5 * t_max * sizeof(R) +
+             (size_t)2 * REP_C * 12 * sizeof(R);
+  if (memory > 0) n += ((size_t)(4 + 2 * (memory + 1)) * 2 * t_max + 4 * (memory + 1) + 16) * sizeof(R);
+  return n;
 }
 
 // Algorithm 1 for one problem on one workgroup of two waves.  The nominal
@@ -803,10 +810,12 @@ __device__ __forceinline__ R circle_e2(const TrackView<R>& tr, R px, R py) {
 }
 
 // Reverse sweep of the shield objective on the stored nominal trajectory,
-// t = t_end .. 0, applying the projected step to V in place.
+// t = t_end .. 0: applies the projected gradient step to V in place, or, with
+// gout, writes the gradient dL/dV there and leaves V unchanged.
 template <class R, int NOBS>
 __device__ void repair_reverse(const DevModel<R>& M, const DevCost<R>& C, const DevObjective<R>& ob,
-                               const TrackView<R>& tr, R* V, int T, int t_end, R step, const R* xs, const int* is) {
+                               const TrackView<R>& tr, R* V, int T, int t_end, R step, const R* xs, const int* is,
+                               R* gout) {
   const bool cost_terms = ob.w_S != R(0);
   R lam[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
   if (cost_terms) {
@@ -838,9 +847,89 @@ __device__ void repair_reverse(const DevModel<R>& M, const DevCost<R>& C, const 
     const R gu1 = gt + ob.w_S * C.ctrl_w[1] * v1;
     const R gv0 = (pass0 ? gu0 : R(0)) + ob.w_S * C.ctrl_w[0] * u0;
     const R gv1 = (pass1 ? gu1 : R(0)) + ob.w_S * C.ctrl_w[1] * u1;
-    V[t] = clamp_r(v0 - step * gv0, M.u_lo[0], M.u_hi[0]);
-    V[T + t] = clamp_r(v1 - step * gv1, M.u_lo[1], M.u_hi[1]);
+    if (gout) {  // gradient only (quasi-Newton shield)
+      gout[t] = gv0;
+      gout[T + t] = gv1;
+    } else {
+      V[t] = clamp_r(v0 - step * gv0, M.u_lo[0], M.u_hi[0]);
+      V[T + t] = clamp_r(v1 - step * gv1, M.u_lo[1], M.u_hi[1]);
+    }
   }
+}
+
+// Block-wide dot product of two LDS vectors of n values (fixed order).
+template <class R>
+__device__ R block_dot(const R* x, const R* y, int n, R* red) {
+  R v = R(0);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += x[i] * y[i];
+  return block_sum(v, red);
+}
+
+// One projected L-BFGS step of the shield by the whole workgroup, given the
+// gradient g at V (LDS): keeps the pair (V - V_prev, g - g_prev) when
+// `have_prev` and its curvature s.y exceeds 0.01 |s| |y|, computes q = H g by
+// the two-loop recursion (H_0 = (s.y / y.y) I of the newest pair, or step * I
+// with no pair), and sets V_prev = V, g_prev = g, V = clip(V - q).
+template <class R>
+__device__ void lbfgs_step(const DevModel<R>& M, R* V, int T, const R* g, R* gprev, R* vprev, R* q, R* Sp, R* Yp,
+                           R* rho, R* alpha, R* psy, R* pyy, R* red, int mem, int stride, R step, bool have_prev,
+                           int& n_pairs, int& head) {
+  const int n = 2 * T;
+  const int cap = mem + 1;  // ring slots: at most `mem` kept pairs plus the candidate
+  if (have_prev && mem > 0) {
+    // candidate pair into the free slot after the newest kept pair
+    const int slot = (head + n_pairs) % cap;
+    R* s = Sp + (size_t)slot * stride;
+    R* y = Yp + (size_t)slot * stride;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      s[i] = V[i] - vprev[i];
+      y[i] = g[i] - gprev[i];
+    }
+    __syncthreads();
+    const R sy = block_dot(s, y, n, red), ss = block_dot(s, s, n, red), yy = block_dot(y, y, n, red);
+    if (sy > R(0.01) * sqrt(ss) * sqrt(yy)) {
+      if (threadIdx.x == 0) {
+        rho[slot] = R(1) / sy;
+        psy[slot] = sy;
+        pyy[slot] = yy;
+      }
+      if (n_pairs == mem) head = (head + 1) % cap;  // drop the oldest
+      else ++n_pairs;
+    }
+    __syncthreads();
+  }
+  R gamma = step;
+  if (n_pairs > 0) {
+    const int nw = (head + n_pairs - 1) % cap;
+    gamma = psy[nw] / pyy[nw];
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] = g[i];
+  __syncthreads();
+  for (int k = n_pairs - 1; k >= 0; --k) {
+    const int sl = (head + k) % cap;
+    const R al = rho[sl] * block_dot(Sp + (size_t)sl * stride, q, n, red);
+    if (threadIdx.x == 0) alpha[sl] = al;
+    const R* y = Yp + (size_t)sl * stride;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] -= al * y[i];
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] *= gamma;
+  __syncthreads();
+  for (int k = 0; k < n_pairs; ++k) {
+    const int sl = (head + k) % cap;
+    const R be = rho[sl] * block_dot(Yp + (size_t)sl * stride, q, n, red);
+    const R* s = Sp + (size_t)sl * stride;
+    const R coef = alpha[sl] - be;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] += s[i] * coef;
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    vprev[i] = V[i];
+    gprev[i] = g[i];
+    const int c = i < T ? 0 : 1;
+    V[i] = clamp_r(V[i] - q[i], M.u_lo[c], M.u_hi[c]);
+  }
+  __syncthreads();
 }
 
 // Algorithm 1 for problem b by one workgroup of at least three waves (threads
@@ -860,6 +949,23 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
   int* is = reinterpret_cast<int*>(xs + 6 * (size_t)(a.p.t_max + 1));
   R* ctl = reinterpret_cast<R*>(is + (a.p.t_max + 1));
   R* vst = ctl + 5 * (size_t)a.p.t_max;  // [2][REP_C][12]
+  // L-BFGS state (memory > 0): gradient, previous iterate and gradient, two-loop
+  // vector, pairs in a ring of memory + 1 slots (kept pair i at (head + i) %
+  // (memory + 1), i = 0 oldest; the next slot takes the candidate), per pair
+  // rho = 1/s.y, alpha, s.y, y.y; reduction buffer
+  const int tm2 = 2 * a.p.t_max, mem = a.memory;
+  R* gq = vst + 2 * REP_C * 12;
+  R* gprev = gq + tm2;
+  R* vprev = gprev + tm2;
+  R* qv = vprev + tm2;
+  R* Sp = qv + tm2;
+  R* Yp = Sp + (size_t)(mem + 1) * tm2;
+  R* prho = Yp + (size_t)(mem + 1) * tm2;
+  R* palpha = prho + (mem + 1);
+  R* psy = palpha + (mem + 1);
+  R* pyy = psy + (mem + 1);
+  R* red = pyy + (mem + 1);
+  int n_pairs = 0, head = 0;
   const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   const DevModel<R>& M = a.M;
   const DevCost<R>& C = a.C;
@@ -972,12 +1078,22 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
     if (w == 1 && lane == 0) *s_last = last;
     __syncthreads();
     const int t_end = cost_terms ? T - 1 : *s_last;
+    if (a.method == 1 && t_end >= 0) {
+      // gradient (zero after the last active transition), then the L-BFGS step
+      for (int t = t_end + 1 + (int)threadIdx.x; t < T; t += blockDim.x) gq[t] = gq[T + t] = R(0);
+      if (w == 0 && lane == 0) repair_reverse<R, NOBS>(M, C, ob, tr, Vs, T, t_end, a.step, xs, is, gq);
+      __syncthreads();
+      lbfgs_step(M, Vs, T, gq, gprev, vprev, qv, Sp, Yp, prho, palpha, psy, pyy, red, mem, tm2, a.step, s > 0,
+                 n_pairs, head);
+      continue;
+    }
     // steps after the last active transition have zero gradient: projection only
     for (int t = t_end + 1 + (int)threadIdx.x; t < T; t += blockDim.x) {
       Vs[t] = clamp_r(Vs[t], M.u_lo[0], M.u_hi[0]);
       Vs[T + t] = clamp_r(Vs[T + t], M.u_lo[1], M.u_hi[1]);
     }
-    if (w == 0 && lane == 0 && t_end >= 0) repair_reverse<R, NOBS>(M, C, ob, tr, Vs, T, t_end, a.step, xs, is);
+    if (w == 0 && lane == 0 && t_end >= 0)
+      repair_reverse<R, NOBS>(M, C, ob, tr, Vs, T, t_end, a.step, xs, is, (R*)nullptr);
     __syncthreads();
     if (t_end < 0) break;
   }

@@ -771,12 +771,14 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   a.repair = 0;
   a.rep = RepairArgs<float>{};
   if (opts->repair && opts->fuse_shield == 0 && block >= 3 * WAVE &&
-      lds_static + p->lds + repair_lds_bytes<float>(batch->t_max) <= (size_t)ctx->max_lds) {
+      lds_static + p->lds + repair_lds_bytes<float>(batch->t_max, opts->repair_opts.method == 1 ?
+                                                                  opts->repair_opts.memory : 0) <=
+          (size_t)ctx->max_lds) {
     const ExecFuse ef{opts->dist, opts->n_dist, bufs->x0, bufs->V, bufs->iter};
     a.repair = 1;
     a.rep = repair_args<float>(ctx, &p->batch, model, cost, &p->track, bufs->x0, bufs->V_plus, &opts->repair_opts,
                                bufs->V_safe, opts->execute ? &ef : nullptr);
-    p->lds += (int)repair_lds_bytes<float>(batch->t_max);
+    p->lds += (int)repair_lds_bytes<float>(batch->t_max, a.rep.memory);
   }
   p->fused_shield = a.repair != 0;
   int per_cu = 0;

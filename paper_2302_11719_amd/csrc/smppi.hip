@@ -452,7 +452,8 @@ extern "C" smppi_status smppi_rollout_backward(smppi_ctx ctx, const smppi_batch*
 template <class R, int NOBS>
 static smppi_status launch_repair(smppi_ctx ctx, const smppi_batch* b, const RepairArgs<R>& a, hipStream_t s,
                                   hipEvent_t e0, hipEvent_t e1) {
-  const size_t lds = stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max) + repair_lds_bytes<R>(a.p.t_max);
+  const size_t lds =
+      stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max) + repair_lds_bytes<R>(a.p.t_max, a.memory);
   if (lds > (size_t)ctx->max_lds)
     return fail(ctx, SMPPI_ERR_SHAPE, "repair needs %zu B of LDS per workgroup (device max %d)", lds, ctx->max_lds);
   if (e0 && e1)  // events stamped with the kernel's own start and end
@@ -476,6 +477,8 @@ RepairArgs<R> smppi::repair_args(smppi_ctx ctx, const smppi_batch* b, const smpp
   a.n_steps = o->n_steps;
   a.step = (R)o->step;
   a.seg_len = adj_seg_len(b->t_max);
+  a.method = o->method;
+  a.memory = o->method == 1 ? o->memory : 0;
   a.exec = ex != nullptr;
   a.ex = ExecuteArgs<R>{};
   if (ex) {
@@ -514,6 +517,9 @@ smppi_status smppi::validate_repair(smppi_ctx ctx, const smppi_repair_opts* o) {
   if (!o) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "repair opts are NULL");
   if (o->n_steps < 0 || o->n_steps > 100000) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "n_steps out of range");
   if (!std::isfinite(o->step)) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "step must be finite");
+  if (o->method != 0 && o->method != 1) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "method must be 0 or 1");
+  if (o->method == 1 && (o->memory < 1 || o->memory > kMaxMemory))
+    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "memory must be in [1, %d]", kMaxMemory);
   return validate_objective(ctx, &o->objective);
 }
 

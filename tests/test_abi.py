@@ -68,8 +68,8 @@ def test_struct_layouts_match_c(tmp_path):
                "smppi_track": L.Track, "smppi_objective": L.Objective, "smppi_repair_opts": L.RepairOpts,
                "smppi_plan_opts": L.PlanOpts, "smppi_plan_buffers": L.PlanBuffers}
     fields = {"smppi_batch": ["k_off", "t_off", "dtype"], "smppi_track": ["window", "obs_max", "obs"],
-              "smppi_cost": ["gamma", "sigma"], "smppi_plan_opts": ["repair_opts", "dist", "use_graph", "n_dist", "pipeline"],
-              "smppi_repair_opts": ["step", "objective"], "smppi_model": ["u_hi"]}
+              "smppi_cost": ["gamma", "sigma"], "smppi_plan_opts": ["repair_opts", "dist", "use_graph", "n_dist", "pipeline", "fuse_shield"],
+              "smppi_repair_opts": ["step", "objective", "method", "memory"], "smppi_model": ["u_hi"]}
     src = ["#include <stdio.h>", "#include <stddef.h>", '#include "smppi.h"', "int main(void){"]
     for cname in structs:
         src.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

@@ -215,9 +215,11 @@ def test_autograd_function():
     assert np.abs(got - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max())
 
 
+@pytest.mark.parametrize("method", ["gradient", "lbfgs"])
 @pytest.mark.parametrize("dtype", [F32, F64])
-def test_shield_repair_vs_oracle(dtype):
-    """Algorithm 1 (10 projected steps, delta = 0.05) on the nominal trajectory."""
+def test_shield_repair_vs_oracle(dtype, method):
+    """Algorithm 1 (10 projected steps, delta = 0.05) on the nominal trajectory, and the
+    projected L-BFGS variant (memory 5) with the same steps and delta."""
     tr_c = W.circle_track(10.0, 1.0)
     probs = [W.Problem(1, 30, tr_c, W.start_state(tr_c, vx=4.0), np.tile([-0.2, 0.6], (30, 1)), 0, 0)]
     for b in range(3):
@@ -227,13 +229,13 @@ def test_shield_repair_vs_oracle(dtype):
     probs = prep(probs, dtype)
     M, C = params(dtype)
     db = core.DeviceBatch(probs, dtype=dtype)
-    say(f"repair {dtype}")
-    Vs = core.shield_repair(ctx(), db, M, C, db.V, 10, 0.05, W.OBJ_SHIELD)
+    say(f"repair {dtype} {method}")
+    Vs = core.shield_repair(ctx(), db, M, C, db.V, 10, 0.05, W.OBJ_SHIELD, method=method, memory=5)
     torch.cuda.synchronize()
     assert ctx().device_errors() == 0
     got = db.controls(Vs)
     for b, p in enumerate(probs):
-        ref = oracle.repair(M, C, p.track, p.x0, p.V, 10, 0.05, W.OBJ_SHIELD)
+        ref = oracle.repair(M, C, p.track, p.x0, p.V, 10, 0.05, W.OBJ_SHIELD, method=method, memory=5)
         tol = 1e-3 * max(np.linalg.norm(p.V), 1.0) if dtype == F32 else 1e-9
         assert np.abs(got[b] - ref).max() <= tol, (b, np.abs(got[b] - ref).max())
     before, _ = oracle.objective(M, C, probs[0].track, probs[0].x0, probs[0].V, W.OBJ_SHIELD)

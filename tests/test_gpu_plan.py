@@ -110,8 +110,9 @@ def test_profiled_launch_matches_and_times(fuse):
     assert ctx().device_errors() == 0
 
 
-@pytest.mark.parametrize("pipeline,block", [(1, 0), (-1, 256), (-1, 128), (-1, 64)])
-def test_fused_shield_matches_separate_shield_kernel(pipeline, block):
+@pytest.mark.parametrize("pipeline,block,method", [(1, 0, "gradient"), (-1, 256, "gradient"), (-1, 128, "gradient"),
+                                                   (-1, 64, "gradient"), (1, 0, "lbfgs"), (-1, 256, "lbfgs")])
+def test_fused_shield_matches_separate_shield_kernel(pipeline, block, method):
     """Shield and execute run by the combining workgroup inside the fused launch equal
     the separate shield kernel bit for bit, over three closed-loop launches (blocks of
     64 and 128 threads have fewer than three waves, so they always use the separate
@@ -119,13 +120,13 @@ def test_fused_shield_matches_separate_shield_kernel(pipeline, block):
     probs = prep(ragged_problems(), F32)
     M, C = params(F32)
     dist = torch.as_tensor(W.disturbances(2, 8 * len(probs)).reshape(-1), dtype=F32, device="cuda")
-    rep = dict(n_steps=4, step=0.05, objective=W.OBJ_SHIELD)
+    rep = dict(n_steps=4, step=0.05, objective=W.OBJ_SHIELD, method=method, memory=3)
     dbs = [core.DeviceBatch(probs, dtype=F32) for _ in range(2)]
     plans = [core.Plan(ctx(), dbs[i], M, C, 11, W.LAMBDA, repair=rep, execute=True, dist=dist.view(8, -1),
                        use_graph=False, pipeline=pipeline, block=block, fuse_shield=(0 if i == 0 else -1))
              for i in range(2)]
     for step in range(3):
-        say(f"fused shield pipeline={pipeline} block={block} step {step}")
+        say(f"fused shield pipeline={pipeline} block={block} {method} step {step}")
         for pl in plans:
             pl.launch()
         torch.cuda.synchronize()
