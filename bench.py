@@ -16,7 +16,7 @@ durations (HIP events), the dominant kernel's roofline, and the FP64 CPU oracle
 on a bounded sample of the headline workload.
 
 usage: python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--skip-cpu] [--quick]
-                       [--forms plain,identical,ragged,large,c3,autotune] [--copy-calibration-mib N]
+                       [--forms plain,identical,ragged,large,c3,shield,autotune,sweep] [--copy-calibration-mib N]
 """
 from __future__ import annotations
 
@@ -39,7 +39,7 @@ FLOP_STEP_PER_OBS = 9     # one circular obstacle barrier + penalty + indicator 
 FLOP_UPDATE_STEP = 4      # w * eps' accumulated for two controls
 PEAK_FP32 = 157.3e12      # MI355X FP32 vector peak (packed FMA on every lane)
 PEAK_HBM = 8.0e12
-FORMS = ("plain", "identical", "ragged", "large", "c3", "shield", "autotune")
+FORMS = ("plain", "identical", "ragged", "large", "c3", "shield", "autotune", "sweep")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_K4096_T50_hbm_traffic.md")
 
 
@@ -55,8 +55,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline only (same as --forms none)")
     ap.add_argument("--forms", default="all",
-                    help="comma list of the extra forms to run: plain, identical, ragged, large, c3, "
-                         "autotune (or all/none)")
+                    help="comma list of the extra forms to run: plain, identical, ragged, large, c3, shield, "
+                         "autotune, sweep (or all/none)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -224,6 +224,8 @@ def extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync, forms):
         _form_shield(ctx, core, W, M, C, rep, sync, out)
     if "autotune" in forms:
         _form_autotune(ctx, core, W, M, C, lam, sync, out, seed)
+    if "sweep" in forms:
+        _form_sweep(ctx, out)
     return out
 
 
@@ -394,6 +396,21 @@ def _form_autotune(ctx, core, W, M, C, lam, sync, out, seed):
                                    "candidates": len(r.table), "top5": r.table[:5], "worst": r.table[-1]}
         _log(f"  autotune {name}: best {r.best} {r.best_ms:.4f} ms; default {info} {np.median(dms):.4f} ms; "
              f"worst {r.table[-1]['kernel_ms']:.4f} ms over {len(r.table)} candidates")
+
+
+def _form_sweep(ctx, out):
+    """Closed-loop collision sweep (the paper's second experiment, on generated tracks):
+    100 runs x 150 steps per cell, K in {64, 256, 1024}, T in {10, 20, 40}, three
+    controllers; target speed 8 m/s on half width 0.9 m, disturbance 0.3."""
+    from paper_2302_11719_amd import sweep
+
+    t0 = time.perf_counter()
+    rows = sweep.sweep(ctx, (64, 256, 1024), (10, 20, 40), runs=100, steps=150, seed=1, v_goal=8.0)
+    out["sweep_collisions"] = {"runs": 100, "steps": 150, "v_goal": 8.0, "half_width": 0.9, "dist_sigma": 0.3,
+                               "cells": rows, "wall_s": time.perf_counter() - t0}
+    for r in rows:
+        _log(f"  sweep K={r['K']} T={r['T']} {r['controller']}: collision rate {r['collision_rate']:.2f}, "
+             f"{r['collisions_per_run']:.2f} collided steps/run, {r['ms_per_step']:.3f} ms/step")
 
 
 def _cpu_model():
