@@ -31,7 +31,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "smppi_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
-_ABI = 5
+_ABI = 6
 _lock = threading.Lock()
 _lib = None
 
@@ -60,6 +60,7 @@ def lib():
                 raise RuntimeError("stale liboracle.so was rebuilt; restart the process")
             L.or_lateral_sq.restype = ctypes.c_double
             L.or_objective.restype = ctypes.c_double
+            L.or_kappa_at.restype = ctypes.c_double
             _lib = L
     return _lib
 
@@ -255,6 +256,39 @@ def lbfgs_direction(g, S, Y, gamma: float) -> np.ndarray:
     lib().or_lbfgs_direction(_p(g), _p(S) if len(S) else None, _p(Y) if len(Y) else None, ctypes.c_int(len(S)),
                              ctypes.c_int(g.size), ctypes.c_double(gamma), _p(d))
     return d
+
+
+def rollout_curv(model, cost, kappa, ds: float, half_width: float, x0, V, K: int, seed: int, pid: int, it: int,
+                 nominal: bool = False, want_eps: bool = True, n_threads: int = 1):
+    """Curvilinear model: per-sample S~ [K], effective noise [K][T][2], indicator margins [K].
+    x0 = (s, e_y, e_psi, v_x, v_y, omega); kappa: periodic curvature table, spacing ds."""
+    V = np.ascontiguousarray(V, dtype=np.float64).reshape(-1, 2)
+    T = V.shape[0]
+    kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+    S, margin = np.zeros(K), np.zeros(K)
+    eps = np.zeros((K, T, 2)) if want_eps else None
+    mp, cp = model_array(model), cost_array(cost)
+    lib().or_rollout_curv(_p(mp), _p(cp), _p(kappa), ctypes.c_int(len(kappa)), ctypes.c_double(ds),
+                          ctypes.c_double(half_width), _p(x0), _p(V), ctypes.c_int(K), ctypes.c_int(T),
+                          ctypes.c_uint32(seed), ctypes.c_uint32(pid), ctypes.c_uint32(it), ctypes.c_int(int(nominal)),
+                          S.ctypes.data_as(ctypes.c_void_p), eps.ctypes.data_as(ctypes.c_void_p) if want_eps else None,
+                          margin.ctypes.data_as(ctypes.c_void_p), ctypes.c_int(n_threads))
+    return S, eps, margin
+
+
+def trajectory_curv(model, kappa, ds: float, x0, V) -> np.ndarray:
+    """States [T+1][6] of the curvilinear model under one control sequence."""
+    V = np.ascontiguousarray(V, dtype=np.float64).reshape(-1, 2)
+    kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+    xs = np.zeros((V.shape[0] + 1, 6))
+    lib().or_trajectory_curv(_p(model_array(model)), _p(kappa), ctypes.c_int(len(kappa)), ctypes.c_double(ds),
+                             _p(x0), _p(V), ctypes.c_int(V.shape[0]), xs.ctypes.data_as(ctypes.c_void_p))
+    return xs
+
+
+def kappa_at(kappa, ds: float, s: float) -> float:
+    kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+    return lib().or_kappa_at(_p(kappa), ctypes.c_int(len(kappa)), ctypes.c_double(ds), ctypes.c_double(s))
 
 
 def trajectory(model, cost, track, x0, V, eps=None):

@@ -385,6 +385,110 @@ R rollout_one(const Model& M, const Cost& C, const Track& tr, const double x0[6]
   return S;
 }
 
+// ---------------------------------------------------------------------------
+// Curvilinear (Frenet-frame) variant of the model (Sec. V-A: the paper's
+// vehicle states include the progress s, lateral error e_y and heading error
+// e_psi along the track, so the track barrier of eq. (23) needs no projection).
+// x = (s, e_y, e_psi, v_x, v_y, omega); the velocity dynamics are the ones
+// above; the kinematics of a frame moving along a path of curvature kappa(s):
+//   ds/dt = (v_x cos e_psi - v_y sin e_psi) / (1 - kappa(s) e_y),
+//   de_y/dt = v_x sin e_psi + v_y cos e_psi,
+//   de_psi/dt = omega - kappa(s) ds/dt.
+// kappa(s): periodic table on a uniform grid s_j = j ds, linear in between
+// (reading: the paper prints no track representation).
+// ---------------------------------------------------------------------------
+struct CurvTrack {
+  const double* kappa;
+  int n;
+  double ds, w;
+};
+
+template <class R>
+R kappa_at(const CurvTrack& ct, R s) {
+  const double jf = std::floor(val(s) / ct.ds);
+  R f = s / R(ct.ds) - R(jf);
+  long j = (long)jf;
+  long j0 = ((j % ct.n) + ct.n) % ct.n, j1 = (j0 + 1) % ct.n;
+  return R(ct.kappa[j0]) * (R(1.0) - f) + R(ct.kappa[j1]) * f;
+}
+
+template <class R>
+void deriv_curv(const Model& M, const CurvTrack& ct, const R x[6], const R u[2], R dx[6]) {
+  R s = x[0], ey = x[1], epsi = x[2], vx = x[3], vy = x[4], om = x[5];
+  R delta = u[0], tau = u[1];
+  R vt = rmax(vx, R(M.v_min));
+  R alpha_f = delta - (vy + R(M.lf) * om) / vt;
+  R alpha_r = R(0.0) - (vy - R(M.lr) * om) / vt;
+  R Fyf = R(M.Cf) * alpha_f;
+  R Fyr = R(M.Cr) * alpha_r;
+  R cd = cos(delta), sd = sin(delta);
+  R k = kappa_at<R>(ct, s);
+  R c = cos(epsi), sn = sin(epsi);
+  R sdot = (vx * c - vy * sn) / (R(1.0) - k * ey);
+  dx[0] = sdot;
+  dx[1] = vx * sn + vy * c;
+  dx[2] = om - k * sdot;
+  dx[3] = R(M.a_max) * tau - R(M.c_v) * vx - Fyf * sd / R(M.m) + vy * om;
+  dx[4] = (Fyf * cd + Fyr) / R(M.m) - vx * om;
+  dx[5] = (R(M.lf) * Fyf * cd - R(M.lr) * Fyr) / R(M.Iz);
+}
+
+template <class R>
+void rk4_step_curv(const Model& M, const CurvTrack& ct, const R x[6], const R u[2], double dt, R out[6]) {
+  R k1[6], k2[6], k3[6], k4[6], xs[6];
+  deriv_curv(M, ct, x, u, k1);
+  for (int i = 0; i < 6; ++i) xs[i] = x[i] + R(0.5 * dt) * k1[i];
+  deriv_curv(M, ct, xs, u, k2);
+  for (int i = 0; i < 6; ++i) xs[i] = x[i] + R(0.5 * dt) * k2[i];
+  deriv_curv(M, ct, xs, u, k3);
+  for (int i = 0; i < 6; ++i) xs[i] = x[i] + R(dt) * k3[i];
+  deriv_curv(M, ct, xs, u, k4);
+  for (int i = 0; i < 6; ++i)
+    out[i] = x[i] + R(dt / 6.0) * (k1[i] + R(2.0) * k2[i] + R(2.0) * k3[i] + k4[i]);
+}
+
+// One sampled trajectory of the curvilinear model: the cost S~ of Algorithm 2
+// with the track barrier h = w^2 - e_y^2 read from the state (eq. (23)), the
+// running cost of eq. (24) on (v_x, e_y), the indicator of eq. (25) for
+// |e_y| > w, the control term and the DCBF penalty as in rollout_one.
+double rollout_one_curv(const Model& M, const Cost& C, const CurvTrack& ct, const double x0[6], const double* V,
+                        int T, const double* eps, double* eps_eff, double* margin_out) {
+  const double alpha = 1.0 - C.beta;
+  double x[6];
+  for (int i = 0; i < 6; ++i) x[i] = x0[i];
+  double h = ct.w * ct.w - x[1] * x[1];
+  double h_prev = h, margin = std::fabs(h);
+  double S = 0.0;
+  for (int t = 0; t <= T; ++t) {
+    const double r = alpha * h_prev - h;
+    const double pen = r > 0.0 ? C.C_cbf * r : 0.0;
+    const bool inside = h >= 0.0;
+    const double dv = x[3] - C.v_g;
+    double q = C.q_v * dv * dv + C.q_ey * (x[1] * x[1]);
+    if (!inside) q = q + C.C_obs;
+    if (t < T) {
+      double u[2], ctrl = 0.0;
+      for (int d = 0; d < 2; ++d) {
+        const double v = V[2 * t + d];
+        u[d] = clampr(v + (eps ? eps[2 * t + d] : 0.0), M.u_lo[d], M.u_hi[d]);
+        if (eps_eff) eps_eff[2 * t + d] = u[d] - v;
+        ctrl = ctrl + C.lambda_u * v * u[d] / (C.sigma[d] * C.sigma[d]);
+      }
+      S = S + (q + ctrl + pen);
+      double xn[6];
+      rk4_step_curv<double>(M, ct, x, u, M.dt, xn);
+      for (int i = 0; i < 6; ++i) x[i] = xn[i];
+      h_prev = h;
+      h = ct.w * ct.w - x[1] * x[1];
+      margin = std::min(margin, std::fabs(h));
+    } else {
+      S = S + (C.phi_w * q + pen);
+    }
+  }
+  if (margin_out) *margin_out = margin;
+  return S;
+}
+
 Track track_from(int kind, const double* circle, const double* poly, int n_poly, double half_width,
                  const double* obs, int n_obs, int window) {
   Track tr;
@@ -420,7 +524,7 @@ void sample_noise(const Cost& C, uint32_t seed, uint32_t pid, uint32_t it, uint3
 // ===========================================================================
 extern "C" {
 
-int or_abi_version(void) { return 5; }
+int or_abi_version(void) { return 6; }
 
 void or_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { philox4x32_10(ctr, key, out); }
 
@@ -488,6 +592,56 @@ void or_rollout(const double* mp, const double* cp, int kind, const double* circ
     }
     for (auto& t : th) t.join();
   }
+}
+
+// Sampled costs of the curvilinear model (same noise streams as or_rollout).
+// x0 = (s, e_y, e_psi, v_x, v_y, omega); kappa: periodic table with spacing ds.
+void or_rollout_curv(const double* mp, const double* cp, const double* kappa, int n_kappa, double ds,
+                     double half_width, const double* x0, const double* V, int K, int T, uint32_t seed,
+                     uint32_t pid, uint32_t it, int nominal, double* S, double* eps_eff, double* margin,
+                     int n_threads) {
+  Model M = model_from(mp);
+  Cost C = cost_from(cp);
+  CurvTrack ct{kappa, n_kappa, ds, half_width};
+  auto work = [&](int m0, int m1) {
+    std::vector<double> eps(2 * T);
+    for (int m = m0; m < m1; ++m) {
+      sample_noise(C, seed, pid, it, (uint32_t)m, T, nominal, eps.data());
+      S[m] = rollout_one_curv(M, C, ct, x0, V, T, eps.data(), eps_eff ? eps_eff + (size_t)2 * T * m : nullptr,
+                              margin ? margin + m : nullptr);
+    }
+  };
+  if (n_threads <= 1) {
+    work(0, K);
+  } else {
+    std::vector<std::thread> th;
+    int chunk = (K + n_threads - 1) / n_threads;
+    for (int i = 0; i < n_threads; ++i) {
+      int a = i * chunk, b = std::min(K, a + chunk);
+      if (a < b) th.emplace_back(work, a, b);
+    }
+    for (auto& t : th) t.join();
+  }
+}
+
+// Nominal trajectory of the curvilinear model, states [T+1][6].
+void or_trajectory_curv(const double* mp, const double* kappa, int n_kappa, double ds, const double* x0,
+                        const double* V, int T, double* xs) {
+  Model M = model_from(mp);
+  CurvTrack ct{kappa, n_kappa, ds, 0.0};
+  double x[6];
+  for (int i = 0; i < 6; ++i) x[i] = xs[i] = x0[i];
+  for (int t = 0; t < T; ++t) {
+    double u[2], xn[6];
+    for (int d = 0; d < 2; ++d) u[d] = clampr(V[2 * t + d], M.u_lo[d], M.u_hi[d]);
+    rk4_step_curv<double>(M, ct, x, u, M.dt, xn);
+    for (int i = 0; i < 6; ++i) x[i] = xs[6 * (t + 1) + i] = xn[i];
+  }
+}
+
+double or_kappa_at(const double* kappa, int n_kappa, double ds, double s) {
+  CurvTrack ct{kappa, n_kappa, ds, 0.0};
+  return kappa_at<double>(ct, s);
 }
 
 // Path-integral weights (eqs. (7), (9), (11)): omega = exp(-(S - min S)/lambda),

@@ -105,6 +105,32 @@ def spline_track(seed: int, half_width: float = 0.9, n_s: int = 512) -> Track:
     return Track(kind=1, circle=np.zeros(3), poly=polyline_from_vertices(P), half_width=half_width)
 
 
+def curvature_table(track: Track, n: int = 1024):
+    """(kappa [n], ds): the centre line's signed curvature (left turns positive) on a
+    uniform arclength grid s_k = k ds of the closed polyline, ds = length / n.  Vertex
+    curvature = turning angle / mean adjacent segment length, then periodic linear
+    interpolation in arclength.  A circle gives the constant 1/R."""
+    if track.kind == 0:
+        R = float(track.circle[2])
+        return np.full(n, 1.0 / R), 2.0 * math.pi * R / n
+    poly = track.poly
+    seg = np.hypot(poly[:, 2], poly[:, 3])
+    th = np.arctan2(poly[:, 3], poly[:, 2])
+    dth = np.angle(np.exp(1j * (th - np.roll(th, 1))))
+    kv = dth / (0.5 * (seg + np.roll(seg, 1)))
+    sv = np.concatenate([[0.0], np.cumsum(seg)[:-1]])
+    L = float(seg.sum())
+    ds = L / n
+    sk = np.arange(n) * ds
+    kappa = np.interp(sk, np.concatenate([sv, [L]]), np.concatenate([kv, [kv[0]]]))
+    return kappa, ds
+
+
+def start_state_curv(vx: float = 3.0) -> np.ndarray:
+    """Curvilinear state (s, e_y, e_psi, v_x, v_y, omega) on the centre line at s = 0."""
+    return np.array([0.0, 0.0, 0.0, vx, 0.0, 0.0])
+
+
 def obstacles(track: Track, seed: int, n: int = 64, margin: float = 0.15, keep_clear: float = 5.0) -> np.ndarray:
     """Circular obstacles at seeded arclength positions and lateral offsets inside the
     track; radius U[0.2, 0.6]; rows (cx, cy, (r + margin)^2, r^2).  The first

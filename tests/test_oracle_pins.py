@@ -465,3 +465,47 @@ def test_rollout_composes_primitives():
             h_prev = h
         tot += C["q_v"] * (x[3] - C["v_g"]) ** 2 + C["q_ey"] * e2 + (C["C_obs"] if h_prev < 0 else 0.0)
         assert S[m] == pytest.approx(tot, rel=1e-13)
+
+
+# ----------------------------------------------------------------------------- curvilinear model
+def test_curvature_table_interpolation():
+    """kappa(s): exact on a constant table, linear between grid points, periodic in s."""
+    ramp = np.arange(8.0)
+    assert oracle.kappa_at(np.full(8, 0.25), 0.5, 3.1) == 0.25
+    assert oracle.kappa_at(ramp, 0.5, 2.5 * 0.5) == pytest.approx(2.5, abs=1e-15)
+    assert oracle.kappa_at(ramp, 0.5, 7.25 * 0.5) == pytest.approx(7.0 * 0.75, abs=1e-15)
+    assert oracle.kappa_at(ramp, 0.5, -0.5 * 0.5) == pytest.approx(7.0 * 0.5, abs=1e-15)
+    assert oracle.kappa_at(ramp, 0.5, 8.0 * 0.5 + 1.0) == pytest.approx(2.0, abs=1e-15)
+
+
+def test_curvilinear_model_on_a_straight_path_is_the_cartesian_model():
+    """Zero curvature: the Frenet kinematics reduce to x' = v_x cos psi - v_y sin psi,
+    y' = v_x sin psi + v_y cos psi, psi' = omega, so (s, e_y, e_psi) follow the
+    Cartesian (x, y, psi) bit for bit."""
+    V = W.test_sequences(1, 40, seed=4, scale=0.6)[0]
+    x0 = np.array([1.0, 0.3, 0.1, 4.0, 0.2, -0.1])
+    xc, _ = oracle.trajectory(M, C, W.circle_track(10.0, 1.0), x0, V)
+    xf = oracle.trajectory_curv(M, np.zeros(16), 1.0, x0, V)
+    assert np.array_equal(xc, xf)
+
+
+def test_curvilinear_model_on_a_circle_matches_the_cartesian_model():
+    """Constant curvature 1/R: mapping (s, e_y, e_psi) to the plane, p = (R - e_y)(cos, sin)(s/R)
+    and psi = s/R + pi/2 + e_psi, follows the Cartesian model on the circle to RK4's
+    coordinate-dependent truncation error; the sampled costs agree likewise (e_y = R - |p|)."""
+    R = 10.0
+    kap, ds = W.curvature_table(W.circle_track(R, 1.0), 256)
+    V = W.test_sequences(1, 40, seed=5, scale=0.5)[0]
+    x0f = np.array([0.0, 0.2, 0.05, 4.0, 0.1, 0.0])
+    xf = oracle.trajectory_curv(M, kap, ds, x0f, V)
+    th = xf[:, 0] / R
+    r = R - xf[:, 1]
+    x0c = np.array([r[0] * np.cos(th[0]), r[0] * np.sin(th[0]), th[0] + np.pi / 2 + xf[0, 2], 4.0, 0.1, 0.0])
+    xc, _ = oracle.trajectory(M, C, W.circle_track(R, 1.0), x0c, V)
+    assert np.abs(xc[:, 0] - r * np.cos(th)).max() < 1e-6
+    assert np.abs(xc[:, 1] - r * np.sin(th)).max() < 1e-6
+    assert np.abs(xc[:, 2] - (th + np.pi / 2 + xf[:, 2])).max() < 1e-6
+    assert np.abs(xc[:, 3:] - xf[:, 3:]).max() < 1e-6
+    Sf, _, _ = oracle.rollout_curv(M, C, kap, ds, 1.0, x0f, V, K=16, seed=3, pid=0, it=0)
+    Sc, _, _ = oracle.rollout(M, C, W.circle_track(R, 1.0), x0c, V, K=16, seed=3, pid=0, it=0)
+    assert np.allclose(Sf, Sc, rtol=2e-5)  # DCBF penalties (C = 1000) amplify the state differences
