@@ -16,7 +16,7 @@ durations (HIP events), the dominant kernel's roofline, and the FP64 CPU oracle
 on a bounded sample of the headline workload.
 
 usage: python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--skip-cpu] [--quick]
-                       [--forms plain,identical,ragged,large,c3,shield,autotune,sweep] [--copy-calibration-mib N]
+                       [--forms plain,identical,ragged,large,c3,shield,autotune,sweep,curvilinear] [--copy-calibration-mib N]
 """
 from __future__ import annotations
 
@@ -37,9 +37,10 @@ if ROOT not in sys.path:
 FLOP_STEP_POLY = 345      # noise, clip, cost, RK4 (4 derivative evaluations), 9-segment window, DCBF
 FLOP_STEP_PER_OBS = 9     # one circular obstacle barrier + penalty + indicator test
 FLOP_UPDATE_STEP = 4      # w * eps' accumulated for two controls
+FLOP_STEP_CURV = 284      # curvilinear model: no window (-117), Frenet kinematics with curvature lookup (+56)
 PEAK_FP32 = 157.3e12      # MI355X FP32 vector peak (packed FMA on every lane)
 PEAK_HBM = 8.0e12
-FORMS = ("plain", "identical", "ragged", "large", "c3", "shield", "autotune", "sweep")
+FORMS = ("plain", "identical", "ragged", "large", "c3", "shield", "autotune", "sweep", "curvilinear")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_K4096_T50_hbm_traffic.md")
 
 
@@ -56,7 +57,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline only (same as --forms none)")
     ap.add_argument("--forms", default="all",
                     help="comma list of the extra forms to run: plain, identical, ragged, large, c3, shield, "
-                         "autotune, sweep (or all/none)")
+                         "autotune, sweep, curvilinear (or all/none)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -226,6 +227,8 @@ def extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync, forms):
         _form_autotune(ctx, core, W, M, C, lam, sync, out, seed)
     if "sweep" in forms:
         _form_sweep(ctx, out)
+    if "curvilinear" in forms:
+        _form_curvilinear(ctx, core, W, M, C, sync, out, seed)
     return out
 
 
@@ -411,6 +414,30 @@ def _form_sweep(ctx, out):
     for r in rows:
         _log(f"  sweep K={r['K']} T={r['T']} {r['controller']}: collision rate {r['collision_rate']:.2f}, "
              f"{r['collisions_per_run']:.2f} collided steps/run, {r['ms_per_step']:.3f} ms/step")
+
+
+def _form_curvilinear(ctx, core, W, M, C, sync, out, seed):
+    """Curvilinear-model rollout (Frenet frame, curvature table of the spline track) at
+    K = 65536, T = 100 beside the Cartesian rollout of the same size on the same track
+    (no obstacles)."""
+    import torch
+
+    K, T = 65536, 100
+    p = W.round_to_f32(W.config1(K=K, T=T))
+    db = core.DeviceBatch([p], dtype=torch.float32)
+    S = db.new_S()
+    t_cart = _time(lambda: core.rollout(ctx, db, M, C, seed, S=S), 20, 3, sync)
+    kap, ds = W.curvature_table(p.track, 1024)
+    pc = W.Problem(K, T, p.track, W.start_state_curv(3.0), p.V, 0, 0)
+    dbc = core.DeviceBatch([W.round_to_f32(pc)], dtype=torch.float32)
+    ct = core.CurvTrackArrays([(kap, ds)], [p.track.half_width])
+    t_curv = _time(lambda: core.rollout_curvilinear(ctx, dbc, ct, M, C, seed, S=S), 20, 3, sync)
+    out["curvilinear_K65536_T100"] = {
+        "rollout_ms": t_curv * 1e3, "rollout_steps_per_s": K * T / t_curv,
+        "achieved_TFLOPs": FLOP_STEP_CURV * K * T / t_curv / 1e12,
+        "cartesian_rollout_ms": t_cart * 1e3, "cartesian_rollout_steps_per_s": K * T / t_cart,
+        "cartesian_achieved_TFLOPs": FLOP_STEP_POLY * K * T / t_cart / 1e12}
+    _log(f"  curvilinear: {out['curvilinear_K65536_T100']}")
 
 
 def _cpu_model():

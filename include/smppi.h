@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define SMPPI_ABI_VERSION 3
+#define SMPPI_ABI_VERSION 4
 
 typedef enum {
   SMPPI_OK = 0,
@@ -126,6 +126,19 @@ typedef struct {
   int32_t obs_max;          /* host: max O_b (<= 64) */
 } smppi_track;
 
+/* Per-problem curvature table of the curvilinear model (Sec. V-A: the vehicle
+ * state is expressed along the track as progress s, lateral error e_y and
+ * heading error e_psi, so the track barrier h = w^2 - e_y^2 of eq. (23) needs no
+ * projection).  kappa(s) is periodic: table entry j at s = j*ds, linear in
+ * between; left turns positive. */
+typedef struct {
+  const int32_t* kappa_off; /* device [B+1] table offsets (N_b >= 2) */
+  const void* kappa;        /* device [sum N][1] dtype */
+  const void* ds;           /* device [B] dtype: grid spacing (> 0) */
+  const void* half_width;   /* device [B] dtype: w */
+  int32_t n_max;            /* host: max N_b (<= 8192) */
+} smppi_curv_track;
+
 /* Differentiated objective of one trajectory (used by the adjoint and repair):
  *   L = w_S S~' + w_sq sum_{j,t<T} viol_{j,t}^2 + w_lin sum_{j, t<n_lin} viol_{j,t},
  *   viol_{j,t} = max(alpha h_j(x_t) - h_j(x_{t+1}), 0),
@@ -182,6 +195,19 @@ smppi_status smppi_rollout(smppi_ctx ctx, const smppi_batch* batch, const smppi_
                            const smppi_cost* cost, const smppi_noise* noise, const smppi_track* track,
                            const void* x0, const void* V, const uint32_t* iter, void* S, void* eps_out,
                            void* stream);
+
+/* The sampled rollout of smppi_rollout for the curvilinear model: state
+ * x = (s, e_y, e_psi, v_x, v_y, omega) with the single-track velocity dynamics
+ * and the Frenet kinematics
+ *   s' = (v_x cos e_psi - v_y sin e_psi) / (1 - kappa(s) e_y),
+ *   e_y' = v_x sin e_psi + v_y cos e_psi,   e_psi' = omega - kappa(s) s';
+ * S~ as in smppi_rollout with the track barrier read from the state (no
+ * obstacles).  x0: device [B][6] dtype in that state order; the other arguments
+ * as in smppi_rollout.  The weights and update calls apply unchanged. */
+smppi_status smppi_rollout_curvilinear(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                                       const smppi_cost* cost, const smppi_noise* noise,
+                                       const smppi_curv_track* track, const void* x0, const void* V,
+                                       const uint32_t* iter, void* S, void* eps_out, void* stream);
 
 /* Path-integral weights (eqs. (7), (9), (11)): w_m = exp(-(S_m - min S)/lambda)
  * / sum, per problem, with non-finite S_m given weight 0.

@@ -22,8 +22,8 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "shape", 3: "dtype", 4: "no device"
 ERR_NO_DEVICE = 4
 
 # Symbols declared in include/smppi.h (checked by the CPU test suite).
-ABI_VERSION = 3  # SMPPI_ABI_VERSION of include/smppi.h this binding matches
-EXPORTS = ("smppi_create", "smppi_destroy", "smppi_last_error", "smppi_status_string", "smppi_abi_version",
+ABI_VERSION = 4  # SMPPI_ABI_VERSION of include/smppi.h this binding matches
+EXPORTS = ("smppi_rollout_curvilinear", "smppi_create", "smppi_destroy", "smppi_last_error", "smppi_status_string", "smppi_abi_version",
            "smppi_reserve", "smppi_device_errors", "smppi_rollout", "smppi_weights", "smppi_update",
            "smppi_rollout_backward", "smppi_shield_repair", "smppi_execute", "smppi_plan_create",
            "smppi_plan_launch", "smppi_plan_destroy", "smppi_plan_info", "smppi_plan_launch_profiled",
@@ -53,6 +53,10 @@ class Batch(ctypes.Structure):
 class Track(ctypes.Structure):
     _fields_ = [("poly_off", c_vp), ("poly", c_vp), ("circle", c_vp), ("half_width", c_vp), ("obs_off", c_vp),
                 ("obs", c_vp), ("window", c_i32), ("poly_max", c_i32), ("obs_max", c_i32)]
+
+
+class CurvTrack(ctypes.Structure):
+    _fields_ = [("kappa_off", c_vp), ("kappa", c_vp), ("ds", c_vp), ("half_width", c_vp), ("n_max", c_i32)]
 
 
 class Objective(ctypes.Structure):
@@ -94,6 +98,8 @@ _SIGS = {
     "smppi_abi_version": (ctypes.c_int, []),
     "smppi_reserve": (c_i32, [c_vp, ctypes.c_uint64]),
     "smppi_device_errors": (c_i32, [c_vp, P(c_u32)]),
+    "smppi_rollout_curvilinear": (c_i32, [c_vp, P(Batch), P(Model), P(Cost), P(Noise), P(CurvTrack), c_vp, c_vp,
+                                          c_vp, c_vp, c_vp, c_vp]),
     "smppi_rollout": (c_i32, [c_vp, P(Batch), P(Model), P(Cost), P(Noise), P(Track), c_vp, c_vp, c_vp, c_vp, c_vp,
                               c_vp]),
     "smppi_weights": (c_i32, [c_vp, P(Batch), c_vp, c_f64, c_vp, c_vp, c_vp]),

@@ -144,6 +144,36 @@ def rollout(ctx: Context, db: DeviceBatch, model: dict, cost: dict, seed: int, n
     return (S, eps.view(db.sum_K, db.t_max, 2)) if want_eps else S
 
 
+class CurvTrackArrays:
+    """Device arrays of smppi_curv_track: per-problem periodic curvature tables
+    (kappa, ds) and half widths, in problem order."""
+
+    def __init__(self, tables, half_widths, dtype=torch.float32, device="cuda"):
+        f = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float64), dtype=dtype, device=device)
+        n = [len(k) for k, _ in tables]
+        self.kappa_off = torch.as_tensor(np.concatenate([[0], np.cumsum(n)]).astype(np.int32), device=device)
+        self.kappa = f(np.concatenate([np.asarray(k, dtype=np.float64) for k, _ in tables]))
+        self.ds = f([d for _, d in tables])
+        self.half_width = f(half_widths)
+        self.n_max = max(n)
+        self.track = L.CurvTrack(self.kappa_off.data_ptr(), self.kappa.data_ptr(), self.ds.data_ptr(),
+                                 self.half_width.data_ptr(), int(self.n_max))
+
+
+def rollout_curvilinear(ctx: Context, db: DeviceBatch, ct: CurvTrackArrays, model: dict, cost: dict, seed: int,
+                        nominal: bool = False, x0=None, S=None, want_eps: bool = False):
+    """smppi_rollout_curvilinear: S~ [sum K] of the curvilinear model; x0 (default db.x0)
+    holds (s, e_y, e_psi, v_x, v_y, omega) per problem."""
+    S = db.new_S() if S is None else S
+    eps = torch.zeros(db.sum_K * db.t_max * 2, dtype=db.dtype, device=db.device) if want_eps else None
+    st = L.lib().smppi_rollout_curvilinear(ctx.h, ctypes.byref(db.batch), ctypes.byref(L.model_struct(model)),
+                                           ctypes.byref(L.cost_struct(cost)), ctypes.byref(_noise(seed, nominal)),
+                                           ctypes.byref(ct.track), _p(db.x0 if x0 is None else x0), _p(db.V),
+                                           _p(db.iter), _p(S), _p(eps), ctypes.c_void_p(_stream()))
+    ctx.check(st, "smppi_rollout_curvilinear")
+    return (S, eps.view(db.sum_K, db.t_max, 2)) if want_eps else S
+
+
 def weights(ctx: Context, db: DeviceBatch, S: torch.Tensor, lam: float):
     """smppi_weights: (w [sum K], stats [B][4])."""
     w = torch.empty_like(S)

@@ -329,6 +329,63 @@ extern "C" smppi_status smppi_rollout(smppi_ctx ctx, const smppi_batch* batch, c
   return rollout_t<double>(ctx, batch, model, cost, noise, track, x0, V, iter, S, eps_out, s);
 }
 
+// ------------------------------------------------------------------ curvilinear rollout
+template <class R>
+static smppi_status rollout_curv_t(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const smppi_cost* c,
+                                   const smppi_noise* n, const smppi_curv_track* t, const void* x0, const void* V,
+                                   const uint32_t* iter, void* S, void* eps_out, hipStream_t s) {
+  CurvArgs<R> a;
+  a.k_off = b->k_off;
+  a.t_off = b->t_off;
+  a.kappa_off = t->kappa_off;
+  a.kappa = static_cast<const R*>(t->kappa);
+  a.ds = static_cast<const R*>(t->ds);
+  a.half_width = static_cast<const R*>(t->half_width);
+  a.x0 = static_cast<const R*>(x0);
+  a.iter = iter;
+  a.V = static_cast<const R*>(V);
+  a.S = static_cast<R*>(S);
+  a.eps_out = static_cast<R*>(eps_out);
+  a.M = dev_model<R>(m);
+  a.C = dev_cost<R>(c);
+  a.k_max = b->k_max;
+  a.t_max = b->t_max;
+  a.n_max = t->n_max;
+  a.pid_base = b->pid_base;
+  a.seed = n->seed;
+  a.nominal = n->nominal;
+  a.err = ctx->err;
+  const int blk = 256;
+  const int gx = b->k_max > 0 ? (b->k_max + blk - 1) / blk : 0;
+  if (gx == 0) return SMPPI_OK;
+  const size_t lds = sizeof(R) * ((size_t)t->n_max + 2 * (size_t)b->t_max);
+  if (lds > (size_t)ctx->max_lds)
+    return fail(ctx, SMPPI_ERR_SHAPE, "curvilinear rollout needs %zu B of LDS per workgroup (device max %d)", lds,
+                ctx->max_lds);
+  hipLaunchKernelGGL((k_rollout_curv<R>), dim3(gx, b->n_problems), dim3(blk), lds, s, a);
+  return check_launch(ctx, "k_rollout_curv");
+}
+
+extern "C" smppi_status smppi_rollout_curvilinear(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                                                  const smppi_cost* cost, const smppi_noise* noise,
+                                                  const smppi_curv_track* track, const void* x0, const void* V,
+                                                  const uint32_t* iter, void* S, void* eps_out, void* stream) {
+  if (!ctx) return SMPPI_ERR_INVALID_ARGUMENT;
+  smppi_status st;
+  if ((st = validate_batch(ctx, batch)) || (st = validate_model(ctx, model)) || (st = validate_cost(ctx, cost)))
+    return st;
+  if (!noise || !track) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "noise and track are required");
+  if (!track->kappa_off || !track->kappa || !track->ds || !track->half_width)
+    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "curvature track arrays are required");
+  if (track->n_max < 2 || track->n_max > 8192) return fail(ctx, SMPPI_ERR_SHAPE, "n_max must be in [2, 8192]");
+  if (!x0 || !V || !iter || !S) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "x0, V, iter, S are required");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (batch->dtype == SMPPI_F32)
+    return rollout_curv_t<float>(ctx, batch, model, cost, noise, track, x0, V, iter, S, eps_out, s);
+  return rollout_curv_t<double>(ctx, batch, model, cost, noise, track, x0, V, iter, S, eps_out, s);
+}
+
 // ------------------------------------------------------------------ weights
 extern "C" smppi_status smppi_weights(smppi_ctx ctx, const smppi_batch* batch, const void* S, double lambda, void* w,
                                       void* stats, void* stream) {
