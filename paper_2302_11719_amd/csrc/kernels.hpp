@@ -793,11 +793,16 @@ struct RepairArgs {
   int seg_len;
   int method;           // 0: Algorithm 1; 1: projected L-BFGS
   int memory;           // L-BFGS pairs (0 with method 0)
+  int par_rev;          // nonzero: reverse sweep with per-step Jacobians computed in parallel
   int exec;             // nonzero: also run the plant step and warm start (ex)
   ExecuteArgs<R> ex;
 };
 
 constexpr int REP_C = 8;  // steps per shield pipeline chunk
+// Parallel reverse sweep: per step the transposed Jacobian of the RK4 step with
+// respect to (x, u) (6 x 8), the local barrier/cost gradients (8) and the
+// control gradient (2).
+constexpr int REP_PAR_PER_STEP = 48 + 8 + 2;
 
 // LDS of the shield beyond the staged problem: states x_0..x_T, segment
 // indices, the per-step control constants (5 per step) and two chunks of RK4
@@ -806,10 +811,11 @@ constexpr int REP_C = 8;  // steps per shield pipeline chunk
 // gradient, the two-loop vector, memory + 1 pair slots (s, y) of 2 t_max
 // values, four scalars per slot and a reduction buffer.
 template <class R>
-__host__ __device__ inline size_t repair_lds_bytes(int t_max, int memory) {
+__host__ __device__ inline size_t repair_lds_bytes(int t_max, int memory, bool par_rev = false) {
   size_t n = (size_t)(t_max + 1) * (6 * sizeof(R) + sizeof(int)) + (size_t)5 * t_max * sizeof(R) +
              (size_t)2 * REP_C * 12 * sizeof(R);
   if (memory > 0) n += ((size_t)(4 + 2 * (memory + 1)) * 2 * t_max + 4 * (memory + 1) + 16) * sizeof(R);
+  if (par_rev) n += (size_t)REP_PAR_PER_STEP * t_max * sizeof(R);
   return n;
 }
 
@@ -915,6 +921,102 @@ __device__ void repair_reverse(const DevModel<R>& M, const DevCost<R>& C, const 
     const R gv0 = (pass0 ? gu0 : R(0)) + ob.w_S * C.ctrl_w[0] * u0;
     const R gv1 = (pass1 ? gu1 : R(0)) + ob.w_S * C.ctrl_w[1] * u1;
     if (gout) {  // gradient only (quasi-Newton shield)
+      gout[t] = gv0;
+      gout[T + t] = gv1;
+    } else {
+      V[t] = clamp_r(v0 - step * gv0, M.u_lo[0], M.u_hi[0]);
+      V[T + t] = clamp_r(v1 - step * gv1, M.u_lo[1], M.u_hi[1]);
+    }
+  }
+}
+
+// The same reverse sweep by the whole workgroup (every thread must call it).
+// The adjoint recursion is linear once the nominal trajectory is fixed:
+//   lam_t = J_t^T (lam_{t+1} + dn_t) + dc_t,   g_t = B_t^T (lam_{t+1} + dn_t),
+// with J_t, B_t the RK4 step's Jacobians with respect to x_t and u_t, dn_t / dc_t
+// the barrier (and cost) gradients of transition t at x_{t+1} / x_t.  Phase A
+// computes [J_t^T; B_t^T] (six vector-Jacobian products with unit cotangents,
+// one per thread) and dn_t, dc_t for every step in parallel; phase B runs the
+// recursion on one lane as 6 x 8 matrix-vector products; phase C applies the
+// projected step (or writes the gradient) for every step in parallel.
+// W: [t_max][REP_PAR_PER_STEP] LDS.
+template <class R, int NOBS>
+__device__ void repair_reverse_par(const DevModel<R>& M, const DevCost<R>& C, const DevObjective<R>& ob,
+                                   const TrackView<R>& tr, R* V, int T, int t_end, R step, const R* xs,
+                                   const int* is, R* gout, R* W) {
+  constexpr int P = REP_PAR_PER_STEP;
+  const bool cost_terms = ob.w_S != R(0);
+  const int nit = 6 * (t_end + 1);
+  for (int k = threadIdx.x; k < nit; k += blockDim.x) {
+    const int t = k / 6, i = k % 6;
+    const R* pp = xs + 6 * t;
+    State<R> xp;
+    xp.px = pp[0]; xp.py = pp[1]; xp.psi = pp[2]; xp.vx = pp[3]; xp.vy = pp[4]; xp.om = pp[5];
+    const R u0 = clamp_r(V[t], M.u_lo[0], M.u_hi[0]);
+    const R u1 = clamp_r(V[T + t], M.u_lo[1], M.u_hi[1]);
+    R lam[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    lam[i] = R(1);
+    R gd = R(0), gt = R(0);
+    rk4_vjp(M, step_ctl(M, u0, u1), xp, lam, gd, gt);
+    R* q = W + (size_t)P * t + 8 * i;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) q[j] = lam[j];
+    q[6] = gd;
+    q[7] = gt;
+    if (i == 0) {
+      const R* pn = pp + 6;
+      State<R> xn;
+      xn.px = pn[0]; xn.py = pn[1]; xn.psi = pn[2]; xn.vx = pn[3]; xn.vy = pn[4]; xn.om = pn[5];
+      R dn[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+      R gpx = R(0), gpy = R(0);
+      penalty_grad<R, NOBS>(C, ob, tr, xp, is[t], xn, is[t + 1], t, dn, gpx, gpy);
+      R dc[6] = {gpx, gpy, R(0), R(0), R(0), R(0)};
+      if (cost_terms) stage_grad(C, tr, xp, is[t], ob.w_S, dc);
+      R* dd = W + (size_t)P * t + 48;
+      dd[0] = dn[0];
+      dd[1] = dn[1];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) dd[2 + j] = dc[j];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    R lam[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    if (cost_terms) {
+      State<R> xT;
+      const R* pT = xs + 6 * T;
+      xT.px = pT[0]; xT.py = pT[1]; xT.psi = pT[2]; xT.vx = pT[3]; xT.vy = pT[4]; xT.om = pT[5];
+      stage_grad(C, tr, xT, is[T], ob.w_S * C.phi_w, lam);
+    }
+    for (int t = t_end; t >= 0; --t) {
+      const R* q = W + (size_t)P * t;
+      lam[0] += q[48];
+      lam[1] += q[49];
+      R nl[8] = {R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+      for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) nl[j] += lam[i] * q[8 * i + j];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) lam[j] = nl[j] + q[50 + j];
+      R* g = W + (size_t)P * t + 56;
+      g[0] = nl[6];
+      g[1] = nl[7];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t <= t_end; t += blockDim.x) {
+    const R* g = W + (size_t)P * t + 56;
+    const R v0 = V[t], v1 = V[T + t];
+    const R u0 = clamp_r(v0, M.u_lo[0], M.u_hi[0]);
+    const R u1 = clamp_r(v1, M.u_lo[1], M.u_hi[1]);
+    const bool pass0 = (v0 >= M.u_lo[0]) && (v0 <= M.u_hi[0]);
+    const bool pass1 = (v1 >= M.u_lo[1]) && (v1 <= M.u_hi[1]);
+    const R gu0 = g[0] + ob.w_S * C.ctrl_w[0] * v0;
+    const R gu1 = g[1] + ob.w_S * C.ctrl_w[1] * v1;
+    const R gv0 = (pass0 ? gu0 : R(0)) + ob.w_S * C.ctrl_w[0] * u0;
+    const R gv1 = (pass1 ? gu1 : R(0)) + ob.w_S * C.ctrl_w[1] * u1;
+    if (gout) {
       gout[t] = gv0;
       gout[T + t] = gv1;
     } else {
@@ -1032,6 +1134,7 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
   R* psy = palpha + (mem + 1);
   R* pyy = psy + (mem + 1);
   R* red = pyy + (mem + 1);
+  R* wpar = mem > 0 ? red + 16 : gq;  // parallel reverse sweep: [t_max][REP_PAR_PER_STEP]
   int n_pairs = 0, head = 0;
   const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   const DevModel<R>& M = a.M;
@@ -1148,7 +1251,10 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
     if (a.method == 1 && t_end >= 0) {
       // gradient (zero after the last active transition), then the L-BFGS step
       for (int t = t_end + 1 + (int)threadIdx.x; t < T; t += blockDim.x) gq[t] = gq[T + t] = R(0);
-      if (w == 0 && lane == 0) repair_reverse<R, NOBS>(M, C, ob, tr, Vs, T, t_end, a.step, xs, is, gq);
+      if (a.par_rev)
+        repair_reverse_par<R, NOBS>(M, C, ob, tr, Vs, T, t_end, a.step, xs, is, gq, wpar);
+      else if (w == 0 && lane == 0)
+        repair_reverse<R, NOBS>(M, C, ob, tr, Vs, T, t_end, a.step, xs, is, gq);
       __syncthreads();
       lbfgs_step(M, Vs, T, gq, gprev, vprev, qv, Sp, Yp, prho, palpha, psy, pyy, red, mem, tm2, a.step, s > 0,
                  n_pairs, head);
@@ -1159,8 +1265,11 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
       Vs[t] = clamp_r(Vs[t], M.u_lo[0], M.u_hi[0]);
       Vs[T + t] = clamp_r(Vs[T + t], M.u_lo[1], M.u_hi[1]);
     }
-    if (w == 0 && lane == 0 && t_end >= 0)
+    if (a.par_rev) {
+      if (t_end >= 0) repair_reverse_par<R, NOBS>(M, C, ob, tr, Vs, T, t_end, a.step, xs, is, (R*)nullptr, wpar);
+    } else if (w == 0 && lane == 0 && t_end >= 0) {
       repair_reverse<R, NOBS>(M, C, ob, tr, Vs, T, t_end, a.step, xs, is, (R*)nullptr);
+    }
     __syncthreads();
     if (t_end < 0) break;
   }

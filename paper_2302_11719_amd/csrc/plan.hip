@@ -770,15 +770,16 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   // combines a problem runs Algorithm 1 on it right away.
   a.repair = 0;
   a.rep = RepairArgs<float>{};
+  const int mem = opts->repair_opts.method == 1 ? opts->repair_opts.memory : 0;
   if (opts->repair && opts->fuse_shield == 0 && block >= 3 * WAVE &&
-      lds_static + p->lds + repair_lds_bytes<float>(batch->t_max, opts->repair_opts.method == 1 ?
-                                                                  opts->repair_opts.memory : 0) <=
-          (size_t)ctx->max_lds) {
+      lds_static + p->lds + repair_lds_bytes<float>(batch->t_max, mem) <= (size_t)ctx->max_lds) {
     const ExecFuse ef{opts->dist, opts->n_dist, bufs->x0, bufs->V, bufs->iter};
     a.repair = 1;
     a.rep = repair_args<float>(ctx, &p->batch, model, cost, &p->track, bufs->x0, bufs->V_plus, &opts->repair_opts,
                                bufs->V_safe, opts->execute ? &ef : nullptr);
-    p->lds += (int)repair_lds_bytes<float>(batch->t_max, a.rep.memory);
+    // the parallel reverse sweep only when its tables fit beside the fused kernel's LDS
+    a.rep.par_rev = lds_static + p->lds + repair_lds_bytes<float>(batch->t_max, mem, true) <= (size_t)ctx->max_lds;
+    p->lds += (int)repair_lds_bytes<float>(batch->t_max, mem, a.rep.par_rev != 0);
   }
   p->fused_shield = a.repair != 0;
   int per_cu = 0;

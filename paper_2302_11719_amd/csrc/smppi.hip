@@ -509,8 +509,8 @@ extern "C" smppi_status smppi_rollout_backward(smppi_ctx ctx, const smppi_batch*
 template <class R, int NOBS>
 static smppi_status launch_repair(smppi_ctx ctx, const smppi_batch* b, const RepairArgs<R>& a, hipStream_t s,
                                   hipEvent_t e0, hipEvent_t e1) {
-  const size_t lds =
-      stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max) + repair_lds_bytes<R>(a.p.t_max, a.memory);
+  const size_t lds = stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max) +
+                     repair_lds_bytes<R>(a.p.t_max, a.memory, a.par_rev != 0);
   if (lds > (size_t)ctx->max_lds)
     return fail(ctx, SMPPI_ERR_SHAPE, "repair needs %zu B of LDS per workgroup (device max %d)", lds, ctx->max_lds);
   if (e0 && e1)  // events stamped with the kernel's own start and end
@@ -536,6 +536,10 @@ RepairArgs<R> smppi::repair_args(smppi_ctx ctx, const smppi_batch* b, const smpp
   a.seg_len = adj_seg_len(b->t_max);
   a.method = o->method;
   a.memory = o->method == 1 ? o->memory : 0;
+  // the parallel reverse sweep when its per-step Jacobians fit in LDS
+  a.par_rev = stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max) +
+                      repair_lds_bytes<R>(a.p.t_max, a.memory, true) <=
+                  (size_t)ctx->max_lds;
   a.exec = ex != nullptr;
   a.ex = ExecuteArgs<R>{};
   if (ex) {
