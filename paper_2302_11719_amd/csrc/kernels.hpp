@@ -930,6 +930,16 @@ __device__ void repair_reverse(const DevModel<R>& M, const DevCost<R>& C, const 
   }
 }
 
+// Value of lane i of the wave (uniform result).
+__device__ __forceinline__ float lane_bcast(float v, int i) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
+}
+__device__ __forceinline__ double lane_bcast(double v, int i) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, i), hi = __builtin_amdgcn_readlane((int)(b >> 32), i);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // The same reverse sweep by the whole workgroup (every thread must call it).
 // The adjoint recursion is linear once the nominal trajectory is fixed:
 //   lam_t = J_t^T (lam_{t+1} + dn_t) + dc_t,   g_t = B_t^T (lam_{t+1} + dn_t),
@@ -937,7 +947,8 @@ __device__ void repair_reverse(const DevModel<R>& M, const DevCost<R>& C, const 
 // the barrier (and cost) gradients of transition t at x_{t+1} / x_t.  Phase A
 // computes [J_t^T; B_t^T] (six vector-Jacobian products with unit cotangents,
 // one per thread) and dn_t, dc_t for every step in parallel; phase B runs the
-// recursion on one lane as 6 x 8 matrix-vector products; phase C applies the
+// recursion as 6 x 8 matrix-vector products on eight lanes of the first wave
+// (lane j forms component j from the lam_i broadcast by readlane); phase C applies the
 // projected step (or writes the gradient) for every step in parallel.
 // W: [t_max][REP_PAR_PER_STEP] LDS.
 template <class R, int NOBS>
@@ -980,28 +991,33 @@ __device__ void repair_reverse_par(const DevModel<R>& M, const DevCost<R>& C, co
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    R lam[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+  if (threadIdx.x < WAVE) {
+    // lane j < 8 holds component j: lam_j for j < 6, the control gradient for j = 6, 7;
+    // each step broadcasts lam_0..5 from their lanes and forms column j of Q^T lam
+    const int j = threadIdx.x & 7;
+    R lam = R(0);
     if (cost_terms) {
       State<R> xT;
       const R* pT = xs + 6 * T;
       xT.px = pT[0]; xT.py = pT[1]; xT.psi = pT[2]; xT.vx = pT[3]; xT.vy = pT[4]; xT.om = pT[5];
-      stage_grad(C, tr, xT, is[T], ob.w_S * C.phi_w, lam);
+      R l6[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+      stage_grad(C, tr, xT, is[T], ob.w_S * C.phi_w, l6);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) lam = j == i ? l6[i] : lam;
     }
     for (int t = t_end; t >= 0; --t) {
       const R* q = W + (size_t)P * t;
-      lam[0] += q[48];
-      lam[1] += q[49];
-      R nl[8] = {R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
+      if (j < 2) lam += q[48 + j];
+      R l[6];
 #pragma unroll
-      for (int i = 0; i < 6; ++i)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) nl[j] += lam[i] * q[8 * i + j];
-#pragma unroll
-      for (int j = 0; j < 6; ++j) lam[j] = nl[j] + q[50 + j];
-      R* g = W + (size_t)P * t + 56;
-      g[0] = nl[6];
-      g[1] = nl[7];
+      for (int i = 0; i < 6; ++i) l[i] = lane_bcast(lam, i);
+      const R nl = ((l[0] * q[j] + l[1] * q[8 + j]) + (l[2] * q[16 + j] + l[3] * q[24 + j])) +
+                   (l[4] * q[32 + j] + l[5] * q[40 + j]);
+      if (j < 6) {
+        lam = nl + q[50 + j];
+      } else if (threadIdx.x < 8) {
+        W[(size_t)P * t + 56 + (j - 6)] = nl;
+      }
     }
   }
   __syncthreads();
