@@ -3,10 +3,10 @@
 Headline workload: the closed-loop configuration, K = 4096 samples, T = 50 steps,
 one problem on a seeded spline track (12 control points, radius 15 +- 4 m,
 half width 0.9 m), disturbance sigma = 0.3 on v_y and omega.  One timed step is
-one receding-horizon Shield-MPPI iteration run by the batched plan in a HIP
-graph: fused rollout + softmax weights + update, the shield (10 projected
-gradient steps of the hand-written adjoint, step 0.05), and execute + warm
-start on the device.  value = rollout-steps/s = K*T*steps / elapsed.
+one receding-horizon Shield-MPPI iteration run by the batched plan as one
+kernel launch: fused rollout + softmax weights + update, then the shield (10
+projected gradient steps of the hand-written adjoint, step 0.05) and execute +
+warm start in the workgroup that combined the problem.  value = rollout-steps/s = K*T*steps / elapsed.
 
 Also measured in the same run (reported beside the headline): the plain
 per-call form (rollout, weights, update, execute launches, no shield), the
@@ -132,48 +132,57 @@ def main():
     _log(f"  {ms_per_step:.4f} ms/iter (events {ev0.elapsed_time(ev1) / steps:.4f}; with an event per iteration: "
          f"mean {per_iter.mean():.4f}, median {np.median(per_iter):.4f}), {value:.4g} rollout-steps/s")
 
-    # per-stage durations of the same work (HIP events between the stages)
-    db_p = core.DeviceBatch([prob], dtype=torch.float32)
-    plan_p = core.Plan(ctx, db_p, M, C, seed, lam, repair=rep, execute=True, dist=dist, use_graph=False)
+    # The headline launch is one kernel (fused rollout/weights/update, shield, plant):
+    # its duration from kernel-stamped events on an eager copy of the same plan.
     n_prof = min(steps, 100)
-    fused, repair_t, exec_t, active, kf, kr = [], [], [], [], [], []
+    db_f = core.DeviceBatch([prob], dtype=torch.float32)
+    plan_f = core.Plan(ctx, db_f, M, C, seed, lam, repair=rep, execute=True, dist=dist, use_graph=False)
+    kl = []
+    for i in range(warm + n_prof):
+        plan_f.launch_profiled()
+        if i >= warm:
+            kl.append(plan_f.kernel_ms()[0])
+    plan_f.close()
+    # Stage split of the same work with the shield as a kernel of its own (HIP events
+    # between the stages; kernel-stamped events on the fused and shield kernels).
+    db_p = core.DeviceBatch([prob], dtype=torch.float32)
+    plan_p = core.Plan(ctx, db_p, M, C, seed, lam, repair=rep, execute=True, dist=dist, use_graph=False,
+                       fuse_shield=-1)
+    fused, repair_t, active, kf, kr = [], [], [], [], []
     for i in range(warm + n_prof):
         plan_p.launch_profiled()
-        f, r, e = plan_p.stage_ms()
+        f, r, _ = plan_p.stage_ms()
         k1, k2 = plan_p.kernel_ms()
         if i >= warm:
             fused.append(f)
             repair_t.append(r)
-            exec_t.append(e)
             kf.append(k1)
             kr.append(k2)
             # the shield changed the MPPI output (some DCBF condition was violated)
             active.append(not torch.equal(plan_p.V_safe, plan_p.V_plus))
+    plan_p.close()
     act = np.array(active)
-    rt = np.array(repair_t)
-    stage = dict(fused_rollout_weights_update_ms=float(np.mean(fused)), shield_repair_ms=float(np.mean(rt)),
-                 execute_ms=float(np.mean(exec_t)), shield_active_fraction=float(act.mean()),
-                 shield_ms_when_active=float(rt[act].mean()) if act.any() else None,
-                 shield_ms_when_idle=float(rt[~act].mean()) if (~act).any() else None,
-                 k_fused_kernel_ms=float(np.mean(kf)), k_repair_kernel_ms=float(np.mean(kr)))
+    kr = np.array(kr)
+    stage = dict(launch_kernel_ms=float(np.mean(kl)),
+                 split_rollout_weights_update_kernel_ms=float(np.mean(kf)),
+                 split_shield_plant_kernel_ms=float(kr.mean()), shield_active_fraction=float(act.mean()),
+                 shield_kernel_ms_when_active=float(kr[act].mean()) if act.any() else None,
+                 shield_kernel_ms_when_idle=float(kr[~act].mean()) if (~act).any() else None)
     _log(f"  stages: {stage}")
 
-    flop_step = FLOP_STEP_POLY + FLOP_UPDATE_STEP
-    dominant = "k_fused" if stage["k_fused_kernel_ms"] >= stage["k_repair_kernel_ms"] else "k_repair"
-    if dominant == "k_fused":
-        flops = K * T * flop_step
-        dur = stage["k_fused_kernel_ms"] * 1e-3
-    else:
-        # one problem: n_s x (forward T steps + reverse T steps with recompute ~ 3x forward)
-        flops = rep["n_steps"] * T * FLOP_STEP_POLY * 4
-        dur = stage["k_repair_kernel_ms"] * 1e-3
+    # roofline of the one kernel: the rollouts and update (the shield's nominal pass,
+    # T steps of one trajectory, is not counted)
+    dominant = "k_fused"
+    flops = K * T * (FLOP_STEP_POLY + FLOP_UPDATE_STEP)
+    dur = stage["launch_kernel_ms"] * 1e-3
     achieved = flops / dur
     from paper_2302_11719_amd.profile_summary import load_traffic
 
-    traffic, why = load_traffic(TRAFFIC_SUMMARY, dominant) if dominant == "k_fused" else (None, "no summary")
-    roofline = {"bound": "alu", "kernel": dominant, "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": traffic,
-                "traffic_unit": "bytes/launch", "flop_per_launch": flops, "avg_launch_ms": dur * 1e3}
+    traffic, why = load_traffic(TRAFFIC_SUMMARY, dominant)
+    roofline = {"bound": "alu", "kernel": "k_fused (rollout, weights, update, shield, plant step)",
+                "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+                "traffic": traffic, "traffic_unit": "bytes/launch", "flop_per_launch": flops,
+                "avg_launch_ms": dur * 1e3}
     if traffic is None:
         roofline["traffic_note"] = why
 
@@ -183,7 +192,7 @@ def main():
         "ms_per_step": ms_per_step, "ms_per_step_median_evented": float(np.median(per_iter)),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "closed-loop Shield-MPPI iteration (batched+adjoint plan, HIP graph): "
+        "config": {"workload": "closed-loop Shield-MPPI iteration (batched+adjoint plan, one launch): "
                                "K=4096, T=50, 1 problem, spline track, shield 10x0.05, plant disturbance 0.3",
                    "K": K, "T": T, "problems": 1, "repair_steps": 10, "parallelism": "single-gpu"},
         "stages_ms": stage,
