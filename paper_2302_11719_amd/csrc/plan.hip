@@ -259,7 +259,7 @@ __device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, co
 template <int NOBS, int BLK, int SPT, bool PIPE>
 __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ float red[BLK / WAVE];
+  __shared__ float red[3 * (BLK / WAVE)];
   __shared__ NoiseSumLds<float, BLK, SPT> L;
   __shared__ int s_tile;
   __shared__ uint32_t s_ticket;
@@ -329,9 +329,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       q += om[j] * om[j];
       if (own[j] && !isfinite(s[j])) nf += 1.f;
     }
-    z = block_sum(z, red);
-    q = block_sum(q, red);
-    nf = block_sum(nf, red);
+    block_sum3(z, q, nf, red);
     float* P = a.part + (size_t)(a.tile_off[b] + kb) * pstride;
     block_noise_sums<float, BLK, SPT>(a.M, a.C, a.p.seed, pid, it, a.p.nominal != 0, Vs, d.T, ms, om, L,
                                       P + PART_HDR);
@@ -388,9 +386,10 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
             q_l += sc * sc * qk[j];
           }
         }
-        Z = block_sum(z_l, red);
-        Q = block_sum(q_l, red);
-        NF = block_sum(nf_l, red);
+        block_sum3(z_l, q_l, nf_l, red);
+        Z = z_l;
+        Q = q_l;
+        NF = nf_l;
       } else {
         float mn_l = INFINITY;
         for (int k = tid; k < ntb; k += BLK) mn_l = fminf(mn_l, P0[(size_t)k * pstride]);
@@ -404,9 +403,10 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
           q_l += sc * sc * Pk[2];
           nf_l += Pk[3];
         }
-        Z = block_sum(z_l, red);
-        Q = block_sum(q_l, red);
-        NF = block_sum(nf_l, red);
+        block_sum3(z_l, q_l, nf_l, red);
+        Z = z_l;
+        Q = q_l;
+        NF = nf_l;
       }
       const float iZ = Z > 0.f ? 1.f / Z : 0.f;
       const float* Vb = a.V + 2 * (size_t)d.t0;
