@@ -190,7 +190,10 @@ smppi_status smppi_device_errors(smppi_ctx ctx, uint32_t* flags);
  * x0: device [B][6] dtype.  V: device control sequences (layout above).
  * iter: device [B] uint32 iteration counters (noise counter word 3).
  * eps_out: NULL, or device [sum K][t_max][2] dtype receiving the effective
- *   noise u - v of every step (debug/test; rows beyond T_b untouched). */
+ *   noise u - v of every step (debug/test; rows beyond T_b untouched).
+ * FP32 with obstacles: a small kernel first copies every problem's obstacles
+ * into padded slots in the ctx scratch (B * 64 * 16 bytes), which the rollout
+ * kernel reads through the scalar cache. */
 smppi_status smppi_rollout(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
                            const smppi_cost* cost, const smppi_noise* noise, const smppi_track* track,
                            const void* x0, const void* V, const uint32_t* iter, void* S, void* eps_out,
@@ -267,7 +270,7 @@ typedef struct {
   int32_t grid;              /* persistent workgroups; 0 = chosen from occupancy */
   int32_t use_graph;         /* nonzero: capture into a hipGraph at creation when a launch
                                 has more than one kernel (one kernel is launched directly) */
-  int32_t pipeline;          /* 1: latency mode (64-sample tiles, three specialised waves
+  int32_t pipeline;          /* 1: latency mode (64-sample tiles, four specialised waves
                                 pipelining noise, dynamics and cost); -1: off; 0: on when
                                 the batch has at most 2*64 samples per compute unit and
                                 no obstacles */
@@ -301,7 +304,10 @@ smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batch, const sm
                                const smppi_plan_opts* opts, const smppi_plan_buffers* bufs,
                                smppi_plan* out);
 /* One MPPI iteration of every problem: rollout, weights and update fused in one
- * persistent launch, then (optionally) the shield and the execute/warm start. */
+ * persistent launch, then (optionally) the shield and the execute/warm start.
+ * With obstacles outside latency mode, a small kernel first copies the current
+ * obstacles into padded slots the plan owns (read through the scalar cache by
+ * the rollouts). */
 smppi_status smppi_plan_launch(smppi_plan plan, void* stream);
 void smppi_plan_destroy(smppi_plan plan);
 /* Profiling: the same work as smppi_plan_launch, enqueued without the graph and

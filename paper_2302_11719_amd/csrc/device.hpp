@@ -463,13 +463,124 @@ __device__ __forceinline__ void lateral_sq_grad(const TrackView<R>& tr, R px, R 
   gy = R(2) * ey;
 }
 
+// ---------------------------------------------------------------- obstacles
+// Circular-obstacle barriers of eqs. (17)-(20) per step: h_i = |p - c_i|^2 -
+// (r_i + margin)^2, penalty sum_i max(alpha h_i(x_t) - h_i(x_{t+1}), 0), and the
+// collision indicator of eq. (25) (|p - c_i| < r_i for some i).  Two sources of
+// the obstacle table, same arithmetic up to rounding order:
+//
+// LdsObstacles: the staged table in LDS, read per lane (broadcast reads), any
+// arithmetic type.  Used by the plain per-call kernels and the FP64 path.
+template <class R>
+struct LdsObstacles {
+  const TrackView<R>* tr;
+  // hob[i] = h_i at (px, py); collision of the point
+  template <int NOBS>
+  __device__ __forceinline__ void init(R px, R py, R* hob, bool& outside) const {
+#pragma unroll
+    for (int i = 0; i < NOBS; ++i) {
+      const Obs<R> o = obs_at(*tr, i);
+      const R ox = px - o.cx, oy = py - o.cy;
+      const R d2 = ox * ox + oy * oy;
+      hob[i] = d2 - o.re2;
+      outside = outside || (d2 < o.r2);
+    }
+  }
+  // one transition to (px, py): pen += sum_i max(alpha hob_i - h_i, 0); hob_i = h_i
+  template <int NOBS>
+  __device__ __forceinline__ void step(R px, R py, R alpha, R* hob, R& pen, bool& outside) const {
+#pragma unroll
+    for (int i = 0; i < NOBS; ++i) {
+      const Obs<R> o = obs_at(*tr, i);
+      const R ox = px - o.cx, oy = py - o.cy;
+      const R d2 = ox * ox + oy * oy;
+      const R hi = d2 - o.re2;
+      pen += fmax(alpha * hob[i] - hi, R(0));
+      hob[i] = hi;
+      outside = outside || (d2 < o.r2);
+    }
+  }
+};
+
+// ScalarObstacles: FP32 table in global memory, the same for the whole wave,
+// laid out per slot as (c_x, c_y, (r + margin)^2, r^2 - (r + margin)^2) with
+// unused slots inert ((0, 0, -1e30, 0): h is about 1e30, never violated, never
+// hit).  The slots are read through the scalar cache into SGPRs in groups of
+// eight (one group ahead of the arithmetic), so the VALU instructions take the
+// obstacle terms as scalar operands: no per-lane copies of the table, no
+// register file pressure from it.  h_i comes from two FMAs (d^2 - re2 folded)
+// and the collision test is min_i (h_i - (r^2 - re2)) < 0, a running min3
+// instead of a compare and mask OR per obstacle.
+typedef const float __attribute__((address_space(4)))* ConstF;
+constexpr int OBS_GROUP = 8;
+struct ScalarObstacles {
+  const float4* slots;  // [NOBS] slots of this problem (uniform address)
+  template <int NOBS, bool INIT>
+  __device__ __forceinline__ void run(float px, float py, float alpha, float* hob, float& pen, float& mo) const {
+    static_assert(NOBS % OBS_GROUP == 0, "obstacle slots come in groups");
+    constexpr int NG = NOBS / OBS_GROUP;
+    // The address passes through an empty asm statement tied to the step's
+    // position (and, per group, to the running sums) so that the loads stay
+    // inside the step loop, one group ahead of their use, instead of being
+    // hoisted out of it (the whole table does not fit in SGPRs).
+    ConstF op = (ConstF)(uintptr_t)slots;
+    asm volatile("" : "+s"(op) : "v"(px), "v"(py));
+    float4 cur[OBS_GROUP], nxt[OBS_GROUP];
+#pragma unroll
+    for (int j = 0; j < OBS_GROUP; ++j) cur[j] = make_float4(op[4 * j], op[4 * j + 1], op[4 * j + 2], op[4 * j + 3]);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      if (g + 1 < NG) {
+        op += 4 * OBS_GROUP;
+        asm volatile("" : "+s"(op) : "v"(pen), "v"(mo));
+#pragma unroll
+        for (int j = 0; j < OBS_GROUP; ++j)
+          nxt[j] = make_float4(op[4 * j], op[4 * j + 1], op[4 * j + 2], op[4 * j + 3]);
+      }
+#pragma unroll
+      for (int j = 0; j < OBS_GROUP; j += 2) {
+        const int i = g * OBS_GROUP + j;
+        float m2[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const float4 o = cur[j + k];
+          const float ox = px - o.x, oy = py - o.y;
+          const float hi = fmaf(ox, ox, fmaf(oy, oy, -o.z));
+          if (!INIT) pen += fmaxf(alpha * hob[i + k] - hi, 0.f);
+          hob[i + k] = hi;
+          m2[k] = hi - o.w;
+        }
+        mo = fminf(mo, fminf(m2[0], m2[1]));  // v_min3
+      }
+      if (g + 1 < NG) {
+#pragma unroll
+        for (int j = 0; j < OBS_GROUP; ++j) cur[j] = nxt[j];
+      }
+    }
+  }
+  template <int NOBS>
+  __device__ __forceinline__ void init(float px, float py, float* hob, bool& outside) const {
+    float pen = 0.f, mo = INFINITY;
+    run<NOBS, true>(px, py, 0.f, hob, pen, mo);
+    outside = outside || (mo < 0.f);
+  }
+  template <int NOBS>
+  __device__ __forceinline__ void step(float px, float py, float alpha, float* hob, float& pen,
+                                       bool& outside) const {
+    float mo = INFINITY;
+    run<NOBS, false>(px, py, alpha, hob, pen, mo);
+    outside = outside || (mo < 0.f);
+  }
+};
+
 // ---------------------------------------------------------------- one sample
 // Modified trajectory cost S~ of one sample (Algorithm 2 inner loop):
 //   S~ = sum_{t<T} [q(x_t) + lambda_u v_t^T Sigma^-1 u_t] + phi_w q(x_T) + sum_{t=0}^{T} C_cbf(z_t).
-// V is [2][T] (steer row, throttle row), read from LDS or global.
-template <class R, int NOBS>
+// V is [2][T] (steer row, throttle row), read from LDS or global.  Obstacles
+// come from `os` (LdsObstacles or ScalarObstacles).
+template <class R, int NOBS, class OS>
 __device__ R rollout_sample(const DevModel<R>& M, const DevCost<R>& C, const TrackView<R>& tr, const State<R>& x0,
-                            const R* __restrict__ V, int T, NoiseStream<R>& ns, R* eps_out) {
+                            const R* __restrict__ V, int T, NoiseStream<R>& ns, R* eps_out, const OS& os) {
   State<R> x = x0;
   // the window around the global nearest segment of x0 returns that segment
   int idx = tr.idx0;
@@ -477,16 +588,15 @@ __device__ R rollout_sample(const DevModel<R>& M, const DevCost<R>& C, const Tra
   R h0 = tr.w2 - ey2;
   bool outside = h0 < R(0);
   R hob[NOBS > 0 ? NOBS : 1];
-  // z_0 = (x_0, x_0): C max((alpha - 1) h(x_0), 0) per barrier.
+  // z_0 = (x_0, x_0): C max((alpha - 1) h(x_0), 0) per barrier, i.e. the
+  // transition penalty with both ends at x_0.
   R S = C.C_cbf * fmax((C.alpha - R(1)) * h0, R(0));
-#pragma unroll
-  for (int i = 0; i < NOBS; ++i) {
-    const Obs<R> o = obs_at(tr, i);
-    const R ox = x.px - o.cx, oy = x.py - o.cy;
-    const R d2 = ox * ox + oy * oy;
-    hob[i] = d2 - o.re2;
-    outside = outside || (d2 < o.r2);
-    S += C.C_cbf * fmax((C.alpha - R(1)) * hob[i], R(0));
+  if (NOBS > 0) {
+    os.template init<NOBS>(x.px, x.py, hob, outside);
+    R pen0 = R(0);
+    bool dummy = false;
+    os.template step<NOBS>(x.px, x.py, C.alpha, hob, pen0, dummy);
+    S += C.C_cbf * pen0;
   }
   for (int t = 0; t < T; ++t) {
     const R v0 = V[t], v1 = V[T + t];
@@ -509,16 +619,7 @@ __device__ R rollout_sample(const DevModel<R>& M, const DevCost<R>& C, const Tra
     R pen = fmax(C.alpha * h0 - h1, R(0));
     h0 = h1;
     outside = h1 < R(0);
-#pragma unroll
-    for (int i = 0; i < NOBS; ++i) {
-      const Obs<R> o = obs_at(tr, i);
-      const R ox = x.px - o.cx, oy = x.py - o.cy;
-      const R d2 = ox * ox + oy * oy;
-      const R hi = d2 - o.re2;
-      pen += fmax(C.alpha * hob[i] - hi, R(0));
-      hob[i] = hi;
-      outside = outside || (d2 < o.r2);
-    }
+    if (NOBS > 0) os.template step<NOBS>(x.px, x.py, C.alpha, hob, pen, outside);
     S += C.C_cbf * pen;
   }
   const R dv = x.vx - C.v_g;
@@ -526,6 +627,12 @@ __device__ R rollout_sample(const DevModel<R>& M, const DevCost<R>& C, const Tra
   if (outside) q += C.C_obs;
   S += C.phi_w * q;
   return S;
+}
+
+template <class R, int NOBS>
+__device__ R rollout_sample(const DevModel<R>& M, const DevCost<R>& C, const TrackView<R>& tr, const State<R>& x0,
+                            const R* __restrict__ V, int T, NoiseStream<R>& ns, R* eps_out) {
+  return rollout_sample<R, NOBS>(M, C, tr, x0, V, T, ns, eps_out, LdsObstacles<R>{&tr});
 }
 
 // Modified trajectory cost S~ of one sample of the curvilinear model: as

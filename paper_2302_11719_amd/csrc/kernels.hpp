@@ -229,7 +229,30 @@ struct RolloutArgs {
   const R* V;
   R* S;
   R* eps_out;
+  const float4* obs_pad;  // FP32 with obstacles: [B][NOBS] slots from k_pad_obs (scalar reads)
 };
+
+// Obstacle slots of every problem for the scalar reads of the FP32 rollouts
+// (ScalarObstacles): (c_x, c_y, (r + margin)^2, r^2 - (r + margin)^2) for the
+// problem's obstacles, the inert slot (0, 0, -1e30, 0) after them, n_slots per
+// problem.  Runs before every launch that reads them, so obstacles the caller
+// moves between launches are seen.  A problem whose obstacle count is out of
+// range gets inert slots only (the rollout kernels flag and skip it).
+// Grid: one workgroup per problem.
+static __global__ void k_pad_obs(const int32_t* __restrict__ obs_off, const float* __restrict__ obs, int obs_max,
+                          int n_slots, float4* __restrict__ out) {
+  const int b = blockIdx.x;
+  const int o0 = obs_off ? obs_off[b] : 0, no = obs_off ? obs_off[b + 1] - o0 : 0;
+  const bool ok = no >= 0 && no <= obs_max;
+  for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
+    float4 v = make_float4(0.f, 0.f, -1e30f, 0.f);
+    if (ok && i < no) {
+      const float* o = obs + 4 * ((size_t)o0 + i);
+      v = make_float4(o[0], o[1], o[2], o[3] - o[2]);
+    }
+    out[(size_t)b * n_slots + i] = v;
+  }
+}
 
 template <class R, int NOBS>
 __global__ __launch_bounds__(256) void k_rollout(RolloutArgs<R> a) {
@@ -252,7 +275,11 @@ __global__ __launch_bounds__(256) void k_rollout(RolloutArgs<R> a) {
   ns.nominal = a.p.nominal != 0;
   const State<R> x0 = load_state(a.p.x0 + 6 * (size_t)b);
   R* eo = a.eps_out ? a.eps_out + (size_t)(d.k0 + m) * a.p.t_max * 2 : nullptr;
-  a.S[d.k0 + m] = rollout_sample<R, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, eo);
+  if constexpr (NOBS > 0 && sizeof(R) == 4)
+    a.S[d.k0 + m] = rollout_sample<R, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, eo,
+                                            ScalarObstacles{a.obs_pad + (size_t)b * NOBS});
+  else
+    a.S[d.k0 + m] = rollout_sample<R, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, eo);
 }
 
 // ============================================================== curvilinear rollout

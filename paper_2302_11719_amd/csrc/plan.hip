@@ -44,6 +44,7 @@ struct FusedArgs {
   uint32_t* exits;           // [1] workgroups that have left the tile loop
   int repair;                // nonzero: the combining workgroup also runs the shield (and execute)
   RepairArgs<float> rep;
+  const float4* obs_pad;     // [B][kMaxObs] obstacle slots for the scalar reads (NOBS > 0, tile mode)
 };
 
 // ---------------------------------------------------------------------------
@@ -313,7 +314,11 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
           ns.pid = pid;
           ns.it = it;
           ns.nominal = a.p.nominal != 0;
-          s[j] = rollout_sample<float, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, nullptr);
+          if constexpr (NOBS > 0)
+            s[j] = rollout_sample<float, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, nullptr,
+                                               ScalarObstacles{a.obs_pad + (size_t)b * NOBS});
+          else
+            s[j] = rollout_sample<float, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, nullptr);
           a.S[d.k0 + ms[j]] = s[j];
         }
         if (isfinite(s[j])) mn = fminf(mn, s[j]);
@@ -548,6 +553,7 @@ struct smppi_plan_s {
   int32_t* tile_off = nullptr;
   float* part = nullptr;
   uint32_t* counters = nullptr;  // [0] queue, [1..B] tickets, [B+1] exits
+  float4* obs_pad = nullptr;     // [B][kMaxObs] obstacle slots (tile mode with obstacles)
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -588,6 +594,11 @@ static smppi_status plan_enqueue(smppi_plan p, hipStream_t s, bool profiled = fa
                        static_cast<const float*>(p->bufs.V), static_cast<float*>(p->bufs.V_plus),
                        static_cast<float*>(p->bufs.stats));
     if ((st = check_launch(ctx, "k_copy_empty"))) return st;
+  }
+  if (p->obs_pad && p->fa.n_tiles > 0) {
+    hipLaunchKernelGGL(k_pad_obs, dim3(B), dim3(kMaxObs), 0, s, static_cast<const int32_t*>(p->track.obs_off),
+                       static_cast<const float*>(p->track.obs), p->fa.p.obs_max, kMaxObs, p->obs_pad);
+    if ((st = check_launch(ctx, "k_pad_obs"))) return st;
   }
   if (p->fa.n_tiles > 0) {
     if (profiled)  // events stamped with the kernel's own start and end
@@ -630,6 +641,7 @@ extern "C" void smppi_plan_destroy(smppi_plan p) {
   if (p->tile_off) (void)hipFree(p->tile_off);
   if (p->part) (void)hipFree(p->part);
   if (p->counters) (void)hipFree(p->counters);
+  if (p->obs_pad) (void)hipFree(p->obs_pad);
   delete p;
 }
 
@@ -740,6 +752,10 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
     return bail(hip_fail(ctx, e, "hipMemcpy(tile_off)"));
   if ((e = hipMemset(p->counters, 0, sizeof(uint32_t) * (B + 2))) != hipSuccess)
     return bail(hip_fail(ctx, e, "hipMemset(counters)"));
+  // tile mode with obstacles reads them through the scalar cache from padded slots
+  if (!pipe && obs_slots(track) > 0 &&
+      (e = hipMalloc(&p->obs_pad, sizeof(float4) * (size_t)B * kMaxObs)) != hipSuccess)
+    return bail(hip_fail(ctx, e, "hipMalloc(obs_pad)"));
 
   FusedArgs& a = p->fa;
   a.p = problem_args<float>(ctx, &p->batch, &p->track, &p->noise, bufs->x0, bufs->iter);
@@ -758,6 +774,7 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   a.queue = p->counters;
   a.tickets = p->counters + 1;
   a.exits = p->counters + 1 + B;
+  a.obs_pad = p->obs_pad;
   p->lds = (int)stage_lds_bytes<float>(track->poly_max, batch->t_max, obs_slots(track));
   hipFuncAttributes fattr{};
   if ((e = hipFuncGetAttributes(&fattr, reinterpret_cast<const void*>(fn))) != hipSuccess)
@@ -790,7 +807,7 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   p->grid = grid;
   // A graph only pays when the launch has several kernels; a single kernel is
   // launched directly (measured: the one-node graph adds about 4 us per launch).
-  const int n_kernels = (any_empty ? 1 : 0) + (n_tiles > 0 ? 1 : 0) + (opts->repair && !p->fused_shield ? 1 : 0) +
+  const int n_kernels = (any_empty ? 1 : 0) + (n_tiles > 0 ? (p->obs_pad ? 2 : 1) : 0) + (opts->repair && !p->fused_shield ? 1 : 0) +
                         (opts->execute && !opts->repair ? 1 : 0);
   if (opts->use_graph && n_kernels > 1) {
     if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess)

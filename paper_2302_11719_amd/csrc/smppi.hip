@@ -292,7 +292,19 @@ static smppi_status launch_rollout(smppi_ctx ctx, const smppi_batch* b, const Ro
   const int gx = b->k_max > 0 ? (b->k_max + blk - 1) / blk : 0;
   if (gx == 0) return SMPPI_OK;
   const size_t lds = stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max);
-  hipLaunchKernelGGL((k_rollout<R, NOBS>), dim3(gx, b->n_problems), dim3(blk), lds, s, a);
+  RolloutArgs<R> ra = a;
+  ra.obs_pad = nullptr;
+  if (NOBS > 0 && sizeof(R) == 4) {
+    // FP32 obstacles go through the scalar cache from padded slots in the scratch buffer
+    smppi_status st = ensure_scratch(ctx, sizeof(float4) * (size_t)b->n_problems * NOBS);
+    if (st) return st;
+    float4* pad = static_cast<float4*>(ctx->scratch);
+    hipLaunchKernelGGL(k_pad_obs, dim3(b->n_problems), dim3(64), 0, s, a.p.obs_off,
+                       reinterpret_cast<const float*>(a.p.obs), a.p.obs_max, NOBS, pad);
+    if ((st = check_launch(ctx, "k_pad_obs"))) return st;
+    ra.obs_pad = pad;
+  }
+  hipLaunchKernelGGL((k_rollout<R, NOBS>), dim3(gx, b->n_problems), dim3(blk), lds, s, ra);
   return check_launch(ctx, "k_rollout");
 }
 
