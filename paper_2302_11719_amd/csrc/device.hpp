@@ -476,7 +476,7 @@ struct LdsObstacles {
   const TrackView<R>* tr;
   // hob[i] = h_i at (px, py); collision of the point
   template <int NOBS>
-  __device__ __forceinline__ void init(R px, R py, R* hob, bool& outside) const {
+  __device__ __forceinline__ void init(R px, R py, R /*alpha*/, R* hob, bool& outside) const {
 #pragma unroll
     for (int i = 0; i < NOBS; ++i) {
       const Obs<R> o = obs_at(*tr, i);
@@ -503,20 +503,25 @@ struct LdsObstacles {
 };
 
 // ScalarObstacles: FP32 table in global memory, the same for the whole wave,
-// laid out per slot as (c_x, c_y, (r + margin)^2, r^2 - (r + margin)^2) with
-// unused slots inert ((0, 0, -1e30, 0): h is about 1e30, never violated, never
-// hit).  The slots are read through the scalar cache into SGPRs in groups of
-// eight (one group ahead of the arithmetic), so the VALU instructions take the
-// obstacle terms as scalar operands: no per-lane copies of the table, no
-// register file pressure from it.  h_i comes from two FMAs (d^2 - re2 folded)
-// and the collision test is min_i (h_i - (r^2 - re2)) < 0, a running min3
-// instead of a compare and mask OR per obstacle.
+// one slot per obstacle: (c_x, c_y, r^2, kappa) with kappa = (1 - alpha)
+// ((r + margin)^2 - r^2); unused slots are inert ((0, 0, -1e30, 0): never
+// violated, never hit).  The slots are read through the scalar cache into
+// SGPRs in groups of eight, one group ahead of the arithmetic, so the VALU
+// instructions take the obstacle terms as scalar operands (no per-lane copies
+// of the table).  The arithmetic is rewritten around g_i = |p - c_i|^2 - r_i^2
+// (two FMAs; collision iff g_i < 0): with h_i = g_i - delta_i, delta_i =
+// (r + margin)^2 - r^2, the transition penalty is
+//   alpha h_i(x_t) - h_i(x_{t+1}) = c_i - g_i(x_{t+1}),  c_i = alpha g_i(x_t) + kappa_i,
+// so each lane carries c_i (updated in place by one FMA), and the collision
+// test is a running min3 of the g_i.
 typedef const float __attribute__((address_space(4)))* ConstF;
 constexpr int OBS_GROUP = 8;
 struct ScalarObstacles {
   const float4* slots;  // [NOBS] slots of this problem (uniform address)
+  // INIT: c_i = alpha g_i + kappa_i only; else also pen += sum_i max(c_i - g_i, 0).
+  // mo = min(mo, min_i g_i).
   template <int NOBS, bool INIT>
-  __device__ __forceinline__ void run(float px, float py, float alpha, float* hob, float& pen, float& mo) const {
+  __device__ __forceinline__ void run(float px, float py, float alpha, float* c, float& pen, float& mo) const {
     static_assert(NOBS % OBS_GROUP == 0, "obstacle slots come in groups");
     constexpr int NG = NOBS / OBS_GROUP;
     // The address passes through an empty asm statement tied to the step's
@@ -525,6 +530,10 @@ struct ScalarObstacles {
     // hoisted out of it (the whole table does not fit in SGPRs).
     ConstF op = (ConstF)(uintptr_t)slots;
     asm volatile("" : "+s"(op) : "v"(px), "v"(py));
+    // alpha in a VGPR: the FMA c = alpha g + kappa then reads one scalar
+    // operand (kappa), within the one-SGPR-per-instruction limit
+    float av = alpha;
+    asm volatile("" : "+v"(av));
     float4 cur[OBS_GROUP], nxt[OBS_GROUP];
 #pragma unroll
     for (int j = 0; j < OBS_GROUP; ++j) cur[j] = make_float4(op[4 * j], op[4 * j + 1], op[4 * j + 2], op[4 * j + 3]);
@@ -540,17 +549,17 @@ struct ScalarObstacles {
 #pragma unroll
       for (int j = 0; j < OBS_GROUP; j += 2) {
         const int i = g * OBS_GROUP + j;
-        float m2[2];
+        float g2[2];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           const float4 o = cur[j + k];
           const float ox = px - o.x, oy = py - o.y;
-          const float hi = fmaf(ox, ox, fmaf(oy, oy, -o.z));
-          if (!INIT) pen += fmaxf(alpha * hob[i + k] - hi, 0.f);
-          hob[i + k] = hi;
-          m2[k] = hi - o.w;
+          const float gi = fmaf(ox, ox, fmaf(oy, oy, -o.z));
+          if (!INIT) pen += fmaxf(c[i + k] - gi, 0.f);
+          c[i + k] = fmaf(av, gi, o.w);
+          g2[k] = gi;
         }
-        mo = fminf(mo, fminf(m2[0], m2[1]));  // v_min3
+        mo = fminf(fminf(mo, g2[0]), g2[1]);  // v_min3
       }
       if (g + 1 < NG) {
 #pragma unroll
@@ -559,16 +568,15 @@ struct ScalarObstacles {
     }
   }
   template <int NOBS>
-  __device__ __forceinline__ void init(float px, float py, float* hob, bool& outside) const {
+  __device__ __forceinline__ void init(float px, float py, float alpha, float* c, bool& outside) const {
     float pen = 0.f, mo = INFINITY;
-    run<NOBS, true>(px, py, 0.f, hob, pen, mo);
+    run<NOBS, true>(px, py, alpha, c, pen, mo);
     outside = outside || (mo < 0.f);
   }
   template <int NOBS>
-  __device__ __forceinline__ void step(float px, float py, float alpha, float* hob, float& pen,
-                                       bool& outside) const {
+  __device__ __forceinline__ void step(float px, float py, float alpha, float* c, float& pen, bool& outside) const {
     float mo = INFINITY;
-    run<NOBS, false>(px, py, alpha, hob, pen, mo);
+    run<NOBS, false>(px, py, alpha, c, pen, mo);
     outside = outside || (mo < 0.f);
   }
 };
@@ -592,7 +600,7 @@ __device__ R rollout_sample(const DevModel<R>& M, const DevCost<R>& C, const Tra
   // transition penalty with both ends at x_0.
   R S = C.C_cbf * fmax((C.alpha - R(1)) * h0, R(0));
   if (NOBS > 0) {
-    os.template init<NOBS>(x.px, x.py, hob, outside);
+    os.template init<NOBS>(x.px, x.py, C.alpha, hob, outside);
     R pen0 = R(0);
     bool dummy = false;
     os.template step<NOBS>(x.px, x.py, C.alpha, hob, pen0, dummy);

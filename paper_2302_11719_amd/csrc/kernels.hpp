@@ -233,14 +233,14 @@ struct RolloutArgs {
 };
 
 // Obstacle slots of every problem for the scalar reads of the FP32 rollouts
-// (ScalarObstacles): (c_x, c_y, (r + margin)^2, r^2 - (r + margin)^2) for the
-// problem's obstacles, the inert slot (0, 0, -1e30, 0) after them, n_slots per
-// problem.  Runs before every launch that reads them, so obstacles the caller
+// (ScalarObstacles): (c_x, c_y, r^2, (1 - alpha) ((r + margin)^2 - r^2)) for
+// the problem's obstacles, the inert slot (0, 0, -1e30, 0) after them, n_slots
+// per problem.  Runs before every launch that reads them, so obstacles the caller
 // moves between launches are seen.  A problem whose obstacle count is out of
 // range gets inert slots only (the rollout kernels flag and skip it).
 // Grid: one workgroup per problem.
 static __global__ void k_pad_obs(const int32_t* __restrict__ obs_off, const float* __restrict__ obs, int obs_max,
-                          int n_slots, float4* __restrict__ out) {
+                          int n_slots, float alpha, float4* __restrict__ out) {
   const int b = blockIdx.x;
   const int o0 = obs_off ? obs_off[b] : 0, no = obs_off ? obs_off[b + 1] - o0 : 0;
   const bool ok = no >= 0 && no <= obs_max;
@@ -248,7 +248,7 @@ static __global__ void k_pad_obs(const int32_t* __restrict__ obs_off, const floa
     float4 v = make_float4(0.f, 0.f, -1e30f, 0.f);
     if (ok && i < no) {
       const float* o = obs + 4 * ((size_t)o0 + i);
-      v = make_float4(o[0], o[1], o[2], o[3] - o[2]);
+      v = make_float4(o[0], o[1], o[3], (1.f - alpha) * (o[2] - o[3]));
     }
     out[(size_t)b * n_slots + i] = v;
   }

@@ -597,7 +597,7 @@ static smppi_status plan_enqueue(smppi_plan p, hipStream_t s, bool profiled = fa
   }
   if (p->obs_pad && p->fa.n_tiles > 0) {
     hipLaunchKernelGGL(k_pad_obs, dim3(B), dim3(kMaxObs), 0, s, static_cast<const int32_t*>(p->track.obs_off),
-                       static_cast<const float*>(p->track.obs), p->fa.p.obs_max, kMaxObs, p->obs_pad);
+                       static_cast<const float*>(p->track.obs), p->fa.p.obs_max, kMaxObs, p->fa.C.alpha, p->obs_pad);
     if ((st = check_launch(ctx, "k_pad_obs"))) return st;
   }
   if (p->fa.n_tiles > 0) {

@@ -300,7 +300,7 @@ static smppi_status launch_rollout(smppi_ctx ctx, const smppi_batch* b, const Ro
     if (st) return st;
     float4* pad = static_cast<float4*>(ctx->scratch);
     hipLaunchKernelGGL(k_pad_obs, dim3(b->n_problems), dim3(64), 0, s, a.p.obs_off,
-                       reinterpret_cast<const float*>(a.p.obs), a.p.obs_max, NOBS, pad);
+                       reinterpret_cast<const float*>(a.p.obs), a.p.obs_max, NOBS, (float)a.C.alpha, pad);
     if ((st = check_launch(ctx, "k_pad_obs"))) return st;
     ra.obs_pad = pad;
   }
