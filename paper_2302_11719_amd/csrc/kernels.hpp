@@ -147,7 +147,9 @@ __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const Prob
 
 template <class R>
 __host__ __device__ inline size_t stage_lds_bytes(int poly_max, int t_max, int obs_max) {
-  return sizeof(R) * (5 * ((size_t)poly_max + 2 * SEG_PAD) + 2 * (size_t)t_max + 4 * (size_t)obs_max);
+  // rounded up to 16 bytes: LDS placed after the staged problem starts aligned
+  const size_t n = sizeof(R) * (5 * ((size_t)poly_max + 2 * SEG_PAD) + 2 * (size_t)t_max + 4 * (size_t)obs_max);
+  return (n + 15) & ~(size_t)15;
 }
 
 template <class R>
@@ -851,6 +853,9 @@ constexpr int REP_C = 8;  // steps per shield pipeline chunk
 // respect to (x, u) (6 x 8), the local barrier/cost gradients (8) and the
 // control gradient (2).
 constexpr int REP_PAR_PER_STEP = 48 + 8 + 2;
+// Per-step control constants of the shield's forward pass, one 16-byte aligned
+// row per step (delta, sin/m, cos/m, l_f cos/I_z, a_max tau, 3 unused).
+constexpr int REP_CTL = 8;
 
 // LDS of the shield beyond the staged problem: states x_0..x_T, segment
 // indices, the per-step control constants (5 per step) and two chunks of RK4
@@ -860,26 +865,26 @@ constexpr int REP_PAR_PER_STEP = 48 + 8 + 2;
 // values, four scalars per slot and a reduction buffer.
 template <class R>
 __host__ __device__ inline size_t repair_lds_bytes(int t_max, int memory, bool par_rev = false) {
-  size_t n = (size_t)(t_max + 1) * (6 * sizeof(R) + sizeof(int)) + (size_t)5 * t_max * sizeof(R) +
+  size_t n = (size_t)(t_max + 1) * (6 * sizeof(R) + sizeof(int)) + (size_t)REP_CTL * t_max * sizeof(R) +
              (size_t)2 * REP_C * 12 * sizeof(R);
   if (memory > 0) n += ((size_t)(4 + 2 * (memory + 1)) * 2 * t_max + 4 * (memory + 1) + 16) * sizeof(R);
   if (par_rev) n += (size_t)REP_PAR_PER_STEP * t_max * sizeof(R);
   return n;
 }
 
-// Algorithm 1 for one problem on one workgroup of two waves.  The nominal
+// Algorithm 1 for one problem on one workgroup of three waves.  The nominal
 // trajectory is short (T+1 states), so every state is kept in LDS and the
 // reverse sweep reads it back instead of recomputing it.  The forward pass is
-// pipelined over chunks of REP_C steps: lane 0 of wave 0 runs the RK4 chain
-// (chunk s), wave 1 follows one chunk behind with the lateral-offset window
-// (one segment per lane, the rule's first minimum picked by ballot) and the
-// obstacle barriers (one obstacle per lane), recording the segment indices and
-// the last transition whose objective term has a non-zero derivative.  The
-// reverse sweep (lane 0) starts at that transition (everything later has a
-// zero gradient, so those controls only get the box projection), and the
-// iteration stops as soon as no such transition is left: the gradient is then
-// exactly zero and every remaining step would be the identity after the
-// projection already applied.
+// pipelined over chunks of REP_C steps (wave 0: velocity part of the RK4
+// chain; wave 2: pose part; wave 1: the lateral-offset window, one segment per
+// lane with the rule's first minimum picked by ballot, and the obstacle
+// barriers, one obstacle per lane), recording the segment indices and the last
+// transition whose objective term has a non-zero derivative.  The reverse
+// sweep starts at that transition (everything later has a zero gradient, so
+// those controls only get the box projection), and the iteration stops as
+// soon as no such transition is left: the gradient is then exactly zero and
+// every remaining step would be the identity after the projection already
+// applied.
 constexpr int REP_BLK = 3 * WAVE;
 
 // Row-rotate of a value across the 16 lanes of each row (DPP row_ror:N).
@@ -895,6 +900,27 @@ __device__ __forceinline__ double row_ror(double v) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+// Minimum over the 16 lanes of each row (four DPP rotations).  FP32 values
+// here are squared distances (non-negative, or +inf): their bit patterns order
+// like unsigned integers, so the reduction runs on integers (no NaN
+// canonicalisation before each min) and the rotation can fold into the min.
+template <class R>
+__device__ __forceinline__ R row_min(R m) {
+  m = fmin(m, row_ror<8>(m));
+  m = fmin(m, row_ror<4>(m));
+  m = fmin(m, row_ror<2>(m));
+  return fmin(m, row_ror<1>(m));
+}
+template <>
+__device__ __forceinline__ float row_min<float>(float v) {
+  unsigned m = __float_as_uint(v);
+  m = min(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x128, 0xF, 0xF, false));
+  m = min(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x124, 0xF, 0xF, false));
+  m = min(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x122, 0xF, 0xF, false));
+  m = min(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x121, 0xF, 0xF, false));
+  return __uint_as_float(m);
+}
+
 // The window rule on the lanes of a row (half width <= 7; the whole wave must
 // be active and c, px, py uniform): lane r of each row holds the r-th offset of
 // the rule's order (0, -1, +1, -2, ...), the row minimum comes from four DPP
@@ -908,18 +934,16 @@ __device__ R row_window(const TrackView<R>& tr, int& c, R px, R py) {
     const int off = r == 0 ? 0 : ((r & 1) ? -((r + 1) >> 1) : (r >> 1));
     dd = seg_dist2(tr, c + off, px, py);  // padded copy: c + off needs no wrap to be read
   }
-  R m = dd;
-  m = fmin(m, row_ror<8>(m));
-  m = fmin(m, row_ror<4>(m));
-  m = fmin(m, row_ror<2>(m));
-  m = fmin(m, row_ror<1>(m));
+  const R m = row_min(dd);
   const unsigned long long bal = __ballot(dd == m) & 0xFFFFull;
-  const int rr = bal ? __ffsll((long long)bal) - 1 : 0;
-  const int off = rr == 0 ? 0 : ((rr & 1) ? -((rr + 1) >> 1) : (rr >> 1));
-  int i = c + off;
+  // slot rr (-1 if none) -> offset: (rr + 1) / 2 with the sign of an odd slot
+  // negative; branch-free scalar arithmetic (rr = -1 and rr = 0 give 0)
+  const int rr = __ffsll((long long)bal) - 1;
+  const int half = (rr + 1) >> 1, neg = -(rr & 1);
+  int i = __builtin_amdgcn_readfirstlane(c) + ((half ^ neg) - neg);
   i += (i < 0) ? tr.n : 0;
   i -= (i >= tr.n) ? tr.n : 0;
-  c = i;
+  c = __builtin_amdgcn_readfirstlane(i);
   return m;
 }
 
@@ -1178,16 +1202,19 @@ __device__ void lbfgs_step(const DevModel<R>& M, R* V, int T, const R* g, R* gpr
 template <class R, int NOBS>
 __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims& d, const TrackView<R>& tr, R* Vs,
                                unsigned char* lds, int* s_last) {
-  R* xs = reinterpret_cast<R*>(lds);
+  // 16-byte aligned rows first (lds is 16-byte aligned): ctl [t_max][REP_CTL],
+  // vst [2][REP_C][12] stage velocities; then states xs [t_max+1][6], segment
+  // indices is [t_max+1]
+  R* ctl = static_cast<R*>(__builtin_assume_aligned(reinterpret_cast<R*>(lds), 16));
+  R* vst = static_cast<R*>(__builtin_assume_aligned(ctl + REP_CTL * (size_t)a.p.t_max, 16));
+  R* xs = vst + 2 * REP_C * 12;
   int* is = reinterpret_cast<int*>(xs + 6 * (size_t)(a.p.t_max + 1));
-  R* ctl = reinterpret_cast<R*>(is + (a.p.t_max + 1));
-  R* vst = ctl + 5 * (size_t)a.p.t_max;  // [2][REP_C][12]
   // L-BFGS state (memory > 0): gradient, previous iterate and gradient, two-loop
   // vector, pairs in a ring of memory + 1 slots (kept pair i at (head + i) %
   // (memory + 1), i = 0 oldest; the next slot takes the candidate), per pair
   // rho = 1/s.y, alpha, s.y, y.y; reduction buffer
   const int tm2 = 2 * a.p.t_max, mem = a.memory;
-  R* gq = vst + 2 * REP_C * 12;
+  R* gq = reinterpret_cast<R*>(is + (a.p.t_max + 1));
   R* gprev = gq + tm2;
   R* vprev = gprev + tm2;
   R* qv = vprev + tm2;
@@ -1214,11 +1241,12 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
     for (int t = threadIdx.x; t < T; t += blockDim.x) {
       const StepCtl<R> sc =
           step_ctl(M, clamp_r(Vs[t], M.u_lo[0], M.u_hi[0]), clamp_r(Vs[T + t], M.u_lo[1], M.u_hi[1]));
-      ctl[t] = sc.delta;
-      ctl[T + t] = sc.sd_m;
-      ctl[2 * T + t] = sc.cd_m;
-      ctl[3 * T + t] = sc.lfcd_Iz;
-      ctl[4 * T + t] = sc.a_tau;
+      R* cr = ctl + REP_CTL * t;
+      cr[0] = sc.delta;
+      cr[1] = sc.sd_m;
+      cr[2] = sc.cd_m;
+      cr[3] = sc.lfcd_Iz;
+      cr[4] = sc.a_tau;
     }
     State<R> x = x0;
     int idx = idx0, last = -1;
@@ -1241,15 +1269,16 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
         R* gb = vst + (st & 1) * (REP_C * 12);
         for (int t = t0; t < t1; ++t) {
           StepCtl<R> sc;
-          sc.delta = ctl[t];
-          sc.sd_m = ctl[T + t];
-          sc.cd_m = ctl[2 * T + t];
-          sc.lfcd_Iz = ctl[3 * T + t];
-          sc.a_tau = ctl[4 * T + t];
+          const R* cr = static_cast<const R*>(__builtin_assume_aligned(ctl + REP_CTL * t, 16));
+          sc.delta = cr[0];
+          sc.sd_m = cr[1];
+          sc.cd_m = cr[2];
+          sc.lfcd_Iz = cr[3];
+          sc.a_tau = cr[4];
           sc.sd = sc.cd = R(0);  // used by the reverse sweep only
           VelStages<R> g;
           rk4_vel(M, sc, x.vx, x.vy, x.om, g);
-          R* gt = gb + 12 * (t - t0);
+          R* gt = static_cast<R*>(__builtin_assume_aligned(gb + 12 * (t - t0), 16));
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             gt[k] = g.vx[k];
@@ -1263,7 +1292,7 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
         const int t0 = (st - 1) * REP_C, t1 = min(T, t0 + REP_C);
         const R* gb = vst + ((st - 1) & 1) * (REP_C * 12);
         for (int t = t0; t < t1; ++t) {
-          const R* gt = gb + 12 * (t - t0);
+          const R* gt = static_cast<const R*>(__builtin_assume_aligned(gb + 12 * (t - t0), 16));
           VelStages<R> g;
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
