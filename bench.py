@@ -11,12 +11,14 @@ warm start in the workgroup that combined the problem.  value = rollout-steps/s 
 Also measured in the same run (reported beside the headline): the plain
 per-call form (rollout, weights, update, execute launches, no shield), the
 batched plan on B identical-shape problems vs the plain per-problem loop, the
-512-problem ragged batch, the K=65536/T=100/64-obstacle rollout, per-stage
-durations (HIP events), the dominant kernel's roofline, and the FP64 CPU oracle
-on a bounded sample of the headline workload.
+512-problem ragged batch, the K=65536/T=100/64-obstacle rollout, the stage
+split (the headline with the shield as a kernel of its own), the dominant
+kernel's roofline, and the FP64 CPU oracle on a bounded sample of the headline
+workload.
 
 usage: python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--skip-cpu] [--quick]
-                       [--forms plain,identical,ragged,large,c3,shield,autotune,sweep,curvilinear] [--copy-calibration-mib N]
+                       [--forms split,plain,identical,ragged,large,c3,shield,autotune,sweep,curvilinear]
+                       [--copy-calibration-mib N]
 """
 from __future__ import annotations
 
@@ -40,7 +42,7 @@ FLOP_UPDATE_STEP = 4      # w * eps' accumulated for two controls
 FLOP_STEP_CURV = 284      # curvilinear model: no window (-117), Frenet kinematics with curvature lookup (+56)
 PEAK_FP32 = 157.3e12      # MI355X FP32 vector peak (packed FMA on every lane)
 PEAK_HBM = 8.0e12
-FORMS = ("plain", "identical", "ragged", "large", "c3", "shield", "autotune", "sweep", "curvilinear")
+FORMS = ("split", "plain", "identical", "ragged", "large", "c3", "shield", "autotune", "sweep", "curvilinear")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_K4096_T50_hbm_traffic.md")
 
 
@@ -56,8 +58,10 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline only (same as --forms none)")
     ap.add_argument("--forms", default="all",
-                    help="comma list of the extra forms to run: plain, identical, ragged, large, c3, shield, "
-                         "autotune, sweep, curvilinear (or all/none)")
+                    help="comma list of the extra forms to run: split (the headline with the shield as a "
+                         "kernel of its own), plain, identical, ragged, large, c3, shield, autotune, sweep, "
+                         "curvilinear (or all/none); without split, every k_fused launch of the run is the "
+                         "headline kernel")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -143,31 +147,9 @@ def main():
         if i >= warm:
             kl.append(plan_f.kernel_ms()[0])
     plan_f.close()
-    # Stage split of the same work with the shield as a kernel of its own (HIP events
-    # between the stages; kernel-stamped events on the fused and shield kernels).
-    db_p = core.DeviceBatch([prob], dtype=torch.float32)
-    plan_p = core.Plan(ctx, db_p, M, C, seed, lam, repair=rep, execute=True, dist=dist, use_graph=False,
-                       fuse_shield=-1)
-    fused, repair_t, active, kf, kr = [], [], [], [], []
-    for i in range(warm + n_prof):
-        plan_p.launch_profiled()
-        f, r, _ = plan_p.stage_ms()
-        k1, k2 = plan_p.kernel_ms()
-        if i >= warm:
-            fused.append(f)
-            repair_t.append(r)
-            kf.append(k1)
-            kr.append(k2)
-            # the shield changed the MPPI output (some DCBF condition was violated)
-            active.append(not torch.equal(plan_p.V_safe, plan_p.V_plus))
-    plan_p.close()
-    act = np.array(active)
-    kr = np.array(kr)
-    stage = dict(launch_kernel_ms=float(np.mean(kl)),
-                 split_rollout_weights_update_kernel_ms=float(np.mean(kf)),
-                 split_shield_plant_kernel_ms=float(kr.mean()), shield_active_fraction=float(act.mean()),
-                 shield_kernel_ms_when_active=float(kr[act].mean()) if act.any() else None,
-                 shield_kernel_ms_when_idle=float(kr[~act].mean()) if (~act).any() else None)
+    stage = dict(launch_kernel_ms=float(np.mean(kl)))
+    if "split" in forms:
+        stage.update(stage_split(ctx, prob, M, C, seed, lam, rep, dist, warm, n_prof))
     _log(f"  stages: {stage}")
 
     # roofline of the one kernel: the rollouts and update (the shield's nominal pass,
@@ -205,6 +187,37 @@ def main():
         result["cpu_baseline"] = cpu_baseline(W, K, T, lam, rep)
     print(json.dumps(result), flush=True)
 
+
+
+def stage_split(ctx, prob, M, C, seed, lam, rep, dist, warm, n_prof):
+    """Stage split of the headline work with the shield as a kernel of its own
+    (kernel-stamped events on the fused and shield kernels)."""
+    import torch
+
+    from paper_2302_11719_amd import core
+
+    db_p = core.DeviceBatch([prob], dtype=torch.float32)
+    plan_p = core.Plan(ctx, db_p, M, C, seed, lam, repair=rep, execute=True, dist=dist, use_graph=False,
+                       fuse_shield=-1)
+    fused, repair_t, active, kf, kr = [], [], [], [], []
+    for i in range(warm + n_prof):
+        plan_p.launch_profiled()
+        f, r, _ = plan_p.stage_ms()
+        k1, k2 = plan_p.kernel_ms()
+        if i >= warm:
+            fused.append(f)
+            repair_t.append(r)
+            kf.append(k1)
+            kr.append(k2)
+            # the shield changed the MPPI output (some DCBF condition was violated)
+            active.append(not torch.equal(plan_p.V_safe, plan_p.V_plus))
+    plan_p.close()
+    act = np.array(active)
+    kr = np.array(kr)
+    return dict(split_rollout_weights_update_kernel_ms=float(np.mean(kf)),
+                split_shield_plant_kernel_ms=float(kr.mean()), shield_active_fraction=float(act.mean()),
+                shield_kernel_ms_when_active=float(kr[act].mean()) if act.any() else None,
+                shield_kernel_ms_when_idle=float(kr[~act].mean()) if (~act).any() else None)
 
 def _time(fn, n, warm, sync):
     for _ in range(warm):
