@@ -6,7 +6,8 @@ means, scales the HBM byte counters by a plain copy kernel of known size, and
 writes/reads the short text summaries kept beside the benchmark.
 
   python -m paper_2302_11719_amd.profile_summary traffic \\
-      --fetch DIR --write DIR --kernel k_fused --copy-bytes N --out FILE --command "..."
+      --fetch DIR --write DIR --kernel NAME [--kernel NAME ...] --copy-bytes N [--trace DIR] \\
+      --out FILE --command "..."
   python -m paper_2302_11719_amd.profile_summary counters --pmc DIR [DIR ...] --trace DIR \\
       --kernel NAME [--kernel NAME ...] --out FILE --command "..."
   python -m paper_2302_11719_amd.profile_summary stats --trace DIR --out FILE --command "..."
@@ -28,6 +29,8 @@ from collections import defaultdict
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 COPY_KERNELS = ("__amd_rocclr_copyBuffer", "copyBuffer")
+PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak (packed FMA); 78.6e12 without packing
+PEAK_HBM = 8.0e12
 
 
 def kernel_sources_digest() -> str:
@@ -112,14 +115,18 @@ def _copy_factor(counters, counter, copy_bytes):
     return None, None
 
 
-def traffic_summary(fetch_dir, write_dir, kernel, copy_bytes):
+def traffic_summary(fetch_dir, write_dir, kernel, copy_bytes, trace=None):
+    """Scaled HBM bytes per dispatch of the kernels matching `kernel` (a name or a
+    list of names); with a kernel trace, also the mean duration and GB/s."""
     fc, wc = read_counters(fetch_dir), read_counters(write_dir)
+    tr = read_trace(trace) if trace else {}
     ff, fcopy = _copy_factor(fc, "FETCH_SIZE", copy_bytes)
     wf, wcopy = _copy_factor(wc, "WRITE_SIZE", copy_bytes)
     out = {"digest": kernel_sources_digest(), "copy_bytes": copy_bytes,
            "copy_fetch_kib": fcopy, "copy_write_kib": wcopy, "fetch_factor": ff, "write_factor": wf,
            "kernels": {}}
-    names = sorted(set(_match(fc, kernel)) | set(_match(wc, kernel)))
+    pats = [kernel] if isinstance(kernel, str) else list(kernel)
+    names = sorted({k for pat in pats for k in set(_match(fc, pat)) | set(_match(wc, pat))})
     for k in names:
         fk = fc.get(k, {}).get("FETCH_SIZE", [])
         wk = wc.get(k, {}).get("WRITE_SIZE", [])
@@ -127,6 +134,35 @@ def traffic_summary(fetch_dir, write_dir, kernel, copy_bytes):
         wb = _mean(wk) * 1024.0 * (wf or float("nan"))
         out["kernels"][k] = {"dispatches": [len(fk), len(wk)], "fetch_kib": _mean(fk), "write_kib": _mean(wk),
                              "fetch_bytes": fb, "write_bytes": wb, "traffic_bytes": fb + wb}
+        if tr.get(k):
+            dur = _mean(tr[k])
+            out["kernels"][k]["duration_ns"] = dur
+            out["kernels"][k]["hbm_gbps"] = (fb + wb) / dur
+            out["kernels"][k]["frac_hbm_peak"] = (fb + wb) / dur / (PEAK_HBM / 1e9)
+    return out
+
+
+def derived(cs, simds=1024, xcds=8):
+    """Derived rates of one kernel's mean counters (keys as rocprofv3 names them):
+    FP32 FLOP from the VALU instruction mix (64 lanes per instruction, FMA = 2),
+    its rate against the vector peaks, and VALU issue utilisation (each wave64
+    VALU instruction holds its SIMD for 4 cycles; GRBM_GUI_ACTIVE counts cycles on
+    every XCD)."""
+    out = {}
+    dur = cs.get("duration_ns", float("nan"))
+    if "SQ_INSTS_VALU_FLOPS_FP32" in cs:
+        fl = 64.0 * cs["SQ_INSTS_VALU_FLOPS_FP32"]
+        out["fp32_flop_per_dispatch"] = fl
+        out["fp32_tflops"] = fl / dur / 1e3
+        out["frac_fp32_peak_packed"] = fl / dur / (PEAK_FP32 / 1e9)
+        out["frac_fp32_peak_unpacked"] = 2 * fl / dur / (PEAK_FP32 / 1e9)
+    if "GRBM_GUI_ACTIVE" in cs:
+        cyc = cs["GRBM_GUI_ACTIVE"] / xcds
+        out["gui_active_ghz"] = cyc / dur
+        if "SQ_INSTS_VALU" in cs:
+            out["valu_issue_util"] = 4.0 * cs["SQ_INSTS_VALU"] / (simds * cyc)
+        if "SQ_ACTIVE_INST_VALU" in cs:
+            out["active_inst_valu_util"] = 4.0 * cs["SQ_ACTIVE_INST_VALU"] / (simds * cyc)
     return out
 
 
@@ -167,15 +203,18 @@ def load_traffic(path, kernel_prefix):
 
 
 def _cmd_traffic(a):
-    s = traffic_summary(a.fetch, a.write, a.kernel, a.copy_bytes)
-    rows = [[k, v["dispatches"], f"{v['fetch_kib']:.1f}", f"{v['write_kib']:.1f}", f"{v['traffic_bytes']:.0f}"]
+    s = traffic_summary(a.fetch, a.write, a.kernel, a.copy_bytes, a.trace)
+    rows = [[k, v["dispatches"], f"{v['fetch_kib']:.1f}", f"{v['write_kib']:.1f}", f"{v['traffic_bytes']:.0f}",
+             f"{v['duration_ns']:.0f}" if "duration_ns" in v else "",
+             f"{v['hbm_gbps']:.2f} ({100 * v['frac_hbm_peak']:.3f} %)" if "hbm_gbps" in v else ""]
             for k, v in s["kernels"].items()]
     body = (f"Plain copy of {a.copy_bytes} bytes (read + write) reads FETCH_SIZE {s['copy_fetch_kib']} KiB and "
             f"WRITE_SIZE {s['copy_write_kib']} KiB; factors (known / counted) fetch {s['fetch_factor']}, "
-            f"write {s['write_factor']}.\n\n"
+            f"write {s['write_factor']}.  GB/s: scaled bytes / mean duration from the kernel trace "
+            f"(fraction of {PEAK_HBM / 1e12:.0f} TB/s).\n\n"
             + _md_table(["kernel", "dispatches (fetch, write run)", "FETCH_SIZE KiB/dispatch",
-                         "WRITE_SIZE KiB/dispatch", "scaled HBM bytes/dispatch"], rows))
-    write_md(a.out, a.title or f"HBM traffic of {a.kernel}", a.command, body, s)
+                         "WRITE_SIZE KiB/dispatch", "scaled HBM bytes/dispatch", "duration ns", "HBM GB/s"], rows))
+    write_md(a.out, a.title or f"HBM traffic of {', '.join(a.kernel)}", a.command, body, s)
 
 
 def _cmd_counters(a):
@@ -192,11 +231,21 @@ def _cmd_counters(a):
             cs = {c: _mean(v) for c, v in merged[k].items()}
             dur = _mean(tr.get(k, [])) if tr else float("nan")
             cs["duration_ns"] = dur
-            payload["kernels"][k] = cs
+            dv = derived(cs, a.simds, a.xcds)
+            payload["kernels"][k] = dict(cs, derived=dv)
             for c in sorted(cs):
                 rows.append([k, c, f"{cs[c]:.6g}"])
+            for c in sorted(dv):
+                rows.append([k, f"derived: {c}", f"{dv[c]:.4g}"])
+    note = ("Derived rows: fp32_flop = 64 x SQ_INSTS_VALU_FLOPS_FP32 (the ADD + MUL + TRANS + 2 FMA "
+            "instruction mix, 64 lanes each), fp32_tflops = that / duration, frac_fp32_peak_packed = of "
+            f"{PEAK_FP32 / 1e12} TFLOP/s, frac_fp32_peak_unpacked = of {PEAK_FP32 / 2e12} (packed FP32 is off in "
+            f"this build); cycles = GRBM_GUI_ACTIVE / {a.xcds} XCDs, gui_active_ghz = cycles / duration (the "
+            "clock for long kernels; a short kernel's count also covers its dispatch, so it reads high); "
+            f"valu_issue_util = 4 cycles x SQ_INSTS_VALU / ({a.simds} SIMDs x cycles), active_inst_valu_util "
+            "the same with SQ_ACTIVE_INST_VALU.\n\n")
     write_md(a.out, a.title or "Counters", a.command,
-             _md_table(["kernel", "counter (mean per dispatch)", "value"], rows), payload)
+             note + _md_table(["kernel", "counter (mean per dispatch)", "value"], rows), payload)
 
 
 def _cmd_stats(a):
@@ -216,12 +265,15 @@ def main(argv=None):
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
-    t.add_argument("--kernel", required=True)
+    t.add_argument("--kernel", action="append", required=True)
     t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--trace")
     c = sub.add_parser("counters")
     c.add_argument("--pmc", nargs="+", required=True)
     c.add_argument("--trace")
     c.add_argument("--kernel", action="append", required=True)
+    c.add_argument("--simds", type=int, default=1024)
+    c.add_argument("--xcds", type=int, default=8)
     s = sub.add_parser("stats")
     s.add_argument("--trace", required=True)
     s.add_argument("--top", type=int, default=20)

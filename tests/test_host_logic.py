@@ -56,6 +56,23 @@ def test_profile_summary_reads_counters_and_scales_traffic(tmp_path):
     assert ps.load_traffic(str(out), "k_fused")[0] is None
 
 
+def test_derived_counter_rates():
+    """FLOP from the instruction mix (64 lanes, FMA = 2), rates against the peaks, and
+    VALU issue utilisation from GRBM cycles summed over the XCDs."""
+    from paper_2302_11719_amd import profile_summary as ps
+    cs = {"SQ_INSTS_VALU_FLOPS_FP32": 1.0e6, "duration_ns": 1.0e4, "GRBM_GUI_ACTIVE": 8 * 2.0e4,
+          "SQ_INSTS_VALU": 2.56e6, "SQ_ACTIVE_INST_VALU": 5.12e6}
+    d = ps.derived(cs, simds=1024, xcds=8)
+    assert d["fp32_flop_per_dispatch"] == pytest.approx(6.4e7)
+    assert d["fp32_tflops"] == pytest.approx(6.4e7 / 1e-5 / 1e12)
+    assert d["frac_fp32_peak_packed"] == pytest.approx(6.4e12 / 157.3e12)
+    assert d["frac_fp32_peak_unpacked"] == pytest.approx(2 * 6.4e12 / 157.3e12)
+    assert d["gui_active_ghz"] == pytest.approx(2.0)
+    assert d["valu_issue_util"] == pytest.approx(4 * 2.56e6 / (1024 * 2.0e4))
+    assert d["active_inst_valu_util"] == pytest.approx(1.0)
+    assert ps.derived({"duration_ns": 1.0}) == {}
+
+
 def test_short_kernel_names():
     from paper_2302_11719_amd.profile_summary import short_name
 
