@@ -848,7 +848,7 @@ struct RepairArgs {
   ExecuteArgs<R> ex;
 };
 
-constexpr int REP_C = 8;  // steps per shield pipeline chunk
+constexpr int REP_C = 4;  // steps per shield pipeline chunk
 // Parallel reverse sweep: per step the transposed Jacobian of the RK4 step with
 // respect to (x, u) (6 x 8), the local barrier/cost gradients (8) and the
 // control gradient (2).

@@ -62,7 +62,7 @@ struct FusedArgs {
 // SIMDs is bound by each wave's per-step chain; splitting the step four ways
 // shortens it.  Same arithmetic as rollout_sample, summed in partial sums
 // (control terms, state terms of each half) instead of one.
-constexpr int PIPE_C = 8;
+constexpr int PIPE_C = 4;
 constexpr int PIPE_BLK = 4 * WAVE;
 
 struct PipeLds {
