@@ -524,11 +524,15 @@ struct ScalarObstacles {
   __device__ __forceinline__ void run(float px, float py, float alpha, float* c, float& pen, float& mo) const {
     static_assert(NOBS % OBS_GROUP == 0, "obstacle slots come in groups");
     constexpr int NG = NOBS / OBS_GROUP;
-    // The address passes through an empty asm statement tied to the step's
-    // position (and, per group, to the running sums) so that the loads stay
+    // The table address is made explicitly uniform (readfirstlane) and each
+    // group's address gets an opaque zero offset from an asm statement tied to
+    // the step's position (then to the running sums), so that the loads stay
     // inside the step loop, one group ahead of their use, instead of being
     // hoisted out of it (the whole table does not fit in SGPRs).
-    ConstF op = (ConstF)(uintptr_t)slots;
+    const uint64_t base = (uint64_t)(uintptr_t)slots;
+    const uint64_t ubase = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
+                           (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)base);
+    ConstF op = (ConstF)(uintptr_t)ubase;
     asm volatile("" : "+s"(op) : "v"(px), "v"(py));
     // alpha in a VGPR: the FMA c = alpha g + kappa then reads one scalar
     // operand (kappa), within the one-SGPR-per-instruction limit

@@ -62,6 +62,11 @@ __device__ __forceinline__ bool load_dims(const ProblemArgs<R>& a, int b, Proble
 // Stages problem b's polyline, obstacles and control sequence in LDS; returns
 // the track view.  LDS layout: seg [poly_max][4] | obs [obs_max][4] |
 // il2 [poly_max] | V [2][t_max].
+//
+// The staging is one memory round trip for the usual sizes: every thread
+// issues its loads (first V element, first obstacle word, up to STAGE_U
+// polyline rows) before the first LDS store.
+constexpr int STAGE_U = 4;
 template <class R>
 __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const ProblemDims& d, const R* __restrict__ Vg,
                                       unsigned char* smem, R** Vs_out) {
@@ -72,22 +77,59 @@ __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const Prob
   R* obs = seg + 4 * ns;
   R* il2 = obs + 4 * a.obs_max;
   R* Vs = il2 + ns;
-  if (d.np > 0)
-    for (int i = threadIdx.x; i < d.np + 2 * SEG_PAD; i += blockDim.x) {
-      const int src = ((i - SEG_PAD) % d.np + d.np) % d.np;
-      const R* s = a.poly + 5 * (size_t)(d.p0 + src);
-      seg[4 * i + 0] = s[0];
-      seg[4 * i + 1] = s[1];
-      seg[4 * i + 2] = s[2];
-      seg[4 * i + 3] = s[3];
-      il2[i] = s[4];
-    }
+  const int tid = threadIdx.x, nt = blockDim.x;
   // Obstacle slots beyond the problem's own count hold an inert barrier
   // (h = |p|^2 + 1e30 > 0 everywhere, never violated, never hit), so the
   // per-step loops run a fixed count without per-obstacle branches.
-  for (int i = threadIdx.x; i < 4 * a.obs_max; i += blockDim.x)
-    obs[i] = i < 4 * d.no ? a.obs[4 * (size_t)d.o0 + i] : ((i & 3) >= 2 ? R(-1e30) : R(0));
-  for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) Vs[i] = Vg[2 * (size_t)d.t0 + i];
+  auto obs_word = [&](int i) { return i < 4 * d.no ? a.obs[4 * (size_t)d.o0 + i] : ((i & 3) >= 2 ? R(-1e30) : R(0)); };
+  const R v_first = tid < 2 * d.T ? Vg[2 * (size_t)d.t0 + tid] : R(0);
+  const R o_first = tid < 4 * a.obs_max ? obs_word(tid) : R(0);
+  // Polyline rows (a_x, a_y, d_x, d_y, 1/|d|^2): the np rows in batches of
+  // STAGE_U per thread, and the 2 SEG_PAD wrapped copies on threads below
+  // 2 SEG_PAD, loaded beside the first batch.
+  const bool pad_t = d.np > 0 && tid < 2 * SEG_PAD;
+  const int pad_slot = tid < SEG_PAD ? tid : d.np + tid;  // slot in the padded copy
+  R prow[5];
+  if (pad_t) {
+    const int src = ((pad_slot - SEG_PAD) % d.np + d.np) % d.np;
+    const R* sp = a.poly + 5 * (size_t)(d.p0 + src);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) prow[c] = sp[c];
+  }
+  for (int r0 = 0; r0 < d.np; r0 += STAGE_U * nt) {
+    R row[STAGE_U][5];
+#pragma unroll
+    for (int u = 0; u < STAGE_U; ++u) {
+      const int k = r0 + u * nt + tid;
+      if (k < d.np) {
+        const R* sp = a.poly + 5 * (size_t)(d.p0 + k);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) row[u][c] = sp[c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < STAGE_U; ++u) {
+      const int k = r0 + u * nt + tid, i = k + SEG_PAD;
+      if (k < d.np) {
+        seg[4 * i + 0] = row[u][0];
+        seg[4 * i + 1] = row[u][1];
+        seg[4 * i + 2] = row[u][2];
+        seg[4 * i + 3] = row[u][3];
+        il2[i] = row[u][4];
+      }
+    }
+  }
+  if (pad_t) {
+    seg[4 * pad_slot + 0] = prow[0];
+    seg[4 * pad_slot + 1] = prow[1];
+    seg[4 * pad_slot + 2] = prow[2];
+    seg[4 * pad_slot + 3] = prow[3];
+    il2[pad_slot] = prow[4];
+  }
+  if (tid < 2 * d.T) Vs[tid] = v_first;
+  for (int i = tid + nt; i < 2 * d.T; i += nt) Vs[i] = Vg[2 * (size_t)d.t0 + i];
+  if (tid < 4 * a.obs_max) obs[tid] = o_first;
+  for (int i = tid + nt; i < 4 * a.obs_max; i += nt) obs[i] = obs_word(i);
   TrackView<R> tr;
   tr.n = d.np;
   tr.window = a.window;
@@ -111,7 +153,7 @@ __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const Prob
     const R px = a.x0[6 * (size_t)b], py = a.x0[6 * (size_t)b + 1];
     R bd = R(INFINITY);
     int bi = 0x7fffffff;
-    for (int i = threadIdx.x; i < d.np; i += blockDim.x) {
+    for (int i = tid; i < d.np; i += nt) {
       const R dd = seg_dist2(tr, i, px, py);
       if (dd < bd) {
         bd = dd;
@@ -127,14 +169,14 @@ __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const Prob
         bi = oi;
       }
     }
-    if (threadIdx.x % WAVE == 0) {
-      s_bd[threadIdx.x / WAVE] = bd;
-      s_bi[threadIdx.x / WAVE] = bi;
+    if (tid % WAVE == 0) {
+      s_bd[tid / WAVE] = bd;
+      s_bi[tid / WAVE] = bi;
     }
     __syncthreads();
     bd = s_bd[0];
     bi = s_bi[0];
-    for (int k = 1; k < (int)(blockDim.x / WAVE); ++k)
+    for (int k = 1; k < nt / WAVE; ++k)
       if (s_bd[k] < bd || (s_bd[k] == bd && s_bi[k] < bi)) {
         bd = s_bd[k];
         bi = s_bi[k];

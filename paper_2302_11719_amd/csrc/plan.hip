@@ -1,6 +1,7 @@
 // Batched plan: hundreds of independent MPPI problems of uneven K and T in one
-// persistent launch.  Workgroups pop (problem, sample-tile) items from a queue
-// ordered longest-horizon first; each tile runs its rollouts, reduces them to a
+// persistent launch.  Workgroups take (problem, sample-tile) items ordered
+// longest-horizon first (workgroup g starts with item g, then pops the rest
+// from a queue); each tile runs its rollouts, reduces them to a
 // split softmax partial (tile min cost, sum of weights, sum of squared weights,
 // weighted noise sums per step) and takes a ticket on its problem; the tile
 // that takes the last ticket combines the partials in tile order (streaming
@@ -271,11 +272,21 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
   float* Vs = nullptr;
   TrackView<float> tr;
   ProblemDims d;
+  // Workgroup g takes tile g first (no queue round trip before the first
+  // rollout; the grid never exceeds the tile count), then tiles gridDim.x + q
+  // for q popped from the queue.
+  bool first = true;
   for (;;) {
-    if (tid == 0) s_tile = (int)atomicAdd(a.queue, 1u);
-    __syncthreads();
-    const int tile = s_tile;
-    __syncthreads();
+    int tile;
+    if (first) {
+      tile = blockIdx.x;
+      first = false;
+    } else {
+      if (tid == 0) s_tile = (int)gridDim.x + (int)atomicAdd(a.queue, 1u);
+      __syncthreads();
+      tile = __builtin_amdgcn_readfirstlane(s_tile);
+      __syncthreads();
+    }
     if (tile >= a.n_tiles) break;
     const int2 tk = a.tiles[tile];
     const int b = __builtin_amdgcn_readfirstlane(tk.x);
