@@ -586,13 +586,43 @@ struct ScalarObstacles {
 };
 
 // ---------------------------------------------------------------- one sample
+// The model and cost constants are the same for every lane; a rollout keeps
+// them in VGPRs (an empty asm statement hides their uniformity), which leaves
+// the SGPRs to the addresses and loop state of the large fused kernels (whose
+// SGPR spills otherwise cost a readlane per reload inside the step loop) and
+// lifts the one-scalar-operand limit of a VALU instruction.
+template <class R>
+__device__ __forceinline__ void in_vgprs(R& x) {}
+template <>
+__device__ __forceinline__ void in_vgprs<float>(float& x) {
+  asm volatile("" : "+v"(x));
+}
+template <class R>
+__device__ __forceinline__ DevModel<R> model_in_vgprs(const DevModel<R>& M) {
+  DevModel<R> v = M;
+  in_vgprs(v.lf); in_vgprs(v.lr); in_vgprs(v.Cf); in_vgprs(v.Cr); in_vgprs(v.a_max); in_vgprs(v.c_v);
+  in_vgprs(v.v_min); in_vgprs(v.dt); in_vgprs(v.inv_m); in_vgprs(v.lr_Iz); in_vgprs(v.lf_Iz);
+  in_vgprs(v.u_lo[0]); in_vgprs(v.u_lo[1]); in_vgprs(v.u_hi[0]); in_vgprs(v.u_hi[1]);
+  return v;
+}
+template <class R>
+__device__ __forceinline__ DevCost<R> cost_in_vgprs(const DevCost<R>& C) {
+  DevCost<R> v = C;
+  in_vgprs(v.v_g); in_vgprs(v.q_v); in_vgprs(v.q_ey); in_vgprs(v.C_obs); in_vgprs(v.phi_w);
+  in_vgprs(v.ctrl_w[0]); in_vgprs(v.ctrl_w[1]); in_vgprs(v.sigma[0]); in_vgprs(v.sigma[1]);
+  in_vgprs(v.C_cbf); in_vgprs(v.alpha);
+  return v;
+}
+
 // Modified trajectory cost S~ of one sample (Algorithm 2 inner loop):
 //   S~ = sum_{t<T} [q(x_t) + lambda_u v_t^T Sigma^-1 u_t] + phi_w q(x_T) + sum_{t=0}^{T} C_cbf(z_t).
 // V is [2][T] (steer row, throttle row), read from LDS or global.  Obstacles
 // come from `os` (LdsObstacles or ScalarObstacles).
 template <class R, int NOBS, class OS>
-__device__ R rollout_sample(const DevModel<R>& M, const DevCost<R>& C, const TrackView<R>& tr, const State<R>& x0,
+__device__ R rollout_sample(const DevModel<R>& Mg, const DevCost<R>& Cg, const TrackView<R>& tr, const State<R>& x0,
                             const R* __restrict__ V, int T, NoiseStream<R>& ns, R* eps_out, const OS& os) {
+  const DevModel<R> M = model_in_vgprs(Mg);
+  const DevCost<R> C = cost_in_vgprs(Cg);
   State<R> x = x0;
   // the window around the global nearest segment of x0 returns that segment
   int idx = tr.idx0;
