@@ -1270,8 +1270,8 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
   R* wpar = mem > 0 ? red + 16 : gq;  // parallel reverse sweep: [t_max][REP_PAR_PER_STEP]
   int n_pairs = 0, head = 0;
   const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-  const DevModel<R>& M = a.M;
-  const DevCost<R>& C = a.C;
+  const DevModel<R> M = model_in_vgprs(a.M);
+  const DevCost<R> C = cost_in_vgprs(a.C);
   const DevObjective<R>& ob = a.ob;
   const bool cost_terms = ob.w_S != R(0);
   const int T = d.T, nch = (T + REP_C - 1) / REP_C;
