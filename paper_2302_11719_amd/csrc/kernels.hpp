@@ -476,9 +476,11 @@ struct NoiseSumLds {
 // noise (no cross-lane reduction); otherwise every lane keeps its own sample
 // and the per-step sums go through wave reductions.  Both orders are fixed.
 template <class R, int BLK, int SPT>
-__device__ void block_noise_sums(const DevModel<R>& M, const DevCost<R>& C, uint32_t seed, uint32_t pid, uint32_t it,
+__device__ void block_noise_sums(const DevModel<R>& Mg, const DevCost<R>& Cg, uint32_t seed, uint32_t pid, uint32_t it,
                                  bool nominal, const R* V, int T, const int (&ms)[SPT], const R (&ws)[SPT],
                                  NoiseSumLds<R, BLK, SPT>& L, R* P) {
+  const DevModel<R> M = model_in_vgprs(Mg);
+  const DevCost<R> C = cost_in_vgprs(Cg);
   constexpr int NW = BLK / WAVE;
   const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
   int n_live = 0;

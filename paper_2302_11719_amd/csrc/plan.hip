@@ -125,8 +125,8 @@ __device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, co
   constexpr int NH = NOBS > 0 ? (NOBS + 1) / 2 : 1;  // obstacles per half
   const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   const int T = d.T, nch = (T + PIPE_C - 1) / PIPE_C;
-  const DevModel<float>& M = a.M;
-  const DevCost<float>& C = a.C;
+  const DevModel<float> M = model_in_vgprs(a.M);
+  const DevCost<float> C = cost_in_vgprs(a.C);
   // wave 0
   NoiseStream<float> ns;
   ns.seed = a.p.seed;
