@@ -54,6 +54,11 @@ __device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
 __device__ __forceinline__ float exp_r(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
 __device__ __forceinline__ double exp_r(double x) { return exp(x); }
 template <class R> __device__ __forceinline__ R clamp_r(R x, R lo, R hi) { return fmin(fmax(x, lo), hi); }
+// Fused multiply-add written out: the model's arithmetic below pairs every
+// product with its sum explicitly, so the compiler has no contraction choices
+// left and every kernel that integrates the model rounds it the same way.
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
 // single v_med3_f32 (lo <= hi)
 template <> __device__ __forceinline__ float clamp_r<float>(float x, float lo, float hi) {
   return __builtin_amdgcn_fmed3f(x, lo, hi);
@@ -171,19 +176,19 @@ __device__ __forceinline__ void vel_deriv(const DevModel<R>& M, const StepCtl<R>
                                           R& dvy, R& dom) {
   const R vt = fmax(vx, M.v_min);
   const R inv = rcp_r(vt);
-  const R Ff = M.Cf * (c.delta - (vy + M.lf * om) * inv);
-  const R Fr = M.Cr * ((M.lr * om - vy) * inv);
-  dvx = c.a_tau - M.c_v * vx - Ff * c.sd_m + vy * om;
-  dvy = Ff * c.cd_m + Fr * M.inv_m - vx * om;
-  dom = Ff * c.lfcd_Iz - Fr * M.lr_Iz;
+  const R Ff = M.Cf * fma_r(-fma_r(M.lf, om, vy), inv, c.delta);  // C_f (delta - (v_y + l_f om) / v)
+  const R Fr = M.Cr * (fma_r(M.lr, om, -vy) * inv);               // C_r (l_r om - v_y) / v
+  dvx = fma_r(vy, om, fma_r(-Ff, c.sd_m, fma_r(-M.c_v, vx, c.a_tau)));
+  dvy = fma_r(-vx, om, fma_r(Ff, c.cd_m, Fr * M.inv_m));
+  dom = fma_r(Ff, c.lfcd_Iz, -(Fr * M.lr_Iz));
 }
 
 template <class R>
 __device__ __forceinline__ void pose_deriv(R psi, R vx, R vy, R& dpx, R& dpy) {
   R sp, cp;
   sincos_r(psi, &sp, &cp);
-  dpx = vx * cp - vy * sp;
-  dpy = vx * sp + vy * cp;
+  dpx = fma_r(vx, cp, -(vy * sp));
+  dpy = fma_r(vx, sp, vy * cp);
 }
 
 template <class R>
@@ -215,21 +220,21 @@ __device__ __forceinline__ void rk4_vel(const DevModel<R>& M, const StepCtl<R>& 
   g.vy[0] = vy;
   g.om[0] = om;
   vel_deriv(M, c, vx, vy, om, a3, a4, a5);
-  g.vx[1] = vx + h2 * a3;
-  g.vy[1] = vy + h2 * a4;
-  g.om[1] = om + h2 * a5;
+  g.vx[1] = fma_r(h2, a3, vx);
+  g.vy[1] = fma_r(h2, a4, vy);
+  g.om[1] = fma_r(h2, a5, om);
   vel_deriv(M, c, g.vx[1], g.vy[1], g.om[1], b3, b4, b5);
-  g.vx[2] = vx + h2 * b3;
-  g.vy[2] = vy + h2 * b4;
-  g.om[2] = om + h2 * b5;
+  g.vx[2] = fma_r(h2, b3, vx);
+  g.vy[2] = fma_r(h2, b4, vy);
+  g.om[2] = fma_r(h2, b5, om);
   vel_deriv(M, c, g.vx[2], g.vy[2], g.om[2], c3, c4, c5);
-  g.vx[3] = vx + h * c3;
-  g.vy[3] = vy + h * c4;
-  g.om[3] = om + h * c5;
+  g.vx[3] = fma_r(h, c3, vx);
+  g.vy[3] = fma_r(h, c4, vy);
+  g.om[3] = fma_r(h, c5, om);
   vel_deriv(M, c, g.vx[3], g.vy[3], g.om[3], d3, d4, d5);
-  vx += h6 * (a3 + R(2) * (b3 + c3) + d3);
-  vy += h6 * (a4 + R(2) * (b4 + c4) + d4);
-  om += h6 * (a5 + R(2) * (b5 + c5) + d5);
+  vx = fma_r(h6, fma_r(R(2), b3 + c3, a3) + d3, vx);
+  vy = fma_r(h6, fma_r(R(2), b4 + c4, a4) + d4, vy);
+  om = fma_r(h6, fma_r(R(2), b5 + c5, a5) + d5, om);
 }
 
 // Pose part of the same step from the stage velocities.
@@ -238,12 +243,12 @@ __device__ __forceinline__ void rk4_pose(const DevModel<R>& M, const VelStages<R
   const R h = M.dt, h2 = R(0.5) * M.dt, h6 = M.dt * R(1.0 / 6.0);
   R a0, a1, b0, b1, c0, c1, d0, d1;
   pose_deriv(psi, g.vx[0], g.vy[0], a0, a1);
-  pose_deriv(psi + h2 * g.om[0], g.vx[1], g.vy[1], b0, b1);
-  pose_deriv(psi + h2 * g.om[1], g.vx[2], g.vy[2], c0, c1);
-  pose_deriv(psi + h * g.om[2], g.vx[3], g.vy[3], d0, d1);
-  px += h6 * (a0 + R(2) * (b0 + c0) + d0);
-  py += h6 * (a1 + R(2) * (b1 + c1) + d1);
-  psi += h6 * (g.om[0] + R(2) * (g.om[1] + g.om[2]) + g.om[3]);
+  pose_deriv(fma_r(h2, g.om[0], psi), g.vx[1], g.vy[1], b0, b1);
+  pose_deriv(fma_r(h2, g.om[1], psi), g.vx[2], g.vy[2], c0, c1);
+  pose_deriv(fma_r(h, g.om[2], psi), g.vx[3], g.vy[3], d0, d1);
+  px = fma_r(h6, fma_r(R(2), b0 + c0, a0) + d0, px);
+  py = fma_r(h6, fma_r(R(2), b1 + c1, a1) + d1, py);
+  psi = fma_r(h6, fma_r(R(2), g.om[1] + g.om[2], g.om[0]) + g.om[3], psi);
 }
 
 // Classic RK4 over dt with the control held.
