@@ -626,8 +626,16 @@ __device__ __forceinline__ DevCost<R> cost_in_vgprs(const DevCost<R>& C) {
 template <class R, int NOBS, class OS>
 __device__ R rollout_sample(const DevModel<R>& Mg, const DevCost<R>& Cg, const TrackView<R>& tr, const State<R>& x0,
                             const R* __restrict__ V, int T, NoiseStream<R>& ns, R* eps_out, const OS& os) {
-  const DevModel<R> M = model_in_vgprs(Mg);
-  const DevCost<R> C = cost_in_vgprs(Cg);
+  // (with obstacles: the kernels run one wave per SIMD, so the VGPRs are free;
+  // without, the copies would cost occupancy)
+  DevModel<R> Mv;
+  DevCost<R> Cv;
+  if constexpr (NOBS > 0) {
+    Mv = model_in_vgprs(Mg);
+    Cv = cost_in_vgprs(Cg);
+  }
+  const DevModel<R>& M = NOBS > 0 ? Mv : Mg;
+  const DevCost<R>& C = NOBS > 0 ? Cv : Cg;
   State<R> x = x0;
   // the window around the global nearest segment of x0 returns that segment
   int idx = tr.idx0;

@@ -475,12 +475,20 @@ struct NoiseSumLds {
 // remain, each thread owns a time step and regenerates only the live samples'
 // noise (no cross-lane reduction); otherwise every lane keeps its own sample
 // and the per-step sums go through wave reductions.  Both orders are fixed.
-template <class R, int BLK, int SPT>
+template <class R, int BLK, int SPT, bool VG = false>
 __device__ void block_noise_sums(const DevModel<R>& Mg, const DevCost<R>& Cg, uint32_t seed, uint32_t pid, uint32_t it,
                                  bool nominal, const R* V, int T, const int (&ms)[SPT], const R (&ws)[SPT],
                                  NoiseSumLds<R, BLK, SPT>& L, R* P) {
-  const DevModel<R> M = model_in_vgprs(Mg);
-  const DevCost<R> C = cost_in_vgprs(Cg);
+  // VG: model and cost constants in VGPRs (for kernels whose occupancy does
+  // not depend on the VGPR count)
+  DevModel<R> Mv;
+  DevCost<R> Cv;
+  if constexpr (VG) {
+    Mv = model_in_vgprs(Mg);
+    Cv = cost_in_vgprs(Cg);
+  }
+  const DevModel<R>& M = VG ? Mv : Mg;
+  const DevCost<R>& C = VG ? Cv : Cg;
   constexpr int NW = BLK / WAVE;
   const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
   int n_live = 0;
@@ -1227,8 +1235,10 @@ __device__ void lbfgs_step(const DevModel<R>& M, R* V, int T, const R* g, R* gpr
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     vprev[i] = V[i];
     gprev[i] = g[i];
-    const int c = i < T ? 0 : 1;
-    V[i] = clamp_r(V[i] - q[i], M.u_lo[c], M.u_hi[c]);
+    // bounds selected, not indexed (a dynamic index into a local copy of the
+    // model would put it in scratch memory)
+    const bool thr = i >= T;
+    V[i] = clamp_r(V[i] - q[i], thr ? M.u_lo[1] : M.u_lo[0], thr ? M.u_hi[1] : M.u_hi[0]);
   }
   __syncthreads();
 }
@@ -1243,7 +1253,9 @@ __device__ void lbfgs_step(const DevModel<R>& M, R* V, int T, const R* g, R* gpr
 // window (one segment per lane), the obstacles (one per lane) and the barrier
 // activity.  The reverse sweep starts at the last active transition, and the
 // iteration loop stops when no transition is active (zero gradient).
-template <class R, int NOBS>
+// VG: model and cost constants in VGPRs (kernels whose occupancy does not
+// depend on the VGPR count: the shield kernel, the latency-mode fused kernel).
+template <class R, int NOBS, bool VG = true>
 __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims& d, const TrackView<R>& tr, R* Vs,
                                unsigned char* lds, int* s_last) {
   // 16-byte aligned rows first (lds is 16-byte aligned): ctl [t_max][REP_CTL],
@@ -1272,8 +1284,14 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
   R* wpar = mem > 0 ? red + 16 : gq;  // parallel reverse sweep: [t_max][REP_PAR_PER_STEP]
   int n_pairs = 0, head = 0;
   const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-  const DevModel<R> M = model_in_vgprs(a.M);
-  const DevCost<R> C = cost_in_vgprs(a.C);
+  DevModel<R> Mv;
+  DevCost<R> Cv;
+  if constexpr (VG) {
+    Mv = model_in_vgprs(a.M);
+    Cv = cost_in_vgprs(a.C);
+  }
+  const DevModel<R>& M = VG ? Mv : a.M;  // without VG: the arguments themselves, no copy
+  const DevCost<R>& C = VG ? Cv : a.C;
   const DevObjective<R>& ob = a.ob;
   const bool cost_terms = ob.w_S != R(0);
   const int T = d.T, nch = (T + REP_C - 1) / REP_C;

@@ -347,7 +347,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
     }
     block_sum3(z, q, nf, red);
     float* P = a.part + (size_t)(a.tile_off[b] + kb) * pstride;
-    block_noise_sums<float, BLK, SPT>(a.M, a.C, a.p.seed, pid, it, a.p.nominal != 0, Vs, d.T, ms, om, L,
+    block_noise_sums<float, BLK, SPT, PIPE>(a.M, a.C, a.p.seed, pid, it, a.p.nominal != 0, Vs, d.T, ms, om, L,
                                       P + PART_HDR);
     if (tid == 0) {
       P[0] = mn;
@@ -495,7 +495,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
         if (a.repair) {
           __syncthreads();
           unsigned char* rl = smem + stage_lds_bytes<float>(a.p.poly_max, a.p.t_max, a.p.obs_max);
-          repair_problem<float, NOBS>(a.rep, b, d, tr, Vs, rl, &s_last);
+          repair_problem<float, NOBS, PIPE>(a.rep, b, d, tr, Vs, rl, &s_last);
           float* out = a.rep.V_safe + 2 * (size_t)d.t0;
           for (int i = tid; i < 2 * d.T; i += BLK) out[i] = Vs[i];
           if (a.rep.exec) execute_problem(a.rep.ex, b, d.t0, d.T, Vs, reinterpret_cast<float*>(rl));
