@@ -258,7 +258,10 @@ __device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, co
   return P.part[0][lane] + P.part[1][lane];
 }
 
-template <int NOBS, int BLK, int SPT, bool PIPE>
+// FUSE: the shield (and execute) code is compiled in (plans that run the shield
+// inside the launch); without it the kernel needs far fewer registers, which
+// raises the occupancy of plans without the shield.
+template <int NOBS, int BLK, int SPT, bool PIPE, bool FUSE>
 __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float red[3 * (BLK / WAVE)];
@@ -491,7 +494,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
         a.stats[4 * b + 3] = NF;
         a.tickets[b] = 0u;
       }
-      if constexpr (BLK >= 3 * WAVE) {
+      if constexpr (FUSE && BLK >= 3 * WAVE) {
         if (a.repair) {
           __syncthreads();
           unsigned char* rl = smem + stage_lds_bytes<float>(a.p.poly_max, a.p.t_max, a.p.obs_max);
@@ -531,16 +534,26 @@ __global__ void k_copy_empty(const int64_t* k_off, const int32_t* t_off, const f
 
 using FusedFn = void (*)(FusedArgs);
 
+// Tile-mode kernel for (block, samples per thread); with fuse, the variant with
+// the shield compiled in (blocks of at least three waves only).
 template <int NOBS>
-FusedFn pick_fused(int blk, int spt) {
+FusedFn pick_fused(int blk, int spt, bool fuse) {
 #define SMPPI_CASE(BL, SP) \
-  if (blk == BL && spt == SP) return k_fused<NOBS, BL, SP, false>;
+  if (blk == BL && spt == SP) return k_fused<NOBS, BL, SP, false, false>;
+#define SMPPI_CASE_F(BL, SP) \
+  if (blk == BL && spt == SP) return fuse ? k_fused<NOBS, BL, SP, false, true> : k_fused<NOBS, BL, SP, false, false>;
   SMPPI_CASE(64, 1) SMPPI_CASE(64, 2) SMPPI_CASE(64, 4)
   SMPPI_CASE(128, 1) SMPPI_CASE(128, 2) SMPPI_CASE(128, 4)
-  SMPPI_CASE(256, 1) SMPPI_CASE(256, 2) SMPPI_CASE(256, 4)
-  SMPPI_CASE(512, 1) SMPPI_CASE(512, 2)
+  SMPPI_CASE_F(256, 1) SMPPI_CASE_F(256, 2) SMPPI_CASE_F(256, 4)
+  SMPPI_CASE_F(512, 1) SMPPI_CASE_F(512, 2)
 #undef SMPPI_CASE
+#undef SMPPI_CASE_F
   return nullptr;
+}
+
+template <int NOBS>
+FusedFn pick_pipe(bool fuse) {
+  return fuse ? k_fused<NOBS, PIPE_BLK, 1, true, true> : k_fused<NOBS, PIPE_BLK, 1, true, false>;
 }
 
 }  // namespace
@@ -708,9 +721,14 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   if (!pipe && tile % block != 0)
     return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "tile must be a multiple of block");
   const int spt = tile / block;
-  FusedFn fn = pipe ? (track->obs_max > 0 ? (FusedFn)k_fused<kMaxObs, PIPE_BLK, 1, true>
-                                          : (FusedFn)k_fused<0, PIPE_BLK, 1, true>)
-                    : (track->obs_max > 0 ? pick_fused<kMaxObs>(block, spt) : pick_fused<0>(block, spt));
+  // the shield inside the launch when asked for and the workgroup has three waves
+  // (the LDS check below may still turn it off)
+  const bool want_fuse = opts->repair && opts->fuse_shield == 0 && block >= 3 * WAVE;
+  auto pick = [&](bool fuse) -> FusedFn {
+    if (pipe) return track->obs_max > 0 ? pick_pipe<kMaxObs>(fuse) : pick_pipe<0>(fuse);
+    return track->obs_max > 0 ? pick_fused<kMaxObs>(block, spt, fuse) : pick_fused<0>(block, spt, fuse);
+  };
+  FusedFn fn = pick(false);
   if (!fn) return fail(ctx, SMPPI_ERR_UNSUPPORTED, "no fused kernel for block %d, tile %d", block, tile);
   std::vector<int32_t> ntile(B), tile_off(B + 1, 0);
   bool any_empty = false;
@@ -790,17 +808,30 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   hipFuncAttributes fattr{};
   if ((e = hipFuncGetAttributes(&fattr, reinterpret_cast<const void*>(fn))) != hipSuccess)
     return bail(hip_fail(ctx, e, "hipFuncGetAttributes"));
-  const size_t lds_static = fattr.sharedSizeBytes;
-  if (lds_static + p->lds > (size_t)ctx->max_lds)
+  if (fattr.sharedSizeBytes + p->lds > (size_t)ctx->max_lds)
     return bail(fail(ctx, SMPPI_ERR_SHAPE, "fused kernel needs %zu B of LDS per workgroup (device max %d)",
-                     lds_static + p->lds, ctx->max_lds));
+                     fattr.sharedSizeBytes + p->lds, ctx->max_lds));
   // The shield (and execute) inside the fused launch: the workgroup that
   // combines a problem runs Algorithm 1 on it right away.
   a.repair = 0;
   a.rep = RepairArgs<float>{};
   const int mem = opts->repair_opts.method == 1 ? opts->repair_opts.memory : 0;
-  if (opts->repair && opts->fuse_shield == 0 && block >= 3 * WAVE &&
-      lds_static + p->lds + repair_lds_bytes<float>(batch->t_max, mem) <= (size_t)ctx->max_lds) {
+  size_t lds_static = fattr.sharedSizeBytes;
+  bool fuse = false;
+  if (want_fuse) {
+    // the variant with the shield compiled in, when its LDS fits
+    const FusedFn fn_f = pick(true);
+    hipFuncAttributes fa2{};
+    if ((e = hipFuncGetAttributes(&fa2, reinterpret_cast<const void*>(fn_f))) != hipSuccess)
+      return bail(hip_fail(ctx, e, "hipFuncGetAttributes"));
+    if (fa2.sharedSizeBytes + p->lds + repair_lds_bytes<float>(batch->t_max, mem) <= (size_t)ctx->max_lds) {
+      fn = fn_f;
+      p->fn = fn;
+      lds_static = fa2.sharedSizeBytes;
+      fuse = true;
+    }
+  }
+  if (fuse) {
     const ExecFuse ef{opts->dist, opts->n_dist, bufs->x0, bufs->V, bufs->iter};
     a.repair = 1;
     a.rep = repair_args<float>(ctx, &p->batch, model, cost, &p->track, bufs->x0, bufs->V_plus, &opts->repair_opts,
