@@ -272,3 +272,41 @@ def test_autotune_picks_a_timed_candidate_and_caches(tmp_path):
     torch.cuda.synchronize()
     assert torch.equal(tp.S, ref.S)
     assert ctx().device_errors() == 0
+
+
+def test_obstacles_moved_between_launches():
+    """FP32 rollouts read the obstacles through padded slots written at every launch:
+    obstacles moved in place between two launches are seen by the plain rollout and by
+    the plan (both against the oracle with the moved obstacles)."""
+    probs = prep(ragged_problems(), F32)
+    M, C = params(F32)
+    db = core.DeviceBatch(probs, dtype=F32)
+    plan = core.Plan(ctx(), db, M, C, 5, W.LAMBDA, use_graph=True, pipeline=-1)
+    b_obs = [b for b, p in enumerate(probs) if len(p.track.obs)]
+    assert b_obs
+    for move in range(2):
+        say(f"moved obstacles, launch {move}")
+        S = core.rollout(ctx(), db, M, C, 5)
+        plan.launch()
+        torch.cuda.synchronize()
+        assert ctx().device_errors() == 0
+        Ss, Sp = db.per_problem(S), db.per_problem(plan.S)
+        for b in b_obs:
+            r = oracle_iteration(probs[b], M, C, 5, W.LAMBDA)
+            ok = r["margin"] > BAND
+            assert ok.sum() > 0
+            assert rel_err(Ss[b], r["S"])[ok].max() <= 1e-4, (move, b)
+            assert rel_err(Sp[b], r["S"])[ok].max() <= 1e-4, (move, b)
+        if move == 0:
+            # move every obstacle of those problems onto the start point's neighbourhood
+            # (changes the costs), in place on the device and in the oracle's copy
+            S_before = Ss
+            for b in b_obs:
+                o = probs[b].track.obs.copy()
+                o[:, 0] = probs[b].x0[0] + 0.5 + 0.1 * np.arange(len(o))
+                o[:, 1] = probs[b].x0[1] - 0.2
+                probs[b].track.obs = o.astype(np.float32).astype(np.float64)
+            new = np.concatenate([p.track.obs.reshape(-1, 4) for p in probs if len(p.track.obs)]).ravel()
+            db.obs.copy_(torch.as_tensor(new, dtype=F32, device="cuda"))
+    assert any(np.abs(Ss[b] - S_before[b]).max() > 0 for b in b_obs)
+    plan.close()
