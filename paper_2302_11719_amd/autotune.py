@@ -1,6 +1,6 @@
 """Launch-geometry autotuner for the batched plan.
 
-The fused kernel of a plan has four knobs: the three-wave latency mode
+The fused kernel of a plan has four knobs: the four-wave latency mode
 (``pipeline``), the workgroup size (``block``: 64, 128, 256, 512), the samples
 per tile (``tile`` = block x samples-per-thread, 1, 2 or 4) and the number of
 persistent workgroups (``grid``; 0 = the occupancy limit).  Which is fastest

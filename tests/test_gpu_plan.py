@@ -27,7 +27,7 @@ def _plain(db, M, C, seed, lam):
 @pytest.mark.parametrize("block,tile,pipeline", [(256, 256, -1), (64, 128, -1), (128, 512, -1), (512, 512, -1),
                                                  (0, 0, 1)])
 def test_plan_matches_plain_path(block, tile, pipeline):
-    """Plan (fused persistent kernel; pipeline = 1 is the three-wave latency mode) against
+    """Plan (fused persistent kernel; pipeline = 1 is the four-wave latency mode) against
     the plain per-call kernels and the oracle.  Costs agree to 1e-5 relative with the plain
     rollout: the same arithmetic, summed in a different order in the latency mode."""
     probs = prep(ragged_problems(), F32)
