@@ -126,7 +126,7 @@ typedef struct {
   int32_t obs_max;          /* host: max O_b (<= 64) */
 } smppi_track;
 
-/* Per-problem curvature table of the curvilinear model (Sec. V-A: the vehicle
+/* Per-problem curvature table of the curvilinear model (Sec. VI-A: the vehicle
  * state is expressed along the track as progress s, lateral error e_y and
  * heading error e_psi, so the track barrier h = w^2 - e_y^2 of eq. (23) needs no
  * projection).  kappa(s) is periodic: table entry j at s = j*ds, linear in

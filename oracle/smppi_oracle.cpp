@@ -386,7 +386,7 @@ R rollout_one(const Model& M, const Cost& C, const Track& tr, const double x0[6]
 }
 
 // ---------------------------------------------------------------------------
-// Curvilinear (Frenet-frame) variant of the model (Sec. V-A: the paper's
+// Curvilinear (Frenet-frame) variant of the model (Sec. VI-A: the paper's
 // vehicle states include the progress s, lateral error e_y and heading error
 // e_psi along the track, so the track barrier of eq. (23) needs no projection).
 // x = (s, e_y, e_psi, v_x, v_y, omega); the velocity dynamics are the ones

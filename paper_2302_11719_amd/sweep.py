@@ -1,4 +1,4 @@
-"""Closed-loop collision sweep: the paper's second experiment (Sec. V, the
+"""Closed-loop collision sweep: the paper's second experiment (Sec. VI-E, the
 collision-rate comparison over sample count and horizon of Figs. 5 and 6) made
 device-resident and batched, on generated tracks.
 
