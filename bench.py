@@ -44,6 +44,14 @@ PEAK_FP32 = 157.3e12      # MI355X FP32 vector peak (packed FMA on every lane)
 PEAK_HBM = 8.0e12
 FORMS = ("split", "plain", "identical", "ragged", "large", "c3", "shield", "autotune", "sweep", "curvilinear")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_K4096_T50_hbm_traffic.md")
+# The paper's own control rates (Sec. VI-G, the vehicle experiment and its results table):
+# context only, other vehicle model, horizon, precision and hardware.
+PAPER_RATES = [
+    {"controller": "MPPI(a)", "samples": 10000, "rate_hz": 150, "hardware": "NVIDIA GTX 1080 Ti"},
+    {"controller": "Shield-MPPI(a)", "samples": 10000, "rate_hz": 55, "hardware": "NVIDIA GTX 1080 Ti"},
+    {"controller": "MPPI(b)", "samples": 20, "rate_hz": 235, "hardware": "Intel Skylake quad-core i7"},
+    {"controller": "Shield-MPPI(b)", "samples": 20, "rate_hz": 220, "hardware": "Intel Skylake quad-core i7"},
+]
 
 
 def _log(msg):
@@ -179,6 +187,9 @@ def main():
                    "K": K, "T": T, "problems": 1, "repair_steps": 10, "parallelism": "single-gpu"},
         "stages_ms": stage,
         "roofline": roofline,
+        "paper_context": {"note": "the paper's reported control rates on its vehicle's hardware (context only; "
+                                  "other model, horizon and hardware)", "rates": PAPER_RATES,
+                          "this_run_rate_hz": 1e3 / ms_per_step, "this_run_samples": K},
     }
 
     if forms:
