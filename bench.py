@@ -308,7 +308,7 @@ def _form_identical(ctx, core, W, M, C, lam, rep, K, T, sync, out, seed):
         t_plain = _time(loop, n_it, 1, sync)
         dbB = core.DeviceBatch(probs, dtype=torch.float32)
         plB = core.Plan(ctx, dbB, M, C, seed, lam, repair=rep, use_graph=True)
-        t_b = _time(plB.launch, n_it, 2, sync)
+        t_b = _time(plB.launch, 20, 3, sync)  # the batched launch is cheap: more repetitions
         out[f"identical_B{B}"] = {"plain_loop_ms": t_plain * 1e3, "batched_adjoint_ms": t_b * 1e3,
                                   "plain_rollout_steps_per_s": B * K * T / t_plain,
                                   "batched_rollout_steps_per_s": B * K * T / t_b, "speedup": t_plain / t_b}
@@ -325,7 +325,7 @@ def _form_ragged(ctx, core, W, M, C, lam, sync, out, seed):
     steps_total = sum(p.K * p.T for p in probs)
     dbR = core.DeviceBatch(probs, dtype=torch.float32)
     plR = core.Plan(ctx, dbR, M, C, seed, lam, use_graph=True)
-    t_r = _time(plR.launch, 5, 2, sync)
+    t_r = _time(plR.launch, 20, 3, sync)
     dbs = [core.DeviceBatch([p], dtype=torch.float32, pid_base=b) for b, p in enumerate(probs)]
 
     def loopR():
