@@ -64,8 +64,8 @@ __device__ __forceinline__ bool load_dims(const ProblemArgs<R>& a, int b, Proble
 // il2 [poly_max] | V [2][t_max].
 //
 // The staging is one memory round trip for the usual sizes: every thread
-// issues its loads (first V element, first obstacle word, up to STAGE_U
-// polyline rows) before the first LDS store.
+// issues its loads (start position, first V element, first obstacle word, up to
+// STAGE_U polyline rows) before the first LDS store.
 constexpr int STAGE_U = 4;
 template <class R>
 __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const ProblemDims& d, const R* __restrict__ Vg,
@@ -78,6 +78,8 @@ __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const Prob
   R* il2 = obs + 4 * a.obs_max;
   R* Vs = il2 + ns;
   const int tid = threadIdx.x, nt = blockDim.x;
+  // start position (for the nearest segment below), loaded with the rest
+  const R px = a.x0[6 * (size_t)b], py = a.x0[6 * (size_t)b + 1];
   // Obstacle slots beyond the problem's own count hold an inert barrier
   // (h = |p|^2 + 1e30 > 0 everywhere, never violated, never hit), so the
   // per-step loops run a fixed count without per-obstacle branches.
@@ -150,7 +152,6 @@ __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const Prob
   if (d.np > 0) {
     __shared__ R s_bd[32];
     __shared__ int s_bi[32];
-    const R px = a.x0[6 * (size_t)b], py = a.x0[6 * (size_t)b + 1];
     R bd = R(INFINITY);
     int bi = 0x7fffffff;
     for (int i = tid; i < d.np; i += nt) {

@@ -441,7 +441,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
         if (one_pass) {
           if (g < G && i < 2 * d.T) {
             const float* Pi = P0 + PART_HDR + i;
-            constexpr int NB = 16;  // loads issued before the first is consumed
+            constexpr int NB = PIPE ? 32 : 16;  // loads in flight (latency mode: one batch covers 64 tiles)
             for (int k0 = g; k0 < ntb; k0 += NB * G) {
               float v[NB], sc[NB];
 #pragma unroll
