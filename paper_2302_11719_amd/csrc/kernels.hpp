@@ -1,4 +1,7 @@
-// gfx950 kernels of the plain (one call per stage) sampled-rollout path.
+// gfx950 kernels of the plain (one call per stage) sampled-rollout path, and
+// the device functions the batched plan shares with it (problem staging, block
+// reductions, noise sums, the shield of Algorithm 1 and its L-BFGS variant,
+// the plant step).
 #pragma once
 
 #include "device.hpp"
@@ -1431,7 +1434,7 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
   }
 }
 
-// One workgroup (two waves) per problem.
+// One workgroup (three waves) per problem.
 template <class R, int NOBS>
 __global__ __launch_bounds__(REP_BLK) void k_repair(RepairArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem[];

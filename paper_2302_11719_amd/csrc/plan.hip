@@ -6,10 +6,14 @@
 // weighted noise sums per step) and takes a ticket on its problem; the tile
 // that takes the last ticket combines the partials in tile order (streaming
 // log-sum-exp rescale) and writes V+ and the weight statistics; the last
-// workgroup to leave re-arms the queue.  The shield (repair) kernel follows on
-// the same stream and, when the plan executes, also runs the plant step and
-// warm start (a separate execute kernel when the shield is off); the sequence
-// is captured once into a HIP graph.
+// workgroup to leave re-arms the queue.  With the shield, the combining
+// workgroup then runs it on the problem (Algorithm 1 or L-BFGS) and, when the
+// plan executes, the plant step and warm start, all in the same launch (a
+// separate shield kernel when the workgroup has fewer than three waves or its
+// LDS does not fit; a separate execute kernel without the shield).  A launch
+// of several kernels (obstacle slots, empty problems, separate shield or
+// execute) is captured once into a HIP graph; a single kernel is launched
+// directly.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
