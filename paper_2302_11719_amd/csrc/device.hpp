@@ -340,12 +340,13 @@ __device__ __forceinline__ Obs<float> obs_at<float>(const TrackView<float>& tr, 
   return Obs<float>{v.x, v.y, v.z, v.w};
 }
 
+// Squared distance from (px, py) to the segment a + lam d, lam in [0, 1]
+// (il2 = 1/|d|^2); the error vector in (*rx_o, *ry_o) when requested.
 template <class R>
-__device__ __forceinline__ R seg_dist2(const TrackView<R>& tr, int i, R px, R py, R* rx_o = nullptr,
-                                       R* ry_o = nullptr) {
-  const R ax = tr.seg[4 * i + 0], ay = tr.seg[4 * i + 1], dx = tr.seg[4 * i + 2], dy = tr.seg[4 * i + 3];
+__device__ __forceinline__ R seg_dist2_row(R ax, R ay, R dx, R dy, R il2, R px, R py, R* rx_o = nullptr,
+                                           R* ry_o = nullptr) {
   const R rx = px - ax, ry = py - ay;
-  R lam = (rx * dx + ry * dy) * tr.il2[i];
+  R lam = (rx * dx + ry * dy) * il2;
   lam = clamp_r(lam, R(0), R(1));
   const R ex = rx - lam * dx, ey = ry - lam * dy;
   if (rx_o) {
@@ -353,6 +354,12 @@ __device__ __forceinline__ R seg_dist2(const TrackView<R>& tr, int i, R px, R py
     *ry_o = ey;
   }
   return ex * ex + ey * ey;
+}
+template <class R>
+__device__ __forceinline__ R seg_dist2(const TrackView<R>& tr, int i, R px, R py, R* rx_o = nullptr,
+                                       R* ry_o = nullptr) {
+  return seg_dist2_row(tr.seg[4 * i + 0], tr.seg[4 * i + 1], tr.seg[4 * i + 2], tr.seg[4 * i + 3], tr.il2[i], px,
+                       py, rx_o, ry_o);
 }
 
 // Global nearest segment (first strict minimum: lowest index on ties).

@@ -62,6 +62,43 @@ __device__ __forceinline__ bool load_dims(const ProblemArgs<R>& a, int b, Proble
   return true;
 }
 
+// Lexicographic minimum of (distance, index) over a wave, in every lane (the
+// whole wave active; an infinite or NaN distance never wins, as in a scan with
+// a strict "<").  FP64: butterfly shuffles.  FP32: distances are non-negative,
+// so their bit patterns order like their values; two integer minima (distance,
+// then the index among the lanes holding it), each four DPP row rotations and
+// a scalar minimum over the four rows.
+__device__ __forceinline__ unsigned wave_min_u32(unsigned m) {
+  m = min(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x128, 0xF, 0xF, false));  // row_ror:8
+  m = min(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x124, 0xF, 0xF, false));  // row_ror:4
+  m = min(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x122, 0xF, 0xF, false));  // row_ror:2
+  m = min(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x121, 0xF, 0xF, false));  // row_ror:1
+  const unsigned r0 = (unsigned)__builtin_amdgcn_readlane((int)m, 0), r1 = (unsigned)__builtin_amdgcn_readlane((int)m, 16);
+  const unsigned r2 = (unsigned)__builtin_amdgcn_readlane((int)m, 32), r3 = (unsigned)__builtin_amdgcn_readlane((int)m, 48);
+  return min(min(r0, r1), min(r2, r3));
+}
+template <class R>
+__device__ __forceinline__ void wave_argmin(R& bd, int& bi) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const R od = __shfl_xor(bd, o, WAVE);
+    const int oi = __shfl_xor(bi, o, WAVE);
+    if (od < bd || (od == bd && oi < bi)) {
+      bd = od;
+      bi = oi;
+    }
+  }
+}
+template <>
+__device__ __forceinline__ void wave_argmin<float>(float& bd, int& bi) {
+  const unsigned key = bd < INFINITY ? __float_as_uint(bd) : 0xFFFFFFFFu;
+  const unsigned m = wave_min_u32(key);
+  const unsigned mi = wave_min_u32(key == m ? (unsigned)bi : 0x7fffffffu);
+  const bool none = m == 0xFFFFFFFFu;
+  bd = none ? INFINITY : __uint_as_float(m);
+  bi = none ? 0x7fffffff : (int)mi;
+}
+
 // Stages problem b's polyline, obstacles and control sequence in LDS; returns
 // the track view.  LDS layout: seg [poly_max][4] | obs [obs_max][4] |
 // il2 [poly_max] | V [2][t_max].
@@ -101,6 +138,11 @@ __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const Prob
 #pragma unroll
     for (int c = 0; c < 5; ++c) prow[c] = sp[c];
   }
+  // Nearest segment to the start position (global search, lowest index on
+  // ties): each thread tracks the first strict minimum over the rows it stages
+  // (increasing index), computed from the rows in registers.
+  R bd = R(INFINITY);
+  int bi = 0x7fffffff;
   for (int r0 = 0; r0 < d.np; r0 += STAGE_U * nt) {
     R row[STAGE_U][5];
 #pragma unroll
@@ -121,6 +163,11 @@ __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const Prob
         seg[4 * i + 2] = row[u][2];
         seg[4 * i + 3] = row[u][3];
         il2[i] = row[u][4];
+        const R dd = seg_dist2_row(row[u][0], row[u][1], row[u][2], row[u][3], row[u][4], px, py);
+        if (dd < bd) {
+          bd = dd;
+          bi = k;
+        }
       }
     }
   }
@@ -149,30 +196,14 @@ __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const Prob
   tr.n_obs = d.no;
   tr.idx0 = 0;
   *Vs_out = Vs;
-  // Nearest segment to the problem's start state (global search; lowest index
-  // on ties), shared by every sample: computed once by the whole workgroup.
-  __syncthreads();
+  // The start segment is shared by every sample: the waves' minima meet in LDS
+  // (the barrier also publishes the staged rows; every caller synchronises
+  // again before the staged problem is used, which also guards s_bd and s_bi
+  // against the next staging).
   if (d.np > 0) {
     __shared__ R s_bd[32];
     __shared__ int s_bi[32];
-    R bd = R(INFINITY);
-    int bi = 0x7fffffff;
-    for (int i = tid; i < d.np; i += nt) {
-      const R dd = seg_dist2(tr, i, px, py);
-      if (dd < bd) {
-        bd = dd;
-        bi = i;
-      }
-    }
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) {
-      const R od = __shfl_xor(bd, o, WAVE);
-      const int oi = __shfl_xor(bi, o, WAVE);
-      if (od < bd || (od == bd && oi < bi)) {
-        bd = od;
-        bi = oi;
-      }
-    }
+    wave_argmin(bd, bi);
     if (tid % WAVE == 0) {
       s_bd[tid / WAVE] = bd;
       s_bi[tid / WAVE] = bi;
@@ -186,7 +217,6 @@ __device__ TrackView<R> stage_problem(const ProblemArgs<R>& a, int b, const Prob
         bi = s_bi[k];
       }
     tr.idx0 = bi == 0x7fffffff ? 0 : bi;
-    __syncthreads();
   }
   return tr;
 }
