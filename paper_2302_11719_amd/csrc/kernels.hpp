@@ -252,6 +252,36 @@ __device__ __forceinline__ R wave_min(R v) {
   for (int o = WAVE / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, WAVE));
   return v;
 }
+// FP32 (the whole wave active): within each 16-lane row, partners lane^1 and
+// lane^2 (quad permutations), then the other quad of the half row and the
+// other half of the row (mirrors; after the first two steps every lane of a
+// quad holds the same value, so a mirror reaches the same partner value as
+// lane^4 and lane^8 would); the four row results then meet as
+// (row0 + row1) + (row2 + row3) through readlane.  Every lane gets the same
+// value, and each kernel reduces in this one order.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+template <>
+__device__ __forceinline__ float wave_sum<float>(float v) {
+  v += dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f<0x141>(v);  // row_half_mirror
+  v += dpp_f<0x140>(v);  // row_mirror
+  return (lane_f(v, 0) + lane_f(v, 16)) + (lane_f(v, 32) + lane_f(v, 48));
+}
+template <>
+__device__ __forceinline__ float wave_min<float>(float v) {
+  v = fminf(v, dpp_f<0xB1>(v));
+  v = fminf(v, dpp_f<0x4E>(v));
+  v = fminf(v, dpp_f<0x141>(v));
+  v = fminf(v, dpp_f<0x140>(v));
+  return fminf(fminf(lane_f(v, 0), lane_f(v, 16)), fminf(lane_f(v, 32), lane_f(v, 48)));
+}
 
 // Block-wide reductions in a fixed order (lane tree, then waves in index order).
 template <class R>
