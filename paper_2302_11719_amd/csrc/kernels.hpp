@@ -296,13 +296,15 @@ __device__ R block_sum(R v, R* red) {
   return s;
 }
 // Three block sums with one exchange (same order as block_sum); red: 3 * waves.
-template <class R>
+// LEAD = false drops the leading barrier, which only guards `red` against
+// readers of its previous use: for callers that have passed a barrier since.
+template <class R, bool LEAD = true>
 __device__ void block_sum3(R& a, R& b, R& c, R* red) {
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
   a = wave_sum(a);
   b = wave_sum(b);
   c = wave_sum(c);
-  __syncthreads();
+  if (LEAD) __syncthreads();
   if (lane == 0) {
     red[wv] = a;
     red[nw + wv] = b;
@@ -316,11 +318,11 @@ __device__ void block_sum3(R& a, R& b, R& c, R* red) {
     c += red[2 * nw + i];
   }
 }
-template <class R>
+template <class R, bool LEAD = true>
 __device__ R block_min(R v, R* red) {
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
   v = wave_min(v);
-  __syncthreads();
+  if (LEAD) __syncthreads();
   if (lane == 0) red[wv] = v;
   __syncthreads();
   R s = red[0];
@@ -609,7 +611,7 @@ __device__ void block_noise_sums(const DevModel<R>& Mg, const DevCost<R>& Cg, ui
         const int t = 2 * (j0 + jj) + (q >> 1);
         if (t < T) P[(q & 1) * T + t] = s;
       }
-      __syncthreads();
+      if (j0 + BLK / G < npairs) __syncthreads();  // red4 is written again
     }
     return;
   }

@@ -268,7 +268,12 @@ __device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, co
 template <int NOBS, int BLK, int SPT, bool PIPE, bool FUSE>
 __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ float red[3 * (BLK / WAVE)];
+  // block reductions: minima in red[0, waves), sums in red[waves, 4 waves); a
+  // tile and a combine each take one minimum then the sums, and every pair is
+  // separated from the next by the ticket barriers, so neither needs its
+  // leading barrier
+  __shared__ float red[4 * (BLK / WAVE)];
+  float* const red_sum = red + BLK / WAVE;
   __shared__ NoiseSumLds<float, BLK, SPT> L;
   __shared__ int s_tile;
   __shared__ uint32_t s_ticket;
@@ -343,7 +348,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       }
     }
     // ---- tile-local softmax partial
-    mn = block_min(mn, red);
+    mn = block_min<float, false>(mn, red);
     float om[SPT], z = 0.f, q = 0.f, nf = 0.f;
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
@@ -352,7 +357,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       q += om[j] * om[j];
       if (own[j] && !isfinite(s[j])) nf += 1.f;
     }
-    block_sum3(z, q, nf, red);
+    block_sum3<float, false>(z, q, nf, red_sum);
     float* P = a.part + (size_t)(a.tile_off[b] + kb) * pstride;
     block_noise_sums<float, BLK, SPT, PIPE>(a.M, a.C, a.p.seed, pid, it, a.p.nominal != 0, Vs, d.T, ms, om, L,
                                       P + PART_HDR);
@@ -397,7 +402,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
             mn_l = fminf(mn_l, mk[j]);
           }
         }
-        gmin = block_min(mn_l, red);
+        gmin = block_min<float, false>(mn_l, red);
         float z_l = 0.f, q_l = 0.f;
 #pragma unroll
         for (int j = 0; j < SPT; ++j) {
@@ -409,14 +414,14 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
             q_l += sc * sc * qk[j];
           }
         }
-        block_sum3(z_l, q_l, nf_l, red);
+        block_sum3<float, false>(z_l, q_l, nf_l, red_sum);
         Z = z_l;
         Q = q_l;
         NF = nf_l;
       } else {
         float mn_l = INFINITY;
         for (int k = tid; k < ntb; k += BLK) mn_l = fminf(mn_l, P0[(size_t)k * pstride]);
-        gmin = block_min(mn_l, red);
+        gmin = block_min<float, false>(mn_l, red);
         float z_l = 0.f, q_l = 0.f, nf_l = 0.f;
         for (int k = tid; k < ntb; k += BLK) {
           const float* Pk = P0 + (size_t)k * pstride;
@@ -426,7 +431,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
           q_l += sc * sc * Pk[2];
           nf_l += Pk[3];
         }
-        block_sum3(z_l, q_l, nf_l, red);
+        block_sum3<float, false>(z_l, q_l, nf_l, red_sum);
         Z = z_l;
         Q = q_l;
         NF = nf_l;
