@@ -379,7 +379,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       // exp(-(min_k - min)/lambda).  The partials were written by other
       // workgroups (other XCDs), so every pass is a round trip to memory: the
       // tile headers are read once into registers and the scales kept in LDS
-      // when the problem has at most BLK*SPT tiles; the V+ pass keeps 16 loads
+      // when the problem has at most BLK*SPT tiles; the V+ pass keeps NB loads
       // in flight per thread.
       const float* P0 = a.part + (size_t)a.tile_off[b] * pstride;
       float* s_sc = L.w;
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       const float iZ = Z > 0.f ? 1.f / Z : 0.f;
       const float* Vb = a.V + 2 * (size_t)d.t0;
       float* Vpb = a.V_plus + 2 * (size_t)d.t0;
-      // V+ pass: thread (g, il) sums tiles g, g+G, ... of output i0 + il (16
+      // V+ pass: thread (g, il) sums tiles g, g+G, ... of output i0 + il (NB
       // loads in flight); the G group sums are then added in group order.
       const int nI = min(2 * d.T, BLK), G = one_pass ? BLK / nI : 1;
       const int g = tid / nI, il = tid % nI;
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
             __syncthreads();
             if (g == 0)
               for (int gg = 1; gg < G; ++gg) acc += s_red[gg * nI + il];
-            __syncthreads();
+            if (i0 + nI < 2 * d.T) __syncthreads();  // s_red is written again (the last chunk: the barrier below)
           }
           if (g != 0) continue;
         } else {
@@ -505,7 +505,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       }
       if constexpr (FUSE && BLK >= 3 * WAVE) {
         if (a.repair) {
-          __syncthreads();
+          // the barrier above published Vs; since then only thread 0 wrote (global memory)
           unsigned char* rl = smem + stage_lds_bytes<float>(a.p.poly_max, a.p.t_max, a.p.obs_max);
           repair_problem<float, NOBS, PIPE>(a.rep, b, d, tr, Vs, rl, &s_last);
           float* out = a.rep.V_safe + 2 * (size_t)d.t0;
