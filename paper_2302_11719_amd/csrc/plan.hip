@@ -5,8 +5,9 @@
 // split softmax partial (tile min cost, sum of weights, sum of squared weights,
 // weighted noise sums per step) and takes a ticket on its problem; the tile
 // that takes the last ticket combines the partials in tile order (streaming
-// log-sum-exp rescale) and writes V+ and the weight statistics; the last
-// workgroup to leave re-arms the queue.  With the shield, the combining
+// log-sum-exp rescale) and writes V+ and the weight statistics; when the grid
+// is smaller than the tile list, the last workgroup to leave re-arms the
+// queue (a grid as large as the list never touches it).  With the shield, the combining
 // workgroup then runs it on the problem (Algorithm 1 or L-BFGS) and, when the
 // plan executes, the plant step and warm start, all in the same launch (a
 // separate shield kernel when the workgroup has fewer than three waves or its
@@ -286,7 +287,10 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
   ProblemDims d;
   // Workgroup g takes tile g first (no queue round trip before the first
   // rollout; the grid never exceeds the tile count), then tiles gridDim.x + q
-  // for q popped from the queue.
+  // for q popped from the queue.  A grid as large as the tile list never uses
+  // the queue (which then stays armed), so a workgroup leaves without the two
+  // atomic round trips of a final pop and the exit count.
+  const bool queued = (int)gridDim.x < a.n_tiles;
   bool first = true;
   for (;;) {
     int tile;
@@ -294,6 +298,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       tile = blockIdx.x;
       first = false;
     } else {
+      if (!queued) break;
       if (tid == 0) s_tile = (int)gridDim.x + (int)atomicAdd(a.queue, 1u);
       __syncthreads();
       tile = __builtin_amdgcn_readfirstlane(s_tile);
@@ -519,7 +524,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
   }
   // The last workgroup to leave re-arms the queue for the next launch (every
   // other workgroup has taken its final, out-of-range, tile by then).
-  if (tid == 0 && atomicAdd(a.exits, 1u) == gridDim.x - 1) {
+  if (queued && tid == 0 && atomicAdd(a.exits, 1u) == gridDim.x - 1) {
     atomicExch(a.queue, 0u);
     atomicExch(a.exits, 0u);
   }

@@ -310,3 +310,31 @@ def test_obstacles_moved_between_launches():
             db.obs.copy_(torch.as_tensor(new, dtype=F32, device="cuda"))
     assert any(np.abs(Ss[b] - S_before[b]).max() > 0 for b in b_obs)
     plan.close()
+
+
+def test_static_and_queued_grids_agree():
+    """A grid as large as the tile list never touches the tile queue; a smaller grid pops
+    it and re-arms it on the way out.  Both take the same tiles and combine them in tile
+    order, so over a closed loop (shield, plant step and warm start in the launch) the
+    two plans stay bit-identical, launch after launch."""
+    probs = prep(ragged_problems(), F32)
+    M, C = params(F32)
+    dist = torch.as_tensor(W.disturbances(3, 8 * len(probs)).reshape(-1), dtype=F32, device="cuda")
+    rep = dict(n_steps=3, step=0.05, objective=W.OBJ_SHIELD)
+    dbs = [core.DeviceBatch(probs, dtype=F32) for _ in range(2)]
+    probe = core.Plan(ctx(), dbs[0], M, C, 4, W.LAMBDA, block=256, tile=256, use_graph=False)
+    n_tiles = probe.info()["n_tiles"]
+    assert n_tiles > 2
+    plans = [core.Plan(ctx(), dbs[i], M, C, 4, W.LAMBDA, block=256, tile=256, grid=g, repair=rep, execute=True,
+                       dist=dist.view(8, -1), use_graph=False) for i, g in enumerate((n_tiles, 2))]
+    assert [p.info()["grid"] for p in plans] == [n_tiles, 2]
+    for step in range(4):
+        say(f"static vs queued grid, launch {step}")
+        for pl in plans:
+            pl.launch()
+        torch.cuda.synchronize()
+        for name in ("x0", "V", "iter"):
+            assert torch.equal(getattr(dbs[0], name), getattr(dbs[1], name)), (step, name)
+        for name in ("S", "V_plus", "stats", "V_safe"):
+            assert torch.equal(getattr(plans[0], name), getattr(plans[1], name)), (step, name)
+    assert ctx().device_errors() == 0
