@@ -1390,6 +1390,26 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
         is[0] = idx0;
       }
     }
+    // one DCBF transition of the nominal trajectory (window wave): track
+    // barrier from e2, obstacle barriers on the lanes; records the last
+    // active transition
+    auto transition = [&](int t, R px, R py, R e2) {
+      const R h = tr.w2 - e2;
+      bool act = C.alpha * hp - h > R(0);
+      hp = h;
+      if (NOBS > 0) {
+        bool ao = false;
+        if (lane < NOBS) {
+          const Obs<R> o = obs_at(tr, lane);
+          const R ox = px - o.cx, oy = py - o.cy;
+          const R hi = ox * ox + oy * oy - o.re2;
+          ao = C.alpha * hob - hi > R(0);
+          hob = hi;
+        }
+        act = act || (__ballot(ao) != 0ull);
+      }
+      if (act && (ob.w_sq != R(0) || (ob.w_lin != R(0) && t < ob.n_lin))) last = t;
+    };
     __syncthreads();
     for (int st = 0; st <= nch + 1; ++st) {
       if (w == 0 && lane == 0 && st < nch) {
@@ -1434,35 +1454,28 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
         }
       } else if (w == 1 && st >= 2) {
         const int t0 = (st - 2) * REP_C, t1 = min(T, t0 + REP_C);
-        for (int t = t0; t < t1; ++t) {
-          const R px = xs[6 * (t + 1)], py = xs[6 * (t + 1) + 1];
-          // window segments on the lanes of a row, min by DPP (no LDS round trip
-          // on the chain through idx); wider windows: one lane, sequential rule
-          R e2;
-          if (tr.n == 0) {
-            e2 = circle_e2(tr, px, py);
-          } else if (tr.window <= 7) {
-            e2 = row_window(tr, idx, px, py);
-          } else {
-            e2 = window_min(tr, idx, px, py);
+        // The chunk's segment indices collect on lanes 0 .. REP_C-1 and are
+        // stored once after the chunk (a store on every step made the next
+        // step wait for it, inside the chain through idx).  The kind of window
+        // is chosen once, outside the step loop.
+        int ic = 0;
+        auto chunk = [&](auto track_e2) {
+          for (int t = t0; t < t1; ++t) {
+            const R px = xs[6 * (t + 1)], py = xs[6 * (t + 1) + 1];
+            const R e2 = track_e2(px, py);
+            ic = lane == t - t0 ? idx : ic;
+            transition(t, px, py, e2);
           }
-          if (lane == 0) is[t + 1] = idx;
-          const R h = tr.w2 - e2;
-          bool act = C.alpha * hp - h > R(0);
-          hp = h;
-          if (NOBS > 0) {
-            bool ao = false;
-            if (lane < NOBS) {
-              const Obs<R> o = obs_at(tr, lane);
-              const R ox = px - o.cx, oy = py - o.cy;
-              const R hi = ox * ox + oy * oy - o.re2;
-              ao = C.alpha * hob - hi > R(0);
-              hob = hi;
-            }
-            act = act || (__ballot(ao) != 0ull);
-          }
-          if (act && (ob.w_sq != R(0) || (ob.w_lin != R(0) && t < ob.n_lin))) last = t;
-        }
+        };
+        // window segments on the lanes of a row, min by DPP (no LDS round trip
+        // on the chain through idx); wider windows: one lane, sequential rule
+        if (tr.n == 0)
+          chunk([&](R px, R py) { return circle_e2(tr, px, py); });
+        else if (tr.window <= 7)
+          chunk([&](R px, R py) { return row_window(tr, idx, px, py); });
+        else
+          chunk([&](R px, R py) { return window_min(tr, idx, px, py); });
+        if (lane < t1 - t0) is[t0 + 1 + lane] = ic;
       }
       __syncthreads();
     }
