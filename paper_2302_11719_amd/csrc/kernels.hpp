@@ -1415,14 +1415,26 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
       if (w == 0 && lane == 0 && st < nch) {
         const int t0 = st * REP_C, t1 = min(T, t0 + REP_C);
         R* gb = vst + (st & 1) * (REP_C * 12);
-        for (int t = t0; t < t1; ++t) {
+        // the chunk's control rows are read before its first store: LDS
+        // returns in order, so a row read after a step's stores would wait for
+        // them inside the RK4 chain
+        R cc[REP_C][5];
+#pragma unroll
+        for (int k = 0; k < REP_C; ++k) {
+          const R* cr = static_cast<const R*>(__builtin_assume_aligned(ctl + REP_CTL * min(t0 + k, t1 - 1), 16));
+#pragma unroll
+          for (int c = 0; c < 5; ++c) cc[k][c] = cr[c];
+        }
+#pragma unroll
+        for (int j = 0; j < REP_C; ++j) {
+          const int t = t0 + j;
+          if (t >= t1) break;
           StepCtl<R> sc;
-          const R* cr = static_cast<const R*>(__builtin_assume_aligned(ctl + REP_CTL * t, 16));
-          sc.delta = cr[0];
-          sc.sd_m = cr[1];
-          sc.cd_m = cr[2];
-          sc.lfcd_Iz = cr[3];
-          sc.a_tau = cr[4];
+          sc.delta = cc[j][0];
+          sc.sd_m = cc[j][1];
+          sc.cd_m = cc[j][2];
+          sc.lfcd_Iz = cc[j][3];
+          sc.a_tau = cc[j][4];
           sc.sd = sc.cd = R(0);  // used by the reverse sweep only
           VelStages<R> g;
           rk4_vel(M, sc, x.vx, x.vy, x.om, g);
@@ -1439,16 +1451,24 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
       } else if (w == 2 && lane == 0 && st >= 1 && st <= nch) {
         const int t0 = (st - 1) * REP_C, t1 = min(T, t0 + REP_C);
         const R* gb = vst + ((st - 1) & 1) * (REP_C * 12);
-        for (int t = t0; t < t1; ++t) {
-          const R* gt = static_cast<const R*>(__builtin_assume_aligned(gb + 12 * (t - t0), 16));
-          VelStages<R> g;
+        // the chunk's stage velocities are read before its first store (as
+        // the control rows in the velocity wave)
+        VelStages<R> gc[REP_C];
+#pragma unroll
+        for (int j = 0; j < REP_C; ++j) {
+          const R* gt = static_cast<const R*>(__builtin_assume_aligned(gb + 12 * min(j, t1 - t0 - 1), 16));
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            g.vx[k] = gt[k];
-            g.vy[k] = gt[4 + k];
-            g.om[k] = gt[8 + k];
+            gc[j].vx[k] = gt[k];
+            gc[j].vy[k] = gt[4 + k];
+            gc[j].om[k] = gt[8 + k];
           }
-          rk4_pose(M, g, x.px, x.py, x.psi);
+        }
+#pragma unroll
+        for (int j = 0; j < REP_C; ++j) {
+          const int t = t0 + j;
+          if (t >= t1) break;
+          rk4_pose(M, gc[j], x.px, x.py, x.psi);
           R* o = xs + 6 * (t + 1);
           o[0] = x.px; o[1] = x.py; o[2] = x.psi;
         }
