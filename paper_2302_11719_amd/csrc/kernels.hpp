@@ -829,9 +829,11 @@ struct ReduceSink {
   R* gp;  // this block's partial [2][T]
   int T;
   int lane;
+  // A sample with zero upstream weight (lanes past K, non-finite costs given
+  // weight 0) contributes exactly zero, even when its own adjoint diverged.
   __device__ __forceinline__ void operator()(int t, R gv0, R gv1) {
-    const R s0 = wave_sum(g * gv0);
-    const R s1 = wave_sum(g * gv1);
+    const R s0 = wave_sum(g != R(0) ? g * gv0 : R(0));
+    const R s1 = wave_sum(g != R(0) ? g * gv1 : R(0));
     if (lane == 0) {
       gp[t] = s0;
       gp[T + t] = s1;

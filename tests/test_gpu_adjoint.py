@@ -1,0 +1,366 @@
+"""GPU parity of the adjoint rollout (smppi_rollout_backward) on the paths the
+full-size workloads take, and edge cases of the sampled-rollout step.
+
+Adjoint: grad_V = sum_m g_m dL_m/dV against the oracle's dual-number gradient
+summed over the samples with g_m != 0 (only those need oracle work, so the
+reference stays cheap at any K).  Several 64-lane workgroups per problem run
+the ticketed cross-workgroup combine.  Tolerance (FP32): relative 1e-3 in norm
+and elementwise 1e-3 of the largest component; FP64: 1e-9.
+"""
+import math
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2302_11719_amd import core
+from paper_2302_11719_amd import workloads as W
+
+from gpu_helpers import ctx, params, prep, rel_err, say
+
+pytestmark = pytest.mark.gpu
+F32, F64 = torch.float32, torch.float64
+BAND = 1e-3
+OBJ_COST = dict(w_S=1.0, w_sq=0.0, w_lin=0.0, n_lin=0)
+OBJ_MIXED = dict(w_S=0.5, w_sq=2.0, w_lin=1.0, n_lin=12)
+
+
+def _oracle_grad_sums(M, C, probs, seed, gs, objective, threads=16):
+    """Per problem: sum over samples m with g[m] != 0 of g[m] * dL_m/dV (dual numbers)."""
+    sig = np.array(C["sigma"])
+    jobs = [(b, int(m)) for b in range(len(probs)) for m in np.nonzero(gs[b])[0]]
+
+    def one(job):
+        b, m = job
+        p = probs[b]
+        eps = oracle.normals(seed, b, p.it, m, p.T) * sig
+        return b, gs[b][m] * oracle.gradient_dual(M, C, p.track, p.x0, p.V, objective, eps)
+
+    out = [np.zeros((p.T, 2)) for p in probs]
+    with ThreadPoolExecutor(threads) as ex:
+        for b, g in ex.map(one, jobs):
+            out[b] += g
+    return out, len(jobs)
+
+
+def _check_grad(got, ref, tol, what):
+    err = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
+    emax = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-30)
+    assert err <= tol and emax <= tol, (what, err, emax)
+    return err
+
+
+def _sparse_g(K, n, rng):
+    """Upstream gradient nonzero on about n samples spread over all 64-lane workgroups,
+    including the last (ragged) sample."""
+    g = np.zeros(K)
+    idx = np.unique(np.concatenate([np.linspace(0, K - 1, n).astype(int), [K - 1]]))
+    g[idx] = rng.uniform(0.5, 1.5, size=len(idx)) * rng.choice([-1.0, 1.0], size=len(idx))
+    return g
+
+
+def _multiblock_problems():
+    specs = [(65, 37, 0, 8), (300, 21, 1, 0), (2048, 50, 2, 16), (130, 9, -1, 0), (64, 12, 3, 0)]
+    out = []
+    for b, (K, T, seed, no) in enumerate(specs):
+        if seed < 0:
+            tr = W.circle_track(10.0, 1.0)
+        else:
+            tr = W.spline_track(seed, 0.9)
+            if no:
+                tr.obs = W.obstacles(tr, seed, no)
+        V = W.test_sequences(1, T, seed=40 + b, scale=0.5)[0]
+        out.append(W.Problem(K=K, T=T, track=tr, x0=W.start_state(tr, vx=2.5 + 0.3 * b), V=V, pid=b, it=b))
+    return out
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("obj", ["total", "mixed"])
+def test_backward_multiblock_ragged(dtype, obj):
+    """K = 65, 300, 2048, 130, 64 (2, 5, 32, 3 and 1 workgroups per problem), horizons 37, 21,
+    50, 9, 12, obstacles on two problems: the cross-workgroup combine against the oracle."""
+    objective = W.OBJ_TOTAL if obj == "total" else OBJ_MIXED
+    probs = prep(_multiblock_problems(), dtype)
+    M, C = params(dtype)
+    rng = np.random.default_rng(7)
+    gs = [_sparse_g(p.K, 12, rng) for p in probs]
+    if dtype == F32:
+        gs = [g.astype(np.float32).astype(np.float64) for g in gs]
+    db = core.DeviceBatch(probs, dtype=dtype)
+    say(f"backward multiblock {dtype} {obj} K={[p.K for p in probs]}")
+    gS = torch.as_tensor(np.concatenate(gs), dtype=dtype, device="cuda")
+    gV = core.rollout_backward(ctx(), db, M, C, 13, gS, objective)
+    torch.cuda.synchronize()
+    assert ctx().device_errors() == 0
+    ref, n = _oracle_grad_sums(M, C, probs, 13, gs, objective)
+    got = db.controls(gV)
+    tol = 1e-3 if dtype == F32 else 1e-9
+    for b in range(len(probs)):
+        e = _check_grad(got[b], ref[b], tol, (b, probs[b].K))
+        say(f"  problem {b} K={probs[b].K}: rel err {e:.2e}")
+
+
+@pytest.mark.parametrize("obj", ["total", "shield"])
+def test_backward_config3_shape_fp32(obj):
+    """The differentiation workload's shape: 64 problems, K = 2048, T = 50 (32 workgroups per
+    problem), FP32, for the total-cost-plus-squared-violations objective and the shield's."""
+    objective = W.OBJ_TOTAL if obj == "total" else W.OBJ_SHIELD
+    probs = W.config3()
+    seqs = W.test_sequences(len(probs), 50, seed=11, scale=0.6)
+    for p, V in zip(probs, seqs):
+        p.V = V
+    probs = prep(probs, F32)
+    M, C = params(F32)
+    rng = np.random.default_rng(3)
+    gs = [_sparse_g(p.K, 6, rng).astype(np.float32).astype(np.float64) for p in probs]
+    db = core.DeviceBatch(probs, dtype=F32)
+    say(f"backward config3 shape fp32 {obj}")
+    gV = core.rollout_backward(ctx(), db, M, C, 21, torch.as_tensor(np.concatenate(gs), dtype=F32, device="cuda"),
+                               objective)
+    torch.cuda.synchronize()
+    assert ctx().device_errors() == 0
+    ref, n = _oracle_grad_sums(M, C, probs, 21, gs, objective)
+    got = db.controls(gV)
+    errs = []
+    for b in range(len(probs)):
+        if np.abs(ref[b]).max() == 0.0:  # shield objective with no violation on these samples
+            assert np.abs(got[b]).max() == 0.0, b
+            continue
+        errs.append(_check_grad(got[b], ref[b], 1e-3, b))
+    say(f"  {n} oracle gradients, {len(errs)} nonzero problems, worst rel err {max(errs):.2e}")
+    assert len(errs) >= (64 if obj == "total" else 8)
+
+
+def test_backward_free_energy_large_fp32():
+    """The large workload (K = 65536, T = 100, 64 obstacles) in the bench's launch: the
+    gradient of the free energy -lambda log sum exp(-S/lambda), i.e. upstream g = the
+    device's own weights at lambda = 1 (1024 workgroups, recomputed states)."""
+    p = prep([W.config4()], F32)[0]
+    p.V = W.round_to_f32(W.Problem(p.K, p.T, p.track, p.x0, W.test_sequences(1, p.T, seed=5, scale=0.3)[0])).V
+    M, C = params(F32)
+    db = core.DeviceBatch([p], dtype=F32)
+    say("backward free energy K=65536 T=100 obs=64")
+    S = core.rollout(ctx(), db, M, C, 0)
+    w, _ = core.weights(ctx(), db, S, W.LAMBDA)
+    gV = core.rollout_backward(ctx(), db, M, C, 0, w, OBJ_COST)
+    torch.cuda.synchronize()
+    assert ctx().device_errors() == 0
+    wn = w.cpu().numpy().astype(np.float64)
+    nz = int((wn != 0).sum())
+    say(f"  {nz} samples with nonzero weight")
+    assert 1 <= nz <= 20000
+    ref, _ = _oracle_grad_sums(M, C, [p], 0, [wn], OBJ_COST)
+    e = _check_grad(db.controls(gV)[0], ref[0], 1e-3, "free energy")
+    say(f"  rel err {e:.2e}")
+    # FP32 weights at lambda = 1 vanish on all but a few samples: an upstream gradient on
+    # two samples of every one of the 1024 workgroups exercises the whole combine
+    g2 = _sparse_g(p.K, 2048, np.random.default_rng(4)).astype(np.float32).astype(np.float64)
+    gV2 = core.rollout_backward(ctx(), db, M, C, 0, torch.as_tensor(g2, dtype=F32, device="cuda"), W.OBJ_TOTAL)
+    torch.cuda.synchronize()
+    ref2, n2 = _oracle_grad_sums(M, C, [p], 0, [g2], W.OBJ_TOTAL)
+    e2 = _check_grad(db.controls(gV2)[0], ref2[0], 1e-3, "all workgroups")
+    say(f"  {n2} samples over all workgroups: rel err {e2:.2e}")
+
+
+def test_backward_zero_weight_diverged_sample_stays_finite():
+    """A problem whose start state is not finite (every trajectory diverges) with zero
+    upstream gradient contributes exactly zero; the other problem is unaffected."""
+    probs = prep(_multiblock_problems()[:2], F32)
+    probs[0].x0 = probs[0].x0.copy()
+    probs[0].x0[3] = np.nan
+    M, C = params(F32)
+    rng = np.random.default_rng(1)
+    gs = [np.zeros(probs[0].K), _sparse_g(probs[1].K, 8, rng).astype(np.float32).astype(np.float64)]
+    db = core.DeviceBatch(probs, dtype=F32)
+    say("backward with a diverged zero-weight problem")
+    gV = core.rollout_backward(ctx(), db, M, C, 2, torch.as_tensor(np.concatenate(gs), dtype=F32, device="cuda"),
+                               W.OBJ_TOTAL)
+    torch.cuda.synchronize()
+    got = db.controls(gV)
+    assert np.all(got[0] == 0.0)
+    sig = np.array(C["sigma"])
+    ref1 = np.zeros((probs[1].T, 2))
+    for m in np.nonzero(gs[1])[0]:
+        eps = oracle.normals(2, 1, probs[1].it, int(m), probs[1].T) * sig
+        ref1 += gs[1][m] * oracle.gradient_dual(M, C, probs[1].track, probs[1].x0, probs[1].V, W.OBJ_TOTAL, eps)
+    _check_grad(got[1], ref1, 1e-3, "finite problem")
+
+
+def test_autograd_gradient_belongs_to_the_forward_state():
+    """A plant step between forward and backward advances the batch's x0 and counter in
+    place; the backward still differentiates the costs the forward computed."""
+    from paper_2302_11719_amd.autograd import SmppiRolloutCost
+
+    p = W.config1(K=130, T=16)
+    p.V = W.test_sequences(1, 16, seed=4, scale=0.5)[0]
+    M, C = params(F64)
+    db = core.DeviceBatch([p], dtype=F64)
+    x_fwd = p.x0.copy()
+    V = db.V.clone().requires_grad_(True)
+    say("autograd with a plant step between forward and backward")
+    S = SmppiRolloutCost.apply(V, ctx(), db, M, C, 6, False)
+    core.execute(ctx(), db, M, db.V, db.V)
+    torch.cuda.synchronize()
+    assert int(db.iter.item()) == p.it + 1
+    g = torch.linspace(0.2, 1.0, p.K, dtype=F64, device="cuda")
+    (S * g).sum().backward()
+    gn = g.cpu().numpy()
+    ref = np.zeros((p.T, 2))
+    for m in range(p.K):
+        eps = oracle.normals(6, 0, p.it, m, p.T) * np.array(C["sigma"])
+        ref += gn[m] * oracle.gradient_dual(M, C, p.track, x_fwd, p.V, OBJ_COST, eps)
+    assert np.abs(db.controls(V.grad)[0] - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max())
+
+
+# ----------------------------------------------------------------------------- edge cases
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_weights_nonfinite_costs(dtype):
+    """NaN and +-Inf costs get weight 0 (the oracle's policy); a problem whose costs are all
+    non-finite gets all-zero weights; stats count the non-finite costs."""
+    rng = np.random.default_rng(5)
+    Ks = [1000, 7, 300, 1]
+    Ss = [rng.uniform(100.0, 140.0, size=k) for k in Ks]
+    Ss[0][[3, 400, 999]] = [np.nan, np.inf, -np.inf]
+    Ss[1][:] = [np.nan, np.inf, -np.inf, np.nan, np.inf, np.nan, -np.inf]
+    Ss[2][::7] = np.nan
+    if dtype == F32:
+        Ss = [s.astype(np.float32).astype(np.float64) for s in Ss]
+    probs = [W.Problem(K=k, T=3, track=W.circle_track(), x0=W.start_state(W.circle_track()), V=np.zeros((3, 2)))
+             for k in Ks]
+    db = core.DeviceBatch(probs, dtype=dtype)
+    say(f"weights with non-finite costs {dtype}")
+    w, stats = core.weights(ctx(), db, torch.as_tensor(np.concatenate(Ss), dtype=dtype, device="cuda"), 2.0)
+    torch.cuda.synchronize()
+    ws, st = db.per_problem(w), stats.cpu().numpy()
+    tol = 1e-6 if dtype == F32 else 1e-13
+    for b, s in enumerate(Ss):
+        w_ref, st_ref = oracle.weights(s, 2.0)
+        assert np.abs(ws[b] - w_ref).max() <= tol, b
+        assert np.all(ws[b][~np.isfinite(s)] == 0.0)
+        assert st[b, 3] == st_ref[3] == (~np.isfinite(s)).sum()
+        if np.isfinite(s).any():
+            assert st[b, 0] == pytest.approx(st_ref[0], rel=1e-7)
+            assert st[b, 2] == pytest.approx(st_ref[2], rel=1e-4)
+        else:
+            assert np.all(ws[b] == 0.0) and st[b, 2] == 0.0
+
+
+def _offset_start(tr, lat, dpsi=0.0, vx=3.0, vertex=0):
+    x0 = W.start_state(tr, vertex=vertex, vx=vx)
+    if tr.kind == 0:
+        x0[0] += lat
+    else:
+        ax, ay, dx, dy = tr.poly[vertex, :4]
+        n = math.hypot(dx, dy)
+        x0[0] += lat * (-dy / n)
+        x0[1] += lat * (dx / n)
+    x0[2] += dpsi
+    return x0
+
+
+def _unsafe_start_problems(K=300, T=25):
+    """Starts outside the safe set: off the track (spline and circle) and inside an obstacle
+    (the z_0 term C max((alpha - 1) h(x_0), 0) is nonzero)."""
+    out = []
+    tr = W.spline_track(4, 0.9)
+    out.append(W.Problem(K, T, tr, _offset_start(tr, 1.3, 0.2), W.test_sequences(1, T, 50, 0.5)[0], 0, 3))
+    trc = W.circle_track(10.0, 1.0)
+    out.append(W.Problem(K + 33, T + 4, trc, _offset_start(trc, -1.6), W.test_sequences(1, T + 4, 51, 0.5)[0], 1, 0))
+    tro = W.spline_track(5, 0.9)
+    x0 = _offset_start(tro, 0.2, 0.0, 3.5)
+    obs = W.obstacles(tro, 5, 16)
+    obs[0] = [x0[0] + 0.1, x0[1] - 0.05, 0.45 ** 2, 0.3 ** 2]  # the start lies inside obstacle 0
+    tro.obs = obs
+    out.append(W.Problem(K - 100, T - 5, tro, x0, W.test_sequences(1, T - 5, 52, 0.5)[0], 2, 1))
+    return out
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_rollout_from_unsafe_starts(dtype):
+    """Costs and the adjoint from starts off the track and inside an obstacle."""
+    probs = prep(_unsafe_start_problems(), dtype)
+    M, C = params(dtype)
+    db = core.DeviceBatch(probs, dtype=dtype)
+    say(f"unsafe starts {dtype}")
+    S = core.rollout(ctx(), db, M, C, 17)
+    torch.cuda.synchronize()
+    assert ctx().device_errors() == 0
+    Ss = db.per_problem(S)
+    tol = 1e-4 if dtype == F32 else 1e-10
+    for b, p in enumerate(probs):
+        _, hs = oracle.trajectory(M, C, p.track, p.x0, np.zeros((1, 2)))
+        assert hs[0].min() < 0.0  # the start is outside the safe set
+        S_ref, _, margin = oracle.rollout(M, C, p.track, p.x0, p.V, p.K, 17, b, p.it, want_eps=False)
+        ok = margin > BAND if dtype == F32 else np.ones(p.K, bool)
+        assert ok.sum() >= p.K // 2
+        assert rel_err(Ss[b], S_ref)[ok].max() <= tol, b
+    rng = np.random.default_rng(2)
+    gs = [_sparse_g(p.K, 8, rng) for p in probs]
+    if dtype == F32:
+        gs = [g.astype(np.float32).astype(np.float64) for g in gs]
+    gV = core.rollout_backward(ctx(), db, M, C, 17, torch.as_tensor(np.concatenate(gs), dtype=dtype, device="cuda"),
+                               OBJ_MIXED)
+    torch.cuda.synchronize()
+    ref, _ = _oracle_grad_sums(M, C, probs, 17, gs, OBJ_MIXED)
+    got = db.controls(gV)
+    for b in range(len(probs)):
+        _check_grad(got[b], ref[b], 1e-3 if dtype == F32 else 1e-9, b)
+
+
+@pytest.mark.parametrize("pipeline", [1, -1])
+def test_plan_from_unsafe_starts(pipeline):
+    """The fused plan (latency mode and throughput mode) from the same unsafe starts."""
+    probs = prep(_unsafe_start_problems(K=512, T=30), F32)
+    if pipeline == 1:  # latency mode runs batches without obstacles
+        probs = probs[:2]
+    M, C = params(F32)
+    db = core.DeviceBatch(probs, dtype=F32)
+    say(f"plan from unsafe starts pipeline={pipeline}")
+    plan = core.Plan(ctx(), db, M, C, 23, W.LAMBDA, use_graph=False, pipeline=pipeline)
+    plan.launch()
+    torch.cuda.synchronize()
+    assert ctx().device_errors() == 0
+    Ss = db.per_problem(plan.S)
+    for b, p in enumerate(probs):
+        S_ref, _, margin = oracle.rollout(M, C, p.track, p.x0, p.V, p.K, 23, b, p.it, want_eps=False)
+        ok = margin > BAND
+        assert rel_err(Ss[b], S_ref)[ok].max() <= 1e-4, b
+
+
+def test_closed_loop_step_with_the_shield_firing():
+    """Closed loop at K = 4096, T = 50 from a start heading off the track: in every one of
+    three receding-horizon steps the shield changes V+ (V_safe != V+), and each step
+    matches the oracle from the device's own state (teacher forcing)."""
+    p = prep([W.config1()], F32)[0]
+    p.x0 = W.round_to_f32(W.Problem(1, 1, p.track, _offset_start(p.track, 0.5, 0.5, 5.0), p.V[:1])).x0
+    M, C = params(F32)
+    db = core.DeviceBatch([p], dtype=F32)
+    rep = dict(n_steps=10, step=0.05, objective=W.OBJ_SHIELD)
+    plan = core.Plan(ctx(), db, M, C, 0, W.LAMBDA, repair=rep, execute=True, use_graph=True)
+    for k in range(3):
+        x_b = db.x0.cpu().numpy().astype(np.float64)
+        V_b = db.controls(db.V)[0].astype(np.float64)
+        it_b = int(db.iter.item())
+        say(f"shield-firing closed loop step {k}")
+        plan.launch()
+        torch.cuda.synchronize()
+        S = plan.S.cpu().numpy().astype(np.float64)
+        S_ref, eps, margin = oracle.rollout(M, C, p.track, x_b, V_b, p.K, 0, 0, it_b)
+        ok = margin > BAND
+        assert rel_err(S, S_ref)[ok].max() <= 1e-4
+        w_ref, _ = oracle.weights(S, W.LAMBDA)
+        Vp = db.controls(plan.V_plus)[0].astype(np.float64)
+        assert np.abs(Vp - oracle.update(V_b, w_ref, eps)).max() <= 1e-5
+        viol, _ = oracle.objective(M, C, p.track, x_b, Vp, W.OBJ_SHIELD)
+        assert viol > 0.0
+        Vs = db.controls(plan.V_safe)[0].astype(np.float64)
+        assert np.abs(Vs - Vp).max() > 1e-3, k  # the shield fired
+        Vs_ref = oracle.repair(M, C, p.track, x_b, Vp, 10, 0.05, W.OBJ_SHIELD)
+        assert np.abs(Vs - Vs_ref).max() <= 1e-3 * max(1.0, np.linalg.norm(Vp))
+        after, _ = oracle.objective(M, C, p.track, x_b, Vs, W.OBJ_SHIELD)
+        assert after < viol
+        x_ref = oracle.execute(M, x_b, Vs[0])
+        assert np.abs(db.x0.cpu().numpy() - x_ref).max() <= 1e-5
+    assert ctx().device_errors() == 0

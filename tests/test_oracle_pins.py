@@ -242,6 +242,34 @@ def test_spline_track_shape():
         assert np.min(np.hypot(P[:, 0] - c[0], P[:, 1] - c[1])) < 0.2
 
 
+def test_spline_is_the_textbook_periodic_cubic():
+    """The track generator's centre line is the periodic C2 interpolating cubic with uniform
+    knots: with knot spacing 1 its knot second derivatives M solve the cyclic system
+    M_{i-1} + 4 M_i + M_{i+1} = 6 (y_{i+1} - 2 y_i + y_{i-1}), and on [i, i+1]
+    S(t) = (1-t) y_i + t y_{i+1} + ((1-t)^3 - (1-t)) M_i / 6 + (t^3 - t) M_{i+1} / 6.
+    Sampled with a multiple of the knot count, every control point is a vertex."""
+    ctrl = W.spline_control_points(3)
+    n, per = len(ctrl), 40
+    P = W.spline_vertices(ctrl, n * per)
+    assert np.abs(P[::per] - ctrl).max() <= 1e-12
+    A = 4.0 * np.eye(n) + np.roll(np.eye(n), 1, axis=1) + np.roll(np.eye(n), -1, axis=1)
+    Mk = np.linalg.solve(A, 6.0 * (np.roll(ctrl, -1, axis=0) - 2.0 * ctrl + np.roll(ctrl, 1, axis=0)))
+    t = (np.arange(per) / per)[:, None]
+    ref = []
+    for i in range(n):
+        j = (i + 1) % n
+        ref.append((1 - t) * ctrl[i] + t * ctrl[j] + ((1 - t) ** 3 - (1 - t)) * Mk[i] / 6.0
+                   + (t ** 3 - t) * Mk[j] / 6.0)
+    assert np.abs(P - np.vstack(ref)).max() <= 1e-12
+    # C2 at the knots, seen on the samples: one-sided second differences agree to O(h)
+    h = 1.0 / per
+    for i in range(n):
+        k = i * per
+        left = (P[k] - 2 * P[k - 1] + P[k - 2]) / h ** 2
+        right = (P[(k + 2) % len(P)] - 2 * P[(k + 1) % len(P)] + P[k]) / h ** 2
+        assert np.abs(left - right).max() <= 4.0 * h * np.abs(Mk).max() + 1e-9
+
+
 # ----------------------------------------------------------------------------- cost
 def _straight_track():
     verts = np.array([[-1000.0, 0.0], [1000.0, 0.0], [1000.0, 100.0], [-1000.0, 100.0]])
@@ -268,6 +296,42 @@ def test_hand_computed_straight_track_cost():
     # repair horizon: only the first transition counted -> no violation
     lin1, _ = oracle.objective(M, C, tr, x0, V, dict(w_S=0.0, w_sq=0.0, w_lin=1.0, n_lin=1))
     assert lin1 == 0.0
+
+
+def _golden_case(tr, x0, T, g, key):
+    V = np.tile([0.0, 1.0], (T, 1))
+    S, eps, _ = oracle.rollout(M, C, tr, x0, V, K=2, seed=0, pid=0, it=0, nominal=True)
+    assert np.allclose(S, g[key + "_S_tilde"], rtol=0, atol=1e-9), (key, S)
+    tot, _ = oracle.objective(M, C, tr, x0, V, dict(w_S=1.0, w_sq=0.0, w_lin=0.0, n_lin=0))
+    assert tot == pytest.approx(g[key + "_S_no_indicator"], abs=1e-9), key
+    lin, _ = oracle.objective(M, C, tr, x0, V, dict(w_S=0.0, w_sq=0.0, w_lin=1.0, n_lin=99))
+    assert lin == pytest.approx(g[key + "_sum_viol"], abs=1e-12), key
+    if key + "_sum_viol_sq" in g:
+        sq, _ = oracle.objective(M, C, tr, x0, V, dict(w_S=0.0, w_sq=1.0, w_lin=0.0, n_lin=0))
+        assert sq == pytest.approx(g[key + "_sum_viol_sq"], abs=1e-12), key
+    # the trajectory's barrier values: h_0 from the track, h_i = |p - c_i|^2 - r_eff^2
+    _, hs = oracle.trajectory(M, C, tr, x0, V)
+    return hs
+
+
+def test_hand_computed_obstacle_and_start_outside_costs():
+    """Worked examples in tests/golden/obstacle_cost.txt: the obstacle barrier with its inflated
+    radius, the collision indicator with the physical radius (switching at a different step than
+    the hinge), and the z_0 term C max((alpha - 1) h(x_0), 0) for starts outside the track and
+    inside an obstacle."""
+    g = {r[0]: float(r[1]) for r in _read_golden("obstacle_cost.txt")}
+    tr = _straight_track()
+    tr.obs = np.array([[0.8, 0.35, 0.55 ** 2, 0.4 ** 2]])
+    hs = _golden_case(tr, np.array([0.0, 0.0, 0.0, 8.0, 0.0, 0.0]), 4, g, "A")
+    assert np.allclose(hs[:, 1], [0.46, -0.02, -0.18, -0.02, 0.46], atol=1e-12)
+    assert np.allclose(hs[:, 0], 1.0, atol=1e-12)
+    tr = _straight_track()
+    hs = _golden_case(tr, np.array([0.0, 1.5, 0.0, 8.0, 0.0, 0.0]), 2, g, "B")
+    assert np.allclose(hs[:, 0], -1.25, atol=1e-12)
+    tr = _straight_track()
+    tr.obs = np.array([[0.0, 0.1, 0.35 ** 2, 0.2 ** 2]])
+    hs = _golden_case(tr, np.array([0.0, 0.0, 0.0, 8.0, 0.0, 0.0]), 2, g, "C")
+    assert np.allclose(hs[:, 1], [-0.1125, 0.0475, 0.5275], atol=1e-12)
 
 
 def test_zero_noise_samples_all_equal_nominal():
