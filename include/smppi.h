@@ -17,10 +17,12 @@
  *    enqueued on it and the call returns without synchronising.  Validation
  *    errors are detected before anything is enqueued.  Faults inside kernels
  *    surface at the caller's next synchronisation.
- *  - Scratch memory is owned by the ctx and grown on demand (a call that needs
- *    more than the ctx holds allocates before it enqueues work; smppi_reserve
- *    pre-sizes it).  A ctx is not thread-safe, and calls made on one ctx must be
- *    ordered on one stream: they share the ctx's scratch.
+ *  - Scratch memory is owned by the ctx and sized by smppi_reserve_batch (or
+ *    by a plan at creation).  No call that enqueues work allocates device
+ *    memory: a call whose batch needs more scratch than the ctx holds returns
+ *    SMPPI_ERR_SHAPE before enqueueing anything.  A ctx is not thread-safe, and
+ *    calls made on one ctx must be ordered on one stream: they share the ctx's
+ *    scratch.
  *  - The library never aborts and never prints; smppi_last_error() describes the
  *    last non-OK status of a ctx.
  *
@@ -39,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SMPPI_ABI_VERSION 4
+#define SMPPI_ABI_VERSION 5
 
 typedef enum {
   SMPPI_OK = 0,
@@ -173,8 +175,15 @@ void smppi_destroy(smppi_ctx ctx);
 const char* smppi_last_error(smppi_ctx ctx);
 const char* smppi_status_string(smppi_status s);
 int smppi_abi_version(void);
-/* Pre-size the ctx scratch to at least `bytes` (optional). */
-smppi_status smppi_reserve(smppi_ctx ctx, uint64_t bytes);
+/* Size the ctx's scratch for the plain calls on any batch within the host
+ * bounds of `batch` (n_problems, k_max, t_max, dtype; its device arrays are not
+ * read): the update's and the adjoint's per-workgroup partials
+ * (dtype bytes x B x ceil(k_max / workgroup samples) x 2 x t_max), the padded
+ * obstacle slots of FP32 rollouts (B x 64 x 16 bytes) and B ticket counters.
+ * Allocates (and synchronises) only when the ctx holds less; the scratch never
+ * shrinks.  Call it before smppi_rollout (FP32 with obstacles), smppi_update
+ * and smppi_rollout_backward, outside timed or captured regions. */
+smppi_status smppi_reserve_batch(smppi_ctx ctx, const smppi_batch* batch);
 /* Synchronise the device, return (and clear) the OR of the input-bound errors
  * kernels detected on device data since the last call: 1 = some T_b outside
  * [1, t_max], 2 = some K_b outside [0, k_max], 4 = some polyline longer than
@@ -192,8 +201,9 @@ smppi_status smppi_device_errors(smppi_ctx ctx, uint32_t* flags);
  * eps_out: NULL, or device [sum K][t_max][2] dtype receiving the effective
  *   noise u - v of every step (debug/test; rows beyond T_b untouched).
  * FP32 with obstacles: a small kernel first copies every problem's obstacles
- * into padded slots in the ctx scratch (B * 64 * 16 bytes), which the rollout
- * kernel reads through the scalar cache. */
+ * into padded slots in the ctx scratch (B * 64 * 16 bytes, see
+ * smppi_reserve_batch), which the rollout kernel reads through the scalar
+ * cache. */
 smppi_status smppi_rollout(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
                            const smppi_cost* cost, const smppi_noise* noise, const smppi_track* track,
                            const void* x0, const void* V, const uint32_t* iter, void* S, void* eps_out,

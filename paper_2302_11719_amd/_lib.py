@@ -22,9 +22,9 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "shape", 3: "dtype", 4: "no device"
 ERR_NO_DEVICE = 4
 
 # Symbols declared in include/smppi.h (checked by the CPU test suite).
-ABI_VERSION = 4  # SMPPI_ABI_VERSION of include/smppi.h this binding matches
+ABI_VERSION = 5  # SMPPI_ABI_VERSION of include/smppi.h this binding matches
 EXPORTS = ("smppi_rollout_curvilinear", "smppi_create", "smppi_destroy", "smppi_last_error", "smppi_status_string", "smppi_abi_version",
-           "smppi_reserve", "smppi_device_errors", "smppi_rollout", "smppi_weights", "smppi_update",
+           "smppi_reserve_batch", "smppi_device_errors", "smppi_rollout", "smppi_weights", "smppi_update",
            "smppi_rollout_backward", "smppi_shield_repair", "smppi_execute", "smppi_plan_create",
            "smppi_plan_launch", "smppi_plan_destroy", "smppi_plan_info", "smppi_plan_launch_profiled",
            "smppi_plan_stage_ms", "smppi_plan_kernel_ms", "smppi_debug_philox")
@@ -96,7 +96,7 @@ _SIGS = {
     "smppi_last_error": (ctypes.c_char_p, [c_vp]),
     "smppi_status_string": (ctypes.c_char_p, [c_i32]),
     "smppi_abi_version": (ctypes.c_int, []),
-    "smppi_reserve": (c_i32, [c_vp, ctypes.c_uint64]),
+    "smppi_reserve_batch": (c_i32, [c_vp, P(Batch)]),
     "smppi_device_errors": (c_i32, [c_vp, P(c_u32)]),
     "smppi_rollout_curvilinear": (c_i32, [c_vp, P(Batch), P(Model), P(Cost), P(Noise), P(CurvTrack), c_vp, c_vp,
                                           c_vp, c_vp, c_vp, c_vp]),

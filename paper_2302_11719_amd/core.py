@@ -34,11 +34,20 @@ class Context:
             raise SmppiError(st, f"smppi_create(device={device})")
         self.h = h
         self.device = device
+        self._reserved = set()
 
     def check(self, st: int, what: str):
         if st:
             msg = L.lib().smppi_last_error(self.h)
             raise SmppiError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def reserve(self, db: "DeviceBatch"):
+        """smppi_reserve_batch for db's bounds (a host call that allocates only when the
+        ctx's scratch is smaller; the calls below make it once per new batch shape)."""
+        key = (db.B, db.batch.k_max, db.batch.t_max, db.batch.dtype)
+        if key not in self._reserved:
+            self.check(L.lib().smppi_reserve_batch(self.h, ctypes.byref(db.batch)), "smppi_reserve_batch")
+            self._reserved.add(key)
 
     def device_errors(self) -> int:
         v = ctypes.c_uint32(0)
@@ -136,6 +145,7 @@ def rollout(ctx: Context, db: DeviceBatch, model: dict, cost: dict, seed: int, n
     """smppi_rollout: per-sample modified costs S~ [sum K] (and effective noise if asked)."""
     S = db.new_S() if S is None else S
     eps = torch.zeros(db.sum_K * db.t_max * 2, dtype=db.dtype, device=db.device) if want_eps else None
+    ctx.reserve(db)
     st = L.lib().smppi_rollout(ctx.h, ctypes.byref(db.batch), ctypes.byref(L.model_struct(model)),
                                ctypes.byref(L.cost_struct(cost)), ctypes.byref(_noise(seed, nominal)),
                                ctypes.byref(db.track), _p(db.x0 if x0 is None else x0), _p(db.V if V is None else V),
@@ -189,6 +199,7 @@ def update(ctx: Context, db: DeviceBatch, model: dict, cost: dict, seed: int, w:
     """smppi_update: V+ in the library layout."""
     V = db.V if V is None else V
     out = db.new_V() if out is None else out
+    ctx.reserve(db)
     st = L.lib().smppi_update(ctx.h, ctypes.byref(db.batch), ctypes.byref(L.model_struct(model)),
                               ctypes.byref(L.cost_struct(cost)), ctypes.byref(_noise(seed, nominal)), _p(V), _p(w),
                               _p(db.iter if iters is None else iters), _p(out), ctypes.c_void_p(_stream()))
@@ -201,12 +212,14 @@ def rollout_backward(ctx: Context, db: DeviceBatch, model: dict, cost: dict, see
     """smppi_rollout_backward: sum_m grad_S[m] dL_m/dV in the library layout."""
     V = db.V if V is None else V
     out = db.new_V() if out is None else out
-    st = L.lib().smppi_rollout_backward(
+    ctx.reserve(db)
+    fn, name = L.lib().smppi_rollout_backward, "smppi_rollout_backward"
+    st = fn(
         ctx.h, ctypes.byref(db.batch), ctypes.byref(L.model_struct(model)), ctypes.byref(L.cost_struct(cost)),
         ctypes.byref(_noise(seed, nominal)), ctypes.byref(db.track), _p(db.x0 if x0 is None else x0), _p(V),
         _p(db.iter if iters is None else iters), _p(grad_S), ctypes.byref(L.objective_struct(objective)), _p(out),
         ctypes.c_void_p(_stream()))
-    ctx.check(st, "smppi_rollout_backward")
+    ctx.check(st, name)
     return out
 
 

@@ -19,7 +19,7 @@ struct smppi_ctx_s {
   int n_tickets = 0;
   uint32_t* err = nullptr;
   std::vector<void*> retired;
-  std::string last;
+  char last[512] = {0};  // message of the last non-OK status
 };
 
 extern "C" smppi_status smppi_device_errors(smppi_ctx ctx, uint32_t* flags);
@@ -40,6 +40,8 @@ smppi_status fail(smppi_ctx ctx, smppi_status s, const char* fmt, ...);
 smppi_status hip_fail(smppi_ctx ctx, hipError_t e, const char* what);
 smppi_status ensure_scratch(smppi_ctx ctx, size_t bytes);
 smppi_status ensure_tickets(smppi_ctx ctx, int n);
+size_t batch_scratch_bytes(const smppi_batch* b);
+smppi_status need_scratch(smppi_ctx ctx, size_t bytes, int tickets, const char* what);
 smppi_status check_launch(smppi_ctx ctx, const char* what);
 smppi_status validate_batch(smppi_ctx ctx, const smppi_batch* b);
 smppi_status validate_model(smppi_ctx ctx, const smppi_model* m);

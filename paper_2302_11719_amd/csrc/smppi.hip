@@ -18,13 +18,11 @@ using namespace smppi;
 
 // ------------------------------------------------------------------ helpers
 smppi_status smppi::fail(smppi_ctx ctx, smppi_status s, const char* fmt, ...) {
-  if (ctx) {
-    char buf[512];
+  if (ctx) {  // formatted into the ctx's fixed buffer: error paths allocate nothing either
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
+    vsnprintf(ctx->last, sizeof(ctx->last), fmt, ap);
     va_end(ap);
-    ctx->last = buf;
   }
   return s;
 }
@@ -58,6 +56,26 @@ smppi_status smppi::ensure_tickets(smppi_ctx ctx, int n) {
   ctx->tickets = static_cast<uint32_t*>(p);
   ctx->n_tickets = want;
   return SMPPI_OK;
+}
+
+// Scratch of the plain calls for a batch within these host bounds: the
+// update's and the adjoint's per-workgroup partials [B][workgroups][2][t_max]
+// and, for FP32 rollouts with obstacles, the padded obstacle slots [B][64].
+size_t smppi::batch_scratch_bytes(const smppi_batch* b) {
+  const size_t r = b->dtype == SMPPI_F32 ? sizeof(float) : sizeof(double);
+  const size_t B = (size_t)b->n_problems, k = (size_t)std::max(0, b->k_max), t = (size_t)b->t_max;
+  const size_t upd = r * B * std::max<size_t>(1, (k + UPD_BLOCK - 1) / UPD_BLOCK) * 2 * t;
+  const size_t bwd = r * B * std::max<size_t>(1, (k + WAVE - 1) / WAVE) * 2 * t;
+  const size_t pad = b->dtype == SMPPI_F32 ? sizeof(float4) * B * kMaxObs : 0;
+  return std::max(upd, std::max(bwd, pad));
+}
+
+smppi_status smppi::need_scratch(smppi_ctx ctx, size_t bytes, int tickets, const char* what) {
+  if (bytes <= ctx->scratch_bytes && tickets <= ctx->n_tickets) return SMPPI_OK;
+  return fail(ctx, SMPPI_ERR_SHAPE,
+              "%s needs %zu B of scratch and %d tickets, the ctx holds %zu B and %d: size it with "
+              "smppi_reserve_batch for this batch first",
+              what, bytes, tickets, ctx->scratch_bytes, ctx->n_tickets);
 }
 
 smppi_status smppi::check_launch(smppi_ctx ctx, const char* what) {
@@ -263,12 +281,15 @@ extern "C" void smppi_destroy(smppi_ctx ctx) {
   delete ctx;
 }
 
-extern "C" const char* smppi_last_error(smppi_ctx ctx) { return ctx ? ctx->last.c_str() : "no ctx"; }
+extern "C" const char* smppi_last_error(smppi_ctx ctx) { return ctx ? ctx->last : "no ctx"; }
 
-extern "C" smppi_status smppi_reserve(smppi_ctx ctx, uint64_t bytes) {
+extern "C" smppi_status smppi_reserve_batch(smppi_ctx ctx, const smppi_batch* batch) {
   if (!ctx) return SMPPI_ERR_INVALID_ARGUMENT;
+  smppi_status st;
+  if ((st = validate_batch(ctx, batch))) return st;
   (void)hipSetDevice(ctx->device);
-  return ensure_scratch(ctx, (size_t)bytes);
+  if ((st = ensure_scratch(ctx, batch_scratch_bytes(batch)))) return st;
+  return ensure_tickets(ctx, batch->n_problems);
 }
 
 extern "C" smppi_status smppi_device_errors(smppi_ctx ctx, uint32_t* flags) {
@@ -296,7 +317,7 @@ static smppi_status launch_rollout(smppi_ctx ctx, const smppi_batch* b, const Ro
   ra.obs_pad = nullptr;
   if (NOBS > 0 && sizeof(R) == 4) {
     // FP32 obstacles go through the scalar cache from padded slots in the scratch buffer
-    smppi_status st = ensure_scratch(ctx, sizeof(float4) * (size_t)b->n_problems * NOBS);
+    smppi_status st = need_scratch(ctx, sizeof(float4) * (size_t)b->n_problems * NOBS, 0, "smppi_rollout");
     if (st) return st;
     float4* pad = static_cast<float4*>(ctx->scratch);
     hipLaunchKernelGGL(k_pad_obs, dim3(b->n_problems), dim3(64), 0, s, a.p.obs_off,
@@ -433,8 +454,9 @@ static smppi_status update_t(smppi_ctx ctx, const smppi_batch* b, const smppi_mo
   a.V_plus = static_cast<R*>(Vp);
   a.nblk_max = std::max(1, (b->k_max + UPD_BLOCK - 1) / UPD_BLOCK);
   smppi_status st;
-  if ((st = ensure_scratch(ctx, sizeof(R) * (size_t)b->n_problems * a.nblk_max * 2 * b->t_max))) return st;
-  if ((st = ensure_tickets(ctx, b->n_problems))) return st;
+  if ((st = need_scratch(ctx, sizeof(R) * (size_t)b->n_problems * a.nblk_max * 2 * b->t_max, b->n_problems,
+                         "smppi_update")))
+    return st;
   a.part = static_cast<R*>(ctx->scratch);
   a.tickets = ctx->tickets;
   hipLaunchKernelGGL((k_update<R>), dim3(a.nblk_max, b->n_problems), dim3(UPD_BLOCK), 0, s, a);
@@ -466,11 +488,17 @@ static smppi_status launch_backward(smppi_ctx ctx, const smppi_batch* b, const B
   return check_launch(ctx, "k_backward");
 }
 
+// Workgroups per problem of the adjoint kernel (one sample per lane).
+static int backward_nblk(const smppi_batch* b) { return std::max(1, (b->k_max + WAVE - 1) / WAVE); }
+
+// The adjoint launch with its scratch given: part = per-workgroup partials
+// [B][nblk][2][t_max] dtype, tickets = B counters that are zero on entry (the
+// combining workgroup of each problem resets its counter).
 template <class R>
-static smppi_status backward_t(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const smppi_cost* c,
-                               const smppi_noise* n, const smppi_track* t, const void* x0, const void* V,
-                               const uint32_t* iter, const void* gS, const smppi_objective* ob, void* gV,
-                               hipStream_t s) {
+static smppi_status backward_launch(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const smppi_cost* c,
+                                    const smppi_noise* n, const smppi_track* t, const void* x0, const void* V,
+                                    const uint32_t* iter, const void* gS, const smppi_objective* ob, void* gV,
+                                    R* part, uint32_t* tickets, hipStream_t s) {
   BackwardArgs<R> a;
   a.p = problem_args<R>(ctx, b, t, n, x0, iter);
   a.M = dev_model<R>(m);
@@ -479,21 +507,45 @@ static smppi_status backward_t(smppi_ctx ctx, const smppi_batch* b, const smppi_
   a.V = static_cast<const R*>(V);
   a.grad_S = static_cast<const R*>(gS);
   a.grad_V = static_cast<R*>(gV);
-  a.nblk_max = std::max(1, (b->k_max + WAVE - 1) / WAVE);
+  a.nblk_max = backward_nblk(b);
   a.seg_len = adj_seg_len(b->t_max);
-  smppi_status st;
-  if ((st = ensure_scratch(ctx, sizeof(R) * (size_t)b->n_problems * a.nblk_max * 2 * b->t_max))) return st;
-  if ((st = ensure_tickets(ctx, b->n_problems))) return st;
-  a.part = static_cast<R*>(ctx->scratch);
-  a.tickets = ctx->tickets;
+  a.part = part;
+  a.tickets = tickets;
   if (t->obs_max > 0) return launch_backward<R, kMaxObs>(ctx, b, a, s);
   return launch_backward<R, 0>(ctx, b, a, s);
+}
+
+template <class R>
+static smppi_status backward_t(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const smppi_cost* c,
+                               const smppi_noise* n, const smppi_track* t, const void* x0, const void* V,
+                               const uint32_t* iter, const void* gS, const smppi_objective* ob, void* gV,
+                               hipStream_t s) {
+  smppi_status st;
+  if ((st = need_scratch(ctx, sizeof(R) * (size_t)b->n_problems * backward_nblk(b) * 2 * b->t_max, b->n_problems,
+                         "smppi_rollout_backward")))
+    return st;
+  return backward_launch<R>(ctx, b, m, c, n, t, x0, V, iter, gS, ob, gV, static_cast<R*>(ctx->scratch),
+                            ctx->tickets, s);
 }
 
 smppi_status smppi::validate_objective(smppi_ctx ctx, const smppi_objective* o) {
   if (!o) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "objective is NULL");
   if (!std::isfinite(o->w_S) || !std::isfinite(o->w_sq) || !std::isfinite(o->w_lin))
     return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "objective weights must be finite");
+  return SMPPI_OK;
+}
+
+static smppi_status validate_backward(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                                      const smppi_cost* cost, const smppi_noise* noise, const smppi_track* track,
+                                      const void* x0, const void* V, const uint32_t* iter, const void* grad_S,
+                                      const smppi_objective* objective, const void* grad_V) {
+  smppi_status st;
+  if ((st = validate_batch(ctx, batch)) || (st = validate_model(ctx, model)) || (st = validate_cost(ctx, cost)) ||
+      (st = validate_track(ctx, track, batch->dtype, batch->t_max)) || (st = validate_objective(ctx, objective)))
+    return st;
+  if (!noise) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "noise is NULL");
+  if (!x0 || !V || !iter || !grad_S || !grad_V)
+    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "x0, V, iter, grad_S, grad_V are required");
   return SMPPI_OK;
 }
 
@@ -504,12 +556,8 @@ extern "C" smppi_status smppi_rollout_backward(smppi_ctx ctx, const smppi_batch*
                                                const smppi_objective* objective, void* grad_V, void* stream) {
   if (!ctx) return SMPPI_ERR_INVALID_ARGUMENT;
   smppi_status st;
-  if ((st = validate_batch(ctx, batch)) || (st = validate_model(ctx, model)) || (st = validate_cost(ctx, cost)) ||
-      (st = validate_track(ctx, track, batch->dtype, batch->t_max)) || (st = validate_objective(ctx, objective)))
+  if ((st = validate_backward(ctx, batch, model, cost, noise, track, x0, V, iter, grad_S, objective, grad_V)))
     return st;
-  if (!noise) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "noise is NULL");
-  if (!x0 || !V || !iter || !grad_S || !grad_V)
-    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "x0, V, iter, grad_S, grad_V are required");
   (void)hipSetDevice(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (batch->dtype == SMPPI_F32)

@@ -88,3 +88,22 @@ def test_struct_layouts_match_c(tmp_path):
         for f in fields.get(cname, []):
             pyf = "lambda_" if f == "lambda" else f
             assert int(got[f"{cname}.{f}"]) == getattr(py, pyf).offset, f"{cname}.{f}"
+
+
+def test_hot_calls_never_allocate():
+    """Device memory is allocated only by smppi_create, smppi_reserve_batch and the plan
+    calls: the scratch-growing helpers are called from smppi_reserve_batch alone, and the
+    hot calls check the reserved size instead (SMPPI_ERR_SHAPE)."""
+    src = open(os.path.join(ROOT, "paper_2302_11719_amd", "csrc", "smppi.hip")).read()
+    body = lambda name: src[src.index(name):]
+    for helper in ("ensure_scratch(", "ensure_tickets("):
+        callers = [m.start() for m in re.finditer(re.escape(helper), src)]
+        # the definition, and one call inside smppi_reserve_batch
+        defs = [i for i in callers if src[max(0, i - 8):i].endswith("smppi::")]
+        calls = [i for i in callers if i not in defs]
+        start = src.index('smppi_reserve_batch(smppi_ctx ctx')
+        end = src.index("\n}\n", start)
+        assert len(defs) == 1 and calls and all(start < i < end for i in calls), helper
+    assert "hipMalloc" not in body("// ------------------------------------------------------------------ rollout")
+    hdr = open(HEADER).read()
+    assert "No call that enqueues work allocates" in hdr and "smppi_reserve_batch" in hdr
