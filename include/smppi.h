@@ -249,6 +249,23 @@ smppi_status smppi_rollout_backward(smppi_ctx ctx, const smppi_batch* batch, con
                                     const uint32_t* iter, const void* grad_S,
                                     const smppi_objective* objective, void* grad_V, void* stream);
 
+/* smppi_rollout_backward for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, same kernels and results, but the ticket
+ * counters and per-workgroup partials live in a fixed scratch array that each
+ * GPU holds for the life of the process (looked up at smppi_create), so no
+ * smppi_reserve_batch is needed and nothing is allocated.  Limits: at most 4096
+ * problems and dtype bytes x B x ceil(k_max / 64) x 2 x t_max <= 8 MiB of
+ * partials, else SMPPI_ERR_SHAPE before anything is enqueued.  Every call on a
+ * GPU shares that GPU's array (the counters are cleared by a kernel at the
+ * start of each call): calls that overlap on one GPU, from any ctx or thread,
+ * race and must be ordered by the caller. */
+smppi_status smppi_rollout_backward_noalloc(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                                            const smppi_cost* cost, const smppi_noise* noise,
+                                            const smppi_track* track, const void* x0, const void* V,
+                                            const uint32_t* iter, const void* grad_S,
+                                            const smppi_objective* objective, void* grad_V, void* stream);
+
 /* Safety shield (Algorithm 1, eq. (22)): V_safe = repair of V_plus from x0 (see
  * smppi_repair_opts).  V_safe may equal V_plus. */
 smppi_status smppi_shield_repair(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,

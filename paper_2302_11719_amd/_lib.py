@@ -25,7 +25,7 @@ ERR_NO_DEVICE = 4
 ABI_VERSION = 5  # SMPPI_ABI_VERSION of include/smppi.h this binding matches
 EXPORTS = ("smppi_rollout_curvilinear", "smppi_create", "smppi_destroy", "smppi_last_error", "smppi_status_string", "smppi_abi_version",
            "smppi_reserve_batch", "smppi_device_errors", "smppi_rollout", "smppi_weights", "smppi_update",
-           "smppi_rollout_backward", "smppi_shield_repair", "smppi_execute", "smppi_plan_create",
+           "smppi_rollout_backward", "smppi_rollout_backward_noalloc", "smppi_shield_repair", "smppi_execute", "smppi_plan_create",
            "smppi_plan_launch", "smppi_plan_destroy", "smppi_plan_info", "smppi_plan_launch_profiled",
            "smppi_plan_stage_ms", "smppi_plan_kernel_ms", "smppi_debug_philox")
 
@@ -106,6 +106,8 @@ _SIGS = {
     "smppi_update": (c_i32, [c_vp, P(Batch), P(Model), P(Cost), P(Noise), c_vp, c_vp, c_vp, c_vp, c_vp]),
     "smppi_rollout_backward": (c_i32, [c_vp, P(Batch), P(Model), P(Cost), P(Noise), P(Track), c_vp, c_vp, c_vp,
                                        c_vp, P(Objective), c_vp, c_vp]),
+    "smppi_rollout_backward_noalloc": (c_i32, [c_vp, P(Batch), P(Model), P(Cost), P(Noise), P(Track), c_vp, c_vp,
+                                               c_vp, c_vp, P(Objective), c_vp, c_vp]),
     "smppi_shield_repair": (c_i32, [c_vp, P(Batch), P(Model), P(Cost), P(Track), c_vp, c_vp, P(RepairOpts), c_vp,
                                     c_vp]),
     "smppi_execute": (c_i32, [c_vp, P(Batch), P(Model), c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),

@@ -208,12 +208,18 @@ def update(ctx: Context, db: DeviceBatch, model: dict, cost: dict, seed: int, w:
 
 
 def rollout_backward(ctx: Context, db: DeviceBatch, model: dict, cost: dict, seed: int, grad_S: torch.Tensor,
-                     objective: dict, nominal: bool = False, V=None, x0=None, iters=None, out=None):
-    """smppi_rollout_backward: sum_m grad_S[m] dL_m/dV in the library layout."""
+                     objective: dict, nominal: bool = False, V=None, x0=None, iters=None, out=None,
+                     noalloc: bool = False):
+    """smppi_rollout_backward: sum_m grad_S[m] dL_m/dV in the library layout.
+    noalloc=True calls smppi_rollout_backward_noalloc (fixed device scratch, nothing
+    reserved or allocated; `out` should then be preallocated by the caller)."""
     V = db.V if V is None else V
     out = db.new_V() if out is None else out
-    ctx.reserve(db)
-    fn, name = L.lib().smppi_rollout_backward, "smppi_rollout_backward"
+    if noalloc:
+        fn, name = L.lib().smppi_rollout_backward_noalloc, "smppi_rollout_backward_noalloc"
+    else:
+        ctx.reserve(db)
+        fn, name = L.lib().smppi_rollout_backward, "smppi_rollout_backward"
     st = fn(
         ctx.h, ctypes.byref(db.batch), ctypes.byref(L.model_struct(model)), ctypes.byref(L.cost_struct(cost)),
         ctypes.byref(_noise(seed, nominal)), ctypes.byref(db.track), _p(db.x0 if x0 is None else x0), _p(V),

@@ -18,6 +18,7 @@ struct smppi_ctx_s {
   uint32_t* tickets = nullptr;
   int n_tickets = 0;
   uint32_t* err = nullptr;
+  void* noalloc = nullptr;  // device address of the fixed scratch of the no-allocation entry point
   std::vector<void*> retired;
   char last[512] = {0};  // message of the last non-OK status
 };

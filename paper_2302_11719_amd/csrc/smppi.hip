@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -246,6 +247,8 @@ extern "C" const char* smppi_status_string(smppi_status s) {
   return "unknown status";
 }
 
+static smppi_status noalloc_setup(smppi_ctx ctx);
+
 extern "C" smppi_status smppi_create(int device, smppi_ctx* out) {
   if (!out) return SMPPI_ERR_INVALID_ARGUMENT;
   *out = nullptr;
@@ -266,6 +269,11 @@ extern "C" smppi_status smppi_create(int device, smppi_ctx* out) {
     return SMPPI_ERR_HIP;
   }
   ctx->err = static_cast<uint32_t*>(e);
+  if (noalloc_setup(ctx) != SMPPI_OK) {
+    (void)hipFree(ctx->err);
+    delete ctx;
+    return SMPPI_ERR_HIP;
+  }
   *out = ctx;
   return SMPPI_OK;
 }
@@ -563,6 +571,82 @@ extern "C" smppi_status smppi_rollout_backward(smppi_ctx ctx, const smppi_batch*
   if (batch->dtype == SMPPI_F32)
     return backward_t<float>(ctx, batch, model, cost, noise, track, x0, V, iter, grad_S, objective, grad_V, s);
   return backward_t<double>(ctx, batch, model, cost, noise, track, x0, V, iter, grad_S, objective, grad_V, s);
+}
+
+// ------------------------------------------------------------------ adjoint without allocation
+// For callers that cannot allocate device memory: the adjoint's ticket
+// counters and per-workgroup partials live in one fixed file-scope device
+// array.  Each GPU the library runs on holds its own copy until the process
+// ends; host code reaches it only through the address hipGetSymbolAddress
+// returned for that device at smppi_create (the array's name is a host-side
+// stand-in, not a device address).  Every call on a GPU shares that GPU's
+// copy: calls that overlap on one GPU race.
+namespace {
+constexpr size_t kNoAllocTicketBytes = 16384;  // 4096 problems
+constexpr size_t kNoAllocBytes = (8u << 20) + kNoAllocTicketBytes;
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char noalloc_scratch[kNoAllocBytes];
+
+namespace smppi {
+__global__ void k_zero_u32(uint32_t* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+}  // namespace smppi
+
+// The array's device address on ctx->device (that device current): looked up
+// once per device, kept for the life of the process.
+static smppi_status noalloc_setup(smppi_ctx ctx) {
+  ctx->noalloc = nullptr;
+  if (ctx->device >= kMaxDevices) return SMPPI_OK;  // the entry point then reports UNSUPPORTED
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[ctx->device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+    if (e != hipSuccess || !p) return hip_fail(ctx, e, "hipGetSymbolAddress(noalloc_scratch)");
+    g_noalloc_ptr[ctx->device] = p;
+  }
+  ctx->noalloc = g_noalloc_ptr[ctx->device];
+  return SMPPI_OK;
+}
+
+extern "C" smppi_status smppi_rollout_backward_noalloc(smppi_ctx ctx, const smppi_batch* batch,
+                                                       const smppi_model* model, const smppi_cost* cost,
+                                                       const smppi_noise* noise, const smppi_track* track,
+                                                       const void* x0, const void* V, const uint32_t* iter,
+                                                       const void* grad_S, const smppi_objective* objective,
+                                                       void* grad_V, void* stream) {
+  if (!ctx) return SMPPI_ERR_INVALID_ARGUMENT;
+  smppi_status st;
+  if ((st = validate_backward(ctx, batch, model, cost, noise, track, x0, V, iter, grad_S, objective, grad_V)))
+    return st;
+  if (!ctx->noalloc) return fail(ctx, SMPPI_ERR_UNSUPPORTED, "no fixed scratch on device %d", ctx->device);
+  const size_t rb = batch->dtype == SMPPI_F32 ? sizeof(float) : sizeof(double);
+  const size_t part = rb * (size_t)batch->n_problems * backward_nblk(batch) * 2 * batch->t_max;
+  if ((size_t)batch->n_problems * sizeof(uint32_t) > kNoAllocTicketBytes ||
+      part > kNoAllocBytes - kNoAllocTicketBytes)
+    return fail(ctx, SMPPI_ERR_SHAPE,
+                "smppi_rollout_backward_noalloc: the batch needs %d ticket counters (max %zu) and %zu B of "
+                "partials (dtype bytes x B x ceil(k_max/64) x 2 x t_max; max %zu)",
+                batch->n_problems, kNoAllocTicketBytes / sizeof(uint32_t), part, kNoAllocBytes - kNoAllocTicketBytes);
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* base = static_cast<unsigned char*>(ctx->noalloc);
+  uint32_t* tickets = reinterpret_cast<uint32_t*>(base);
+  // the counters must start at zero: cleared by a kernel (capturable; no memset node)
+  hipLaunchKernelGGL(k_zero_u32, dim3((batch->n_problems + 255) / 256), dim3(256), 0, s, tickets,
+                     batch->n_problems);
+  if ((st = check_launch(ctx, "k_zero_u32"))) return st;
+  void* pp = base + kNoAllocTicketBytes;
+  if (batch->dtype == SMPPI_F32)
+    return backward_launch<float>(ctx, batch, model, cost, noise, track, x0, V, iter, grad_S, objective, grad_V,
+                                  static_cast<float*>(pp), tickets, s);
+  return backward_launch<double>(ctx, batch, model, cost, noise, track, x0, V, iter, grad_S, objective, grad_V,
+                                 static_cast<double*>(pp), tickets, s);
 }
 
 // ------------------------------------------------------------------ repair
