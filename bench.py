@@ -17,7 +17,8 @@ kernel's roofline, and the FP64 CPU oracle on a bounded sample of the headline
 workload.
 
 usage: python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--skip-cpu] [--quick]
-                       [--forms split,plain,identical,ragged,large,c3,shield,autotune,sweep,curvilinear]
+                       [--forms split,active,plain,identical,ragged,large,c0,c3,c4adj,shield,autotune,sweep,
+                                curvilinear]
                        [--copy-calibration-mib N]
 """
 from __future__ import annotations
@@ -42,7 +43,8 @@ FLOP_UPDATE_STEP = 4      # w * eps' accumulated for two controls
 FLOP_STEP_CURV = 284      # curvilinear model: no window (-117), Frenet kinematics with curvature lookup (+56)
 PEAK_FP32 = 157.3e12      # MI355X FP32 vector peak (packed FMA on every lane)
 PEAK_HBM = 8.0e12
-FORMS = ("split", "plain", "identical", "ragged", "large", "c3", "shield", "autotune", "sweep", "curvilinear")
+FORMS = ("split", "active", "plain", "identical", "ragged", "large", "c0", "c3", "c4adj", "shield", "autotune", "sweep",
+         "curvilinear")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_K4096_T50_hbm_traffic.md")
 # The paper's own control rates (Sec. VI-G, the vehicle experiment and its results table):
 # context only, other vehicle model, horizon, precision and hardware.
@@ -67,9 +69,10 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline only (same as --forms none)")
     ap.add_argument("--forms", default="all",
                     help="comma list of the extra forms to run: split (the headline with the shield as a "
-                         "kernel of its own), plain, identical, ragged, large, c3, shield, autotune, sweep, "
-                         "curvilinear (or all/none); without split, every k_fused launch of the run is the "
-                         "headline kernel")
+                         "kernel of its own), active (the headline from a start where the shield fires), plain, "
+                         "identical, ragged, large, c0 (FP64), c3 (adjoint repair), c4adj (free-energy "
+                         "adjoint), shield, autotune, sweep, curvilinear (or all/none); without split and "
+                         "active, every k_fused launch of the run is the headline kernel")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -244,6 +247,8 @@ def _time(fn, n, warm, sync):
 def extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync, forms):
     out = {}
     seed = 0
+    if "active" in forms:
+        _form_active(ctx, core, W, M, C, lam, rep, K, T, sync, out, seed)
     if "plain" in forms:
         _form_plain(ctx, core, W, M, C, lam, K, T, sync, out, seed)
     if "identical" in forms:
@@ -252,8 +257,12 @@ def extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync, forms):
         _form_ragged(ctx, core, W, M, C, lam, sync, out, seed)
     if "large" in forms:
         _form_large(ctx, core, W, M, C, lam, sync, out, seed)
+    if "c0" in forms:
+        _form_c0(ctx, core, W, lam, sync, out, seed)
     if "c3" in forms:
         _form_c3(ctx, core, W, M, C, lam, rep, sync, out, seed)
+    if "c4adj" in forms:
+        _form_c4_adjoint(ctx, core, W, M, C, lam, sync, out, seed)
     if "shield" in forms:
         _form_shield(ctx, core, W, M, C, rep, sync, out)
     if "autotune" in forms:
@@ -263,6 +272,55 @@ def extra_forms(ctx, core, W, M, C, lam, rep, K, T, sync, forms):
     if "curvilinear" in forms:
         _form_curvilinear(ctx, core, W, M, C, sync, out, seed)
     return out
+
+
+def _active_fraction(db, V_plus, V_safe):
+    """Fraction of problems whose shield output differs from the MPPI output (the shield
+    changed the controls because some DCBF condition was violated)."""
+    a, b = db.controls(V_plus), db.controls(V_safe)
+    return float(np.mean([not np.array_equal(x, y) for x, y in zip(a, b)]))
+
+
+def _offset_start(W, tr, lat, dpsi, vx):
+    x0 = W.start_state(tr, vx=vx)
+    ax, ay, dx, dy = tr.poly[0, :4]
+    n = float(np.hypot(dx, dy))
+    x0[0] += lat * (-dy / n)
+    x0[1] += lat * (dx / n)
+    x0[2] += dpsi
+    return x0
+
+
+def _form_active(ctx, core, W, M, C, lam, rep, K, T, sync, out, seed):
+    """The headline launch (K = 4096, T = 50, shield 10 x 0.05) from a start 0.5 m off the
+    centre line, heading 0.5 rad towards the edge at 5 m/s: the MPPI output violates the
+    DCBF condition and the shield repairs it in every launch (no plant step, so every
+    launch repeats the same iteration).  Beside it: the same launch from the headline's
+    start (shield idle)."""
+    import torch
+
+    res = {}
+    for name, off in (("active", (0.5, 0.5, 5.0)), ("idle", None)):
+        p = W.config1(K=K, T=T)
+        if off:
+            p.x0 = _offset_start(W, p.track, *off)
+        p = W.round_to_f32(p)
+        db = core.DeviceBatch([p], dtype=torch.float32)
+        pl = core.Plan(ctx, db, M, C, seed, lam, repair=rep, execute=False, use_graph=True)
+        dt = _time(pl.launch, 200, 20, sync)
+        frac = _active_fraction(db, pl.V_plus, pl.V_safe)
+        pl.close()
+        plp = core.Plan(ctx, db, M, C, seed, lam, repair=rep, execute=False, use_graph=False)
+        kl = []
+        for i in range(120):
+            plp.launch_profiled()
+            if i >= 20:
+                kl.append(plp.kernel_ms()[0])
+        plp.close()
+        res[name] = {"ms_per_iter": dt * 1e3, "rollout_steps_per_s": K * T / dt, "kernel_ms": float(np.mean(kl)),
+                     "shield_active_fraction": frac}
+    out["headline_shield_active_vs_idle"] = res
+    _log(f"  shield active vs idle: {res}")
 
 
 def _form_plain(ctx, core, W, M, C, lam, K, T, sync, out, seed):
@@ -311,7 +369,8 @@ def _form_identical(ctx, core, W, M, C, lam, rep, K, T, sync, out, seed):
         t_b = _time(plB.launch, 20, 3, sync)  # the batched launch is cheap: more repetitions
         out[f"identical_B{B}"] = {"plain_loop_ms": t_plain * 1e3, "batched_adjoint_ms": t_b * 1e3,
                                   "plain_rollout_steps_per_s": B * K * T / t_plain,
-                                  "batched_rollout_steps_per_s": B * K * T / t_b, "speedup": t_plain / t_b}
+                                  "batched_rollout_steps_per_s": B * K * T / t_b, "speedup": t_plain / t_b,
+                                  "shield_active_fraction": _active_fraction(dbB, plB.V_plus, plB.V_safe)}
         _log(f"  B={B}: {out[f'identical_B{B}']}")
         plB.close()
         del dbs, dbB
@@ -362,20 +421,93 @@ def _form_large(ctx, core, W, M, C, lam, sync, out, seed):
     pl4.close()
 
 
-def _form_c3(ctx, core, W, M, C, lam, rep, sync, out, seed):
+def _form_c0(ctx, core, W, lam, sync, out, seed):
+    """Config 0: one plain MPPI iteration in FP64 (K = 256, T = 20, circle track):
+    rollout, weights, update as separate calls; latency per iteration."""
     import torch
 
-    # config 3: 64 problems x (K=2048, T=50), batched plan with and without the shield
+    p = W.config0()
+    db = core.DeviceBatch([p], dtype=torch.float64)
+
+    def it():
+        S = core.rollout(ctx, db, W.MODEL, W.COST, seed)
+        w, _ = core.weights(ctx, db, S, lam)
+        core.update(ctx, db, W.MODEL, W.COST, seed, w)
+
+    dt = _time(it, 500, 50, sync)
+    out["c0_fp64_K256_T20"] = {"ms_per_iter": dt * 1e3, "rollout_steps_per_s": p.K * p.T / dt, "dtype": "f64"}
+    _log(f"  c0: {out['c0_fp64_K256_T20']}")
+
+
+def _form_c3(ctx, core, W, M, C, lam, rep, sync, out, seed):
+    """Config 3: 64 problems x (K = 2048, T = 50); the shield's objective is the total cost
+    plus the summed squared DCBF violations, whose gradient does not vanish, so all 10
+    projected-gradient steps (0.05) run on every problem.  Batched+adjoint plan (one
+    fused launch + the repair kernel, HIP graph) with and without the repair, against the
+    plain per-problem loop (rollout, weights, update, repair calls per problem)."""
+    import torch
+
+    rep3 = dict(n_steps=10, step=0.05, objective=W.OBJ_TOTAL)
     p3 = [W.round_to_f32(p) for p in W.config3()]
     db3 = core.DeviceBatch(p3, dtype=torch.float32)
-    pa = core.Plan(ctx, db3, M, C, seed, lam, repair=rep, use_graph=True)
+    pa = core.Plan(ctx, db3, M, C, seed, lam, repair=rep3, use_graph=True)
     pb = core.Plan(ctx, db3, M, C, seed, lam, use_graph=True)
     ta = _time(pa.launch, 20, 3, sync)
     tb = _time(pb.launch, 20, 3, sync)
-    out["c3_B64_K2048_T50"] = {"with_shield_ms": ta * 1e3, "without_shield_ms": tb * 1e3}
+    frac = _active_fraction(db3, pa.V_plus, pa.V_safe)
+    dbs = [core.DeviceBatch([p], dtype=torch.float32, pid_base=b) for b, p in enumerate(p3)]
+
+    def loop(repair):
+        for d in dbs:
+            S = core.rollout(ctx, d, M, C, seed)
+            w, _ = core.weights(ctx, d, S, lam)
+            Vp = core.update(ctx, d, M, C, seed, w)
+            if repair:
+                core.shield_repair(ctx, d, M, C, Vp, 10, 0.05, W.OBJ_TOTAL)
+
+    tla = _time(lambda: loop(True), 5, 1, sync)
+    tlb = _time(lambda: loop(False), 5, 1, sync)
+    # the shield's own objective (Algorithm 1 hinge), which stops once V+ is safe
+    pc = core.Plan(ctx, db3, M, C, seed, lam, repair=rep, use_graph=True)
+    tc = _time(pc.launch, 20, 3, sync)
+    frac_c = _active_fraction(db3, pc.V_plus, pc.V_safe)
+    steps = sum(p.K * p.T for p in p3)
+    out["c3_B64_K2048_T50"] = {
+        "objective": "total cost + sum of squared DCBF violations, 10 steps x 0.05",
+        "batched_with_repair_ms": ta * 1e3, "batched_without_repair_ms": tb * 1e3,
+        "plain_loop_with_repair_ms": tla * 1e3, "plain_loop_without_repair_ms": tlb * 1e3,
+        "speedup_with_repair": tla / ta, "batched_with_repair_rollout_steps_per_s": steps / ta,
+        "shield_active_fraction": frac,
+        "shield_objective": {"with_shield_ms": tc * 1e3, "shield_active_fraction": frac_c}}
     _log(f"  c3: {out['c3_B64_K2048_T50']}")
-    pa.close()
-    pb.close()
+    for pl in (pa, pb, pc):
+        pl.close()
+
+
+def _form_c4_adjoint(ctx, core, W, M, C, lam, sync, out, seed):
+    """Config 4's adjoint: the gradient of the free energy -lambda log sum exp(-S/lambda)
+    (upstream g = the weights) at K = 65536, T = 100 with 64 obstacles, states recomputed
+    from checkpoints; the adjoint kernel alone and rollout + weights + adjoint."""
+    import torch
+
+    p4 = W.round_to_f32(W.config4())
+    db4 = core.DeviceBatch([p4], dtype=torch.float32)
+    obj = dict(w_S=1.0, w_sq=0.0, w_lin=0.0, n_lin=0)
+    S = core.rollout(ctx, db4, M, C, seed)
+    w, _ = core.weights(ctx, db4, S, lam)
+    gV = db4.new_V()
+    t_adj = _time(lambda: core.rollout_backward(ctx, db4, M, C, seed, w, obj, out=gV), 10, 2, sync)
+
+    def full():
+        S2 = core.rollout(ctx, db4, M, C, seed, S=S)
+        w2, _ = core.weights(ctx, db4, S2, lam)
+        core.rollout_backward(ctx, db4, M, C, seed, w2, obj, out=gV)
+
+    t_full = _time(full, 10, 2, sync)
+    steps = p4.K * p4.T
+    out["c4_free_energy_adjoint"] = {"adjoint_ms": t_adj * 1e3, "adjoint_rollout_steps_per_s": steps / t_adj,
+                                     "rollout_weights_adjoint_ms": t_full * 1e3}
+    _log(f"  c4 adjoint: {out['c4_free_energy_adjoint']}")
 
 
 def _form_shield(ctx, core, W, M, C, rep, sync, out):
@@ -502,6 +634,66 @@ def _oracle_closed_loop(W, K, T, lam, rep, threads, budget_s, max_it):
             return n_it, el
 
 
+def _oracle_iteration_time(W, probs, lam, threads, repair=None):
+    """Wall time of one oracle MPPI iteration over the given problems (rollout threaded
+    over samples, then weights, update and optionally the repair, problem by problem)."""
+    import oracle
+
+    t0 = time.perf_counter()
+    for b, p in enumerate(probs):
+        r = oracle.mppi_iteration(W.MODEL, W.COST, p.track, p.x0, p.V, p.K, 0, b, p.it, lam, n_threads=threads)
+        if repair:
+            oracle.repair(W.MODEL, W.COST, p.track, p.x0, r["V_plus"], repair["n_steps"], repair["step"],
+                          repair["objective"])
+    return time.perf_counter() - t0
+
+
+def oracle_configs(W, lam, cores):
+    """The oracle timed on the other workloads (same inputs as the GPU forms): config 0
+    whole (median of 5), config 2 once on all threads and on a sample of its problems on
+    one thread, config 3 (with the 10-step repair) on all threads and on a sample on one
+    thread, config 4 (64 obstacles) on all threads and on a sample of its samples on one
+    thread.  Rates are rollout-steps per second of the sampled work."""
+    import oracle
+
+    res = {}
+    p0 = W.config0()
+    t_n = float(np.median([_oracle_iteration_time(W, [p0], lam, cores) for _ in range(5)]))
+    t_1 = float(np.median([_oracle_iteration_time(W, [p0], lam, 1) for _ in range(5)]))
+    st0 = p0.K * p0.T
+    res["c0_fp64_K256_T20"] = {"ms_per_iter": t_n * 1e3, "rollout_steps_per_s": st0 / t_n,
+                               "single_thread": {"ms_per_iter": t_1 * 1e3, "rollout_steps_per_s": st0 / t_1}}
+    p2 = W.config2()
+    st2 = sum(p.K * p.T for p in p2)
+    t_n = _oracle_iteration_time(W, p2, lam, cores)
+    sample = p2[::32]
+    t_1 = _oracle_iteration_time(W, sample, lam, 1)
+    st2s = sum(p.K * p.T for p in sample)
+    res["c2_ragged_B512"] = {"ms_per_iter": t_n * 1e3, "rollout_steps_per_s": st2 / t_n,
+                             "single_thread": {"rollout_steps_per_s": st2s / t_1, "problems": len(sample),
+                                               "ms": t_1 * 1e3}}
+    rep3 = dict(n_steps=10, step=0.05, objective=W.OBJ_TOTAL)
+    p3 = W.config3()
+    st3 = sum(p.K * p.T for p in p3)
+    t_n = _oracle_iteration_time(W, p3, lam, cores, rep3)
+    t_1 = _oracle_iteration_time(W, p3[:4], lam, 1, rep3)
+    res["c3_B64_K2048_T50_repair"] = {"ms_per_iter": t_n * 1e3, "rollout_steps_per_s": st3 / t_n,
+                                      "single_thread": {"problems": 4, "ms": t_1 * 1e3,
+                                                        "ms_per_iter_64_extrapolated": 16 * t_1 * 1e3}}
+    p4 = W.config4()
+    t0 = time.perf_counter()
+    oracle.rollout(W.MODEL, W.COST, p4.track, p4.x0, p4.V, p4.K, 0, 0, 0, want_eps=False, n_threads=cores)
+    t_n = time.perf_counter() - t0
+    ms = np.arange(0, p4.K, 16)
+    t0 = time.perf_counter()
+    oracle.rollout(W.MODEL, W.COST, p4.track, p4.x0, p4.V, 0, 0, 0, 0, want_eps=False, samples=ms)
+    t_1 = time.perf_counter() - t0
+    res["c4_K65536_T100_obs64_rollout"] = {"ms": t_n * 1e3, "rollout_steps_per_s": p4.K * p4.T / t_n,
+                                           "single_thread": {"samples": len(ms),
+                                                             "rollout_steps_per_s": len(ms) * p4.T / t_1}}
+    return res
+
+
 def cpu_baseline(W, K, T, lam, rep):
     """The FP64 oracle, as it stands, on a bounded sample of the headline workload:
     a few closed-loop iterations (rollout of all K samples, weights, update, shield,
@@ -515,7 +707,8 @@ def cpu_baseline(W, K, T, lam, rep):
             "single_thread": {"value": K * T * n1 / el1, "ms_per_iter": 1e3 * el1 / n1, "iterations": n1},
             "cpu": _cpu_model(),
             "sample": f"{n_it} closed-loop iterations of the headline workload (K={K}, T={T}, shield on), "
-                      f"FP64 oracle, rollout threaded over {cores} host threads; {n1} more on one thread"}
+                      f"FP64 oracle, rollout threaded over {cores} host threads; {n1} more on one thread",
+            "other_configs": oracle_configs(W, lam, cores)}
 
 
 if __name__ == "__main__":
