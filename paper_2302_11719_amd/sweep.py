@@ -103,11 +103,27 @@ def make_runs(runs: int, K: int, T: int, seed: int = 0, n_obs: int = 0, half_wid
     return out
 
 
-def run_cell(ctx: core.Context, K: int, T: int, controller: str, runs: int = 100, steps: int = 100,
-             seed: int = 0, n_obs: int = 0, dist_sigma: float = 0.3, lam: float = W.LAMBDA,
-             repair: Optional[dict] = None, v_goal: Optional[float] = None, half_width: float = 0.9) -> Cell:
-    """One (K, T, controller) cell of the sweep (v_goal: target speed of the state
-    cost, default the workload's)."""
+@dataclass
+class CellSetup:
+    """The device objects of one cell: its plan (closed loop on the device), batch,
+    problems, model and cost constants (FP32-rounded), disturbances [steps][runs][2]
+    and shield options (None without the shield)."""
+    plan: core.Plan
+    db: core.DeviceBatch
+    probs: List[W.Problem]
+    model: dict
+    cost: dict
+    dist: np.ndarray
+    repair: Optional[dict]
+    seed: int
+    lam: float
+
+
+def setup_cell(ctx: core.Context, K: int, T: int, controller: str, runs: int, steps: int, seed: int = 0,
+               n_obs: int = 0, dist_sigma: float = 0.3, lam: float = W.LAMBDA, repair: Optional[dict] = None,
+               v_goal: Optional[float] = None, half_width: float = 0.9, use_graph: bool = True) -> CellSetup:
+    """Builds one (K, T, controller) cell: `runs` problems and the plan that advances
+    all of them by one receding-horizon step per launch."""
     if controller not in CONTROLLERS:
         raise ValueError(controller)
     cost = dict(W.COST)
@@ -118,12 +134,23 @@ def run_cell(ctx: core.Context, K: int, T: int, controller: str, runs: int = 100
     M, C = W.params_f32(W.MODEL, cost)
     probs = make_runs(runs, K, T, seed, n_obs, half_width)
     db = core.DeviceBatch(probs, dtype=torch.float32)
-    dist = W.disturbances(seed + 17, steps * runs, sigma=dist_sigma).reshape(steps, runs, 2)
-    dist_t = torch.as_tensor(dist.astype(np.float32), device="cuda")
+    dist = W.disturbances(seed + 17, steps * runs, sigma=dist_sigma).reshape(steps, runs, 2).astype(np.float32)
+    dist_t = torch.as_tensor(dist, device="cuda")
     rep = None
     if controller == "shield":
         rep = repair or dict(n_steps=10, step=0.05, objective=W.OBJ_SHIELD)
-    plan = core.Plan(ctx, db, M, C, seed, lam, repair=rep, execute=True, dist=dist_t, use_graph=True)
+    plan = core.Plan(ctx, db, M, C, seed, lam, repair=rep, execute=True, dist=dist_t, use_graph=use_graph)
+    plan._dist_keep = dist_t
+    return CellSetup(plan, db, probs, M, C, dist, rep, seed, lam)
+
+
+def run_cell(ctx: core.Context, K: int, T: int, controller: str, runs: int = 100, steps: int = 100,
+             seed: int = 0, n_obs: int = 0, dist_sigma: float = 0.3, lam: float = W.LAMBDA,
+             repair: Optional[dict] = None, v_goal: Optional[float] = None, half_width: float = 0.9) -> Cell:
+    """One (K, T, controller) cell of the sweep (v_goal: target speed of the state
+    cost, default the workload's)."""
+    cs = setup_cell(ctx, K, T, controller, runs, steps, seed, n_obs, dist_sigma, lam, repair, v_goal, half_width)
+    plan, db, probs = cs.plan, cs.db, cs.probs
     tracks = [p.track for p in probs]
     hit = np.zeros(runs, dtype=bool)
     count = np.zeros(runs, dtype=np.int64)

@@ -364,3 +364,28 @@ def test_closed_loop_step_with_the_shield_firing():
         x_ref = oracle.execute(M, x_b, Vs[0])
         assert np.abs(db.x0.cpu().numpy() - x_ref).max() <= 1e-5
     assert ctx().device_errors() == 0
+
+
+def test_backward_fp32_against_central_differences():
+    """The differentiation workload's check in FP32: the device gradient of the total cost
+    plus squared DCBF violations (T = 50, nominal trajectories) against FP64 central
+    differences (h = 1e-6) on 8 seeded sequences; stencils in which a hinge, clip or window
+    decision switches are left out (the oracle detects them)."""
+    M, C = params(F32)
+    tr = W.round_to_f32(W.config1(K=1, T=50)).track
+    x0 = W.round_to_f32(W.config1(K=1, T=50)).x0
+    seqs = [W.round_to_f32(W.Problem(1, 50, tr, x0, V)).V for V in W.test_sequences(8, 50, seed=3, scale=0.5)]
+    probs = [W.Problem(1, 50, tr, x0, V, b, 0) for b, V in enumerate(seqs)]
+    db = core.DeviceBatch(probs, dtype=F32)
+    say("backward fp32 vs FD, 8 sequences T=50")
+    gV = core.rollout_backward(ctx(), db, M, C, 0, torch.ones(8, dtype=F32, device="cuda"), W.OBJ_TOTAL,
+                               nominal=True)
+    torch.cuda.synchronize()
+    checked = 0
+    for b, V in enumerate(seqs):
+        fd, valid = oracle.gradient_fd(M, C, tr, x0, V, W.OBJ_TOTAL, None, 1e-6)
+        g = db.controls(gV)[b]
+        scale = np.abs(fd[valid]).max()
+        assert np.abs(g - fd)[valid].max() <= 1e-3 * scale, b
+        checked += valid.sum()
+    assert checked >= 8 * 100 * 0.9
