@@ -31,7 +31,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "smppi_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
-_ABI = 6
+_ABI = 7
 _lock = threading.Lock()
 _lib = None
 
@@ -60,6 +60,7 @@ def lib():
                 raise RuntimeError("stale liboracle.so was rebuilt; restart the process")
             L.or_lateral_sq.restype = ctypes.c_double
             L.or_objective.restype = ctypes.c_double
+            L.or_objective_c8.restype = ctypes.c_double
             L.or_kappa_at.restype = ctypes.c_double
             _lib = L
     return _lib
@@ -258,32 +259,118 @@ def lbfgs_direction(g, S, Y, gamma: float) -> np.ndarray:
     return d
 
 
-def rollout_curv(model, cost, kappa, ds: float, half_width: float, x0, V, K: int, seed: int, pid: int, it: int,
-                 nominal: bool = False, want_eps: bool = True, n_threads: int = 1):
-    """Curvilinear model: per-sample S~ [K], effective noise [K][T][2], indicator margins [K].
-    x0 = (s, e_y, e_psi, v_x, v_y, omega); kappa: periodic curvature table, spacing ds."""
+WHEEL_KEYS = ("r_w", "I_w", "C_x")
+
+
+def wheels_array(wheels: dict) -> np.ndarray:
+    return np.array([wheels[k] for k in WHEEL_KEYS], dtype=np.float64)
+
+
+class _CurvArgs:
+    """Contiguous arrays of one curvilinear track: periodic curvature table, spacing, half width."""
+
+    def __init__(self, kappa, ds: float, half_width: float = 0.0):
+        self.kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+        self.ds = float(ds)
+        self.w = float(half_width)
+
+    def args(self):
+        return (_p(self.kappa), ctypes.c_int(len(self.kappa)), ctypes.c_double(self.ds))
+
+
+def deriv_c8(model, wheels, kappa, ds: float, x, u) -> np.ndarray:
+    """f of the eight-state curvilinear model; x = (v_x, v_y, r, omega_F, omega_R, e_psi, e_y, s)."""
+    out = np.zeros(8)
+    ca = _CurvArgs(kappa, ds)
+    lib().or_deriv_c8(_p(model_array(model)), _p(wheels_array(wheels)), *ca.args(),
+                      _p(np.ascontiguousarray(x, dtype=np.float64)), _p(np.ascontiguousarray(u, dtype=np.float64)),
+                      _p(out))
+    return out
+
+
+def rollout_c8(model, wheels, cost, kappa, ds: float, half_width: float, x0, V, K: int, seed: int, pid: int, it: int,
+               nominal: bool = False, want_eps: bool = True, n_threads: int = 1):
+    """Eight-state curvilinear model: per-sample S~ [K], effective noise [K][T][2], indicator margins [K]."""
     V = np.ascontiguousarray(V, dtype=np.float64).reshape(-1, 2)
     T = V.shape[0]
-    kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+    ca = _CurvArgs(kappa, ds, half_width)
     S, margin = np.zeros(K), np.zeros(K)
     eps = np.zeros((K, T, 2)) if want_eps else None
-    mp, cp = model_array(model), cost_array(cost)
-    lib().or_rollout_curv(_p(mp), _p(cp), _p(kappa), ctypes.c_int(len(kappa)), ctypes.c_double(ds),
-                          ctypes.c_double(half_width), _p(x0), _p(V), ctypes.c_int(K), ctypes.c_int(T),
-                          ctypes.c_uint32(seed), ctypes.c_uint32(pid), ctypes.c_uint32(it), ctypes.c_int(int(nominal)),
-                          S.ctypes.data_as(ctypes.c_void_p), eps.ctypes.data_as(ctypes.c_void_p) if want_eps else None,
-                          margin.ctypes.data_as(ctypes.c_void_p), ctypes.c_int(n_threads))
+    lib().or_rollout_c8(_p(model_array(model)), _p(wheels_array(wheels)), _p(cost_array(cost)), *ca.args(),
+                        ctypes.c_double(ca.w), _p(np.ascontiguousarray(x0, dtype=np.float64)), _p(V), ctypes.c_int(K),
+                        ctypes.c_int(T), ctypes.c_uint32(seed), ctypes.c_uint32(pid), ctypes.c_uint32(it),
+                        ctypes.c_int(int(nominal)), _p(S), _p(eps) if want_eps else None, _p(margin),
+                        ctypes.c_int(n_threads))
     return S, eps, margin
 
 
-def trajectory_curv(model, kappa, ds: float, x0, V) -> np.ndarray:
-    """States [T+1][6] of the curvilinear model under one control sequence."""
+def trajectory_c8(model, wheels, kappa, ds: float, x0, V, eps=None) -> np.ndarray:
+    """States [T+1][8] of the eight-state curvilinear model under V (+ raw noise eps [T][2])."""
     V = np.ascontiguousarray(V, dtype=np.float64).reshape(-1, 2)
-    kappa = np.ascontiguousarray(kappa, dtype=np.float64)
-    xs = np.zeros((V.shape[0] + 1, 6))
-    lib().or_trajectory_curv(_p(model_array(model)), _p(kappa), ctypes.c_int(len(kappa)), ctypes.c_double(ds),
-                             _p(x0), _p(V), ctypes.c_int(V.shape[0]), xs.ctypes.data_as(ctypes.c_void_p))
+    ca = _CurvArgs(kappa, ds)
+    xs = np.zeros((V.shape[0] + 1, 8))
+    lib().or_trajectory_c8(_p(model_array(model)), _p(wheels_array(wheels)), *ca.args(),
+                           _p(np.ascontiguousarray(x0, dtype=np.float64)), _p(V), ctypes.c_int(V.shape[0]),
+                           _p(eps) if eps is not None else None, _p(xs))
     return xs
+
+
+def objective_c8(model, wheels, cost, kappa, ds: float, half_width: float, x0, V, obj, eps=None):
+    """(L, decision signature) of one curvilinear trajectory."""
+    V = np.ascontiguousarray(V, dtype=np.float64).reshape(-1, 2)
+    ca = _CurvArgs(kappa, ds, half_width)
+    sig = ctypes.c_uint64(0)
+    L = lib().or_objective_c8(_p(model_array(model)), _p(wheels_array(wheels)), _p(cost_array(cost)), *ca.args(),
+                              ctypes.c_double(ca.w), _p(np.ascontiguousarray(x0, dtype=np.float64)), _p(V),
+                              ctypes.c_int(V.shape[0]), _p(eps) if eps is not None else None, *_objective_args(obj),
+                              ctypes.byref(sig))
+    return L, sig.value
+
+
+def gradient_dual_c8(model, wheels, cost, kappa, ds: float, half_width: float, x0, V, obj, eps=None) -> np.ndarray:
+    V = np.ascontiguousarray(V, dtype=np.float64).reshape(-1, 2)
+    ca = _CurvArgs(kappa, ds, half_width)
+    g = np.zeros_like(V)
+    lib().or_gradient_dual_c8(_p(model_array(model)), _p(wheels_array(wheels)), _p(cost_array(cost)), *ca.args(),
+                              ctypes.c_double(ca.w), _p(np.ascontiguousarray(x0, dtype=np.float64)), _p(V),
+                              ctypes.c_int(V.shape[0]), _p(eps) if eps is not None else None, *_objective_args(obj),
+                              _p(g))
+    return g
+
+
+def gradient_fd_c8(model, wheels, cost, kappa, ds: float, half_width: float, x0, V, obj, eps=None, h: float = 1e-6):
+    V = np.ascontiguousarray(V, dtype=np.float64).reshape(-1, 2)
+    ca = _CurvArgs(kappa, ds, half_width)
+    g = np.zeros_like(V)
+    valid = np.zeros(V.shape, dtype=np.int32)
+    lib().or_gradient_fd_c8(_p(model_array(model)), _p(wheels_array(wheels)), _p(cost_array(cost)), *ca.args(),
+                            ctypes.c_double(ca.w), _p(np.ascontiguousarray(x0, dtype=np.float64)), _p(V),
+                            ctypes.c_int(V.shape[0]), _p(eps) if eps is not None else None, *_objective_args(obj),
+                            ctypes.c_double(h), _p(g), _p(valid, np.int32))
+    return g, valid.astype(bool)
+
+
+def repair_c8(model, wheels, cost, kappa, ds: float, half_width: float, x0, V_plus, n_steps: int, step: float,
+              obj) -> np.ndarray:
+    """Algorithm 1 on the eight-state curvilinear model; V_plus [T][2]."""
+    V_plus = np.ascontiguousarray(V_plus, dtype=np.float64).reshape(-1, 2)
+    ca = _CurvArgs(kappa, ds, half_width)
+    out = np.zeros_like(V_plus)
+    lib().or_repair_c8(_p(model_array(model)), _p(wheels_array(wheels)), _p(cost_array(cost)), *ca.args(),
+                       ctypes.c_double(ca.w), _p(np.ascontiguousarray(x0, dtype=np.float64)), _p(V_plus),
+                       ctypes.c_int(V_plus.shape[0]), ctypes.c_int(n_steps), ctypes.c_double(step),
+                       *_objective_args(obj), _p(out))
+    return out
+
+
+def execute_c8(model, wheels, kappa, ds: float, x, u0, dist=None) -> np.ndarray:
+    """Disturbed plant step of the curvilinear model: x+ = f(x, clip(u0)) + w, w on (v_y, r)."""
+    u0 = np.clip(np.asarray(u0, dtype=np.float64), model["u_lo"], model["u_hi"])
+    xn = trajectory_c8(model, wheels, kappa, ds, x, u0.reshape(1, 2))[1].copy()
+    if dist is not None:
+        xn[1] += dist[0]
+        xn[2] += dist[1]
+    return xn
 
 
 def kappa_at(kappa, ds: float, s: float) -> float:

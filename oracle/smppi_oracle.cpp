@@ -386,17 +386,36 @@ R rollout_one(const Model& M, const Cost& C, const Track& tr, const double x0[6]
 }
 
 // ---------------------------------------------------------------------------
-// Curvilinear (Frenet-frame) variant of the model (Sec. VI-A: the paper's
-// vehicle states include the progress s, lateral error e_y and heading error
-// e_psi along the track, so the track barrier of eq. (23) needs no projection).
-// x = (s, e_y, e_psi, v_x, v_y, omega); the velocity dynamics are the ones
-// above; the kinematics of a frame moving along a path of curvature kappa(s):
-//   ds/dt = (v_x cos e_psi - v_y sin e_psi) / (1 - kappa(s) e_y),
-//   de_y/dt = v_x sin e_psi + v_y cos e_psi,
-//   de_psi/dt = omega - kappa(s) ds/dt.
-// kappa(s): periodic table on a uniform grid s_j = j ds, linear in between
-// (reading: the paper prints no track representation).
+// Curvilinear eight-state model (Sec. VI-A): the vehicle's state is
+// x = (v_x, v_y, r, omega_F, omega_R, e_psi, e_y, s) -- body velocities, yaw
+// rate, front and rear wheel speeds, heading error, lateral deviation and
+// progress along the centre line -- and the track barrier of eq. (23),
+// h = w^2 - e_y^2, is read from the state.  The paper names these states and a
+// single-track bicycle model but prints neither equations nor constants.  The
+// reading taken here:
+//  - lateral tyre forces as in the six-state model, linear in slip angle;
+//  - longitudinal tyre forces linear in wheel slip,
+//      F_x = C_x (r_w omega - v_w) / v~,   v~ = max(v_x, v_min),
+//    v_w the wheel centre's speed along its rolling direction (front:
+//    v_x cos(delta) + (v_y + l_f r) sin(delta); rear: v_x);
+//  - the throttle drives the rear axle with torque m a_max r_w T, so that with
+//    both wheels at their equilibrium speeds (F_xF = 0, F_xR = m a_max T) the
+//    body equations are exactly the six-state model's:
+//      I_w omega_F' = -r_w F_xF,   I_w omega_R' = m a_max r_w T - r_w F_xR;
+//  - body equations with the front axle's forces rotated by the steering angle:
+//      v_x' = (F_xR + F_xF cos(delta) - F_yF sin(delta)) / m - c_v v_x + v_y r,
+//      v_y' = (F_yR + F_xF sin(delta) + F_yF cos(delta)) / m - v_x r,
+//      r'   = (l_f (F_xF sin(delta) + F_yF cos(delta)) - l_r F_yR) / I_z;
+//  - Frenet kinematics along a path of curvature kappa(s):
+//      s' = (v_x cos(e_psi) - v_y sin(e_psi)) / (1 - kappa(s) e_y),
+//      e_y' = v_x sin(e_psi) + v_y cos(e_psi),   e_psi' = r - kappa(s) s'.
+// kappa(s): periodic table on a uniform grid s_j = j ds, linear in between.
 // ---------------------------------------------------------------------------
+struct Wheels {
+  double r_w, I_w, C_x;
+};
+Wheels wheels_from(const double* p) { return Wheels{p[0], p[1], p[2]}; }
+
 struct CurvTrack {
   const double* kappa;
   int n;
@@ -413,79 +432,104 @@ R kappa_at(const CurvTrack& ct, R s) {
 }
 
 template <class R>
-void deriv_curv(const Model& M, const CurvTrack& ct, const R x[6], const R u[2], R dx[6]) {
-  R s = x[0], ey = x[1], epsi = x[2], vx = x[3], vy = x[4], om = x[5];
-  R delta = u[0], tau = u[1];
+void deriv_c8(const Model& M, const Wheels& Wh, const CurvTrack& ct, const R x[8], const R u[2], R dx[8]) {
+  R vx = x[0], vy = x[1], r = x[2], wF = x[3], wR = x[4], epsi = x[5], ey = x[6], s = x[7];
+  R delta = u[0], thr = u[1];
   R vt = rmax(vx, R(M.v_min));
-  R alpha_f = delta - (vy + R(M.lf) * om) / vt;
-  R alpha_r = R(0.0) - (vy - R(M.lr) * om) / vt;
-  R Fyf = R(M.Cf) * alpha_f;
-  R Fyr = R(M.Cr) * alpha_r;
   R cd = cos(delta), sd = sin(delta);
+  R FyF = R(M.Cf) * (delta - (vy + R(M.lf) * r) / vt);
+  R FyR = R(M.Cr) * ((R(M.lr) * r - vy) / vt);
+  R vwF = vx * cd + (vy + R(M.lf) * r) * sd;
+  R FxF = R(Wh.C_x) * (R(Wh.r_w) * wF - vwF) / vt;
+  R FxR = R(Wh.C_x) * (R(Wh.r_w) * wR - vx) / vt;
   R k = kappa_at<R>(ct, s);
-  R c = cos(epsi), sn = sin(epsi);
-  R sdot = (vx * c - vy * sn) / (R(1.0) - k * ey);
-  dx[0] = sdot;
-  dx[1] = vx * sn + vy * c;
-  dx[2] = om - k * sdot;
-  dx[3] = R(M.a_max) * tau - R(M.c_v) * vx - Fyf * sd / R(M.m) + vy * om;
-  dx[4] = (Fyf * cd + Fyr) / R(M.m) - vx * om;
-  dx[5] = (R(M.lf) * Fyf * cd - R(M.lr) * Fyr) / R(M.Iz);
+  R ce = cos(epsi), se = sin(epsi);
+  R sdot = (vx * ce - vy * se) / (R(1.0) - k * ey);
+  dx[0] = (FxR + FxF * cd - FyF * sd) / R(M.m) - R(M.c_v) * vx + vy * r;
+  dx[1] = (FyR + FxF * sd + FyF * cd) / R(M.m) - vx * r;
+  dx[2] = (R(M.lf) * (FxF * sd + FyF * cd) - R(M.lr) * FyR) / R(M.Iz);
+  dx[3] = R(0.0) - R(Wh.r_w) * FxF / R(Wh.I_w);
+  dx[4] = (R(M.m * M.a_max * Wh.r_w) * thr - R(Wh.r_w) * FxR) / R(Wh.I_w);
+  dx[5] = r - k * sdot;
+  dx[6] = vx * se + vy * ce;
+  dx[7] = sdot;
 }
 
 template <class R>
-void rk4_step_curv(const Model& M, const CurvTrack& ct, const R x[6], const R u[2], double dt, R out[6]) {
-  R k1[6], k2[6], k3[6], k4[6], xs[6];
-  deriv_curv(M, ct, x, u, k1);
-  for (int i = 0; i < 6; ++i) xs[i] = x[i] + R(0.5 * dt) * k1[i];
-  deriv_curv(M, ct, xs, u, k2);
-  for (int i = 0; i < 6; ++i) xs[i] = x[i] + R(0.5 * dt) * k2[i];
-  deriv_curv(M, ct, xs, u, k3);
-  for (int i = 0; i < 6; ++i) xs[i] = x[i] + R(dt) * k3[i];
-  deriv_curv(M, ct, xs, u, k4);
-  for (int i = 0; i < 6; ++i)
+void rk4_step_c8(const Model& M, const Wheels& Wh, const CurvTrack& ct, const R x[8], const R u[2], double dt,
+                 R out[8]) {
+  R k1[8], k2[8], k3[8], k4[8], xs[8];
+  deriv_c8(M, Wh, ct, x, u, k1);
+  for (int i = 0; i < 8; ++i) xs[i] = x[i] + R(0.5 * dt) * k1[i];
+  deriv_c8(M, Wh, ct, xs, u, k2);
+  for (int i = 0; i < 8; ++i) xs[i] = x[i] + R(0.5 * dt) * k2[i];
+  deriv_c8(M, Wh, ct, xs, u, k3);
+  for (int i = 0; i < 8; ++i) xs[i] = x[i] + R(dt) * k3[i];
+  deriv_c8(M, Wh, ct, xs, u, k4);
+  for (int i = 0; i < 8; ++i)
     out[i] = x[i] + R(dt / 6.0) * (k1[i] + R(2.0) * k2[i] + R(2.0) * k3[i] + k4[i]);
 }
 
-// One sampled trajectory of the curvilinear model: the cost S~ of Algorithm 2
-// with the track barrier h = w^2 - e_y^2 read from the state (eq. (23)), the
-// running cost of eq. (24) on (v_x, e_y), the indicator of eq. (25) for
-// |e_y| > w, the control term and the DCBF penalty as in rollout_one.
-double rollout_one_curv(const Model& M, const Cost& C, const CurvTrack& ct, const double x0[6], const double* V,
-                        int T, const double* eps, double* eps_eff, double* margin_out) {
+// One sampled trajectory of the curvilinear model (Algorithm 2 inner loop):
+// S~ with the running cost of eq. (24) on (v_x, e_y), the indicator of eq. (25)
+// for |e_y| > w, the control term and the DCBF penalty of eqs. (17)-(20) on the
+// track barrier (z_0 term included), as rollout_one; the objective for
+// differentiation likewise.
+template <class R>
+R rollout_one_c8(const Model& M, const Wheels& Wh, const Cost& C, const CurvTrack& ct, const double x0[8],
+                 const R* V, int T, const double* eps, double* eps_eff, const Objective* ob, R* obj_out,
+                 SampleOut* so) {
   const double alpha = 1.0 - C.beta;
-  double x[6];
-  for (int i = 0; i < 6; ++i) x[i] = x0[i];
-  double h = ct.w * ct.w - x[1] * x[1];
-  double h_prev = h, margin = std::fabs(h);
-  double S = 0.0;
+  R x[8];
+  for (int i = 0; i < 8; ++i) x[i] = R(x0[i]);
+  R h_cur = R(ct.w * ct.w) - x[6] * x[6], h_prev = h_cur;
+  double margin = std::fabs(val(h_cur));
+  uint64_t sig = 0;
+  R S = R(0.0), S_noind = R(0.0), obj_extra = R(0.0);
   for (int t = 0; t <= T; ++t) {
-    const double r = alpha * h_prev - h;
-    const double pen = r > 0.0 ? C.C_cbf * r : 0.0;
-    const bool inside = h >= 0.0;
-    const double dv = x[3] - C.v_g;
-    double q = C.q_v * dv * dv + C.q_ey * (x[1] * x[1]);
-    if (!inside) q = q + C.C_obs;
-    if (t < T) {
-      double u[2], ctrl = 0.0;
-      for (int d = 0; d < 2; ++d) {
-        const double v = V[2 * t + d];
-        u[d] = clampr(v + (eps ? eps[2 * t + d] : 0.0), M.u_lo[d], M.u_hi[d]);
-        if (eps_eff) eps_eff[2 * t + d] = u[d] - v;
-        ctrl = ctrl + C.lambda_u * v * u[d] / (C.sigma[d] * C.sigma[d]);
+    R pen = R(0.0);
+    R rr = R(alpha) * h_prev - h_cur;
+    bool act = val(rr) > 0.0;
+    sig = mix(sig, act);
+    if (act) {
+      pen = R(C.C_cbf) * rr;
+      if (t >= 1) {
+        obj_extra = obj_extra + R(ob ? ob->w_sq : 0.0) * rr * rr;
+        if (ob && t - 1 < ob->n_lin) obj_extra = obj_extra + R(ob->w_lin) * rr;
       }
-      S = S + (q + ctrl + pen);
-      double xn[6];
-      rk4_step_curv<double>(M, ct, x, u, M.dt, xn);
-      for (int i = 0; i < 6; ++i) x[i] = xn[i];
-      h_prev = h;
-      h = ct.w * ct.w - x[1] * x[1];
-      margin = std::min(margin, std::fabs(h));
+    }
+    const bool inside = val(h_cur) >= 0.0;
+    R dv = x[0] - R(C.v_g);
+    R qn = R(C.q_v) * dv * dv + R(C.q_ey) * x[6] * x[6];
+    R qv = inside ? qn : qn + R(C.C_obs);
+    if (t < T) {
+      R u[2], ctrl = R(0.0);
+      for (int d = 0; d < 2; ++d) {
+        R v = V[2 * t + d];
+        R raw = v + R(eps ? eps[2 * t + d] : 0.0);
+        bool lo = val(raw) < M.u_lo[d], hi = val(raw) > M.u_hi[d];
+        sig = mix(sig, (uint64_t)(lo + 2 * hi));
+        u[d] = clampr(raw, M.u_lo[d], M.u_hi[d]);
+        if (eps_eff) eps_eff[2 * t + d] = val(u[d]) - val(v);
+        ctrl = ctrl + R(C.lambda_u) * v * u[d] / R(C.sigma[d] * C.sigma[d]);
+      }
+      S = S + (qv + ctrl + pen);
+      S_noind = S_noind + (qn + ctrl + pen);
+      sig = mix(sig, val(x[0]) > M.v_min);
+      sig = mix(sig, (uint64_t)(int64_t)std::floor(val(x[7]) / ct.ds));
+      R xn[8];
+      rk4_step_c8<R>(M, Wh, ct, x, u, M.dt, xn);
+      for (int i = 0; i < 8; ++i) x[i] = xn[i];
+      h_prev = h_cur;
+      h_cur = R(ct.w * ct.w) - x[6] * x[6];
+      margin = std::min(margin, std::fabs(val(h_cur)));
     } else {
-      S = S + (C.phi_w * q + pen);
+      S = S + (R(C.phi_w) * qv + pen);
+      S_noind = S_noind + (R(C.phi_w) * qn + pen);
     }
   }
-  if (margin_out) *margin_out = margin;
+  if (so) { so->S = val(S); so->margin = margin; so->sig = sig; }
+  if (obj_out) *obj_out = R(ob ? ob->w_S : 0.0) * S_noind + obj_extra;
   return S;
 }
 
@@ -524,7 +568,7 @@ void sample_noise(const Cost& C, uint32_t seed, uint32_t pid, uint32_t it, uint3
 // ===========================================================================
 extern "C" {
 
-int or_abi_version(void) { return 6; }
+int or_abi_version(void) { return 7; }
 
 void or_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { philox4x32_10(ctr, key, out); }
 
@@ -594,21 +638,31 @@ void or_rollout(const double* mp, const double* cp, int kind, const double* circ
   }
 }
 
-// Sampled costs of the curvilinear model (same noise streams as or_rollout).
-// x0 = (s, e_y, e_psi, v_x, v_y, omega); kappa: periodic table with spacing ds.
-void or_rollout_curv(const double* mp, const double* cp, const double* kappa, int n_kappa, double ds,
-                     double half_width, const double* x0, const double* V, int K, int T, uint32_t seed,
-                     uint32_t pid, uint32_t it, int nominal, double* S, double* eps_eff, double* margin,
-                     int n_threads) {
+// ---- curvilinear eight-state model.  x: [8] (v_x, v_y, r, omega_F, omega_R,
+// e_psi, e_y, s); wp: (r_w, I_w, C_x); kappa: periodic table with spacing ds.
+void or_deriv_c8(const double* mp, const double* wp, const double* kappa, int n_kappa, double ds, const double* x,
+                 const double* u, double* dx) {
+  CurvTrack ct{kappa, n_kappa, ds, 0.0};
+  deriv_c8<double>(model_from(mp), wheels_from(wp), ct, x, u, dx);
+}
+
+// Sampled costs (same noise streams as or_rollout).
+void or_rollout_c8(const double* mp, const double* wp, const double* cp, const double* kappa, int n_kappa, double ds,
+                   double half_width, const double* x0, const double* V, int K, int T, uint32_t seed, uint32_t pid,
+                   uint32_t it, int nominal, double* S, double* eps_eff, double* margin, int n_threads) {
   Model M = model_from(mp);
+  Wheels Wh = wheels_from(wp);
   Cost C = cost_from(cp);
   CurvTrack ct{kappa, n_kappa, ds, half_width};
   auto work = [&](int m0, int m1) {
     std::vector<double> eps(2 * T);
     for (int m = m0; m < m1; ++m) {
       sample_noise(C, seed, pid, it, (uint32_t)m, T, nominal, eps.data());
-      S[m] = rollout_one_curv(M, C, ct, x0, V, T, eps.data(), eps_eff ? eps_eff + (size_t)2 * T * m : nullptr,
-                              margin ? margin + m : nullptr);
+      SampleOut so;
+      rollout_one_c8<double>(M, Wh, C, ct, x0, V, T, eps.data(),
+                             eps_eff ? eps_eff + (size_t)2 * T * m : nullptr, nullptr, nullptr, &so);
+      S[m] = so.S;
+      if (margin) margin[m] = so.margin;
     }
   };
   if (n_threads <= 1) {
@@ -624,18 +678,89 @@ void or_rollout_curv(const double* mp, const double* cp, const double* kappa, in
   }
 }
 
-// Nominal trajectory of the curvilinear model, states [T+1][6].
-void or_trajectory_curv(const double* mp, const double* kappa, int n_kappa, double ds, const double* x0,
-                        const double* V, int T, double* xs) {
+// Trajectory under V (+ raw noise eps, or nominal), states [T+1][8].
+void or_trajectory_c8(const double* mp, const double* wp, const double* kappa, int n_kappa, double ds,
+                      const double* x0, const double* V, int T, const double* eps, double* xs) {
   Model M = model_from(mp);
+  Wheels Wh = wheels_from(wp);
   CurvTrack ct{kappa, n_kappa, ds, 0.0};
-  double x[6];
-  for (int i = 0; i < 6; ++i) x[i] = xs[i] = x0[i];
+  double x[8];
+  for (int i = 0; i < 8; ++i) x[i] = xs[i] = x0[i];
   for (int t = 0; t < T; ++t) {
-    double u[2], xn[6];
-    for (int d = 0; d < 2; ++d) u[d] = clampr(V[2 * t + d], M.u_lo[d], M.u_hi[d]);
-    rk4_step_curv<double>(M, ct, x, u, M.dt, xn);
-    for (int i = 0; i < 6; ++i) x[i] = xs[6 * (t + 1) + i] = xn[i];
+    double u[2], xn[8];
+    for (int d = 0; d < 2; ++d) u[d] = clampr(V[2 * t + d] + (eps ? eps[2 * t + d] : 0.0), M.u_lo[d], M.u_hi[d]);
+    rk4_step_c8<double>(M, Wh, ct, x, u, M.dt, xn);
+    for (int i = 0; i < 8; ++i) x[i] = xs[8 * (t + 1) + i] = xn[i];
+  }
+}
+
+double or_objective_c8(const double* mp, const double* wp, const double* cp, const double* kappa, int n_kappa,
+                       double ds, double half_width, const double* x0, const double* V, int T, const double* eps,
+                       double w_S, double w_sq, double w_lin, int n_lin, uint64_t* sig) {
+  CurvTrack ct{kappa, n_kappa, ds, half_width};
+  Objective ob{w_S, w_sq, w_lin, n_lin};
+  double L;
+  SampleOut so;
+  rollout_one_c8<double>(model_from(mp), wheels_from(wp), cost_from(cp), ct, x0, V, T, eps, nullptr, &ob, &L,
+                         &so);
+  if (sig) *sig = so.sig;
+  return L;
+}
+
+// Exact gradient of the objective with respect to V ([T][2]) by dual numbers.
+void or_gradient_dual_c8(const double* mp, const double* wp, const double* cp, const double* kappa, int n_kappa,
+                         double ds, double half_width, const double* x0, const double* V, int T, const double* eps,
+                         double w_S, double w_sq, double w_lin, int n_lin, double* grad) {
+  Model M = model_from(mp);
+  Wheels Wh = wheels_from(wp);
+  Cost C = cost_from(cp);
+  CurvTrack ct{kappa, n_kappa, ds, half_width};
+  Objective ob{w_S, w_sq, w_lin, n_lin};
+  std::vector<Dual> Vd(2 * T);
+  for (int i = 0; i < 2 * T; ++i) {
+    for (int k = 0; k < 2 * T; ++k) Vd[k] = Dual(V[k], k == i ? 1.0 : 0.0);
+    Dual L;
+    rollout_one_c8<Dual>(M, Wh, C, ct, x0, Vd.data(), T, eps, nullptr, &ob, &L, nullptr);
+    grad[i] = L.d;
+  }
+}
+
+// Central differences with the kink detector (as or_gradient_fd).
+void or_gradient_fd_c8(const double* mp, const double* wp, const double* cp, const double* kappa, int n_kappa,
+                       double ds, double half_width, const double* x0, const double* V, int T, const double* eps,
+                       double w_S, double w_sq, double w_lin, int n_lin, double h, double* grad, int* valid) {
+  std::vector<double> Vp(V, V + 2 * T);
+  uint64_t s0, sp, sm;
+  or_objective_c8(mp, wp, cp, kappa, n_kappa, ds, half_width, x0, V, T, eps, w_S, w_sq, w_lin, n_lin, &s0);
+  for (int i = 0; i < 2 * T; ++i) {
+    Vp[i] = V[i] + h;
+    double Lp = or_objective_c8(mp, wp, cp, kappa, n_kappa, ds, half_width, x0, Vp.data(), T, eps, w_S, w_sq,
+                                w_lin, n_lin, &sp);
+    Vp[i] = V[i] - h;
+    double Lm = or_objective_c8(mp, wp, cp, kappa, n_kappa, ds, half_width, x0, Vp.data(), T, eps, w_S, w_sq,
+                                w_lin, n_lin, &sm);
+    Vp[i] = V[i];
+    grad[i] = (Lp - Lm) / (2.0 * h);
+    valid[i] = (sp == s0 && sm == s0) ? 1 : 0;
+  }
+}
+
+// Safety shield (Algorithm 1) on the curvilinear model: n_s times
+// V <- clip(V - delta grad L(V)) on the nominal trajectory from x0.
+void or_repair_c8(const double* mp, const double* wp, const double* cp, const double* kappa, int n_kappa,
+                  double ds, double half_width, const double* x0, const double* V_plus, int T, int n_steps,
+                  double delta, double w_S, double w_sq, double w_lin, int n_lin, double* V_safe) {
+  Model M = model_from(mp);
+  std::vector<double> g(2 * T);
+  for (int i = 0; i < 2 * T; ++i) V_safe[i] = V_plus[i];
+  for (int s = 0; s < n_steps; ++s) {
+    or_gradient_dual_c8(mp, wp, cp, kappa, n_kappa, ds, half_width, x0, V_safe, T, nullptr, w_S, w_sq, w_lin, n_lin,
+                        g.data());
+    for (int t = 0; t < T; ++t)
+      for (int d = 0; d < 2; ++d) {
+        double v = V_safe[2 * t + d] - delta * g[2 * t + d];
+        V_safe[2 * t + d] = std::min(std::max(v, M.u_lo[d]), M.u_hi[d]);
+      }
   }
 }
 

@@ -126,9 +126,19 @@ def curvature_table(track: Track, n: int = 1024):
     return kappa, ds
 
 
-def start_state_curv(vx: float = 3.0) -> np.ndarray:
-    """Curvilinear state (s, e_y, e_psi, v_x, v_y, omega) on the centre line at s = 0."""
-    return np.array([0.0, 0.0, 0.0, vx, 0.0, 0.0])
+# Wheels of the eight-state curvilinear model (the paper's state with front and
+# rear wheel speeds): wheel radius, wheel inertia per axle, longitudinal slip
+# stiffness per axle.  Chosen so that the wheel-spin modes (about
+# C_x (1/m + r_w^2/I_w) / v_min = 35 1/s at the slowest) stay inside RK4's
+# stability region at dt = 0.05 s.
+WHEELS = dict(r_w=0.05, I_w=0.01, C_x=60.0)
+
+
+def start_state_c8(vx: float = 3.0, e_y: float = 0.0, e_psi: float = 0.0, s: float = 0.0) -> np.ndarray:
+    """Eight-state curvilinear start (v_x, v_y, r, omega_F, omega_R, e_psi, e_y, s): straight
+    running with both wheels rolling freely (omega = v_x / r_w)."""
+    w = vx / WHEELS["r_w"]
+    return np.array([vx, 0.0, 0.0, w, w, e_psi, e_y, s])
 
 
 def obstacles(track: Track, seed: int, n: int = 64, margin: float = 0.15, keep_clear: float = 5.0) -> np.ndarray:
@@ -249,3 +259,7 @@ def params_f32(model: dict, cost: dict):
     m2 = {k: (tuple(r(x) for x in v) if isinstance(v, tuple) else r(v)) for k, v in model.items()}
     c2 = {k: (tuple(r(x) for x in v) if isinstance(v, tuple) else r(v)) for k, v in cost.items()}
     return m2, c2
+
+
+def wheels_f32(wheels: dict = None) -> dict:
+    return {k: float(np.float32(v)) for k, v in (wheels or WHEELS).items()}

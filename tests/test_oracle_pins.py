@@ -542,34 +542,151 @@ def test_curvature_table_interpolation():
     assert oracle.kappa_at(ramp, 0.5, 8.0 * 0.5 + 1.0) == pytest.approx(2.0, abs=1e-15)
 
 
-def test_curvilinear_model_on_a_straight_path_is_the_cartesian_model():
-    """Zero curvature: the Frenet kinematics reduce to x' = v_x cos psi - v_y sin psi,
-    y' = v_x sin psi + v_y cos psi, psi' = omega, so (s, e_y, e_psi) follow the
-    Cartesian (x, y, psi) bit for bit."""
-    V = W.test_sequences(1, 40, seed=4, scale=0.6)[0]
-    x0 = np.array([1.0, 0.3, 0.1, 4.0, 0.2, -0.1])
-    xc, _ = oracle.trajectory(M, C, W.circle_track(10.0, 1.0), x0, V)
-    xf = oracle.trajectory_curv(M, np.zeros(16), 1.0, x0, V)
-    assert np.array_equal(xc, xf)
+# ----------------------------------------------------------------------------- eight-state curvilinear model
+WH = W.WHEELS
 
 
-def test_curvilinear_model_on_a_circle_matches_the_cartesian_model():
-    """Constant curvature 1/R: mapping (s, e_y, e_psi) to the plane, p = (R - e_y)(cos, sin)(s/R)
-    and psi = s/R + pi/2 + e_psi, follows the Cartesian model on the circle to RK4's
-    coordinate-dependent truncation error; the sampled costs agree likewise (e_y = R - |p|)."""
-    R = 10.0
-    kap, ds = W.curvature_table(W.circle_track(R, 1.0), 256)
-    V = W.test_sequences(1, 40, seed=5, scale=0.5)[0]
-    x0f = np.array([0.0, 0.2, 0.05, 4.0, 0.1, 0.0])
-    xf = oracle.trajectory_curv(M, kap, ds, x0f, V)
-    th = xf[:, 0] / R
-    r = R - xf[:, 1]
-    x0c = np.array([r[0] * np.cos(th[0]), r[0] * np.sin(th[0]), th[0] + np.pi / 2 + xf[0, 2], 4.0, 0.1, 0.0])
-    xc, _ = oracle.trajectory(M, C, W.circle_track(R, 1.0), x0c, V)
-    assert np.abs(xc[:, 0] - r * np.cos(th)).max() < 1e-6
-    assert np.abs(xc[:, 1] - r * np.sin(th)).max() < 1e-6
-    assert np.abs(xc[:, 2] - (th + np.pi / 2 + xf[:, 2])).max() < 1e-6
-    assert np.abs(xc[:, 3:] - xf[:, 3:]).max() < 1e-6
-    Sf, _, _ = oracle.rollout_curv(M, C, kap, ds, 1.0, x0f, V, K=16, seed=3, pid=0, it=0)
-    Sc, _, _ = oracle.rollout(M, C, W.circle_track(R, 1.0), x0c, V, K=16, seed=3, pid=0, it=0)
-    assert np.allclose(Sf, Sc, rtol=2e-5)  # DCBF penalties (C = 1000) amplify the state differences
+def _slaved_wheels(x, u):
+    """Wheel speeds at which both wheels are in equilibrium (closed form of the model
+    card): front free rolling, rear slip giving F_xR = m a_max T."""
+    vx, vy, r = x[0], x[1], x[2]
+    vt = max(vx, M["v_min"])
+    v_front = vx * math.cos(u[0]) + (vy + M["lf"] * r) * math.sin(u[0])
+    w_front = v_front / WH["r_w"]
+    w_rear = (vx + vt * M["m"] * M["a_max"] * u[1] / WH["C_x"]) / WH["r_w"]
+    return w_front, w_rear
+
+
+def test_c8_slaved_wheels_reduce_to_the_six_state_model():
+    """With both wheel speeds at their equilibrium (no wheel acceleration), the eight-state
+    body equations are the six-state model's (the drive reaches the body as m a_max T,
+    the front wheel carries no longitudinal force), on straight and curved tracks, above
+    and below v_min."""
+    rng = np.random.default_rng(11)
+    for k in range(200):
+        vx = rng.uniform(0.3, 8.0)
+        x = np.array([vx, rng.normal(0, 0.5), rng.normal(0, 0.8), 0.0, 0.0, rng.normal(0, 0.3),
+                      rng.normal(0, 0.5), rng.uniform(0, 50)])
+        u = np.array([rng.uniform(-0.4, 0.4), rng.uniform(-1, 1)])
+        x[3], x[4] = _slaved_wheels(x, u)
+        kap = np.full(8, 0.0 if k % 2 else 0.07)
+        d8 = oracle.deriv_c8(M, WH, kap, 2.0, x, u)
+        d6 = oracle.deriv(M, np.array([0.0, 0.0, 0.3, x[0], x[1], x[2]]), u)
+        assert abs(d8[3]) <= 1e-9 * max(1.0, abs(x[3])) and abs(d8[4]) <= 1e-9 * max(1.0, abs(x[4]))
+        assert np.allclose(d8[0:3], d6[3:6], rtol=1e-12, atol=1e-10), k
+    # away from equilibrium the wheels accelerate towards it: spinning the rear wheel
+    # faster than equilibrium decelerates it and pushes the body forward
+    x = np.array([4.0, 0.0, 0.0, 80.0, 0.0, 0.0, 0.0, 0.0])
+    u = np.array([0.0, 0.5])
+    x[3], x[4] = _slaved_wheels(x, u)
+    d0 = oracle.deriv_c8(M, WH, np.zeros(8), 1.0, x, u)
+    x[4] += 5.0
+    d1 = oracle.deriv_c8(M, WH, np.zeros(8), 1.0, x, u)
+    assert d1[4] < 0.0 and d1[0] > d0[0]
+
+
+@pytest.mark.parametrize("R", [np.inf, 12.0, -9.0])
+def test_c8_frenet_kinematics_follow_the_plane(R):
+    """Constant curvature 1/R (left turn for R > 0; straight for R = inf): mapping (s, e_y,
+    e_psi) to the plane, p = c + (R - e_y)(cos th, sin th) with th = s/R and heading
+    psi = th + pi/2 + e_psi (straight: p = (s, e_y), psi = e_psi), the chain rule on the
+    model's (s', e_y', e_psi') gives p' = (v_x cos psi - v_y sin psi, v_x sin psi + v_y cos psi)
+    and psi' = r: the body velocities seen in the plane."""
+    kap = np.full(16, 0.0 if np.isinf(R) else 1.0 / R)
+    rng = np.random.default_rng(3)
+    for _ in range(100):
+        x = np.array([rng.uniform(1, 6), rng.normal(0, 0.5), rng.normal(0, 1), 60, 60, rng.normal(0, 0.4),
+                      rng.normal(0, 0.8), rng.uniform(0, 20)])
+        d = oracle.deriv_c8(M, WH, kap, 0.7, x, np.array([0.1, 0.2]))
+        vx, vy, r, ep, ey, s = x[0], x[1], x[2], x[5], x[6], x[7]
+        if np.isinf(R):
+            psi = ep
+            p_dot = np.array([d[7], d[6]])
+            psi_dot = d[5]
+        else:
+            th = s / R
+            psi = th + np.pi / 2 + ep
+            rad = R - ey
+            p_dot = -d[6] * np.array([np.cos(th), np.sin(th)]) + rad * (d[7] / R) * np.array([-np.sin(th), np.cos(th)])
+            psi_dot = d[7] / R + d[5]
+        planar = np.array([vx * np.cos(psi) - vy * np.sin(psi), vx * np.sin(psi) + vy * np.cos(psi)])
+        assert np.allclose(p_dot, planar, rtol=1e-12, atol=1e-12)
+        assert psi_dot == pytest.approx(r, abs=1e-12)
+
+
+def test_c8_hand_computed_cost():
+    """Worked example in tests/golden/curvilinear_cost.txt: uniform drifting motion with the
+    wheels in equilibrium, the cost bookkeeping of Algorithm 2 and eq. (20)."""
+    g = {r[0]: float(r[1]) for r in _read_golden("curvilinear_cost.txt")}
+    kap, ds, w = np.zeros(8), 1.0, 0.5
+    x0 = np.array([8.0, 0.0, 0.0, 160.0, 192.0, np.pi / 6, 0.0, 0.0])
+    V = np.tile([0.0, 1.0], (3, 1))
+    xs = oracle.trajectory_c8(M, WH, kap, ds, x0, V)
+    assert np.allclose(xs[:, 6], [0.0, 0.2, 0.4, 0.6], atol=1e-12)
+    assert np.allclose(xs[:, [0, 1, 2, 3, 4, 5]], x0[[0, 1, 2, 3, 4, 5]], atol=1e-10)
+    S, eps, _ = oracle.rollout_c8(M, WH, C, kap, ds, w, x0, V, K=2, seed=0, pid=0, it=0, nominal=True)
+    assert np.allclose(S, g["S_tilde"], rtol=0, atol=1e-8)
+    tot, _ = oracle.objective_c8(M, WH, C, kap, ds, w, x0, V, dict(w_S=1.0, w_sq=0.0, w_lin=0.0, n_lin=0))
+    lin, _ = oracle.objective_c8(M, WH, C, kap, ds, w, x0, V, W.OBJ_SHIELD)
+    sq, _ = oracle.objective_c8(M, WH, C, kap, ds, w, x0, V, dict(w_S=0.0, w_sq=1.0, w_lin=0.0, n_lin=0))
+    assert tot == pytest.approx(g["S_no_indicator"], abs=1e-8)
+    assert lin == pytest.approx(g["sum_viol"], abs=1e-11)
+    assert sq == pytest.approx(g["sum_viol_sq"], abs=1e-11)
+
+
+@pytest.mark.parametrize("obj", [W.OBJ_TOTAL, W.OBJ_SHIELD, dict(w_S=0.3, w_sq=2.0, w_lin=1.0, n_lin=9)])
+def test_c8_dual_gradient_matches_central_differences(obj):
+    kap, ds = W.curvature_table(W.spline_track(2), 512)
+    x0 = W.start_state_c8(4.0, e_y=0.3, e_psi=0.1)
+    V = W.test_sequences(1, 25, seed=8, scale=0.7)[0]
+    eps = oracle.normals(1, 0, 0, 3, 25) * np.array(C["sigma"])
+    g = oracle.gradient_dual_c8(M, WH, C, kap, ds, 0.9, x0, V, obj, eps)
+    fd, valid = oracle.gradient_fd_c8(M, WH, C, kap, ds, 0.9, x0, V, obj, eps, 1e-6)
+    assert valid.mean() > 0.8
+    scale = max(np.abs(fd[valid]).max(), 1e-9)
+    assert np.abs(g - fd)[valid].max() <= 1e-6 * scale
+
+
+def test_c8_shield_noop_without_violations_and_decrease_with():
+    kap, ds = W.curvature_table(W.circle_track(10.0, 1.0), 256)
+    x0 = W.start_state_c8(3.0)
+    Vc = np.tile([0.026, 0.375], (30, 1))
+    lin, _ = oracle.objective_c8(M, WH, C, kap, ds, 1.0, x0, Vc, W.OBJ_SHIELD)
+    assert lin == 0.0
+    assert np.array_equal(oracle.repair_c8(M, WH, C, kap, ds, 1.0, x0, Vc, 10, 0.05, W.OBJ_SHIELD), Vc)
+    x1 = W.start_state_c8(5.0, e_y=-0.5, e_psi=-0.5)
+    V1 = np.zeros((30, 2))
+    before, _ = oracle.objective_c8(M, WH, C, kap, ds, 1.0, x1, V1, W.OBJ_SHIELD)
+    Vs = oracle.repair_c8(M, WH, C, kap, ds, 1.0, x1, V1, 10, 0.05, W.OBJ_SHIELD)
+    after, _ = oracle.objective_c8(M, WH, C, kap, ds, 1.0, x1, Vs, W.OBJ_SHIELD)
+    assert before > 0.0 and after < before
+    assert np.all(Vs >= np.array(M["u_lo"])) and np.all(Vs <= np.array(M["u_hi"]))
+
+
+def test_c8_work_energy_balance():
+    """Work-energy theorem for body and wheels: d/dt [1/2 m (v_x^2 + v_y^2) + 1/2 I_z r^2 +
+    1/2 I_w (omega_F^2 + omega_R^2)] equals the drive power on the rear wheel, the drag
+    power, and each tyre force times its contact slip velocity (longitudinal: wheel centre
+    speed minus r_w omega; lateral: the contact point's sideways speed in the wheel frame).
+    Away from equilibrium every force acts, so this fixes the rotation of the front forces,
+    the moment arms and the wheel reactions."""
+    rng = np.random.default_rng(9)
+    m, Iz, lf, lr = M["m"], M["Iz"], M["lf"], M["lr"]
+    rw, Iw, Cx = WH["r_w"], WH["I_w"], WH["C_x"]
+    for _ in range(50):
+        vx = rng.uniform(1.5, 7.0)
+        x = np.array([vx, rng.normal(0, 0.5), rng.normal(0, 1), vx / rw + rng.normal(0, 8), vx / rw + rng.normal(0, 8),
+                      0.1, 0.2, 3.0])
+        u = np.array([rng.uniform(-0.4, 0.4), rng.uniform(-1, 1)])
+        d = oracle.deriv_c8(M, WH, np.full(8, 0.05), 1.0, x, u)
+        vy, r, wF, wR = x[1], x[2], x[3], x[4]
+        dE = m * (vx * d[0] + vy * d[1]) + Iz * r * d[2] + Iw * (wF * d[3] + wR * d[4])
+        cd, sd = math.cos(u[0]), math.sin(u[0])
+        v_wF = vx * cd + (vy + lf * r) * sd          # front wheel centre along its rolling direction
+        v_latF = -vx * sd + (vy + lf * r) * cd       # and sideways
+        FxF, FxR = Cx * (rw * wF - v_wF) / vx, Cx * (rw * wR - vx) / vx
+        FyF = M["Cf"] * (u[0] - (vy + lf * r) / vx)
+        FyR = M["Cr"] * (lr * r - vy) / vx
+        power = (m * M["a_max"] * rw * u[1] * wR - m * M["c_v"] * vx * vx + FxF * (v_wF - rw * wF)
+                 + FxR * (vx - rw * wR) + FyF * v_latF + FyR * (vy - lr * r))
+        assert dE == pytest.approx(power, rel=1e-11, abs=1e-9)
