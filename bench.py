@@ -40,7 +40,8 @@ if ROOT not in sys.path:
 FLOP_STEP_POLY = 345      # noise, clip, cost, RK4 (4 derivative evaluations), 9-segment window, DCBF
 FLOP_STEP_PER_OBS = 9     # one circular obstacle barrier + penalty + indicator test
 FLOP_UPDATE_STEP = 4      # w * eps' accumulated for two controls
-FLOP_STEP_CURV = 284      # curvilinear model: no window (-117), Frenet kinematics with curvature lookup (+56)
+FLOP_STEP_C8 = 400        # eight-state curvilinear model: 4 derivative evaluations of ~69 (tyre and wheel forces,
+                          # curvature lookup, Frenet kinematics), RK4 stages and combine 96, noise, clip, cost, DCBF
 PEAK_FP32 = 157.3e12      # MI355X FP32 vector peak (packed FMA on every lane)
 PEAK_HBM = 8.0e12
 FORMS = ("split", "active", "plain", "identical", "ragged", "large", "c0", "c3", "c4adj", "shield", "autotune", "sweep",
@@ -582,9 +583,11 @@ def _form_sweep(ctx, out):
 
 
 def _form_curvilinear(ctx, core, W, M, C, sync, out, seed):
-    """Curvilinear-model rollout (Frenet frame, curvature table of the spline track) at
-    K = 65536, T = 100 beside the Cartesian rollout of the same size on the same track
-    (no obstacles)."""
+    """The eight-state curvilinear model (the paper's vehicle state, with wheel speeds):
+    its rollout at K = 65536, T = 100 beside the Cartesian rollout of the same size on the
+    same track (no obstacles), its free-energy adjoint at the same size, and one
+    closed-loop Shield-MPPI iteration at K = 4096, T = 50 through the plain calls
+    (rollout, weights, update, shield, plant step)."""
     import torch
 
     K, T = 65536, 100
@@ -593,16 +596,37 @@ def _form_curvilinear(ctx, core, W, M, C, sync, out, seed):
     S = db.new_S()
     t_cart = _time(lambda: core.rollout(ctx, db, M, C, seed, S=S), 20, 3, sync)
     kap, ds = W.curvature_table(p.track, 1024)
-    pc = W.Problem(K, T, p.track, W.start_state_curv(3.0), p.V, 0, 0)
+    WH = W.wheels_f32()
+    pc = W.Problem(K, T, p.track, W.start_state_c8(3.0), p.V, 0, 0)
     dbc = core.DeviceBatch([W.round_to_f32(pc)], dtype=torch.float32)
     ct = core.CurvTrackArrays([(kap, ds)], [p.track.half_width])
-    t_curv = _time(lambda: core.rollout_curvilinear(ctx, dbc, ct, M, C, seed, S=S), 20, 3, sync)
-    out["curvilinear_K65536_T100"] = {
+    t_curv = _time(lambda: core.rollout_curvilinear(ctx, dbc, ct, M, WH, C, seed, S=S), 20, 3, sync)
+    w, _ = core.weights(ctx, dbc, core.rollout_curvilinear(ctx, dbc, ct, M, WH, C, seed), W.LAMBDA)
+    gV = dbc.new_V()
+    obj = dict(w_S=1.0, w_sq=0.0, w_lin=0.0, n_lin=0)
+    t_adj = _time(lambda: core.rollout_backward_curvilinear(ctx, dbc, ct, M, WH, C, seed, w, obj, out=gV), 10, 2,
+                  sync)
+    # closed loop: Algorithm 2 with Algorithm 1 through the plain calls
+    Kl, Tl = 4096, 50
+    pl = W.Problem(Kl, Tl, p.track, W.start_state_c8(3.0), np.zeros((Tl, 2)), 0, 0)
+    dbl = core.DeviceBatch([W.round_to_f32(pl)], dtype=torch.float32)
+
+    def loop_iter():
+        Sl = core.rollout_curvilinear(ctx, dbl, ct, M, WH, C, seed)
+        wl, _ = core.weights(ctx, dbl, Sl, W.LAMBDA)
+        Vp = core.update(ctx, dbl, M, C, seed, wl)
+        Vs = core.shield_repair_curvilinear(ctx, dbl, ct, M, WH, C, Vp, 10, 0.05, W.OBJ_SHIELD)
+        core.execute_curvilinear(ctx, dbl, ct, M, WH, Vs, Vp)
+
+    t_loop = _time(loop_iter, 50, 5, sync)
+    out["curvilinear8_K65536_T100"] = {
         "rollout_ms": t_curv * 1e3, "rollout_steps_per_s": K * T / t_curv,
-        "achieved_TFLOPs": FLOP_STEP_CURV * K * T / t_curv / 1e12,
+        "achieved_TFLOPs": FLOP_STEP_C8 * K * T / t_curv / 1e12,
+        "free_energy_adjoint_ms": t_adj * 1e3,
         "cartesian_rollout_ms": t_cart * 1e3, "cartesian_rollout_steps_per_s": K * T / t_cart,
-        "cartesian_achieved_TFLOPs": FLOP_STEP_POLY * K * T / t_cart / 1e12}
-    _log(f"  curvilinear: {out['curvilinear_K65536_T100']}")
+        "cartesian_achieved_TFLOPs": FLOP_STEP_POLY * K * T / t_cart / 1e12,
+        "closed_loop_K4096_T50_ms_per_iter": t_loop * 1e3}
+    _log(f"  curvilinear: {out['curvilinear8_K65536_T100']}")
 
 
 def _cpu_model():

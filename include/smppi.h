@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SMPPI_ABI_VERSION 5
+#define SMPPI_ABI_VERSION 6
 
 typedef enum {
   SMPPI_OK = 0,
@@ -141,6 +141,27 @@ typedef struct {
   int32_t n_max;            /* host: max N_b (<= 8192) */
 } smppi_curv_track;
 
+/* Wheels of the eight-state curvilinear model (Sec. VI-A names the state
+ * x = (v_x, v_y, r, omega_F, omega_R, e_psi, e_y, s): body velocities, yaw rate,
+ * front and rear wheel speeds, heading error, lateral deviation, progress; the
+ * paper prints no equations, so the library's reading is):
+ *   F_yF = C_f (delta - (v_y + l_f r)/v~),  F_yR = C_r (l_r r - v_y)/v~,  v~ = max(v_x, v_min),
+ *   F_xF = C_x (r_w omega_F - v_x cos(delta) - (v_y + l_f r) sin(delta))/v~,
+ *   F_xR = C_x (r_w omega_R - v_x)/v~,
+ *   v_x' = (F_xR + F_xF cos(delta) - F_yF sin(delta))/m - c_v v_x + v_y r,
+ *   v_y' = (F_yR + F_xF sin(delta) + F_yF cos(delta))/m - v_x r,
+ *   r'   = (l_f (F_xF sin(delta) + F_yF cos(delta)) - l_r F_yR)/I_z,
+ *   omega_F' = -r_w F_xF / I_w,  omega_R' = (m a_max r_w T - r_w F_xR)/I_w,
+ *   s' = (v_x cos(e_psi) - v_y sin(e_psi))/(1 - kappa(s) e_y),
+ *   e_y' = v_x sin(e_psi) + v_y cos(e_psi),  e_psi' = r - kappa(s) s',
+ * with the smppi_model constants; at the wheels' equilibrium speeds the body
+ * equations are the six-state model's. */
+typedef struct {
+  double r_w;  /* wheel radius (m) */
+  double I_w;  /* wheel inertia per axle (kg m^2) */
+  double C_x;  /* longitudinal slip stiffness per axle (N) */
+} smppi_wheels;
+
 /* Differentiated objective of one trajectory (used by the adjoint and repair):
  *   L = w_S S~' + w_sq sum_{j,t<T} viol_{j,t}^2 + w_lin sum_{j, t<n_lin} viol_{j,t},
  *   viol_{j,t} = max(alpha h_j(x_t) - h_j(x_{t+1}), 0),
@@ -209,18 +230,43 @@ smppi_status smppi_rollout(smppi_ctx ctx, const smppi_batch* batch, const smppi_
                            const void* x0, const void* V, const uint32_t* iter, void* S, void* eps_out,
                            void* stream);
 
-/* The sampled rollout of smppi_rollout for the curvilinear model: state
- * x = (s, e_y, e_psi, v_x, v_y, omega) with the single-track velocity dynamics
- * and the Frenet kinematics
- *   s' = (v_x cos e_psi - v_y sin e_psi) / (1 - kappa(s) e_y),
- *   e_y' = v_x sin e_psi + v_y cos e_psi,   e_psi' = omega - kappa(s) s';
- * S~ as in smppi_rollout with the track barrier read from the state (no
- * obstacles).  x0: device [B][6] dtype in that state order; the other arguments
- * as in smppi_rollout.  The weights and update calls apply unchanged. */
+/* The sampled rollout of smppi_rollout for the eight-state curvilinear model
+ * (smppi_wheels): x0 device [B][8] dtype in the state order
+ * (v_x, v_y, r, omega_F, omega_R, e_psi, e_y, s); S~ as in smppi_rollout with
+ * q = q_v (v_x - v_g)^2 + q_ey e_y^2 + C_obs [|e_y| > w] and the DCBF penalty on
+ * h = w^2 - e_y^2 (no obstacles).  V, iter, S, eps_out and the noise as in
+ * smppi_rollout; smppi_weights and smppi_update apply unchanged. */
 smppi_status smppi_rollout_curvilinear(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
-                                       const smppi_cost* cost, const smppi_noise* noise,
+                                       const smppi_wheels* wheels, const smppi_cost* cost, const smppi_noise* noise,
                                        const smppi_curv_track* track, const void* x0, const void* V,
                                        const uint32_t* iter, void* S, void* eps_out, void* stream);
+
+/* Adjoint of smppi_rollout_curvilinear (as smppi_rollout_backward, with the
+ * barrier read from e_y): grad_V = sum_m grad_S[m] dL_m/dV, states recomputed
+ * from per-sample checkpoints.  Scratch as smppi_rollout_backward
+ * (smppi_reserve_batch). */
+smppi_status smppi_rollout_backward_curvilinear(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                                                const smppi_wheels* wheels, const smppi_cost* cost,
+                                                const smppi_noise* noise, const smppi_curv_track* track,
+                                                const void* x0, const void* V, const uint32_t* iter,
+                                                const void* grad_S, const smppi_objective* objective, void* grad_V,
+                                                void* stream);
+
+/* Safety shield (Algorithm 1, eq. (22)) on the curvilinear model: method 0 of
+ * smppi_repair_opts only (SMPPI_ERR_UNSUPPORTED otherwise).  V_safe may equal
+ * V_plus. */
+smppi_status smppi_shield_repair_curvilinear(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                                             const smppi_wheels* wheels, const smppi_cost* cost,
+                                             const smppi_curv_track* track, const void* x0, const void* V_plus,
+                                             const smppi_repair_opts* opts, void* V_safe, void* stream);
+
+/* Execute and warm start on the curvilinear model (as smppi_execute): x [B][8]
+ * <- RK4(x, clipped first control of V_exec) + (0, dist_vy, dist_r, 0, ...),
+ * V <- V_plus shifted one step, iter += 1. */
+smppi_status smppi_execute_curvilinear(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                                       const smppi_wheels* wheels, const smppi_curv_track* track, const void* V_exec,
+                                       const void* V_plus, const void* dist, int32_t n_dist, void* x, void* V,
+                                       uint32_t* iter, void* stream);
 
 /* Path-integral weights (eqs. (7), (9), (11)): w_m = exp(-(S_m - min S)/lambda)
  * / sum, per problem, with non-finite S_m given weight 0.

@@ -22,8 +22,9 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "shape", 3: "dtype", 4: "no device"
 ERR_NO_DEVICE = 4
 
 # Symbols declared in include/smppi.h (checked by the CPU test suite).
-ABI_VERSION = 5  # SMPPI_ABI_VERSION of include/smppi.h this binding matches
-EXPORTS = ("smppi_rollout_curvilinear", "smppi_create", "smppi_destroy", "smppi_last_error", "smppi_status_string", "smppi_abi_version",
+ABI_VERSION = 6  # SMPPI_ABI_VERSION of include/smppi.h this binding matches
+EXPORTS = ("smppi_rollout_curvilinear", "smppi_rollout_backward_curvilinear", "smppi_shield_repair_curvilinear",
+           "smppi_execute_curvilinear", "smppi_create", "smppi_destroy", "smppi_last_error", "smppi_status_string", "smppi_abi_version",
            "smppi_reserve_batch", "smppi_device_errors", "smppi_rollout", "smppi_weights", "smppi_update",
            "smppi_rollout_backward", "smppi_rollout_backward_noalloc", "smppi_shield_repair", "smppi_execute", "smppi_plan_create",
            "smppi_plan_launch", "smppi_plan_destroy", "smppi_plan_info", "smppi_plan_launch_profiled",
@@ -57,6 +58,10 @@ class Track(ctypes.Structure):
 
 class CurvTrack(ctypes.Structure):
     _fields_ = [("kappa_off", c_vp), ("kappa", c_vp), ("ds", c_vp), ("half_width", c_vp), ("n_max", c_i32)]
+
+
+class Wheels(ctypes.Structure):
+    _fields_ = [("r_w", c_f64), ("I_w", c_f64), ("C_x", c_f64)]
 
 
 class Objective(ctypes.Structure):
@@ -98,8 +103,14 @@ _SIGS = {
     "smppi_abi_version": (ctypes.c_int, []),
     "smppi_reserve_batch": (c_i32, [c_vp, P(Batch)]),
     "smppi_device_errors": (c_i32, [c_vp, P(c_u32)]),
-    "smppi_rollout_curvilinear": (c_i32, [c_vp, P(Batch), P(Model), P(Cost), P(Noise), P(CurvTrack), c_vp, c_vp,
-                                          c_vp, c_vp, c_vp, c_vp]),
+    "smppi_rollout_curvilinear": (c_i32, [c_vp, P(Batch), P(Model), P(Wheels), P(Cost), P(Noise), P(CurvTrack),
+                                          c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "smppi_rollout_backward_curvilinear": (c_i32, [c_vp, P(Batch), P(Model), P(Wheels), P(Cost), P(Noise),
+                                                   P(CurvTrack), c_vp, c_vp, c_vp, c_vp, P(Objective), c_vp, c_vp]),
+    "smppi_shield_repair_curvilinear": (c_i32, [c_vp, P(Batch), P(Model), P(Wheels), P(Cost), P(CurvTrack), c_vp,
+                                                c_vp, P(RepairOpts), c_vp, c_vp]),
+    "smppi_execute_curvilinear": (c_i32, [c_vp, P(Batch), P(Model), P(Wheels), P(CurvTrack), c_vp, c_vp, c_vp,
+                                          c_i32, c_vp, c_vp, c_vp, c_vp]),
     "smppi_rollout": (c_i32, [c_vp, P(Batch), P(Model), P(Cost), P(Noise), P(Track), c_vp, c_vp, c_vp, c_vp, c_vp,
                               c_vp]),
     "smppi_weights": (c_i32, [c_vp, P(Batch), c_vp, c_f64, c_vp, c_vp, c_vp]),
@@ -167,6 +178,10 @@ def cost_struct(d: dict) -> Cost:
         setattr(c, k, float(d[k]))
     c.sigma[0], c.sigma[1] = d["sigma"]
     return c
+
+
+def wheels_struct(d: dict) -> Wheels:
+    return Wheels(float(d["r_w"]), float(d["I_w"]), float(d["C_x"]))
 
 
 def objective_struct(d: dict) -> Objective:

@@ -170,18 +170,60 @@ class CurvTrackArrays:
                                  self.half_width.data_ptr(), int(self.n_max))
 
 
-def rollout_curvilinear(ctx: Context, db: DeviceBatch, ct: CurvTrackArrays, model: dict, cost: dict, seed: int,
-                        nominal: bool = False, x0=None, S=None, want_eps: bool = False):
-    """smppi_rollout_curvilinear: S~ [sum K] of the curvilinear model; x0 (default db.x0)
-    holds (s, e_y, e_psi, v_x, v_y, omega) per problem."""
+def rollout_curvilinear(ctx: Context, db: DeviceBatch, ct: CurvTrackArrays, model: dict, wheels: dict, cost: dict,
+                        seed: int, nominal: bool = False, x0=None, V=None, iters=None, S=None, want_eps: bool = False):
+    """smppi_rollout_curvilinear: S~ [sum K] of the eight-state curvilinear model; x0
+    (default db.x0) holds (v_x, v_y, r, omega_F, omega_R, e_psi, e_y, s) per problem."""
     S = db.new_S() if S is None else S
     eps = torch.zeros(db.sum_K * db.t_max * 2, dtype=db.dtype, device=db.device) if want_eps else None
     st = L.lib().smppi_rollout_curvilinear(ctx.h, ctypes.byref(db.batch), ctypes.byref(L.model_struct(model)),
-                                           ctypes.byref(L.cost_struct(cost)), ctypes.byref(_noise(seed, nominal)),
-                                           ctypes.byref(ct.track), _p(db.x0 if x0 is None else x0), _p(db.V),
-                                           _p(db.iter), _p(S), _p(eps), ctypes.c_void_p(_stream()))
+                                           ctypes.byref(L.wheels_struct(wheels)), ctypes.byref(L.cost_struct(cost)),
+                                           ctypes.byref(_noise(seed, nominal)), ctypes.byref(ct.track),
+                                           _p(db.x0 if x0 is None else x0), _p(db.V if V is None else V),
+                                           _p(db.iter if iters is None else iters), _p(S), _p(eps),
+                                           ctypes.c_void_p(_stream()))
     ctx.check(st, "smppi_rollout_curvilinear")
     return (S, eps.view(db.sum_K, db.t_max, 2)) if want_eps else S
+
+
+def rollout_backward_curvilinear(ctx: Context, db: DeviceBatch, ct: CurvTrackArrays, model: dict, wheels: dict,
+                                 cost: dict, seed: int, grad_S: torch.Tensor, objective: dict, nominal: bool = False,
+                                 x0=None, V=None, iters=None, out=None):
+    """smppi_rollout_backward_curvilinear: sum_m grad_S[m] dL_m/dV (library layout)."""
+    out = db.new_V() if out is None else out
+    ctx.reserve(db)
+    st = L.lib().smppi_rollout_backward_curvilinear(
+        ctx.h, ctypes.byref(db.batch), ctypes.byref(L.model_struct(model)), ctypes.byref(L.wheels_struct(wheels)),
+        ctypes.byref(L.cost_struct(cost)), ctypes.byref(_noise(seed, nominal)), ctypes.byref(ct.track),
+        _p(db.x0 if x0 is None else x0), _p(db.V if V is None else V), _p(db.iter if iters is None else iters),
+        _p(grad_S), ctypes.byref(L.objective_struct(objective)), _p(out), ctypes.c_void_p(_stream()))
+    ctx.check(st, "smppi_rollout_backward_curvilinear")
+    return out
+
+
+def shield_repair_curvilinear(ctx: Context, db: DeviceBatch, ct: CurvTrackArrays, model: dict, wheels: dict,
+                              cost: dict, V_plus: torch.Tensor, n_steps: int, step: float, objective: dict, x0=None,
+                              out=None):
+    """smppi_shield_repair_curvilinear: Algorithm 1 on the curvilinear model."""
+    out = db.new_V() if out is None else out
+    opts = L.repair_opts(n_steps, step, objective, "gradient")
+    st = L.lib().smppi_shield_repair_curvilinear(
+        ctx.h, ctypes.byref(db.batch), ctypes.byref(L.model_struct(model)), ctypes.byref(L.wheels_struct(wheels)),
+        ctypes.byref(L.cost_struct(cost)), ctypes.byref(ct.track), _p(db.x0 if x0 is None else x0), _p(V_plus),
+        ctypes.byref(opts), _p(out), ctypes.c_void_p(_stream()))
+    ctx.check(st, "smppi_shield_repair_curvilinear")
+    return out
+
+
+def execute_curvilinear(ctx: Context, db: DeviceBatch, ct: CurvTrackArrays, model: dict, wheels: dict,
+                        V_exec: torch.Tensor, V_plus: torch.Tensor, dist: Optional[torch.Tensor] = None,
+                        n_dist: int = 0):
+    """smppi_execute_curvilinear: advances db.x0 (eight states), warm-starts db.V, increments db.iter."""
+    st = L.lib().smppi_execute_curvilinear(ctx.h, ctypes.byref(db.batch), ctypes.byref(L.model_struct(model)),
+                                           ctypes.byref(L.wheels_struct(wheels)), ctypes.byref(ct.track), _p(V_exec),
+                                           _p(V_plus), _p(dist), int(n_dist), _p(db.x0), _p(db.V), _p(db.iter),
+                                           ctypes.c_void_p(_stream()))
+    ctx.check(st, "smppi_execute_curvilinear")
 
 
 def weights(ctx: Context, db: DeviceBatch, S: torch.Tensor, lam: float):

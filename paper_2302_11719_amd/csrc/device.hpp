@@ -260,50 +260,14 @@ __device__ __forceinline__ void rk4(const DevModel<R>& M, const StepCtl<R>& c, S
 }
 
 // ---------------------------------------------------------------- curvilinear model
-// State (s, e_y, e_psi, v_x, v_y, omega) along a path of curvature kappa(s):
-// the velocity part is rk4_vel; the Frenet kinematics replace the pose part.
+// Track of the curvilinear model: the periodic curvature table kappa(j ds)
+// (LDS or global), its length, spacing and the half width squared.
 template <class R>
 struct CurvView {
-  const R* kappa;  // LDS [n], periodic: kappa(j ds)
+  const R* kappa;
   int n;
   R ds, w2;
 };
-
-template <class R>
-__device__ __forceinline__ R kappa_at(const CurvView<R>& cv, R s) {
-  const R jf = floor(s / cv.ds);
-  const R f = s / cv.ds - jf;
-  int j = (int)jf % cv.n;
-  j += j < 0 ? cv.n : 0;
-  const int j1 = j + 1 == cv.n ? 0 : j + 1;
-  return cv.kappa[j] * (R(1) - f) + cv.kappa[j1] * f;
-}
-
-template <class R>
-__device__ __forceinline__ void frenet_deriv(const CurvView<R>& cv, R s, R ey, R epsi, R vx, R vy, R om, R& d_s,
-                                             R& d_ey, R& d_epsi) {
-  const R k = kappa_at(cv, s);
-  R sp, cp;
-  sincos_r(epsi, &sp, &cp);
-  d_s = (vx * cp - vy * sp) / (R(1) - k * ey);
-  d_ey = vx * sp + vy * cp;
-  d_epsi = om - k * d_s;
-}
-
-// Frenet part of a classic RK4 step from the stage velocities.
-template <class R>
-__device__ __forceinline__ void rk4_frenet(const DevModel<R>& M, const CurvView<R>& cv, const VelStages<R>& g, R& s,
-                                           R& ey, R& epsi) {
-  const R h = M.dt, h2 = R(0.5) * M.dt, h6 = M.dt * R(1.0 / 6.0);
-  R a0, a1, a2, b0, b1, b2, c0, c1, c2, d0, d1, d2;
-  frenet_deriv(cv, s, ey, epsi, g.vx[0], g.vy[0], g.om[0], a0, a1, a2);
-  frenet_deriv(cv, s + h2 * a0, ey + h2 * a1, epsi + h2 * a2, g.vx[1], g.vy[1], g.om[1], b0, b1, b2);
-  frenet_deriv(cv, s + h2 * b0, ey + h2 * b1, epsi + h2 * b2, g.vx[2], g.vy[2], g.om[2], c0, c1, c2);
-  frenet_deriv(cv, s + h * c0, ey + h * c1, epsi + h * c2, g.vx[3], g.vy[3], g.om[3], d0, d1, d2);
-  s += h6 * (a0 + R(2) * b0 + R(2) * c0 + d0);
-  ey += h6 * (a1 + R(2) * b1 + R(2) * c1 + d1);
-  epsi += h6 * (a2 + R(2) * b2 + R(2) * c2 + d2);
-}
 
 // ---------------------------------------------------------------- track
 // Polyline segments are staged in LDS as (a_x, a_y, d_x, d_y) plus 1/|d|^2.
@@ -695,45 +659,6 @@ template <class R, int NOBS>
 __device__ R rollout_sample(const DevModel<R>& M, const DevCost<R>& C, const TrackView<R>& tr, const State<R>& x0,
                             const R* __restrict__ V, int T, NoiseStream<R>& ns, R* eps_out) {
   return rollout_sample<R, NOBS>(M, C, tr, x0, V, T, ns, eps_out, LdsObstacles<R>{&tr});
-}
-
-// Modified trajectory cost S~ of one sample of the curvilinear model: as
-// rollout_sample with the track barrier h = w^2 - e_y^2 read from the state.
-// x0 = (s, e_y, e_psi, v_x, v_y, omega).
-template <class R>
-__device__ R rollout_sample_curv(const DevModel<R>& M, const DevCost<R>& C, const CurvView<R>& cv, const R* x0,
-                                 const R* __restrict__ V, int T, NoiseStream<R>& ns, R* eps_out) {
-  R s = x0[0], ey = x0[1], epsi = x0[2], vx = x0[3], vy = x0[4], om = x0[5];
-  R h0 = cv.w2 - ey * ey;
-  bool outside = h0 < R(0);
-  R S = C.C_cbf * fmax((C.alpha - R(1)) * h0, R(0));
-  for (int t = 0; t < T; ++t) {
-    const R v0 = V[t], v1 = V[T + t];
-    R e0, e1;
-    ns.at(t, C.sigma[0], C.sigma[1], e0, e1);
-    const R u0 = clamp_r(v0 + e0, M.u_lo[0], M.u_hi[0]);
-    const R u1 = clamp_r(v1 + e1, M.u_lo[1], M.u_hi[1]);
-    if (eps_out) {
-      eps_out[2 * t] = u0 - v0;
-      eps_out[2 * t + 1] = u1 - v1;
-    }
-    const R dv = vx - C.v_g;
-    R q = C.q_v * dv * dv + C.q_ey * (ey * ey);
-    if (outside) q += C.C_obs;
-    S += q + (C.ctrl_w[0] * v0 * u0 + C.ctrl_w[1] * v1 * u1);
-    VelStages<R> g;
-    rk4_vel(M, step_ctl(M, u0, u1), vx, vy, om, g);
-    rk4_frenet(M, cv, g, s, ey, epsi);
-    const R h1 = cv.w2 - ey * ey;
-    S += C.C_cbf * fmax(C.alpha * h0 - h1, R(0));
-    h0 = h1;
-    outside = h1 < R(0);
-  }
-  const R dv = vx - C.v_g;
-  R q = C.q_v * dv * dv + C.q_ey * (ey * ey);
-  if (outside) q += C.C_obs;
-  S += C.phi_w * q;
-  return S;
 }
 
 // ---------------------------------------------------------------- adjoint

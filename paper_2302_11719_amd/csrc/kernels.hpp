@@ -392,73 +392,6 @@ __global__ __launch_bounds__(256) void k_rollout(RolloutArgs<R> a) {
     a.S[d.k0 + m] = rollout_sample<R, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, eo);
 }
 
-// ============================================================== curvilinear rollout
-template <class R>
-struct CurvArgs {
-  const int64_t* k_off;
-  const int32_t* t_off;
-  const int32_t* kappa_off;
-  const R* kappa;
-  const R* ds;
-  const R* half_width;
-  const R* x0;
-  const uint32_t* iter;
-  const R* V;
-  R* S;
-  R* eps_out;
-  DevModel<R> M;
-  DevCost<R> C;
-  int32_t k_max, t_max, n_max, pid_base;
-  uint32_t seed;
-  int32_t nominal;
-  uint32_t* err;
-};
-
-// One sample per lane; the problem's curvature table and V staged in LDS
-// ([n_max] | [2][t_max]).
-template <class R>
-__global__ __launch_bounds__(256) void k_rollout_curv(CurvArgs<R> a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  R* kap = reinterpret_cast<R*>(smem);
-  R* Vs = kap + a.n_max;
-  const int b = blockIdx.y;
-  const int64_t k0 = a.k_off[b], K = a.k_off[b + 1] - k0;
-  const int t0 = a.t_off[b], T = a.t_off[b + 1] - t0;
-  const int c0 = a.kappa_off[b], n = a.kappa_off[b + 1] - c0;
-  uint32_t e = 0;
-  if (T < 1 || T > a.t_max) e |= DERR_T;
-  if (K < 0 || K > a.k_max) e |= DERR_K;
-  if (n < 2 || n > a.n_max) e |= DERR_POLY;
-  if (e) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) atomicOr(a.err, e);
-    return;
-  }
-  const int m_base = blockIdx.x * blockDim.x;
-  if (m_base >= K) return;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) kap[i] = a.kappa[c0 + i];
-  for (int i = threadIdx.x; i < 2 * T; i += blockDim.x) Vs[i] = a.V[2 * (size_t)t0 + i];
-  __syncthreads();
-  const int m = m_base + threadIdx.x;
-  if (m >= K) return;
-  CurvView<R> cv;
-  cv.kappa = kap;
-  cv.n = n;
-  cv.ds = a.ds[b];
-  const R w = a.half_width[b];
-  cv.w2 = w * w;
-  NoiseStream<R> ns;
-  ns.seed = a.seed;
-  ns.m = (uint32_t)m;
-  ns.pid = (uint32_t)(a.pid_base + b);
-  ns.it = a.iter[b];
-  ns.nominal = a.nominal != 0;
-  R x0[6];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) x0[i] = a.x0[6 * (size_t)b + i];
-  R* eo = a.eps_out ? a.eps_out + (size_t)(k0 + m) * a.t_max * 2 : nullptr;
-  a.S[k0 + m] = rollout_sample_curv<R>(a.M, a.C, cv, x0, Vs, T, ns, eo);
-}
-
 // ============================================================== weights
 template <class R>
 __global__ __launch_bounds__(256) void k_weights(const int64_t* __restrict__ k_off, const R* __restrict__ S,

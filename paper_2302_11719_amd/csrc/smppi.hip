@@ -14,6 +14,7 @@
 #include "../../include/smppi.h"
 #include "common.hpp"
 #include "kernels.hpp"
+#include "curv8.hpp"
 
 using namespace smppi;
 
@@ -370,12 +371,24 @@ extern "C" smppi_status smppi_rollout(smppi_ctx ctx, const smppi_batch* batch, c
   return rollout_t<double>(ctx, batch, model, cost, noise, track, x0, V, iter, S, eps_out, s);
 }
 
-// ------------------------------------------------------------------ curvilinear rollout
+// ------------------------------------------------------------------ curvilinear model
+static smppi_status validate_curv(smppi_ctx ctx, const smppi_wheels* wh, const smppi_curv_track* t) {
+  if (!wh) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "wheels are required");
+  if (!(wh->r_w > 0.0) || !(wh->I_w > 0.0) || !(wh->C_x > 0.0) || !std::isfinite(wh->r_w) ||
+      !std::isfinite(wh->I_w) || !std::isfinite(wh->C_x))
+    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "wheels: r_w, I_w, C_x must be finite and > 0");
+  if (!t) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "track is required");
+  if (!t->kappa_off || !t->kappa || !t->ds || !t->half_width)
+    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "curvature track arrays are required");
+  if (t->n_max < 2 || t->n_max > 8192) return fail(ctx, SMPPI_ERR_SHAPE, "n_max must be in [2, 8192]");
+  return SMPPI_OK;
+}
+
 template <class R>
-static smppi_status rollout_curv_t(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const smppi_cost* c,
-                                   const smppi_noise* n, const smppi_curv_track* t, const void* x0, const void* V,
-                                   const uint32_t* iter, void* S, void* eps_out, hipStream_t s) {
-  CurvArgs<R> a;
+static C8Args<R> c8_args(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const smppi_wheels* wh,
+                         const smppi_cost* c, const smppi_noise* n, const smppi_curv_track* t, const void* x0,
+                         const void* V, const uint32_t* iter) {
+  C8Args<R> a;
   a.k_off = b->k_off;
   a.t_off = b->t_off;
   a.kappa_off = t->kappa_off;
@@ -385,46 +398,188 @@ static smppi_status rollout_curv_t(smppi_ctx ctx, const smppi_batch* b, const sm
   a.x0 = static_cast<const R*>(x0);
   a.iter = iter;
   a.V = static_cast<const R*>(V);
-  a.S = static_cast<R*>(S);
-  a.eps_out = static_cast<R*>(eps_out);
   a.M = dev_model<R>(m);
+  a.Wh.r_w = (R)wh->r_w;
+  a.Wh.C_x = (R)wh->C_x;
+  a.Wh.rw_Iw = (R)(wh->r_w / wh->I_w);
+  a.Wh.drive_Iw = (R)(m->m * m->a_max * wh->r_w / wh->I_w);
   a.C = dev_cost<R>(c);
+  a.B = b->n_problems;
   a.k_max = b->k_max;
   a.t_max = b->t_max;
   a.n_max = t->n_max;
   a.pid_base = b->pid_base;
-  a.seed = n->seed;
-  a.nominal = n->nominal;
+  a.seed = n ? n->seed : 0u;
+  a.nominal = n ? n->nominal : 1;
   a.err = ctx->err;
+  return a;
+}
+
+template <class R>
+static smppi_status rollout_c8_t(smppi_ctx ctx, const smppi_batch* b, const C8Args<R>& a, void* S, void* eps_out,
+                                 hipStream_t s) {
   const int blk = 256;
   const int gx = b->k_max > 0 ? (b->k_max + blk - 1) / blk : 0;
   if (gx == 0) return SMPPI_OK;
-  const size_t lds = sizeof(R) * ((size_t)t->n_max + 2 * (size_t)b->t_max);
+  const size_t lds = c8_stage_bytes<R>(a.n_max, a.t_max);
   if (lds > (size_t)ctx->max_lds)
     return fail(ctx, SMPPI_ERR_SHAPE, "curvilinear rollout needs %zu B of LDS per workgroup (device max %d)", lds,
                 ctx->max_lds);
-  hipLaunchKernelGGL((k_rollout_curv<R>), dim3(gx, b->n_problems), dim3(blk), lds, s, a);
-  return check_launch(ctx, "k_rollout_curv");
+  hipLaunchKernelGGL((k_rollout_c8<R>), dim3(gx, b->n_problems), dim3(blk), lds, s, a, static_cast<R*>(S),
+                     static_cast<R*>(eps_out));
+  return check_launch(ctx, "k_rollout_c8");
 }
 
 extern "C" smppi_status smppi_rollout_curvilinear(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
-                                                  const smppi_cost* cost, const smppi_noise* noise,
-                                                  const smppi_curv_track* track, const void* x0, const void* V,
-                                                  const uint32_t* iter, void* S, void* eps_out, void* stream) {
+                                                  const smppi_wheels* wheels, const smppi_cost* cost,
+                                                  const smppi_noise* noise, const smppi_curv_track* track,
+                                                  const void* x0, const void* V, const uint32_t* iter, void* S,
+                                                  void* eps_out, void* stream) {
   if (!ctx) return SMPPI_ERR_INVALID_ARGUMENT;
   smppi_status st;
-  if ((st = validate_batch(ctx, batch)) || (st = validate_model(ctx, model)) || (st = validate_cost(ctx, cost)))
+  if ((st = validate_batch(ctx, batch)) || (st = validate_model(ctx, model)) || (st = validate_cost(ctx, cost)) ||
+      (st = validate_curv(ctx, wheels, track)))
     return st;
-  if (!noise || !track) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "noise and track are required");
-  if (!track->kappa_off || !track->kappa || !track->ds || !track->half_width)
-    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "curvature track arrays are required");
-  if (track->n_max < 2 || track->n_max > 8192) return fail(ctx, SMPPI_ERR_SHAPE, "n_max must be in [2, 8192]");
+  if (!noise) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "noise is NULL");
   if (!x0 || !V || !iter || !S) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "x0, V, iter, S are required");
   (void)hipSetDevice(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (batch->dtype == SMPPI_F32)
-    return rollout_curv_t<float>(ctx, batch, model, cost, noise, track, x0, V, iter, S, eps_out, s);
-  return rollout_curv_t<double>(ctx, batch, model, cost, noise, track, x0, V, iter, S, eps_out, s);
+    return rollout_c8_t<float>(ctx, batch, c8_args<float>(ctx, batch, model, wheels, cost, noise, track, x0, V, iter),
+                               S, eps_out, s);
+  return rollout_c8_t<double>(ctx, batch, c8_args<double>(ctx, batch, model, wheels, cost, noise, track, x0, V, iter),
+                              S, eps_out, s);
+}
+
+template <class R>
+static smppi_status backward_c8_t(smppi_ctx ctx, const smppi_batch* b, const C8Args<R>& a,
+                                  const smppi_objective* ob, const void* gS, void* gV, hipStream_t s) {
+  C8BackwardArgs<R> g;
+  g.a = a;
+  g.ob = dev_objective<R>(ob);
+  g.grad_S = static_cast<const R*>(gS);
+  g.grad_V = static_cast<R*>(gV);
+  g.nblk_max = std::max(1, (b->k_max + WAVE - 1) / WAVE);
+  g.seg_len = adj_seg_len(b->t_max);
+  smppi_status st;
+  if ((st = need_scratch(ctx, sizeof(R) * (size_t)b->n_problems * g.nblk_max * 2 * b->t_max, b->n_problems,
+                         "smppi_rollout_backward_curvilinear")))
+    return st;
+  g.part = static_cast<R*>(ctx->scratch);
+  g.tickets = ctx->tickets;
+  const size_t lds = c8_stage_bytes<R>(a.n_max, a.t_max) + c8_adj_lds_bytes<R>(a.t_max, g.seg_len);
+  if (lds > (size_t)ctx->max_lds)
+    return fail(ctx, SMPPI_ERR_SHAPE, "curvilinear adjoint needs %zu B of LDS per workgroup (device max %d)", lds,
+                ctx->max_lds);
+  hipLaunchKernelGGL((k_backward_c8<R>), dim3(g.nblk_max, b->n_problems), dim3(WAVE), lds, s, g);
+  return check_launch(ctx, "k_backward_c8");
+}
+
+extern "C" smppi_status smppi_rollout_backward_curvilinear(
+    smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model, const smppi_wheels* wheels,
+    const smppi_cost* cost, const smppi_noise* noise, const smppi_curv_track* track, const void* x0, const void* V,
+    const uint32_t* iter, const void* grad_S, const smppi_objective* objective, void* grad_V, void* stream) {
+  if (!ctx) return SMPPI_ERR_INVALID_ARGUMENT;
+  smppi_status st;
+  if ((st = validate_batch(ctx, batch)) || (st = validate_model(ctx, model)) || (st = validate_cost(ctx, cost)) ||
+      (st = validate_curv(ctx, wheels, track)) || (st = validate_objective(ctx, objective)))
+    return st;
+  if (!noise) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "noise is NULL");
+  if (!x0 || !V || !iter || !grad_S || !grad_V)
+    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "x0, V, iter, grad_S, grad_V are required");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (batch->dtype == SMPPI_F32)
+    return backward_c8_t<float>(ctx, batch,
+                                c8_args<float>(ctx, batch, model, wheels, cost, noise, track, x0, V, iter), objective,
+                                grad_S, grad_V, s);
+  return backward_c8_t<double>(ctx, batch,
+                               c8_args<double>(ctx, batch, model, wheels, cost, noise, track, x0, V, iter), objective,
+                               grad_S, grad_V, s);
+}
+
+template <class R>
+static smppi_status repair_c8_t(smppi_ctx ctx, const smppi_batch* b, const C8Args<R>& a,
+                                const smppi_repair_opts* o, const void* Vp, void* Vs, hipStream_t s) {
+  C8RepairArgs<R> r;
+  r.a = a;
+  r.ob = dev_objective<R>(&o->objective);
+  r.V_plus = static_cast<const R*>(Vp);
+  r.V_safe = static_cast<R*>(Vs);
+  r.n_steps = o->n_steps;
+  r.step = (R)o->step;
+  const size_t lds = c8_repair_lds_bytes<R>(a.n_max, a.t_max);
+  if (lds > (size_t)ctx->max_lds)
+    return fail(ctx, SMPPI_ERR_SHAPE, "curvilinear shield needs %zu B of LDS per workgroup (device max %d)", lds,
+                ctx->max_lds);
+  hipLaunchKernelGGL((k_repair_c8<R>), dim3(b->n_problems), dim3(WAVE), lds, s, r);
+  return check_launch(ctx, "k_repair_c8");
+}
+
+extern "C" smppi_status smppi_shield_repair_curvilinear(smppi_ctx ctx, const smppi_batch* batch,
+                                                        const smppi_model* model, const smppi_wheels* wheels,
+                                                        const smppi_cost* cost, const smppi_curv_track* track,
+                                                        const void* x0, const void* V_plus,
+                                                        const smppi_repair_opts* opts, void* V_safe, void* stream) {
+  if (!ctx) return SMPPI_ERR_INVALID_ARGUMENT;
+  smppi_status st;
+  if ((st = validate_batch(ctx, batch)) || (st = validate_model(ctx, model)) || (st = validate_cost(ctx, cost)) ||
+      (st = validate_curv(ctx, wheels, track)) || (st = validate_repair(ctx, opts)))
+    return st;
+  if (opts->method != 0)
+    return fail(ctx, SMPPI_ERR_UNSUPPORTED, "the curvilinear shield implements Algorithm 1 (method 0) only");
+  if (!x0 || !V_plus || !V_safe) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "x0, V_plus, V_safe are required");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (batch->dtype == SMPPI_F32)
+    return repair_c8_t<float>(
+        ctx, batch, c8_args<float>(ctx, batch, model, wheels, cost, nullptr, track, x0, V_plus, nullptr), opts, V_plus,
+        V_safe, s);
+  return repair_c8_t<double>(
+      ctx, batch, c8_args<double>(ctx, batch, model, wheels, cost, nullptr, track, x0, V_plus, nullptr), opts, V_plus,
+      V_safe, s);
+}
+
+template <class R>
+static smppi_status execute_c8_t(smppi_ctx ctx, const smppi_batch* b, const C8Args<R>& a, const void* Ve,
+                                 const void* Vp, const void* dist, int32_t n_dist, void* x, void* V, uint32_t* iter,
+                                 hipStream_t s) {
+  C8ExecArgs<R> e;
+  e.a = a;
+  e.V_exec = static_cast<const R*>(Ve);
+  e.V_plus = static_cast<const R*>(Vp);
+  e.dist = static_cast<const R*>(dist);
+  e.n_dist = n_dist;
+  e.x = static_cast<R*>(x);
+  e.V = static_cast<R*>(V);
+  e.iter = iter;
+  hipLaunchKernelGGL((k_execute_c8<R>), dim3(b->n_problems), dim3(WAVE), sizeof(R) * 2 * b->t_max, s, e);
+  return check_launch(ctx, "k_execute_c8");
+}
+
+extern "C" smppi_status smppi_execute_curvilinear(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                                                  const smppi_wheels* wheels, const smppi_curv_track* track,
+                                                  const void* V_exec, const void* V_plus, const void* dist,
+                                                  int32_t n_dist, void* x, void* V, uint32_t* iter, void* stream) {
+  if (!ctx) return SMPPI_ERR_INVALID_ARGUMENT;
+  smppi_status st;
+  if ((st = validate_batch(ctx, batch)) || (st = validate_model(ctx, model)) ||
+      (st = validate_curv(ctx, wheels, track)))
+    return st;
+  if (!V_exec || !V_plus || !x || !V || !iter)
+    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "V_exec, V_plus, x, V, iter are required");
+  if (dist && n_dist < 0) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "n_dist must be >= 0");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  smppi_cost dummy{};
+  dummy.sigma[0] = dummy.sigma[1] = 1.0;
+  if (batch->dtype == SMPPI_F32)
+    return execute_c8_t<float>(ctx, batch,
+                               c8_args<float>(ctx, batch, model, wheels, &dummy, nullptr, track, x, V_plus, nullptr),
+                               V_exec, V_plus, dist, n_dist, x, V, iter, s);
+  return execute_c8_t<double>(ctx, batch,
+                              c8_args<double>(ctx, batch, model, wheels, &dummy, nullptr, track, x, V_plus, nullptr),
+                              V_exec, V_plus, dist, n_dist, x, V, iter, s);
 }
 
 // ------------------------------------------------------------------ weights

@@ -67,11 +67,11 @@ def test_struct_layouts_match_c(tmp_path):
     structs = {"smppi_model": L.Model, "smppi_cost": L.Cost, "smppi_noise": L.Noise, "smppi_batch": L.Batch,
                "smppi_track": L.Track, "smppi_objective": L.Objective, "smppi_repair_opts": L.RepairOpts,
                "smppi_plan_opts": L.PlanOpts, "smppi_plan_buffers": L.PlanBuffers,
-               "smppi_curv_track": L.CurvTrack}
+               "smppi_curv_track": L.CurvTrack, "smppi_wheels": L.Wheels}
     fields = {"smppi_batch": ["k_off", "t_off", "dtype"], "smppi_track": ["window", "obs_max", "obs"],
               "smppi_cost": ["gamma", "sigma"], "smppi_plan_opts": ["repair_opts", "dist", "use_graph", "n_dist", "pipeline", "fuse_shield"],
               "smppi_repair_opts": ["step", "objective", "method", "memory"], "smppi_model": ["u_hi"],
-              "smppi_curv_track": ["ds", "half_width", "n_max"]}
+              "smppi_curv_track": ["ds", "half_width", "n_max"], "smppi_wheels": ["I_w", "C_x"]}
     src = ["#include <stdio.h>", "#include <stddef.h>", '#include "smppi.h"', "int main(void){"]
     for cname in structs:
         src.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
