@@ -286,7 +286,9 @@ smppi_status smppi_update(smppi_ctx ctx, const smppi_batch* batch, const smppi_m
 
 /* Adjoint rollout: grad_V = sum_m grad_S[m] dL_m/dV for the objective above,
  * where sample m's trajectory uses the same noise as smppi_rollout.  States are
- * recomputed from per-sample checkpoints instead of being stored.  grad_V has the
+ * recomputed from per-sample checkpoints (every ceil(sqrt(t_max)) steps, in the
+ * ctx scratch) instead of being stored.  Every 64 samples write a partial; a second small kernel adds them in a fixed order
+ * (the result does not depend on scheduling).  grad_V has the
  * layout of V (dtype).  Gradients pass through the clip where it is inactive and
  * through the hinge where it is active (one-sided at ties). */
 smppi_status smppi_rollout_backward(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
@@ -301,8 +303,11 @@ smppi_status smppi_rollout_backward(smppi_ctx ctx, const smppi_batch* batch, con
  * counters and per-workgroup partials live in a fixed scratch array that each
  * GPU holds for the life of the process (looked up at smppi_create), so no
  * smppi_reserve_batch is needed and nothing is allocated.  Limits: at most 4096
- * problems and dtype bytes x B x ceil(k_max / 64) x 2 x t_max <= 8 MiB of
- * partials, else SMPPI_ERR_SHAPE before anything is enqueued.  Every call on a
+ * ticket counters (B x ceil(2 t_max / 64)) and at most 64 MiB of partials,
+ * slice sums and per-lane checkpoints (about dtype bytes x B x n x (2 t_max +
+ * 9 t_max / ceil(sqrt(t_max))) + 4 B, n = ceil(k_max / 64); K = 65536 at
+ * T = 100 needs about 19 MB), else SMPPI_ERR_SHAPE before anything is
+ * enqueued.  Every call on a
  * GPU shares that GPU's array (the counters are cleared by a kernel at the
  * start of each call): calls that overlap on one GPU, from any ctx or thread,
  * race and must be ordered by the caller. */

@@ -41,6 +41,16 @@ smppi_status fail(smppi_ctx ctx, smppi_status s, const char* fmt, ...);
 smppi_status hip_fail(smppi_ctx ctx, hipError_t e, const char* what);
 smppi_status ensure_scratch(smppi_ctx ctx, size_t bytes);
 smppi_status ensure_tickets(smppi_ctx ctx, int n);
+struct AdjScratch {
+  size_t r;            // dtype bytes
+  int nblk;            // adjoint workgroups per problem (ceil(k_max / 64))
+  int n_slices;        // slices of the partial sum (ceil(nblk / SUM_SLICE))
+  int n_chunks;        // 64-output chunks of a control sequence (ceil(2 t_max / 64))
+  size_t part_bytes, slice_bytes, tickets;  // slice_bytes includes the [B] validity flags at its end
+  size_t ck_off, ck_bytes;                   // checkpoint region: offset in the scratch, size
+  int n_problems;
+};
+AdjScratch adjoint_scratch(const smppi_batch* b);
 size_t batch_scratch_bytes(const smppi_batch* b);
 smppi_status need_scratch(smppi_ctx ctx, size_t bytes, int tickets, const char* what);
 smppi_status check_launch(smppi_ctx ctx, const char* what);

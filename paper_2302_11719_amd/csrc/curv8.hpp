@@ -418,8 +418,9 @@ __global__ __launch_bounds__(256) void k_rollout_c8(C8Args<R> a, R* S, R* eps_ou
 }
 
 // Reverse sweep of one lane's trajectory with checkpoints every seg_len steps
-// (ck [n_ck][8][64]) and one recomputed segment (sx [seg_len+1][8][64]) in
-// LDS; sink(t, dL/dv_t0, dL/dv_t1) for t descending.
+// (ck [n_ck][8][64], global scratch of the workgroup) and one recomputed
+// segment (sx [seg_len+1][8][64], LDS); sink(t, dL/dv_t0, dL/dv_t1) for t
+// descending.
 template <class R, class Sink>
 __device__ void adjoint_lane_c8(const DevModel<R>& M, const DevWheels<R>& Wh, const DevCost<R>& C,
                                 const DevObjective<R>& ob, const CurvView<R>& cv, const C8<R>& x0, const R* V, int T,
@@ -476,9 +477,8 @@ __device__ void adjoint_lane_c8(const DevModel<R>& M, const DevWheels<R>& Wh, co
 }
 
 template <class R>
-__host__ __device__ inline size_t c8_adj_lds_bytes(int t_max, int seg_len) {
-  const int n_ck = (t_max + seg_len - 1) / seg_len;
-  return (size_t)(n_ck + seg_len + 1) * 8 * WAVE * sizeof(R);
+__host__ __device__ inline size_t c8_adj_lds_bytes(int /*t_max*/, int seg_len) {
+  return (size_t)(seg_len + 1) * 8 * WAVE * sizeof(R);
 }
 
 template <class R>
@@ -487,23 +487,24 @@ struct C8BackwardArgs {
   DevObjective<R> ob;
   const R* grad_S;
   R* grad_V;
-  R* part;            // [B][nblk_max][2][t_max]
-  uint32_t* tickets;  // [B], zero on entry; the combining workgroup resets its counter
+  R* part;            // [B][nblk_max][2][t_max]: per-workgroup partials, summed by k_sum_partials
+  uint32_t* valid;    // [B]: 1 when the problem's sizes are valid (written by workgroup 0)
+  unsigned char* ck;  // [B][nblk_max] blocks of adj_ck_bytes_per_wg(t_max, seg_len, 8): checkpoints
   int nblk_max;
   int seg_len;
 };
 
 // grad_V = sum_m grad_S[m] dL_m/dV: one 64-lane workgroup per 64 samples, grid
-// (nblk_max, B); per-workgroup partials combined by the last workgroup of each
-// problem (ticket).
+// (nblk_max, B); each workgroup writes its partial (k_sum_partials adds them).
 template <class R>
 __global__ __launch_bounds__(WAVE) void k_backward_c8(C8BackwardArgs<R> g) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t s_ticket;
   const C8Args<R>& a = g.a;
   const int b = blockIdx.y;
   C8Dims d;
-  if (!c8_dims(a, b, d)) return;
+  const bool ok = c8_dims(a, b, d);
+  if (blockIdx.x == 0 && threadIdx.x == 0) g.valid[b] = ok ? 1u : 0u;
+  if (!ok) return;
   R* gVb = g.grad_V + 2 * (size_t)d.t0;
   if (d.K == 0) {
     if (blockIdx.x == 0)
@@ -514,9 +515,9 @@ __global__ __launch_bounds__(WAVE) void k_backward_c8(C8BackwardArgs<R> g) {
   if ((int)blockIdx.x >= nblk) return;
   R* Vs;
   const CurvView<R> cv = c8_stage(a, b, d, reinterpret_cast<R*>(smem), &Vs);
-  R* ck = reinterpret_cast<R*>(smem + c8_stage_bytes<R>(a.n_max, a.t_max));
-  const int n_ck = (a.t_max + g.seg_len - 1) / g.seg_len;
-  R* sx = ck + (size_t)n_ck * 8 * WAVE;
+  R* sx = reinterpret_cast<R*>(smem + c8_stage_bytes<R>(a.n_max, a.t_max));
+  R* ck = reinterpret_cast<R*>(g.ck + ((size_t)b * g.nblk_max + blockIdx.x) *
+                                          adj_ck_bytes_per_wg<R>(a.t_max, g.seg_len, 8));
   __syncthreads();
   const int lane = threadIdx.x;
   const int m = blockIdx.x * WAVE + lane;
@@ -528,20 +529,6 @@ __global__ __launch_bounds__(WAVE) void k_backward_c8(C8BackwardArgs<R> g) {
   sink.lane = lane;
   adjoint_lane_c8(a.M, a.Wh, a.C, g.ob, cv, load_c8(a.x0 + 8 * (size_t)b), Vs, d.T, ns, ck, sx, g.seg_len, lane,
                   sink);
-  ticket_release();
-  __syncthreads();
-  if (lane == 0) s_ticket = atomicAdd(&g.tickets[b], 1u);
-  __syncthreads();
-  if (s_ticket == (uint32_t)(nblk - 1)) {
-    ticket_acquire();
-    const R* g0 = g.part + (size_t)b * g.nblk_max * 2 * a.t_max;
-    for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) {
-      R acc = R(0);
-      for (int k = 0; k < nblk; ++k) acc += g0[(size_t)k * 2 * a.t_max + i];
-      gVb[i] = acc;
-    }
-    if (lane == 0) g.tickets[b] = 0u;
-  }
 }
 
 template <class R>

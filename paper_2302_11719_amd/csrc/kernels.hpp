@@ -630,15 +630,26 @@ __global__ __launch_bounds__(UPD_BLOCK) void k_update(UpdateArgs<R> a) {
 }
 
 // ============================================================== adjoint
-// Per-lane reverse sweep with checkpoints every `seg_len` steps kept in LDS and
-// the states of one segment recomputed into LDS (layout [slot][component][lane]).
+// Per-lane reverse sweep with checkpoints every `seg_len` steps (global scratch
+// of the workgroup: written once, read once per segment) and the states of one
+// segment recomputed into LDS (layout [slot][component][lane]).  Keeping only
+// the segment in LDS leaves room for enough workgroups per CU that the large
+// batches run in one wave of workgroups.
 template <class R>
 struct AdjLds {
-  R* ck;      // [n_ck][6][64]
-  int* cki;   // [n_ck][64]
-  R* sx;      // [seg_len+1][6][64]
-  int* sxi;   // [seg_len+1][64]
+  R* ck;      // global [n_ck][6][64]
+  int* cki;   // global [n_ck][64]
+  R* sx;      // LDS [seg_len+1][6][64]
+  int* sxi;   // LDS [seg_len+1][64]
 };
+
+// Global checkpoint storage of the adjoint: per (problem, workgroup) n_ck slots
+// of `comp` values and one index per lane.
+template <class R>
+__host__ __device__ inline size_t adj_ck_bytes_per_wg(int t_max, int seg_len, int comp) {
+  const int n_ck = (t_max + seg_len - 1) / seg_len;
+  return (size_t)n_ck * WAVE * (comp * sizeof(R) + sizeof(int));
+}
 
 template <class R>
 __device__ __forceinline__ void adj_store(R* base, int* ibase, int slot, int lane, const State<R>& x, int idx) {
@@ -666,9 +677,8 @@ __device__ __forceinline__ State<R> adj_load(const R* base, const int* ibase, in
 }
 
 template <class R>
-__host__ __device__ inline size_t adj_lds_bytes(int t_max, int seg_len) {
-  const int n_ck = (t_max + seg_len - 1) / seg_len;
-  return (size_t)(n_ck + seg_len + 1) * WAVE * (6 * sizeof(R) + sizeof(int));
+__host__ __device__ inline size_t adj_lds_bytes(int /*t_max*/, int seg_len) {
+  return (size_t)(seg_len + 1) * WAVE * (6 * sizeof(R) + sizeof(int));
 }
 
 // Reverse sweep of one lane's trajectory.  `V` is [2][T] in LDS.  For every t
@@ -750,8 +760,9 @@ struct BackwardArgs {
   const R* V;
   const R* grad_S;
   R* grad_V;
-  R* part;            // [B][nblk_max][2][t_max]
-  uint32_t* tickets;  // [B]
+  R* part;            // [B][nblk_max][2][t_max]: per-workgroup partials, summed by k_sum_partials
+  uint32_t* valid;    // [B]: 1 when the problem's sizes are valid (written by workgroup 0)
+  unsigned char* ck;  // [B][nblk_max] blocks of adj_ck_bytes_per_wg(t_max, seg_len, 6): checkpoints
   int nblk_max;
   int seg_len;
 };
@@ -777,10 +788,11 @@ struct ReduceSink {
 template <class R, int NOBS>
 __global__ __launch_bounds__(WAVE) void k_backward(BackwardArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t s_ticket;
   const int b = blockIdx.y;
   ProblemDims d;
-  if (!load_dims(a.p, b, d)) return;
+  const bool ok = load_dims(a.p, b, d);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.valid[b] = ok ? 1u : 0u;
+  if (!ok) return;
   R* gVb = a.grad_V + 2 * (size_t)d.t0;
   if (d.K == 0) {
     if (blockIdx.x == 0)
@@ -794,10 +806,11 @@ __global__ __launch_bounds__(WAVE) void k_backward(BackwardArgs<R> a) {
   unsigned char* rest = smem + stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max);
   const int n_ck = (a.p.t_max + a.seg_len - 1) / a.seg_len;
   AdjLds<R> L;
-  L.ck = reinterpret_cast<R*>(rest);
-  L.sx = L.ck + (size_t)n_ck * 6 * WAVE;
-  L.cki = reinterpret_cast<int*>(L.sx + (size_t)(a.seg_len + 1) * 6 * WAVE);
-  L.sxi = L.cki + n_ck * WAVE;
+  L.sx = reinterpret_cast<R*>(rest);
+  L.sxi = reinterpret_cast<int*>(L.sx + (size_t)(a.seg_len + 1) * 6 * WAVE);
+  unsigned char* ckb = a.ck + ((size_t)b * a.nblk_max + blockIdx.x) * adj_ck_bytes_per_wg<R>(a.p.t_max, a.seg_len, 6);
+  L.ck = reinterpret_cast<R*>(ckb);
+  L.cki = reinterpret_cast<int*>(L.ck + (size_t)n_ck * 6 * WAVE);
   __syncthreads();
   const int lane = threadIdx.x;
   const int m = blockIdx.x * WAVE + lane;
@@ -814,20 +827,70 @@ __global__ __launch_bounds__(WAVE) void k_backward(BackwardArgs<R> a) {
   sink.lane = lane;
   const State<R> x0 = load_state(a.p.x0 + 6 * (size_t)b);
   adjoint_lane<R, NOBS>(a.M, a.C, a.ob, tr, x0, Vs, d.T, ns, L, a.seg_len, lane, sink);
+}
+
+// Sum of the adjoint's per-workgroup partials: out[2 t0_b + i] = sum over the
+// problem's nblk_b = ceil(K_b / 64) rows of part[b][k][i], i < 2 T_b, in a fixed
+// order (each slice of SUM_SLICE consecutive rows in row order, then the slices
+// in order), so the result does not depend on scheduling.  Grid (n_chunks, B,
+// n_slices) of 64 threads, chunk = 64 consecutive outputs: every workgroup sums
+// one slice of one chunk; with more than one slice the last workgroup of a
+// (problem, chunk) to finish (ticket, zero on entry and reset on exit) adds the
+// slice sums.  Problems with K_b = 0 (the adjoint wrote zeros) or invalid sizes
+// (flagged by the adjoint) are skipped.
+constexpr int SUM_SLICE = 32;
+
+template <class R>
+struct SumArgs {
+  const int64_t* k_off;
+  const int32_t* t_off;
+  int t_max, nblk_max, n_slices_max, n_chunks;
+  const R* part;      // [B][nblk_max][2][t_max]
+  const uint32_t* valid;  // [B]: the adjoint processed the problem
+  R* slice;           // [B][n_slices_max][2][t_max]
+  uint32_t* tickets;  // [B][n_chunks]
+  R* out;             // [sum 2T]
+};
+
+template <class R>
+__global__ __launch_bounds__(WAVE) void k_sum_partials(SumArgs<R> a) {
+  __shared__ uint32_t s_ticket;
+  const int b = blockIdx.y, chunk = blockIdx.x, sl = blockIdx.z;
+  const int64_t K = a.k_off[b + 1] - a.k_off[b];
+  const int t0 = a.t_off[b], T = a.t_off[b + 1] - t0;
+  if (!a.valid[b] || K <= 0 || T < 1 || T > a.t_max || (K + WAVE - 1) / WAVE > a.nblk_max) return;
+  const int nblk = (int)((K + WAVE - 1) / WAVE);
+  const int ns = (nblk + SUM_SLICE - 1) / SUM_SLICE;
+  if (sl >= ns || chunk * WAVE >= 2 * T) return;
+  const int i = chunk * WAVE + threadIdx.x;
+  const bool valid = i < 2 * T;
+  const int k0 = sl * SUM_SLICE, k1 = min(nblk, k0 + SUM_SLICE);
+  const size_t row = 2 * (size_t)a.t_max;
+  R acc = R(0);
+  if (valid) {
+    const R* p = a.part + ((size_t)b * a.nblk_max + k0) * row + i;
+#pragma unroll 8
+    for (int k = 0; k < k1 - k0; ++k) acc += p[(size_t)k * row];
+  }
+  if (ns == 1) {
+    if (valid) a.out[2 * (size_t)t0 + i] = acc;
+    return;
+  }
+  if (valid) a.slice[((size_t)b * a.n_slices_max + sl) * row + i] = acc;
   ticket_release();
   __syncthreads();
-  if (lane == 0) s_ticket = atomicAdd(&a.tickets[b], 1u);
+  uint32_t* tk = a.tickets + (size_t)b * a.n_chunks + chunk;
+  if (threadIdx.x == 0) s_ticket = atomicAdd(tk, 1u);
   __syncthreads();
-  if (s_ticket == (uint32_t)(nblk - 1)) {
+  if (s_ticket == (uint32_t)(ns - 1)) {
     ticket_acquire();
-    const R* g0 = a.part + (size_t)b * a.nblk_max * 2 * a.p.t_max;
-    for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) {
-      R acc = R(0);
-#pragma unroll 8
-      for (int k = 0; k < nblk; ++k) acc += g0[(size_t)k * 2 * a.p.t_max + i];
-      gVb[i] = acc;
+    if (valid) {
+      const R* q = a.slice + (size_t)b * a.n_slices_max * row + i;
+      R tot = R(0);
+      for (int k = 0; k < ns; ++k) tot += q[(size_t)k * row];
+      a.out[2 * (size_t)t0 + i] = tot;
     }
-    if (lane == 0) a.tickets[b] = 0u;
+    if (threadIdx.x == 0) *tk = 0u;
   }
 }
 

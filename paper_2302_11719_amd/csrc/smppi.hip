@@ -60,14 +60,39 @@ smppi_status smppi::ensure_tickets(smppi_ctx ctx, int n) {
   return SMPPI_OK;
 }
 
+// The adjoint's scratch for a batch: per-workgroup partials [B][nblk][2][t_max],
+// slice sums [B][ceil(nblk / SUM_SLICE)][2][t_max] (dtype) and ticket counters
+// [B][ceil(2 t_max / 64)] for the sum kernel.
+AdjScratch smppi::adjoint_scratch(const smppi_batch* b) {
+  AdjScratch a;
+  a.r = b->dtype == SMPPI_F32 ? sizeof(float) : sizeof(double);
+  a.nblk = std::max(1, (std::max(0, b->k_max) + WAVE - 1) / WAVE);
+  a.n_slices = (a.nblk + SUM_SLICE - 1) / SUM_SLICE;
+  a.n_chunks = (2 * b->t_max + WAVE - 1) / WAVE;
+  const size_t row = a.r * 2 * (size_t)b->t_max;
+  a.part_bytes = row * b->n_problems * a.nblk;
+  // slice sums, then the per-problem validity flags (16-byte aligned)
+  a.slice_bytes = ((row * b->n_problems * a.n_slices + 15) & ~(size_t)15) + sizeof(uint32_t) * b->n_problems;
+  // checkpoints (8 state components covers both models), 256-byte aligned
+  const int seg = adj_seg_len(b->t_max);
+  a.ck_off = (a.part_bytes + a.slice_bytes + 255) & ~(size_t)255;
+  a.ck_bytes = (size_t)b->n_problems * a.nblk * (a.r == sizeof(float) ? adj_ck_bytes_per_wg<float>(b->t_max, seg, 8)
+                                                                      : adj_ck_bytes_per_wg<double>(b->t_max, seg, 8));
+  a.tickets = (size_t)b->n_problems * a.n_chunks;
+  a.n_problems = b->n_problems;
+  return a;
+}
+
 // Scratch of the plain calls for a batch within these host bounds: the
-// update's and the adjoint's per-workgroup partials [B][workgroups][2][t_max]
-// and, for FP32 rollouts with obstacles, the padded obstacle slots [B][64].
+// update's per-workgroup partials [B][workgroups][2][t_max], the adjoint's
+// (adjoint_scratch) and, for FP32 rollouts with obstacles, the padded obstacle
+// slots [B][64].
 size_t smppi::batch_scratch_bytes(const smppi_batch* b) {
   const size_t r = b->dtype == SMPPI_F32 ? sizeof(float) : sizeof(double);
   const size_t B = (size_t)b->n_problems, k = (size_t)std::max(0, b->k_max), t = (size_t)b->t_max;
   const size_t upd = r * B * std::max<size_t>(1, (k + UPD_BLOCK - 1) / UPD_BLOCK) * 2 * t;
-  const size_t bwd = r * B * std::max<size_t>(1, (k + WAVE - 1) / WAVE) * 2 * t;
+  const AdjScratch adj = adjoint_scratch(b);
+  const size_t bwd = adj.ck_off + adj.ck_bytes;
   const size_t pad = b->dtype == SMPPI_F32 ? sizeof(float4) * B * kMaxObs : 0;
   return std::max(upd, std::max(bwd, pad));
 }
@@ -298,7 +323,7 @@ extern "C" smppi_status smppi_reserve_batch(smppi_ctx ctx, const smppi_batch* ba
   if ((st = validate_batch(ctx, batch))) return st;
   (void)hipSetDevice(ctx->device);
   if ((st = ensure_scratch(ctx, batch_scratch_bytes(batch)))) return st;
-  return ensure_tickets(ctx, batch->n_problems);
+  return ensure_tickets(ctx, (int)std::max<size_t>(batch->n_problems, adjoint_scratch(batch).tickets));
 }
 
 extern "C" smppi_status smppi_device_errors(smppi_ctx ctx, uint32_t* flags) {
@@ -369,6 +394,33 @@ extern "C" smppi_status smppi_rollout(smppi_ctx ctx, const smppi_batch* batch, c
   if (batch->dtype == SMPPI_F32)
     return rollout_t<float>(ctx, batch, model, cost, noise, track, x0, V, iter, S, eps_out, s);
   return rollout_t<double>(ctx, batch, model, cost, noise, track, x0, V, iter, S, eps_out, s);
+}
+
+// The per-problem validity flags at the end of the adjoint scratch.
+static uint32_t* adjoint_valid(const AdjScratch& as, void* scratch) {
+  return reinterpret_cast<uint32_t*>(static_cast<unsigned char*>(scratch) + as.part_bytes + as.slice_bytes) -
+         as.n_problems;
+}
+
+// The sum of the adjoint's per-workgroup partials into grad_V (k_sum_partials):
+// part and slice sums in `scratch` (adjoint_scratch layout), counters zero on entry.
+template <class R>
+static smppi_status launch_sum_partials(smppi_ctx ctx, const smppi_batch* b, const AdjScratch& as, void* scratch,
+                                        uint32_t* tickets, void* gV, hipStream_t s) {
+  SumArgs<R> sa;
+  sa.k_off = b->k_off;
+  sa.t_off = b->t_off;
+  sa.t_max = b->t_max;
+  sa.nblk_max = as.nblk;
+  sa.n_slices_max = as.n_slices;
+  sa.n_chunks = as.n_chunks;
+  sa.part = static_cast<const R*>(scratch);
+  sa.slice = reinterpret_cast<R*>(static_cast<unsigned char*>(scratch) + as.part_bytes);
+  sa.valid = adjoint_valid(as, scratch);
+  sa.tickets = tickets;
+  sa.out = static_cast<R*>(gV);
+  hipLaunchKernelGGL((k_sum_partials<R>), dim3(as.n_chunks, b->n_problems, as.n_slices), dim3(WAVE), 0, s, sa);
+  return check_launch(ctx, "k_sum_partials");
 }
 
 // ------------------------------------------------------------------ curvilinear model
@@ -459,20 +511,22 @@ static smppi_status backward_c8_t(smppi_ctx ctx, const smppi_batch* b, const C8A
   g.ob = dev_objective<R>(ob);
   g.grad_S = static_cast<const R*>(gS);
   g.grad_V = static_cast<R*>(gV);
-  g.nblk_max = std::max(1, (b->k_max + WAVE - 1) / WAVE);
+  const AdjScratch as = adjoint_scratch(b);
+  g.nblk_max = as.nblk;
   g.seg_len = adj_seg_len(b->t_max);
   smppi_status st;
-  if ((st = need_scratch(ctx, sizeof(R) * (size_t)b->n_problems * g.nblk_max * 2 * b->t_max, b->n_problems,
-                         "smppi_rollout_backward_curvilinear")))
+  if ((st = need_scratch(ctx, as.ck_off + as.ck_bytes, (int)as.tickets, "smppi_rollout_backward_curvilinear")))
     return st;
   g.part = static_cast<R*>(ctx->scratch);
-  g.tickets = ctx->tickets;
+  g.valid = adjoint_valid(as, ctx->scratch);
+  g.ck = static_cast<unsigned char*>(ctx->scratch) + as.ck_off;
   const size_t lds = c8_stage_bytes<R>(a.n_max, a.t_max) + c8_adj_lds_bytes<R>(a.t_max, g.seg_len);
   if (lds > (size_t)ctx->max_lds)
     return fail(ctx, SMPPI_ERR_SHAPE, "curvilinear adjoint needs %zu B of LDS per workgroup (device max %d)", lds,
                 ctx->max_lds);
   hipLaunchKernelGGL((k_backward_c8<R>), dim3(g.nblk_max, b->n_problems), dim3(WAVE), lds, s, g);
-  return check_launch(ctx, "k_backward_c8");
+  if ((st = check_launch(ctx, "k_backward_c8"))) return st;
+  return launch_sum_partials<R>(ctx, b, as, ctx->scratch, ctx->tickets, gV, s);
 }
 
 extern "C" smppi_status smppi_rollout_backward_curvilinear(
@@ -651,17 +705,14 @@ static smppi_status launch_backward(smppi_ctx ctx, const smppi_batch* b, const B
   return check_launch(ctx, "k_backward");
 }
 
-// Workgroups per problem of the adjoint kernel (one sample per lane).
-static int backward_nblk(const smppi_batch* b) { return std::max(1, (b->k_max + WAVE - 1) / WAVE); }
-
-// The adjoint launch with its scratch given: part = per-workgroup partials
-// [B][nblk][2][t_max] dtype, tickets = B counters that are zero on entry (the
-// combining workgroup of each problem resets its counter).
+// The adjoint launch with its scratch given (adjoint_scratch layout: partials
+// then slice sums; counters zero on entry, reset by the sum kernel).
 template <class R>
 static smppi_status backward_launch(smppi_ctx ctx, const smppi_batch* b, const smppi_model* m, const smppi_cost* c,
                                     const smppi_noise* n, const smppi_track* t, const void* x0, const void* V,
                                     const uint32_t* iter, const void* gS, const smppi_objective* ob, void* gV,
-                                    R* part, uint32_t* tickets, hipStream_t s) {
+                                    void* scratch, uint32_t* tickets, hipStream_t s) {
+  const AdjScratch as = adjoint_scratch(b);
   BackwardArgs<R> a;
   a.p = problem_args<R>(ctx, b, t, n, x0, iter);
   a.M = dev_model<R>(m);
@@ -670,12 +721,14 @@ static smppi_status backward_launch(smppi_ctx ctx, const smppi_batch* b, const s
   a.V = static_cast<const R*>(V);
   a.grad_S = static_cast<const R*>(gS);
   a.grad_V = static_cast<R*>(gV);
-  a.nblk_max = backward_nblk(b);
+  a.nblk_max = as.nblk;
   a.seg_len = adj_seg_len(b->t_max);
-  a.part = part;
-  a.tickets = tickets;
-  if (t->obs_max > 0) return launch_backward<R, kMaxObs>(ctx, b, a, s);
-  return launch_backward<R, 0>(ctx, b, a, s);
+  a.part = static_cast<R*>(scratch);
+  a.valid = adjoint_valid(as, scratch);
+  a.ck = static_cast<unsigned char*>(scratch) + as.ck_off;
+  smppi_status st = t->obs_max > 0 ? launch_backward<R, kMaxObs>(ctx, b, a, s) : launch_backward<R, 0>(ctx, b, a, s);
+  if (st) return st;
+  return launch_sum_partials<R>(ctx, b, as, scratch, tickets, gV, s);
 }
 
 template <class R>
@@ -684,11 +737,10 @@ static smppi_status backward_t(smppi_ctx ctx, const smppi_batch* b, const smppi_
                                const uint32_t* iter, const void* gS, const smppi_objective* ob, void* gV,
                                hipStream_t s) {
   smppi_status st;
-  if ((st = need_scratch(ctx, sizeof(R) * (size_t)b->n_problems * backward_nblk(b) * 2 * b->t_max, b->n_problems,
-                         "smppi_rollout_backward")))
+  const AdjScratch as = adjoint_scratch(b);
+  if ((st = need_scratch(ctx, as.ck_off + as.ck_bytes, (int)as.tickets, "smppi_rollout_backward")))
     return st;
-  return backward_launch<R>(ctx, b, m, c, n, t, x0, V, iter, gS, ob, gV, static_cast<R*>(ctx->scratch),
-                            ctx->tickets, s);
+  return backward_launch<R>(ctx, b, m, c, n, t, x0, V, iter, gS, ob, gV, ctx->scratch, ctx->tickets, s);
 }
 
 smppi_status smppi::validate_objective(smppi_ctx ctx, const smppi_objective* o) {
@@ -738,7 +790,7 @@ extern "C" smppi_status smppi_rollout_backward(smppi_ctx ctx, const smppi_batch*
 // copy: calls that overlap on one GPU race.
 namespace {
 constexpr size_t kNoAllocTicketBytes = 16384;  // 4096 problems
-constexpr size_t kNoAllocBytes = (8u << 20) + kNoAllocTicketBytes;
+constexpr size_t kNoAllocBytes = (64u << 20) + kNoAllocTicketBytes;
 constexpr int kMaxDevices = 64;
 std::mutex g_noalloc_mu;
 void* g_noalloc_ptr[kMaxDevices] = {};
@@ -780,28 +832,28 @@ extern "C" smppi_status smppi_rollout_backward_noalloc(smppi_ctx ctx, const smpp
   if ((st = validate_backward(ctx, batch, model, cost, noise, track, x0, V, iter, grad_S, objective, grad_V)))
     return st;
   if (!ctx->noalloc) return fail(ctx, SMPPI_ERR_UNSUPPORTED, "no fixed scratch on device %d", ctx->device);
-  const size_t rb = batch->dtype == SMPPI_F32 ? sizeof(float) : sizeof(double);
-  const size_t part = rb * (size_t)batch->n_problems * backward_nblk(batch) * 2 * batch->t_max;
-  if ((size_t)batch->n_problems * sizeof(uint32_t) > kNoAllocTicketBytes ||
-      part > kNoAllocBytes - kNoAllocTicketBytes)
+  const AdjScratch as = adjoint_scratch(batch);
+  const size_t part = as.ck_off + as.ck_bytes;
+  if (as.tickets * sizeof(uint32_t) > kNoAllocTicketBytes || part > kNoAllocBytes - kNoAllocTicketBytes)
     return fail(ctx, SMPPI_ERR_SHAPE,
-                "smppi_rollout_backward_noalloc: the batch needs %d ticket counters (max %zu) and %zu B of "
-                "partials (dtype bytes x B x ceil(k_max/64) x 2 x t_max; max %zu)",
-                batch->n_problems, kNoAllocTicketBytes / sizeof(uint32_t), part, kNoAllocBytes - kNoAllocTicketBytes);
+                "smppi_rollout_backward_noalloc: the batch needs %zu ticket counters (B x ceil(2 t_max / 64); "
+                "max %zu) and %zu B of partials, slice sums and checkpoints (about dtype bytes x B x n x "
+                "(2 t_max + 9 t_max / seg) + 4 B, n = ceil(k_max / 64), seg = ceil(sqrt(t_max)); max %zu)",
+                as.tickets, kNoAllocTicketBytes / sizeof(uint32_t), part, kNoAllocBytes - kNoAllocTicketBytes);
   (void)hipSetDevice(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   unsigned char* base = static_cast<unsigned char*>(ctx->noalloc);
   uint32_t* tickets = reinterpret_cast<uint32_t*>(base);
   // the counters must start at zero: cleared by a kernel (capturable; no memset node)
-  hipLaunchKernelGGL(k_zero_u32, dim3((batch->n_problems + 255) / 256), dim3(256), 0, s, tickets,
-                     batch->n_problems);
+  const int nt = (int)as.tickets;
+  hipLaunchKernelGGL(k_zero_u32, dim3((nt + 255) / 256), dim3(256), 0, s, tickets, nt);
   if ((st = check_launch(ctx, "k_zero_u32"))) return st;
   void* pp = base + kNoAllocTicketBytes;
   if (batch->dtype == SMPPI_F32)
-    return backward_launch<float>(ctx, batch, model, cost, noise, track, x0, V, iter, grad_S, objective, grad_V,
-                                  static_cast<float*>(pp), tickets, s);
-  return backward_launch<double>(ctx, batch, model, cost, noise, track, x0, V, iter, grad_S, objective, grad_V,
-                                 static_cast<double*>(pp), tickets, s);
+    return backward_launch<float>(ctx, batch, model, cost, noise, track, x0, V, iter, grad_S, objective, grad_V, pp,
+                                  tickets, s);
+  return backward_launch<double>(ctx, batch, model, cost, noise, track, x0, V, iter, grad_S, objective, grad_V, pp,
+                                 tickets, s);
 }
 
 // ------------------------------------------------------------------ repair
