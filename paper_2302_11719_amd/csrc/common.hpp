@@ -48,6 +48,7 @@ struct AdjScratch {
   int n_chunks;        // 64-output chunks of a control sequence (ceil(2 t_max / 64))
   size_t part_bytes, slice_bytes, tickets;  // slice_bytes includes the [B] validity flags at its end
   size_t ck_off, ck_bytes;                   // checkpoint region: offset in the scratch, size
+  size_t pad_off, pad_bytes;                 // FP32 obstacle slots: offset, size
   int n_problems;
 };
 AdjScratch adjoint_scratch(const smppi_batch* b);

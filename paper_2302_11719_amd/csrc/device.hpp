@@ -559,6 +559,56 @@ struct ScalarObstacles {
     run<NOBS, false>(px, py, alpha, c, pen, mo);
     outside = outside || (mo < 0.f);
   }
+  // Adjoint of the obstacle transitions from p (= x_t) to q (= x_{t+1}), the
+  // slots read as in run(): with g(p) = |p - c|^2 - r^2, the DCBF residual is
+  // r_i = alpha g_i(p) + kappa_i - g_i(q) = alpha h_i(x_t) - h_i(x_{t+1}); where
+  // r_i > 0 its cotangent is base + w_sq2 r_i (base = w_S C + w_lin [t < n_lin],
+  // w_sq2 = 2 w_sq), and dr/dq = -2 (q - c), dr/dp = 2 alpha (p - c).  Adds the
+  // q part to (lqx, lqy) and the p part to (lpx, lpy).
+  template <int NOBS>
+  __device__ __forceinline__ void grad(float ppx, float ppy, float qpx, float qpy, float alpha, float base,
+                                       float w_sq2, float& lqx, float& lqy, float& lpx, float& lpy) const {
+    static_assert(NOBS % OBS_GROUP == 0, "obstacle slots come in groups");
+    constexpr int NG = NOBS / OBS_GROUP;
+    const uint64_t b64 = (uint64_t)(uintptr_t)slots;
+    const uint64_t ubase = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(b64 >> 32)) << 32) |
+                           (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b64);
+    ConstF op = (ConstF)(uintptr_t)ubase;
+    asm volatile("" : "+s"(op) : "v"(ppx), "v"(qpx));
+    float av = alpha;
+    asm volatile("" : "+v"(av));
+    float4 cur[OBS_GROUP], nxt[OBS_GROUP];
+#pragma unroll
+    for (int j = 0; j < OBS_GROUP; ++j) cur[j] = make_float4(op[4 * j], op[4 * j + 1], op[4 * j + 2], op[4 * j + 3]);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      if (g + 1 < NG) {
+        op += 4 * OBS_GROUP;
+        asm volatile("" : "+s"(op) : "v"(lqx), "v"(lpx));
+#pragma unroll
+        for (int j = 0; j < OBS_GROUP; ++j)
+          nxt[j] = make_float4(op[4 * j], op[4 * j + 1], op[4 * j + 2], op[4 * j + 3]);
+      }
+#pragma unroll
+      for (int j = 0; j < OBS_GROUP; ++j) {
+        const float4 o = cur[j];
+        const float ax = ppx - o.x, ay = ppy - o.y, bx = qpx - o.x, by = qpy - o.y;
+        const float gp = fmaf(ax, ax, fmaf(ay, ay, -o.z));
+        const float gq = fmaf(bx, bx, fmaf(by, by, -o.z));
+        const float r = fmaf(av, gp, o.w) - gq;
+        const float k2 = r > 0.f ? 2.f * fmaf(w_sq2, r, base) : 0.f;
+        lqx = fmaf(-k2, bx, lqx);
+        lqy = fmaf(-k2, by, lqy);
+        const float k2a = k2 * av;
+        lpx = fmaf(k2a, ax, lpx);
+        lpy = fmaf(k2a, ay, lpy);
+      }
+      if (g + 1 < NG) {
+#pragma unroll
+        for (int j = 0; j < OBS_GROUP; ++j) cur[j] = nxt[j];
+      }
+    }
+  }
 };
 
 // ---------------------------------------------------------------- one sample

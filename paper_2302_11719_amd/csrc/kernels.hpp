@@ -684,10 +684,12 @@ __host__ __device__ inline size_t adj_lds_bytes(int /*t_max*/, int seg_len) {
 // Reverse sweep of one lane's trajectory.  `V` is [2][T] in LDS.  For every t
 // (descending) calls sink(t, dL/dv_{t,0}, dL/dv_{t,1}); the sink may modify V[t]
 // (the repair does), which is safe because V[t'] for t' >= t is never read again.
+// FP32 with obstacles: `slots` (k_pad_obs) gives the obstacle transitions
+// through the scalar cache (ScalarObstacles::grad) instead of the LDS table.
 template <class R, int NOBS, class Sink>
 __device__ void adjoint_lane(const DevModel<R>& M, const DevCost<R>& C, const DevObjective<R>& ob,
                              const TrackView<R>& tr, const State<R>& x0, R* V, int T, NoiseStream<R>& ns,
-                             const AdjLds<R>& L, int seg_len, int lane, Sink& sink) {
+                             const AdjLds<R>& L, int seg_len, int lane, Sink& sink, const float4* slots = nullptr) {
   // forward with checkpoints
   State<R> x = x0;
   int idx = tr.idx0;
@@ -725,7 +727,15 @@ __device__ void adjoint_lane(const DevModel<R>& M, const DevCost<R>& C, const De
       const State<R> xp = adj_load(L.sx, L.sxi, t - t0, lane, ip);
       const State<R> xn = adj_load(L.sx, L.sxi, t - t0 + 1, lane, in_);
       R gpx = R(0), gpy = R(0);
-      penalty_grad<R, NOBS>(C, ob, tr, xp, ip, xn, in_, t, lam, gpx, gpy);
+      if constexpr (NOBS > 0 && sizeof(R) == sizeof(float)) {
+        // track barrier as usual, obstacles from the scalar slots
+        penalty_grad<R, 0>(C, ob, tr, xp, ip, xn, in_, t, lam, gpx, gpy);
+        const R base = ob.w_S * C.C_cbf + ((t < ob.n_lin) ? ob.w_lin : R(0));
+        ScalarObstacles{slots}.template grad<NOBS>(xp.px, xp.py, xn.px, xn.py, C.alpha, base, R(2) * ob.w_sq,
+                                                   lam[0], lam[1], gpx, gpy);
+      } else {
+        penalty_grad<R, NOBS>(C, ob, tr, xp, ip, xn, in_, t, lam, gpx, gpy);
+      }
       R e0, e1;
       // descending: the pair (t-1, t) is regenerated at odd t or at the segment's last step
       if ((t & 1) == 1 || t == t1 - 1) ns.gen(t);
@@ -763,6 +773,7 @@ struct BackwardArgs {
   R* part;            // [B][nblk_max][2][t_max]: per-workgroup partials, summed by k_sum_partials
   uint32_t* valid;    // [B]: 1 when the problem's sizes are valid (written by workgroup 0)
   unsigned char* ck;  // [B][nblk_max] blocks of adj_ck_bytes_per_wg(t_max, seg_len, 6): checkpoints
+  const float4* obs_pad;  // FP32 with obstacles: [B][NOBS] slots from k_pad_obs (scalar reads)
   int nblk_max;
   int seg_len;
 };
@@ -826,7 +837,8 @@ __global__ __launch_bounds__(WAVE) void k_backward(BackwardArgs<R> a) {
   sink.T = d.T;
   sink.lane = lane;
   const State<R> x0 = load_state(a.p.x0 + 6 * (size_t)b);
-  adjoint_lane<R, NOBS>(a.M, a.C, a.ob, tr, x0, Vs, d.T, ns, L, a.seg_len, lane, sink);
+  adjoint_lane<R, NOBS>(a.M, a.C, a.ob, tr, x0, Vs, d.T, ns, L, a.seg_len, lane, sink,
+                        a.obs_pad ? a.obs_pad + (size_t)b * NOBS : nullptr);
 }
 
 // Sum of the adjoint's per-workgroup partials: out[2 t0_b + i] = sum over the

@@ -78,6 +78,9 @@ AdjScratch smppi::adjoint_scratch(const smppi_batch* b) {
   a.ck_off = (a.part_bytes + a.slice_bytes + 255) & ~(size_t)255;
   a.ck_bytes = (size_t)b->n_problems * a.nblk * (a.r == sizeof(float) ? adj_ck_bytes_per_wg<float>(b->t_max, seg, 8)
                                                                       : adj_ck_bytes_per_wg<double>(b->t_max, seg, 8));
+  // padded obstacle slots of the FP32 adjoint ([B][64] float4), after the checkpoints
+  a.pad_off = (a.ck_off + a.ck_bytes + 255) & ~(size_t)255;
+  a.pad_bytes = b->dtype == SMPPI_F32 ? sizeof(float4) * (size_t)b->n_problems * kMaxObs : 0;
   a.tickets = (size_t)b->n_problems * a.n_chunks;
   a.n_problems = b->n_problems;
   return a;
@@ -92,7 +95,7 @@ size_t smppi::batch_scratch_bytes(const smppi_batch* b) {
   const size_t B = (size_t)b->n_problems, k = (size_t)std::max(0, b->k_max), t = (size_t)b->t_max;
   const size_t upd = r * B * std::max<size_t>(1, (k + UPD_BLOCK - 1) / UPD_BLOCK) * 2 * t;
   const AdjScratch adj = adjoint_scratch(b);
-  const size_t bwd = adj.ck_off + adj.ck_bytes;
+  const size_t bwd = adj.pad_off + adj.pad_bytes;
   const size_t pad = b->dtype == SMPPI_F32 ? sizeof(float4) * B * kMaxObs : 0;
   return std::max(upd, std::max(bwd, pad));
 }
@@ -251,9 +254,13 @@ ProblemArgs<R> smppi::problem_args(smppi_ctx ctx, const smppi_batch* b, const sm
 template ProblemArgs<float> smppi::problem_args<float>(smppi_ctx, const smppi_batch*, const smppi_track*,
                                                        const smppi_noise*, const void*, const uint32_t*);
 
+// Steps per recomputed segment of the adjoint: ceil(sqrt(t_max)) (fewest
+// checkpoint plus segment slots), at most 12 so that the segment held in LDS
+// (13 slots) leaves room for four workgroups per CU beside a 512-segment track;
+// longer horizons only keep more checkpoints in the global scratch.
 int smppi::adj_seg_len(int t_max) {
   int s = (int)std::ceil(std::sqrt((double)t_max));
-  return s < 1 ? 1 : s;
+  return s < 1 ? 1 : (s > 12 ? 12 : s);
 }
 
 // ------------------------------------------------------------------ context
@@ -726,7 +733,17 @@ static smppi_status backward_launch(smppi_ctx ctx, const smppi_batch* b, const s
   a.part = static_cast<R*>(scratch);
   a.valid = adjoint_valid(as, scratch);
   a.ck = static_cast<unsigned char*>(scratch) + as.ck_off;
-  smppi_status st = t->obs_max > 0 ? launch_backward<R, kMaxObs>(ctx, b, a, s) : launch_backward<R, 0>(ctx, b, a, s);
+  a.obs_pad = nullptr;
+  smppi_status st;
+  if (t->obs_max > 0 && sizeof(R) == sizeof(float)) {
+    // FP32 obstacles through the scalar cache, from padded slots (as the rollout)
+    float4* pad = reinterpret_cast<float4*>(static_cast<unsigned char*>(scratch) + as.pad_off);
+    hipLaunchKernelGGL(k_pad_obs, dim3(b->n_problems), dim3(64), 0, s, a.p.obs_off,
+                       reinterpret_cast<const float*>(a.p.obs), a.p.obs_max, kMaxObs, (float)a.C.alpha, pad);
+    if ((st = check_launch(ctx, "k_pad_obs"))) return st;
+    a.obs_pad = pad;
+  }
+  st = t->obs_max > 0 ? launch_backward<R, kMaxObs>(ctx, b, a, s) : launch_backward<R, 0>(ctx, b, a, s);
   if (st) return st;
   return launch_sum_partials<R>(ctx, b, as, scratch, tickets, gV, s);
 }
@@ -738,7 +755,7 @@ static smppi_status backward_t(smppi_ctx ctx, const smppi_batch* b, const smppi_
                                hipStream_t s) {
   smppi_status st;
   const AdjScratch as = adjoint_scratch(b);
-  if ((st = need_scratch(ctx, as.ck_off + as.ck_bytes, (int)as.tickets, "smppi_rollout_backward")))
+  if ((st = need_scratch(ctx, as.pad_off + as.pad_bytes, (int)as.tickets, "smppi_rollout_backward")))
     return st;
   return backward_launch<R>(ctx, b, m, c, n, t, x0, V, iter, gS, ob, gV, ctx->scratch, ctx->tickets, s);
 }
@@ -833,7 +850,7 @@ extern "C" smppi_status smppi_rollout_backward_noalloc(smppi_ctx ctx, const smpp
     return st;
   if (!ctx->noalloc) return fail(ctx, SMPPI_ERR_UNSUPPORTED, "no fixed scratch on device %d", ctx->device);
   const AdjScratch as = adjoint_scratch(batch);
-  const size_t part = as.ck_off + as.ck_bytes;
+  const size_t part = as.pad_off + as.pad_bytes;
   if (as.tickets * sizeof(uint32_t) > kNoAllocTicketBytes || part > kNoAllocBytes - kNoAllocTicketBytes)
     return fail(ctx, SMPPI_ERR_SHAPE,
                 "smppi_rollout_backward_noalloc: the batch needs %zu ticket counters (B x ceil(2 t_max / 64); "
