@@ -36,7 +36,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # Algorithmic FP32 operation counts per rollout-step (FMA = 2, transcendental = 1,
-# compares/selects not counted); derivation in DESIGN.md, section "Roofline".
+# compares/selects not counted), counted term by term from the device code.
 FLOP_STEP_POLY = 345      # noise, clip, cost, RK4 (4 derivative evaluations), 9-segment window, DCBF
 FLOP_STEP_PER_OBS = 9     # one circular obstacle barrier + penalty + indicator test
 FLOP_UPDATE_STEP = 4      # w * eps' accumulated for two controls

@@ -11,8 +11,8 @@
 // A Computationally Efficient Robust MPC Method Using Control Barrier
 // Functions" (arXiv 2302.11719).  Notation: K samples, T horizon steps (the
 // paper writes M samples and horizon K).  Every function below cites the
-// passage it follows.  Readings of silent or garbled passages are listed in
-// the design doc and repeated here in one line where they are applied.
+// passage it follows.  Where the paper is silent or garbled, the reading taken
+// is stated in one line where it is applied.
 //
 // Built with: g++ -O2 -std=c++17 -ffp-contract=off -fPIC -shared (no SIMD
 // intrinsics, no fast-math), so every expression rounds as written.

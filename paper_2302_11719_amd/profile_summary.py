@@ -2,8 +2,17 @@
 
 rocprofv3 writes one CSV row per (dispatch, counter) for ``--pmc`` runs and one
 row per dispatch for ``--kernel-trace``.  This module reduces them to per-kernel
-means, scales the HBM byte counters by a plain copy kernel of known size, and
+means, turns the memory-side request counters into bytes per dispatch, and
 writes/reads the short text summaries kept beside the benchmark.
+
+Bytes read past L2 come either from the read requests by size,
+32 TCC_EA0_RDREQ_32B + 64 TCC_EA0_RDREQ_64B + 128 TCC_EA0_RDREQ_128B (exact; a
+plain copy kernel of known size is then only a check), or from FETCH_SIZE
+scaled by that copy kernel.  FETCH_SIZE counts a 128-byte read as 64 bytes on
+this GPU, so the copy (all 128-byte reads) gives a factor near 2, while
+instruction fetches (64-byte reads) are counted in full: for a kernel whose
+reads are mostly code, the scaled FETCH_SIZE overstates its bytes.  Bytes
+written come from WRITE_SIZE, which the copy reproduces exactly.
 
   python -m paper_2302_11719_amd.profile_summary traffic \\
       --fetch DIR --write DIR --kernel NAME [--kernel NAME ...] --copy-bytes N [--trace DIR] \\
@@ -115,22 +124,50 @@ def _copy_factor(counters, counter, copy_bytes):
     return None, None
 
 
+RDREQ = (("TCC_EA0_RDREQ_32B_sum", 32), ("TCC_EA0_RDREQ_64B_sum", 64), ("TCC_EA0_RDREQ_128B_sum", 128))
+
+
+def read_bytes(cs):
+    """Bytes read past L2 per dispatch from the read requests by size, or None
+    when the run did not take those counters."""
+    if not all(c in cs for c, _ in RDREQ):
+        return None
+    cols = [cs[c] for c, _ in RDREQ]
+    return [sum(n * b for n, (_, b) in zip(v, RDREQ)) for v in zip(*cols)]
+
+
 def traffic_summary(fetch_dir, write_dir, kernel, copy_bytes, trace=None):
-    """Scaled HBM bytes per dispatch of the kernels matching `kernel` (a name or a
-    list of names); with a kernel trace, also the mean duration and GB/s."""
+    """HBM bytes per dispatch of the kernels matching `kernel` (a name or a list
+    of names); with a kernel trace, also the mean duration and GB/s.  The read
+    side is exact when `fetch_dir` holds the request-size counters, else
+    FETCH_SIZE scaled by the copy kernel."""
     fc, wc = read_counters(fetch_dir), read_counters(write_dir)
     tr = read_trace(trace) if trace else {}
-    ff, fcopy = _copy_factor(fc, "FETCH_SIZE", copy_bytes)
+    by_size = any(read_bytes(cs) is not None for cs in fc.values())
+    if by_size:
+        ff, fcopy = None, None
+        for k, cs in fc.items():
+            if any(c in k for c in COPY_KERNELS) and read_bytes(cs):
+                fcopy = max(read_bytes(cs)) / 1024.0
+                ff = copy_bytes / (fcopy * 1024.0) if fcopy > 0 else None
+                break
+    else:
+        ff, fcopy = _copy_factor(fc, "FETCH_SIZE", copy_bytes)
     wf, wcopy = _copy_factor(wc, "WRITE_SIZE", copy_bytes)
     out = {"digest": kernel_sources_digest(), "copy_bytes": copy_bytes,
+           "read_method": "request sizes" if by_size else "FETCH_SIZE x copy factor",
            "copy_fetch_kib": fcopy, "copy_write_kib": wcopy, "fetch_factor": ff, "write_factor": wf,
            "kernels": {}}
     pats = [kernel] if isinstance(kernel, str) else list(kernel)
     names = sorted({k for pat in pats for k in set(_match(fc, pat)) | set(_match(wc, pat))})
     for k in names:
-        fk = fc.get(k, {}).get("FETCH_SIZE", [])
+        if by_size:
+            fk = [b / 1024.0 for b in (read_bytes(fc.get(k, {})) or [])]
+            fb = _mean(fk) * 1024.0
+        else:
+            fk = fc.get(k, {}).get("FETCH_SIZE", [])
+            fb = _mean(fk) * 1024.0 * (ff or float("nan"))
         wk = wc.get(k, {}).get("WRITE_SIZE", [])
-        fb = _mean(fk) * 1024.0 * (ff or float("nan"))
         wb = _mean(wk) * 1024.0 * (wf or float("nan"))
         out["kernels"][k] = {"dispatches": [len(fk), len(wk)], "fetch_kib": _mean(fk), "write_kib": _mean(wk),
                              "fetch_bytes": fb, "write_bytes": wb, "traffic_bytes": fb + wb}
@@ -156,6 +193,14 @@ def derived(cs, simds=1024, xcds=8):
         out["fp32_tflops"] = fl / dur / 1e3
         out["frac_fp32_peak_packed"] = fl / dur / (PEAK_FP32 / 1e9)
         out["frac_fp32_peak_unpacked"] = 2 * fl / dur / (PEAK_FP32 / 1e9)
+    if "SQC_TC_INST_REQ" in cs:
+        # instruction caches fetch 64-byte lines from L2
+        out["l2_instruction_request_bytes"] = 64.0 * cs["SQC_TC_INST_REQ"]
+    if "TCC_MISS_sum" in cs:
+        # L2 lines are 128 bytes
+        out["l2_miss_line_bytes"] = 128.0 * cs["TCC_MISS_sum"]
+        if "TCC_HIT_sum" in cs:
+            out["l2_hit_rate"] = cs["TCC_HIT_sum"] / max(cs["TCC_HIT_sum"] + cs["TCC_MISS_sum"], 1.0)
     if "GRBM_GUI_ACTIVE" in cs:
         cyc = cs["GRBM_GUI_ACTIVE"] / xcds
         out["gui_active_ghz"] = cyc / dur
@@ -208,12 +253,20 @@ def _cmd_traffic(a):
              f"{v['duration_ns']:.0f}" if "duration_ns" in v else "",
              f"{v['hbm_gbps']:.2f} ({100 * v['frac_hbm_peak']:.3f} %)" if "hbm_gbps" in v else ""]
             for k, v in s["kernels"].items()]
-    body = (f"Plain copy of {a.copy_bytes} bytes (read + write) reads FETCH_SIZE {s['copy_fetch_kib']} KiB and "
-            f"WRITE_SIZE {s['copy_write_kib']} KiB; factors (known / counted) fetch {s['fetch_factor']}, "
-            f"write {s['write_factor']}.  GB/s: scaled bytes / mean duration from the kernel trace "
-            f"(fraction of {PEAK_HBM / 1e12:.0f} TB/s).\n\n"
-            + _md_table(["kernel", "dispatches (fetch, write run)", "FETCH_SIZE KiB/dispatch",
-                         "WRITE_SIZE KiB/dispatch", "scaled HBM bytes/dispatch", "duration ns", "HBM GB/s"], rows))
+    if s["read_method"] == "request sizes":
+        how = (f"Read bytes = 32 RDREQ_32B + 64 RDREQ_64B + 128 RDREQ_128B (TCC_EA0, summed over the L2 "
+               f"channels), used as counted; the plain copy of {a.copy_bytes} bytes reads {s['copy_fetch_kib']} KiB "
+               f"by the same sum (known / counted {s['fetch_factor']}, a check, not applied).  Write bytes = "
+               f"WRITE_SIZE; the copy writes {s['copy_write_kib']} KiB by it (factor {s['write_factor']}, applied).")
+        fcol = "read KiB/dispatch (by request size)"
+    else:
+        how = (f"Plain copy of {a.copy_bytes} bytes (read + write) reads FETCH_SIZE {s['copy_fetch_kib']} KiB and "
+               f"WRITE_SIZE {s['copy_write_kib']} KiB; factors (known / counted) fetch {s['fetch_factor']}, "
+               f"write {s['write_factor']}, applied.")
+        fcol = "FETCH_SIZE KiB/dispatch"
+    body = (how + f"  GB/s: bytes / mean duration from the kernel trace (fraction of {PEAK_HBM / 1e12:.0f} TB/s)."
+            "\n\n" + _md_table(["kernel", "dispatches (read, write run)", fcol, "WRITE_SIZE KiB/dispatch",
+                                 "HBM bytes/dispatch", "duration ns", "HBM GB/s"], rows))
     write_md(a.out, a.title or f"HBM traffic of {', '.join(a.kernel)}", a.command, body, s)
 
 
@@ -243,7 +296,9 @@ def _cmd_counters(a):
             f"this build); cycles = GRBM_GUI_ACTIVE / {a.xcds} XCDs, gui_active_ghz = cycles / duration (the "
             "clock for long kernels; a short kernel's count also covers its dispatch, so it reads high); "
             f"valu_issue_util = 4 cycles x SQ_INSTS_VALU / ({a.simds} SIMDs x cycles), active_inst_valu_util "
-            "the same with SQ_ACTIVE_INST_VALU.\n\n")
+            "the same with SQ_ACTIVE_INST_VALU; l2_instruction_request_bytes = 64 x SQC_TC_INST_REQ (instruction "
+            "cache lines requested from L2), l2_miss_line_bytes = 128 x TCC_MISS_sum, l2_hit_rate = hits / "
+            "(hits + misses).\n\n")
     write_md(a.out, a.title or "Counters", a.command,
              note + _md_table(["kernel", "counter (mean per dispatch)", "value"], rows), payload)
 

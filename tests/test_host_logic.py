@@ -56,6 +56,36 @@ def test_profile_summary_reads_counters_and_scales_traffic(tmp_path):
     assert ps.load_traffic(str(out), "k_fused")[0] is None
 
 
+def test_profile_summary_reads_bytes_by_request_size(tmp_path):
+    """With the request-size counters the read bytes are 32/64/128 per request,
+    unscaled; the copy kernel only yields a check factor."""
+    from paper_2302_11719_amd import profile_summary as ps
+
+    def write(d, rows):
+        os.makedirs(d, exist_ok=True)
+        with open(os.path.join(d, "p_counter_collection.csv"), "w") as fh:
+            fh.write('"Dispatch_Id","Kernel_Name","Counter_Name","Counter_Value"\n')
+            for r in rows:
+                fh.write(",".join(str(x) for x in r) + "\n")
+
+    n = 1 << 20
+    kf = '"void (anonymous namespace)::k_fused<0, 256, 1, true>(FusedArgs)"'
+    rows = [(1, '"__amd_rocclr_copyBuffer"', '"TCC_EA0_RDREQ_32B_sum"', 0),
+            (1, '"__amd_rocclr_copyBuffer"', '"TCC_EA0_RDREQ_64B_sum"', 0),
+            (1, '"__amd_rocclr_copyBuffer"', '"TCC_EA0_RDREQ_128B_sum"', n // 128)]
+    for disp, (a, b, c) in ((2, (1, 10, 2)), (3, (3, 30, 6))):
+        rows += [(disp, kf, '"TCC_EA0_RDREQ_32B_sum"', a), (disp, kf, '"TCC_EA0_RDREQ_64B_sum"', b),
+                 (disp, kf, '"TCC_EA0_RDREQ_128B_sum"', c)]
+    write(tmp_path / "f", rows)
+    write(tmp_path / "w", [(1, '"__amd_rocclr_copyBuffer"', '"WRITE_SIZE"', n / 1024), (2, kf, '"WRITE_SIZE"', 1.0)])
+    s = ps.traffic_summary(str(tmp_path / "f"), str(tmp_path / "w"), "k_fused", n)
+    k = s["kernels"]["k_fused<0, 256, 1, true>"]
+    assert s["read_method"] == "request sizes" and s["fetch_factor"] == pytest.approx(1.0)
+    mean_read = ((32 + 640 + 256) + (96 + 1920 + 768)) / 2
+    assert k["fetch_bytes"] == pytest.approx(mean_read)
+    assert k["traffic_bytes"] == pytest.approx(mean_read + 1024.0)
+
+
 def test_derived_counter_rates():
     """FLOP from the instruction mix (64 lanes, FMA = 2), rates against the peaks, and
     VALU issue utilisation from GRBM cycles summed over the XCDs."""
