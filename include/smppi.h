@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SMPPI_ABI_VERSION 6
+#define SMPPI_ABI_VERSION 7
 
 typedef enum {
   SMPPI_OK = 0,
@@ -401,6 +401,59 @@ smppi_status smppi_plan_stage_ms(smppi_plan plan, float* fused_ms, float* repair
 smppi_status smppi_plan_kernel_ms(smppi_plan plan, float* fused_ms, float* repair_ms);
 /* Launch geometry the plan uses (any output pointer may be NULL). */
 smppi_status smppi_plan_info(smppi_plan plan, int32_t* grid, int32_t* block, int32_t* tile, int32_t* n_tiles);
+
+/* ---- launch-geometry autotuner (plan helper) ---------------------------------
+ * The fused plan kernel has four knobs: the four-wave latency mode, the
+ * workgroup size, the samples per tile and the number of persistent
+ * workgroups.  Which is fastest depends on the batch shape (a few thousand
+ * samples are bound by each wave's per-step chain, hundreds of thousands by
+ * VALU issue, ragged batches by the tail of the tile queue), so the tuner
+ * times candidates on the caller's own batch. */
+typedef struct {
+  int32_t pipeline;  /* 1: latency mode (block, tile ignored); -1: tile mode */
+  int32_t block;     /* tile mode: 64, 128, 256 or 512 */
+  int32_t tile;      /* tile mode: samples per tile, a multiple of block */
+  int32_t grid;      /* persistent workgroups; 0 = from occupancy */
+  float kernel_ms;   /* output: median fused-kernel time; negative when the
+                        candidate could not be built for this batch */
+} smppi_tune_entry;
+
+/* The default candidate set for n_cu compute units (host only, no device):
+ * latency mode, then block {64,128,256,512} x samples per thread {1,2,4}
+ * (block x samples <= 1024) x grid {occupancy, 1, 2, 4 per CU}.  Writes up to
+ * cap entries to out (may be NULL with cap 0) and returns the set's size. */
+int32_t smppi_autotune_candidates(int32_t n_cu, smppi_tune_entry* out, int32_t cap);
+
+/* Shape key under which a tuning result is cached (host only, no device):
+ * "B<n>-sk<round(8 log2 sum K)>-kmax<K>-tmax<T>-tmean<mean T, 1 decimal>-obs<0|1>-cu<n_cu>"
+ * from host copies of the batch's CSR offsets (k_off_host [B+1], t_off_host
+ * [B+1]).  INVALID_ARGUMENT on NULL pointers, B < 1 or a key longer than cap - 1. */
+smppi_status smppi_autotune_key(int32_t n_problems, const int64_t* k_off_host, const int32_t* t_off_host,
+                                int32_t has_obstacles, int32_t n_cu, char* out, int32_t cap);
+
+/* Times each candidate (cands [n_cands] host, or the default set when cands is
+ * NULL) on this batch: a plan with the shield, execute and graph off, warmup +
+ * reps profiled launches, the median of the fused kernel's own duration.
+ * table (host, table_cap entries, may be NULL) receives the candidates, the
+ * timed ones fastest first, then those that cannot be built for this batch
+ * (kernel_ms = -1); *n_table their count (entries beyond table_cap are
+ * dropped); *best the fastest.  bufs as for a plan
+ * (V_safe unused); x0, V and iter are only read, S, V_plus and stats are
+ * overwritten.  With cache_path (host string, may be NULL): a result stored
+ * under the batch's shape key is returned without timing, *cached = 1 (table
+ * then holds that one entry), unless force; a new result replaces the key's line
+ * of the file (text, one "key pipeline block tile grid kernel_ms" line per key,
+ * written to a temporary file in the same directory and renamed; the directory
+ * must exist).  Not for hot loops: it creates plans (device allocations),
+ * synchronises the device and does file I/O.  Errors: as smppi_plan_create for
+ * the batch; SMPPI_ERR_SHAPE when no candidate can be built; SMPPI_ERR_HIP on
+ * cache I/O failure (the timing result is still returned). */
+smppi_status smppi_autotune(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                            const smppi_cost* cost, const smppi_noise* noise, const smppi_track* track,
+                            double lambda, const smppi_plan_buffers* bufs, const smppi_tune_entry* cands,
+                            int32_t n_cands, int32_t reps, int32_t warmup, const char* cache_path, int32_t force,
+                            smppi_tune_entry* best, int32_t* cached, smppi_tune_entry* table, int32_t table_cap,
+                            int32_t* n_table, void* stream);
 
 /* ---- test hooks: the device generator, evaluated on its own ---------------- */
 

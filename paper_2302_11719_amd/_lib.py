@@ -22,13 +22,14 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "shape", 3: "dtype", 4: "no device"
 ERR_NO_DEVICE = 4
 
 # Symbols declared in include/smppi.h (checked by the CPU test suite).
-ABI_VERSION = 6  # SMPPI_ABI_VERSION of include/smppi.h this binding matches
+ABI_VERSION = 7  # SMPPI_ABI_VERSION of include/smppi.h this binding matches
 EXPORTS = ("smppi_rollout_curvilinear", "smppi_rollout_backward_curvilinear", "smppi_shield_repair_curvilinear",
            "smppi_execute_curvilinear", "smppi_create", "smppi_destroy", "smppi_last_error", "smppi_status_string", "smppi_abi_version",
            "smppi_reserve_batch", "smppi_device_errors", "smppi_rollout", "smppi_weights", "smppi_update",
            "smppi_rollout_backward", "smppi_rollout_backward_noalloc", "smppi_shield_repair", "smppi_execute", "smppi_plan_create",
            "smppi_plan_launch", "smppi_plan_destroy", "smppi_plan_info", "smppi_plan_launch_profiled",
-           "smppi_plan_stage_ms", "smppi_plan_kernel_ms", "smppi_debug_philox")
+           "smppi_plan_stage_ms", "smppi_plan_kernel_ms", "smppi_autotune", "smppi_autotune_candidates",
+           "smppi_autotune_key", "smppi_debug_philox")
 
 
 class Model(ctypes.Structure):
@@ -93,6 +94,11 @@ class PlanBuffers(ctypes.Structure):
                 ("V_safe", c_vp)]
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("pipeline", c_i32), ("block", c_i32), ("tile", c_i32), ("grid", c_i32),
+                ("kernel_ms", ctypes.c_float)]
+
+
 P = ctypes.POINTER
 
 _SIGS = {
@@ -130,6 +136,11 @@ _SIGS = {
     "smppi_plan_launch_profiled": (c_i32, [c_vp, c_vp]),
     "smppi_plan_stage_ms": (c_i32, [c_vp, P(ctypes.c_float), P(ctypes.c_float), P(ctypes.c_float)]),
     "smppi_plan_kernel_ms": (c_i32, [c_vp, P(ctypes.c_float), P(ctypes.c_float)]),
+    "smppi_autotune": (c_i32, [c_vp, P(Batch), P(Model), P(Cost), P(Noise), P(Track), c_f64, P(PlanBuffers),
+                               P(TuneEntry), c_i32, c_i32, c_i32, ctypes.c_char_p, c_i32, P(TuneEntry), P(c_i32),
+                               P(TuneEntry), c_i32, P(c_i32), c_vp]),
+    "smppi_autotune_candidates": (c_i32, [c_i32, P(TuneEntry), c_i32]),
+    "smppi_autotune_key": (c_i32, [c_i32, P(c_i64), P(c_i32), c_i32, c_i32, ctypes.c_char_p, c_i32]),
     "smppi_debug_philox": (c_i32, [c_vp, c_vp, P(c_u32), c_i64, c_vp, c_vp]),
 }
 

@@ -20,7 +20,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -943,5 +945,178 @@ extern "C" smppi_status smppi_plan_info(smppi_plan p, int32_t* grid, int32_t* bl
   if (block) *block = p->block;
   if (tile) *tile = p->fa.tile;
   if (n_tiles) *n_tiles = p->fa.n_tiles;
+  return SMPPI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch-geometry autotuner.
+
+namespace {
+
+constexpr int kTuneBlocks[] = {64, 128, 256, 512};
+constexpr int kTuneSpt[] = {1, 2, 4};
+constexpr int kTuneGridPerCu[] = {0, 1, 2, 4};  // 0: occupancy-derived
+
+std::vector<smppi_tune_entry> default_candidates(int n_cu) {
+  std::vector<smppi_tune_entry> c;
+  c.push_back(smppi_tune_entry{1, 0, 0, 0, 0.f});
+  for (int block : kTuneBlocks)
+    for (int spt : kTuneSpt) {
+      if (block * spt > 1024) continue;
+      for (int g : kTuneGridPerCu) c.push_back(smppi_tune_entry{-1, block, block * spt, g * n_cu, 0.f});
+    }
+  return c;
+}
+
+// The cache file: one "key pipeline block tile grid kernel_ms" line per key.
+bool cache_lookup(const char* path, const std::string& key, smppi_tune_entry* e) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char k[256];
+  smppi_tune_entry t{};
+  bool found = false;
+  while (std::fscanf(f, "%255s %d %d %d %d %f", k, &t.pipeline, &t.block, &t.tile, &t.grid, &t.kernel_ms) == 6)
+    if (key == k) {
+      *e = t;
+      found = true;
+    }
+  std::fclose(f);
+  return found;
+}
+
+bool cache_store(const char* path, const std::string& key, const smppi_tune_entry& e) {
+  std::vector<std::string> keep;
+  if (FILE* f = std::fopen(path, "r")) {
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+      char k[256];
+      if (std::sscanf(line, "%255s", k) == 1 && key != k) keep.emplace_back(line);
+    }
+    std::fclose(f);
+  }
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  bool ok = true;
+  for (const std::string& l : keep) ok = ok && std::fputs(l.c_str(), f) >= 0;
+  ok = ok && std::fprintf(f, "%s %d %d %d %d %.6g\n", key.c_str(), e.pipeline, e.block, e.tile, e.grid,
+                          (double)e.kernel_ms) > 0;
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok || std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" int32_t smppi_autotune_candidates(int32_t n_cu, smppi_tune_entry* out, int32_t cap) {
+  const std::vector<smppi_tune_entry> c = default_candidates(std::max(0, n_cu));
+  for (int i = 0; out && i < cap && i < (int)c.size(); ++i) out[i] = c[i];
+  return (int32_t)c.size();
+}
+
+extern "C" smppi_status smppi_autotune_key(int32_t n_problems, const int64_t* k_off_host, const int32_t* t_off_host,
+                                           int32_t has_obstacles, int32_t n_cu, char* out, int32_t cap) {
+  if (n_problems < 1 || !k_off_host || !t_off_host || !out || cap < 1) return SMPPI_ERR_INVALID_ARGUMENT;
+  int64_t sum_k = 0, k_max = 0;
+  int32_t t_max = 0;
+  double t_sum = 0.0;
+  for (int b = 0; b < n_problems; ++b) {
+    const int64_t K = k_off_host[b + 1] - k_off_host[b];
+    const int32_t T = t_off_host[b + 1] - t_off_host[b];
+    sum_k += K;
+    k_max = std::max(k_max, K);
+    t_max = std::max(t_max, T);
+    t_sum += T;
+  }
+  const long octave = sum_k > 0 ? std::lround(8.0 * std::log2((double)sum_k)) : -1;
+  const int n = std::snprintf(out, (size_t)cap, "B%d-sk%ld-kmax%lld-tmax%d-tmean%.1f-obs%d-cu%d", n_problems, octave,
+                              (long long)k_max, t_max, t_sum / n_problems, has_obstacles ? 1 : 0, n_cu);
+  return (n < 0 || n >= cap) ? SMPPI_ERR_INVALID_ARGUMENT : SMPPI_OK;
+}
+
+extern "C" smppi_status smppi_autotune(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
+                                       const smppi_cost* cost, const smppi_noise* noise, const smppi_track* track,
+                                       double lambda, const smppi_plan_buffers* bufs, const smppi_tune_entry* cands,
+                                       int32_t n_cands, int32_t reps, int32_t warmup, const char* cache_path,
+                                       int32_t force, smppi_tune_entry* best, int32_t* cached,
+                                       smppi_tune_entry* table, int32_t table_cap, int32_t* n_table, void* stream) {
+  if (!ctx) return SMPPI_ERR_INVALID_ARGUMENT;
+  if (!best || !bufs || !batch || !track) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "batch, track, bufs, best are required");
+  if (cands && n_cands < 1) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "n_cands must be >= 1 with cands");
+  if (reps < 1 || warmup < 0) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "reps must be >= 1, warmup >= 0");
+  if (table_cap < 0 || (table_cap > 0 && !table)) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "table_cap without table");
+  smppi_status st = validate_batch(ctx, batch);
+  if (st) return st;
+  if (cached) *cached = 0;
+  if (n_table) *n_table = 0;
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int B = batch->n_problems;
+  std::vector<int64_t> koff(B + 1);
+  std::vector<int32_t> toff(B + 1);
+  hipError_t e = hipMemcpy(koff.data(), batch->k_off, sizeof(int64_t) * (B + 1), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(k_off)");
+  e = hipMemcpy(toff.data(), batch->t_off, sizeof(int32_t) * (B + 1), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(t_off)");
+  char keybuf[256];
+  if ((st = smppi_autotune_key(B, koff.data(), toff.data(), track->obs_max > 0, ctx->n_cu, keybuf, sizeof keybuf)))
+    return fail(ctx, st, "batch shape key");
+  const std::string key(keybuf);
+  if (cache_path && !force) {
+    smppi_tune_entry hit{};
+    if (cache_lookup(cache_path, key, &hit)) {
+      *best = hit;
+      if (cached) *cached = 1;
+      if (table && table_cap > 0) table[0] = hit;
+      if (n_table) *n_table = 1;
+      return SMPPI_OK;
+    }
+  }
+  const std::vector<smppi_tune_entry> cand =
+      cands ? std::vector<smppi_tune_entry>(cands, cands + n_cands) : default_candidates(ctx->n_cu);
+  smppi_plan_opts o{};
+  o.lambda = lambda;
+  o.use_graph = 0;
+  o.fuse_shield = -1;
+  smppi_plan_buffers pb = *bufs;
+  pb.V_safe = nullptr;
+  std::vector<smppi_tune_entry> done, skipped;
+  std::vector<float> ms;
+  for (smppi_tune_entry c : cand) {
+    o.pipeline = c.pipeline == 1 ? 1 : -1;
+    o.block = c.pipeline == 1 ? 0 : c.block;
+    o.tile = c.pipeline == 1 ? 0 : c.tile;
+    o.grid = c.grid;
+    smppi_plan p = nullptr;
+    if (smppi_plan_create(ctx, batch, model, cost, noise, track, &o, &pb, &p) != SMPPI_OK) {
+      c.kernel_ms = -1.f;  // not buildable for this batch (block, LDS)
+      skipped.push_back(c);
+      continue;
+    }
+    ms.clear();
+    for (int i = 0; i < warmup + reps && st == SMPPI_OK; ++i) {
+      float f = 0.f;
+      if ((st = smppi_plan_launch_profiled(p, s)) == SMPPI_OK && (st = smppi_plan_kernel_ms(p, &f, nullptr)) == SMPPI_OK &&
+          i >= warmup)
+        ms.push_back(f);
+    }
+    smppi_plan_destroy(p);
+    if (st) return st;
+    std::nth_element(ms.begin(), ms.begin() + ms.size() / 2, ms.end());
+    c.kernel_ms = ms[ms.size() / 2];
+    done.push_back(c);
+  }
+  if (done.empty()) return fail(ctx, SMPPI_ERR_SHAPE, "no candidate geometry can be built for this batch");
+  std::stable_sort(done.begin(), done.end(),
+                   [](const smppi_tune_entry& x, const smppi_tune_entry& y) { return x.kernel_ms < y.kernel_ms; });
+  *best = done[0];
+  done.insert(done.end(), skipped.begin(), skipped.end());
+  for (int i = 0; table && i < table_cap && i < (int)done.size(); ++i) table[i] = done[i];
+  if (n_table) *n_table = (int32_t)done.size();
+  if (cache_path && !cache_store(cache_path, key, done[0]))
+    return fail(ctx, SMPPI_ERR_HIP, "could not write the tuning cache %s", cache_path);
   return SMPPI_OK;
 }

@@ -25,6 +25,29 @@ def test_autotune_candidates_and_shape_key():
     assert k1 == autotune.shape_key(fake, 256) and k1 != autotune.shape_key(fake, 128)
     fake2 = types.SimpleNamespace(K=[100, 301], T=[20, 40], B=2, track=types.SimpleNamespace(obs_max=64))
     assert autotune.shape_key(fake2, 256) != k1
+    # sum K = 400: round(8 log2 400) = 69
+    assert k1 == "B2-sk69-kmax300-tmax40-tmean30.0-obs0-cu256"
+
+
+def test_autotune_key_rejects_bad_arguments():
+    """smppi_autotune_key validates its host arguments (no device needed)."""
+    pytest.importorskip("torch")
+    import ctypes
+
+    import numpy as np
+
+    from paper_2302_11719_amd import _lib as L
+
+    k = np.array([0, 10], dtype=np.int64)
+    t = np.array([0, 5], dtype=np.int32)
+    pk, pt = k.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    buf = ctypes.create_string_buffer(64)
+    assert L.lib().smppi_autotune_key(1, pk, pt, 0, 8, buf, 64) == 0
+    assert buf.value == b"B1-sk27-kmax10-tmax5-tmean5.0-obs0-cu8"
+    assert L.lib().smppi_autotune_key(0, pk, pt, 0, 8, buf, 64) == 1
+    assert L.lib().smppi_autotune_key(1, None, pt, 0, 8, buf, 64) == 1
+    assert L.lib().smppi_autotune_key(1, pk, pt, 0, 8, buf, 10) == 1  # key does not fit
+    assert L.lib().smppi_autotune_candidates(8, None, 0) == 45
 
 
 def test_profile_summary_reads_counters_and_scales_traffic(tmp_path):
