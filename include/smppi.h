@@ -384,8 +384,8 @@ smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batch, const sm
 /* One MPPI iteration of every problem: rollout, weights and update fused in one
  * persistent launch, then (optionally) the shield and the execute/warm start.
  * With obstacles outside latency mode, a small kernel first copies the current
- * obstacles into padded slots the plan owns (read through the scalar cache by
- * the rollouts). */
+ * obstacles into padded slots the plan owns (one slot per lane of each wave
+ * of the rollouts). */
 smppi_status smppi_plan_launch(smppi_plan plan, void* stream);
 void smppi_plan_destroy(smppi_plan plan);
 /* Profiling: the same work as smppi_plan_launch, enqueued without the graph and

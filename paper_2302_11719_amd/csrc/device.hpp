@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace smppi {
 
 constexpr int WAVE = 64;
@@ -478,135 +480,155 @@ struct LdsObstacles {
   }
 };
 
-// ScalarObstacles: FP32 table in global memory, the same for the whole wave,
-// one slot per obstacle: (c_x, c_y, r^2, kappa) with kappa = (1 - alpha)
-// ((r + margin)^2 - r^2); unused slots are inert ((0, 0, -1e30, 0): never
-// violated, never hit).  The slots are read through the scalar cache into
-// SGPRs in groups of eight, one group ahead of the arithmetic, so the VALU
-// instructions take the obstacle terms as scalar operands (no per-lane copies
-// of the table).  The arithmetic is rewritten around g_i = |p - c_i|^2 - r_i^2
-// (two FMAs; collision iff g_i < 0): with h_i = g_i - delta_i, delta_i =
-// (r + margin)^2 - r^2, the transition penalty is
-//   alpha h_i(x_t) - h_i(x_{t+1}) = c_i - g_i(x_{t+1}),  c_i = alpha g_i(x_t) + kappa_i,
-// so each lane carries c_i (updated in place by one FMA), and the collision
-// test is a running min3 of the g_i.
-typedef const float __attribute__((address_space(4)))* ConstF;
-constexpr int OBS_GROUP = 8;
-struct ScalarObstacles {
-  const float4* slots;  // [NOBS] slots of this problem (uniform address)
-  // INIT: c_i = alpha g_i + kappa_i only; else also pen += sum_i max(c_i - g_i, 0).
-  // mo = min(mo, min_i g_i).
-  template <int NOBS, bool INIT>
-  __device__ __forceinline__ void run(float px, float py, float alpha, float* c, float& pen, float& mo) const {
-    static_assert(NOBS % OBS_GROUP == 0, "obstacle slots come in groups");
-    constexpr int NG = NOBS / OBS_GROUP;
-    // The table address is made explicitly uniform (readfirstlane) and each
-    // group's address gets an opaque zero offset from an asm statement tied to
-    // the step's position (then to the running sums), so that the loads stay
-    // inside the step loop, one group ahead of their use, instead of being
-    // hoisted out of it (the whole table does not fit in SGPRs).
-    const uint64_t base = (uint64_t)(uintptr_t)slots;
-    const uint64_t ubase = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
-                           (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)base);
-    ConstF op = (ConstF)(uintptr_t)ubase;
-    asm volatile("" : "+s"(op) : "v"(px), "v"(py));
-    // alpha in a VGPR: the FMA c = alpha g + kappa then reads one scalar
-    // operand (kappa), within the one-SGPR-per-instruction limit
-    float av = alpha;
-    asm volatile("" : "+v"(av));
-    float4 cur[OBS_GROUP], nxt[OBS_GROUP];
+// ---------------------------------------------------------------- wave reductions
+// Whole-wave reductions; every lane gets the result.
+template <class R>
+__device__ __forceinline__ R wave_sum(R v) {
 #pragma unroll
-    for (int j = 0; j < OBS_GROUP; ++j) cur[j] = make_float4(op[4 * j], op[4 * j + 1], op[4 * j + 2], op[4 * j + 3]);
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+template <class R>
+__device__ __forceinline__ R wave_min(R v) {
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      if (g + 1 < NG) {
-        op += 4 * OBS_GROUP;
-        asm volatile("" : "+s"(op) : "v"(pen), "v"(mo));
+  for (int o = WAVE / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+// FP32 (the whole wave active): within each 16-lane row, partners lane^1 and
+// lane^2 (quad permutations), then the other quad of the half row and the
+// other half of the row (mirrors; after the first two steps every lane of a
+// quad holds the same value, so a mirror reaches the same partner value as
+// lane^4 and lane^8 would); the four row results then meet as
+// (row0 + row1) + (row2 + row3) through readlane.  Every lane gets the same
+// value, and each kernel reduces in this one order.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+template <>
+__device__ __forceinline__ float wave_sum<float>(float v) {
+  v += dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f<0x141>(v);  // row_half_mirror
+  v += dpp_f<0x140>(v);  // row_mirror
+  return (lane_f(v, 0) + lane_f(v, 16)) + (lane_f(v, 32) + lane_f(v, 48));
+}
+template <>
+__device__ __forceinline__ float wave_min<float>(float v) {
+  v = fminf(v, dpp_f<0xB1>(v));
+  v = fminf(v, dpp_f<0x4E>(v));
+  v = fminf(v, dpp_f<0x141>(v));
+  v = fminf(v, dpp_f<0x140>(v));
+  return fminf(fminf(lane_f(v, 0), lane_f(v, 16)), fminf(lane_f(v, 32), lane_f(v, 48)));
+}
+template <class R>
+__device__ __forceinline__ R wave_max(R v) {
 #pragma unroll
-        for (int j = 0; j < OBS_GROUP; ++j)
-          nxt[j] = make_float4(op[4 * j], op[4 * j + 1], op[4 * j + 2], op[4 * j + 3]);
-      }
-#pragma unroll
-      for (int j = 0; j < OBS_GROUP; j += 2) {
-        const int i = g * OBS_GROUP + j;
-        float g2[2];
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          const float4 o = cur[j + k];
-          const float ox = px - o.x, oy = py - o.y;
-          const float gi = fmaf(ox, ox, fmaf(oy, oy, -o.z));
-          if (!INIT) pen += fmaxf(c[i + k] - gi, 0.f);
-          c[i + k] = fmaf(av, gi, o.w);
-          g2[k] = gi;
-        }
-        mo = fminf(fminf(mo, g2[0]), g2[1]);  // v_min3
-      }
-      if (g + 1 < NG) {
-#pragma unroll
-        for (int j = 0; j < OBS_GROUP; ++j) cur[j] = nxt[j];
-      }
-    }
+  for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+template <>
+__device__ __forceinline__ float wave_max<float>(float v) {
+  v = fmaxf(v, dpp_f<0xB1>(v));
+  v = fmaxf(v, dpp_f<0x4E>(v));
+  v = fmaxf(v, dpp_f<0x141>(v));
+  v = fmaxf(v, dpp_f<0x140>(v));
+  return fmaxf(fmaxf(lane_f(v, 0), lane_f(v, 16)), fmaxf(lane_f(v, 32), lane_f(v, 48)));
+}
+
+// WaveObstacles: the FP32 obstacle barriers of a whole wave of samples of one
+// problem.  The table holds one slot per obstacle, (c_x, c_y, r^2, kappa) with
+// kappa = (1 - alpha) ((r + margin)^2 - r^2), unused slots inert
+// ((0, 0, -1e30, 0)); lane j keeps slot j in registers.  With g_i(p) =
+// |p - c_i|^2 - r_i^2 (collision iff g_i < 0) and h_i = g_i - delta_i,
+// delta_i = (r + margin)^2 - r^2, the DCBF transition term of eqs. (17)-(20) is
+//   alpha h_i(x_t) - h_i(x_{t+1}) = alpha g_i(p) + kappa_i - g_i(q),
+// p, q the positions at t and t+1.
+//
+// Most obstacles are far from every sample of a wave, and for those the term is
+// exactly zero: with a = |q - c| and s = |q - p|, |p - c| <= a + s gives
+//   alpha g(p) + kappa - g(q) <= F(a) = -(1 - alpha) a^2 + 2 alpha s a + alpha s^2
+//                                     + (1 - alpha) r^2 + kappa,
+// which decreases in a beyond alpha s / (1 - alpha).  So once per transition the
+// wave takes the bounding box of its q's and its largest step s (wave
+// reductions), each lane j bounds a from below for obstacle j by its distance to
+// the box, and obstacle j is skipped when F at that bound, with the largest step,
+// is below minus a rounding margin (then also g(q) > 0: no collision either).
+// The remaining obstacles are evaluated for every lane, in index order, with the
+// same FP32 operations as a full sweep, so the sums are the same bits (a skipped
+// term would have added exactly zero).  The whole wave must be active.
+struct WaveObstacles {
+  float4 mine;  // slot of obstacle `lane` (inert beyond the table)
+
+  __device__ __forceinline__ WaveObstacles() : mine(make_float4(0.f, 0.f, -1e30f, 0.f)) {}
+  __device__ __forceinline__ WaveObstacles(const float4* slots, int n_slots) {
+    const int lane = threadIdx.x % WAVE;
+    mine = lane < n_slots ? slots[lane] : make_float4(0.f, 0.f, -1e30f, 0.f);
   }
-  template <int NOBS>
-  __device__ __forceinline__ void init(float px, float py, float alpha, float* c, bool& outside) const {
-    float pen = 0.f, mo = INFINITY;
-    run<NOBS, true>(px, py, alpha, c, pen, mo);
-    outside = outside || (mo < 0.f);
+
+  // Obstacles that may contribute to the transition p -> q of some lane (bit i).
+  __device__ __forceinline__ uint64_t live(float ppx, float ppy, float qpx, float qpy, float alpha) const {
+    const float lox = wave_min(qpx), hix = wave_max(qpx);
+    const float loy = wave_min(qpy), hiy = wave_max(qpy);
+    const float dsx = qpx - ppx, dsy = qpy - ppy;
+    const float s2 = wave_max(fmaf(dsx, dsx, dsy * dsy));
+    // lower bound of the distance from obstacle `lane` to any q, upper bound of
+    // any step (a relative 2^-20 and 1e-6 absolute cover the FP32 rounding)
+    const float ex = fmaxf(fmaxf(lox - mine.x, mine.x - hix), 0.f);
+    const float ey = fmaxf(fmaxf(loy - mine.y, mine.y - hiy), 0.f);
+    const float A = sqrtf(fmaf(ex, ex, ey * ey)) * (1.f - 0x1p-20f);
+    const float S = sqrtf(s2) * (1.f + 0x1p-20f) + 1e-6f;
+    const float om = 1.f - alpha;
+    const float F = fmaf(-om * A, A, fmaf(2.f * alpha * S, A, fmaf(alpha * S, S, fmaf(om, mine.z, mine.w))));
+    const float AS = A + S;
+    const bool skip = alpha > 0.f && om > 0.f && om * A >= alpha * S && F + fmaf(1e-4f * AS, AS, 1e-4f) <= 0.f;
+    // a non-finite bound (a lane that diverged to infinity) keeps every obstacle
+    return __ballot(!skip);
   }
-  template <int NOBS>
-  __device__ __forceinline__ void step(float px, float py, float alpha, float* c, float& pen, bool& outside) const {
+
+  // pen += sum_i max(alpha g_i(p) + kappa_i - g_i(q), 0); outside |= min_i g_i(q) < 0.
+  __device__ __forceinline__ void step(float ppx, float ppy, float qpx, float qpy, float alpha, float& pen,
+                                       bool& outside) const {
+    uint64_t m = live(ppx, ppy, qpx, qpy, alpha);
     float mo = INFINITY;
-    run<NOBS, false>(px, py, alpha, c, pen, mo);
+    while (m) {
+      const int i = (int)__builtin_ctzll(m);
+      m &= m - 1;
+      const float cx = lane_f(mine.x, i), cy = lane_f(mine.y, i), r2 = lane_f(mine.z, i), kap = lane_f(mine.w, i);
+      const float ax = ppx - cx, ay = ppy - cy;
+      const float g0 = fmaf(ax, ax, fmaf(ay, ay, -r2));
+      const float bx = qpx - cx, by = qpy - cy;
+      const float g1 = fmaf(bx, bx, fmaf(by, by, -r2));
+      pen += fmaxf(fmaf(alpha, g0, kap) - g1, 0.f);
+      mo = fminf(mo, g1);
+    }
     outside = outside || (mo < 0.f);
   }
-  // Adjoint of the obstacle transitions from p (= x_t) to q (= x_{t+1}), the
-  // slots read as in run(): with g(p) = |p - c|^2 - r^2, the DCBF residual is
-  // r_i = alpha g_i(p) + kappa_i - g_i(q) = alpha h_i(x_t) - h_i(x_{t+1}); where
-  // r_i > 0 its cotangent is base + w_sq2 r_i (base = w_S C + w_lin [t < n_lin],
-  // w_sq2 = 2 w_sq), and dr/dq = -2 (q - c), dr/dp = 2 alpha (p - c).  Adds the
-  // q part to (lqx, lqy) and the p part to (lpx, lpy).
-  template <int NOBS>
+
+  // Adjoint of step: with r_i = alpha g_i(p) + kappa_i - g_i(q), where r_i > 0 its
+  // cotangent is base + w_sq2 r_i (base = w_S C + w_lin [t < n_lin], w_sq2 =
+  // 2 w_sq), and dr/dq = -2 (q - c), dr/dp = 2 alpha (p - c).  Adds the q part to
+  // (lqx, lqy) and the p part to (lpx, lpy).
   __device__ __forceinline__ void grad(float ppx, float ppy, float qpx, float qpy, float alpha, float base,
                                        float w_sq2, float& lqx, float& lqy, float& lpx, float& lpy) const {
-    static_assert(NOBS % OBS_GROUP == 0, "obstacle slots come in groups");
-    constexpr int NG = NOBS / OBS_GROUP;
-    const uint64_t b64 = (uint64_t)(uintptr_t)slots;
-    const uint64_t ubase = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(b64 >> 32)) << 32) |
-                           (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b64);
-    ConstF op = (ConstF)(uintptr_t)ubase;
-    asm volatile("" : "+s"(op) : "v"(ppx), "v"(qpx));
-    float av = alpha;
-    asm volatile("" : "+v"(av));
-    float4 cur[OBS_GROUP], nxt[OBS_GROUP];
-#pragma unroll
-    for (int j = 0; j < OBS_GROUP; ++j) cur[j] = make_float4(op[4 * j], op[4 * j + 1], op[4 * j + 2], op[4 * j + 3]);
-#pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      if (g + 1 < NG) {
-        op += 4 * OBS_GROUP;
-        asm volatile("" : "+s"(op) : "v"(lqx), "v"(lpx));
-#pragma unroll
-        for (int j = 0; j < OBS_GROUP; ++j)
-          nxt[j] = make_float4(op[4 * j], op[4 * j + 1], op[4 * j + 2], op[4 * j + 3]);
-      }
-#pragma unroll
-      for (int j = 0; j < OBS_GROUP; ++j) {
-        const float4 o = cur[j];
-        const float ax = ppx - o.x, ay = ppy - o.y, bx = qpx - o.x, by = qpy - o.y;
-        const float gp = fmaf(ax, ax, fmaf(ay, ay, -o.z));
-        const float gq = fmaf(bx, bx, fmaf(by, by, -o.z));
-        const float r = fmaf(av, gp, o.w) - gq;
-        const float k2 = r > 0.f ? 2.f * fmaf(w_sq2, r, base) : 0.f;
-        lqx = fmaf(-k2, bx, lqx);
-        lqy = fmaf(-k2, by, lqy);
-        const float k2a = k2 * av;
-        lpx = fmaf(k2a, ax, lpx);
-        lpy = fmaf(k2a, ay, lpy);
-      }
-      if (g + 1 < NG) {
-#pragma unroll
-        for (int j = 0; j < OBS_GROUP; ++j) cur[j] = nxt[j];
-      }
+    uint64_t m = live(ppx, ppy, qpx, qpy, alpha);
+    while (m) {
+      const int i = (int)__builtin_ctzll(m);
+      m &= m - 1;
+      const float cx = lane_f(mine.x, i), cy = lane_f(mine.y, i), r2 = lane_f(mine.z, i), kap = lane_f(mine.w, i);
+      const float ax = ppx - cx, ay = ppy - cy, bx = qpx - cx, by = qpy - cy;
+      const float gp = fmaf(ax, ax, fmaf(ay, ay, -r2));
+      const float gq = fmaf(bx, bx, fmaf(by, by, -r2));
+      const float r = fmaf(alpha, gp, kap) - gq;
+      const float k2 = r > 0.f ? 2.f * fmaf(w_sq2, r, base) : 0.f;
+      lqx = fmaf(-k2, bx, lqx);
+      lqy = fmaf(-k2, by, lqy);
+      const float k2a = k2 * alpha;
+      lpx = fmaf(k2a, ax, lpx);
+      lpy = fmaf(k2a, ay, lpy);
     }
   }
 };
@@ -643,7 +665,7 @@ __device__ __forceinline__ DevCost<R> cost_in_vgprs(const DevCost<R>& C) {
 // Modified trajectory cost S~ of one sample (Algorithm 2 inner loop):
 //   S~ = sum_{t<T} [q(x_t) + lambda_u v_t^T Sigma^-1 u_t] + phi_w q(x_T) + sum_{t=0}^{T} C_cbf(z_t).
 // V is [2][T] (steer row, throttle row), read from LDS or global.  Obstacles
-// come from `os` (LdsObstacles or ScalarObstacles).
+// come from `os` (LdsObstacles, or WaveObstacles: FP32, the whole wave active).
 template <class R, int NOBS, class OS>
 __device__ R rollout_sample(const DevModel<R>& Mg, const DevCost<R>& Cg, const TrackView<R>& tr, const State<R>& x0,
                             const R* __restrict__ V, int T, NoiseStream<R>& ns, R* eps_out, const OS& os) {
@@ -663,11 +685,16 @@ __device__ R rollout_sample(const DevModel<R>& Mg, const DevCost<R>& Cg, const T
   R ey2 = lateral_sq(tr, x.px, x.py, idx);
   R h0 = tr.w2 - ey2;
   bool outside = h0 < R(0);
-  R hob[NOBS > 0 ? NOBS : 1];
+  constexpr bool WV = std::is_same<OS, WaveObstacles>::value;  // FP32 wave-level obstacles
+  R hob[NOBS > 0 && !WV ? NOBS : 1];
   // z_0 = (x_0, x_0): C max((alpha - 1) h(x_0), 0) per barrier, i.e. the
   // transition penalty with both ends at x_0.
   R S = C.C_cbf * fmax((C.alpha - R(1)) * h0, R(0));
-  if (NOBS > 0) {
+  if constexpr (NOBS > 0 && WV) {
+    R pen0 = R(0);
+    os.step(x.px, x.py, x.px, x.py, C.alpha, pen0, outside);
+    S += C.C_cbf * pen0;
+  } else if constexpr (NOBS > 0) {
     os.template init<NOBS>(x.px, x.py, C.alpha, hob, outside);
     R pen0 = R(0);
     bool dummy = false;
@@ -689,13 +716,15 @@ __device__ R rollout_sample(const DevModel<R>& Mg, const DevCost<R>& Cg, const T
     if (outside) q += C.C_obs;
     S += q + (C.ctrl_w[0] * v0 * u0 + C.ctrl_w[1] * v1 * u1);
     const StepCtl<R> sc = step_ctl(M, u0, u1);
+    const R ppx = x.px, ppy = x.py;
     rk4(M, sc, x);
     ey2 = lateral_sq(tr, x.px, x.py, idx);
     const R h1 = tr.w2 - ey2;
     R pen = fmax(C.alpha * h0 - h1, R(0));
     h0 = h1;
     outside = h1 < R(0);
-    if (NOBS > 0) os.template step<NOBS>(x.px, x.py, C.alpha, hob, pen, outside);
+    if constexpr (NOBS > 0 && WV) os.step(ppx, ppy, x.px, x.py, C.alpha, pen, outside);
+    else if constexpr (NOBS > 0) os.template step<NOBS>(x.px, x.py, C.alpha, hob, pen, outside);
     S += C.C_cbf * pen;
   }
   const R dv = x.vx - C.v_g;

@@ -240,49 +240,6 @@ __device__ __forceinline__ State<R> load_state(const R* x) {
   return s;
 }
 
-template <class R>
-__device__ __forceinline__ R wave_sum(R v) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-  return v;
-}
-template <class R>
-__device__ __forceinline__ R wave_min(R v) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, WAVE));
-  return v;
-}
-// FP32 (the whole wave active): within each 16-lane row, partners lane^1 and
-// lane^2 (quad permutations), then the other quad of the half row and the
-// other half of the row (mirrors; after the first two steps every lane of a
-// quad holds the same value, so a mirror reaches the same partner value as
-// lane^4 and lane^8 would); the four row results then meet as
-// (row0 + row1) + (row2 + row3) through readlane.  Every lane gets the same
-// value, and each kernel reduces in this one order.
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float lane_f(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-template <>
-__device__ __forceinline__ float wave_sum<float>(float v) {
-  v += dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f<0x141>(v);  // row_half_mirror
-  v += dpp_f<0x140>(v);  // row_mirror
-  return (lane_f(v, 0) + lane_f(v, 16)) + (lane_f(v, 32) + lane_f(v, 48));
-}
-template <>
-__device__ __forceinline__ float wave_min<float>(float v) {
-  v = fminf(v, dpp_f<0xB1>(v));
-  v = fminf(v, dpp_f<0x4E>(v));
-  v = fminf(v, dpp_f<0x141>(v));
-  v = fminf(v, dpp_f<0x140>(v));
-  return fminf(fminf(lane_f(v, 0), lane_f(v, 16)), fminf(lane_f(v, 32), lane_f(v, 48)));
-}
-
 // Block-wide reductions in a fixed order (lane tree, then waves in index order).
 template <class R>
 __device__ R block_sum(R v, R* red) {
@@ -339,11 +296,11 @@ struct RolloutArgs {
   const R* V;
   R* S;
   R* eps_out;
-  const float4* obs_pad;  // FP32 with obstacles: [B][NOBS] slots from k_pad_obs (scalar reads)
+  const float4* obs_pad;  // FP32 with obstacles: [B][NOBS] slots from k_pad_obs (WaveObstacles)
 };
 
-// Obstacle slots of every problem for the scalar reads of the FP32 rollouts
-// (ScalarObstacles): (c_x, c_y, r^2, (1 - alpha) ((r + margin)^2 - r^2)) for
+// Obstacle slots of every problem for the FP32 rollouts and adjoint
+// (WaveObstacles): (c_x, c_y, r^2, (1 - alpha) ((r + margin)^2 - r^2)) for
 // the problem's obstacles, the inert slot (0, 0, -1e30, 0) after them, n_slots
 // per problem.  Runs before every launch that reads them, so obstacles the caller
 // moves between launches are seen.  A problem whose obstacle count is out of
@@ -376,20 +333,26 @@ __global__ __launch_bounds__(256) void k_rollout(RolloutArgs<R> a) {
   const TrackView<R> tr = stage_problem(a.p, b, d, a.V, smem, &Vs);
   __syncthreads();
   const int m = m_base + threadIdx.x;
-  if (m >= d.K) return;
+  constexpr bool WV = NOBS > 0 && sizeof(R) == 4;
+  // The wave-level obstacle evaluation needs every lane of a wave: lanes past K
+  // in a wave that has samples run a copy of the last sample and store nothing.
+  if (WV ? (m - (int)(threadIdx.x % WAVE) >= d.K) : (m >= d.K)) return;
+  const bool own = m < d.K;
+  const int mr = own ? m : d.K - 1;
   NoiseStream<R> ns;
   ns.seed = a.p.seed;
-  ns.m = (uint32_t)m;
+  ns.m = (uint32_t)mr;
   ns.pid = (uint32_t)(a.p.pid_base + b);
   ns.it = a.p.iter[b];
   ns.nominal = a.p.nominal != 0;
   const State<R> x0 = load_state(a.p.x0 + 6 * (size_t)b);
-  R* eo = a.eps_out ? a.eps_out + (size_t)(d.k0 + m) * a.p.t_max * 2 : nullptr;
-  if constexpr (NOBS > 0 && sizeof(R) == 4)
-    a.S[d.k0 + m] = rollout_sample<R, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, eo,
-                                            ScalarObstacles{a.obs_pad + (size_t)b * NOBS});
+  R* eo = (a.eps_out && own) ? a.eps_out + (size_t)(d.k0 + m) * a.p.t_max * 2 : nullptr;
+  R s;
+  if constexpr (WV)
+    s = rollout_sample<R, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, eo, WaveObstacles(a.obs_pad + (size_t)b * NOBS, NOBS));
   else
-    a.S[d.k0 + m] = rollout_sample<R, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, eo);
+    s = rollout_sample<R, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, eo);
+  if (own) a.S[d.k0 + m] = s;
 }
 
 // ============================================================== weights
@@ -685,11 +648,13 @@ __host__ __device__ inline size_t adj_lds_bytes(int /*t_max*/, int seg_len) {
 // (descending) calls sink(t, dL/dv_{t,0}, dL/dv_{t,1}); the sink may modify V[t]
 // (the repair does), which is safe because V[t'] for t' >= t is never read again.
 // FP32 with obstacles: `slots` (k_pad_obs) gives the obstacle transitions
-// through the scalar cache (ScalarObstacles::grad) instead of the LDS table.
+// for the whole wave (WaveObstacles::grad) instead of the LDS table.
 template <class R, int NOBS, class Sink>
 __device__ void adjoint_lane(const DevModel<R>& M, const DevCost<R>& C, const DevObjective<R>& ob,
                              const TrackView<R>& tr, const State<R>& x0, R* V, int T, NoiseStream<R>& ns,
                              const AdjLds<R>& L, int seg_len, int lane, Sink& sink, const float4* slots = nullptr) {
+  WaveObstacles wob;  // FP32 with obstacles: this lane's slot, read once
+  if constexpr (NOBS > 0 && sizeof(R) == sizeof(float)) wob = WaveObstacles(slots, NOBS);
   // forward with checkpoints
   State<R> x = x0;
   int idx = tr.idx0;
@@ -728,11 +693,10 @@ __device__ void adjoint_lane(const DevModel<R>& M, const DevCost<R>& C, const De
       const State<R> xn = adj_load(L.sx, L.sxi, t - t0 + 1, lane, in_);
       R gpx = R(0), gpy = R(0);
       if constexpr (NOBS > 0 && sizeof(R) == sizeof(float)) {
-        // track barrier as usual, obstacles from the scalar slots
+        // track barrier as usual, obstacles for the whole wave from the slots
         penalty_grad<R, 0>(C, ob, tr, xp, ip, xn, in_, t, lam, gpx, gpy);
         const R base = ob.w_S * C.C_cbf + ((t < ob.n_lin) ? ob.w_lin : R(0));
-        ScalarObstacles{slots}.template grad<NOBS>(xp.px, xp.py, xn.px, xn.py, C.alpha, base, R(2) * ob.w_sq,
-                                                   lam[0], lam[1], gpx, gpy);
+        wob.grad(xp.px, xp.py, xn.px, xn.py, C.alpha, base, R(2) * ob.w_sq, lam[0], lam[1], gpx, gpy);
       } else {
         penalty_grad<R, NOBS>(C, ob, tr, xp, ip, xn, in_, t, lam, gpx, gpy);
       }
@@ -773,7 +737,7 @@ struct BackwardArgs {
   R* part;            // [B][nblk_max][2][t_max]: per-workgroup partials, summed by k_sum_partials
   uint32_t* valid;    // [B]: 1 when the problem's sizes are valid (written by workgroup 0)
   unsigned char* ck;  // [B][nblk_max] blocks of adj_ck_bytes_per_wg(t_max, seg_len, 6): checkpoints
-  const float4* obs_pad;  // FP32 with obstacles: [B][NOBS] slots from k_pad_obs (scalar reads)
+  const float4* obs_pad;  // FP32 with obstacles: [B][NOBS] slots from k_pad_obs (WaveObstacles)
   int nblk_max;
   int seg_len;
 };

@@ -52,7 +52,7 @@ struct FusedArgs {
   uint32_t* exits;           // [1] workgroups that have left the tile loop
   int repair;                // nonzero: the combining workgroup also runs the shield (and execute)
   RepairArgs<float> rep;
-  const float4* obs_pad;     // [B][kMaxObs] obstacle slots for the scalar reads (NOBS > 0, tile mode)
+  const float4* obs_pad;     // [B][kMaxObs] obstacle slots (WaveObstacles; NOBS > 0, tile mode)
 };
 
 // ---------------------------------------------------------------------------
@@ -332,24 +332,31 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       if (own[0]) a.S[d.k0 + ms[0]] = sv;
       if (isfinite(s[0])) mn = s[0];
     } else {
+      // (with obstacles every lane of a wave that has samples runs: the wave-level
+      // obstacle evaluation needs the whole wave; lanes past K copy the last sample)
+      const WaveObstacles wob = NOBS > 0 ? WaveObstacles(a.obs_pad + (size_t)b * NOBS, NOBS) : WaveObstacles();
 #pragma unroll
       for (int j = 0; j < SPT; ++j) {
         ms[j] = kb * a.tile + j * BLK + tid;
         own[j] = ms[j] < d.K;
         s[j] = INFINITY;
-        if (own[j]) {
+        const bool run = NOBS > 0 ? (ms[j] - (int)(tid % WAVE) < d.K) : own[j];
+        if (run) {
           NoiseStream<float> ns;
           ns.seed = a.p.seed;
-          ns.m = (uint32_t)ms[j];
+          ns.m = (uint32_t)(own[j] ? ms[j] : d.K - 1);
           ns.pid = pid;
           ns.it = it;
           ns.nominal = a.p.nominal != 0;
+          float sv;
           if constexpr (NOBS > 0)
-            s[j] = rollout_sample<float, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, nullptr,
-                                               ScalarObstacles{a.obs_pad + (size_t)b * NOBS});
+            sv = rollout_sample<float, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, nullptr, wob);
           else
-            s[j] = rollout_sample<float, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, nullptr);
-          a.S[d.k0 + ms[j]] = s[j];
+            sv = rollout_sample<float, NOBS>(a.M, a.C, tr, x0, Vs, d.T, ns, nullptr);
+          if (own[j]) {
+            s[j] = sv;
+            a.S[d.k0 + ms[j]] = sv;
+          }
         }
         if (isfinite(s[j])) mn = fminf(mn, s[j]);
       }
@@ -797,7 +804,7 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
     return bail(hip_fail(ctx, e, "hipMemcpy(tile_off)"));
   if ((e = hipMemset(p->counters, 0, sizeof(uint32_t) * (B + 2))) != hipSuccess)
     return bail(hip_fail(ctx, e, "hipMemset(counters)"));
-  // tile mode with obstacles reads them through the scalar cache from padded slots
+  // tile mode with obstacles reads them from padded slots (one per lane of each wave)
   if (!pipe && obs_slots(track) > 0 &&
       (e = hipMalloc(&p->obs_pad, sizeof(float4) * (size_t)B * kMaxObs)) != hipSuccess)
     return bail(hip_fail(ctx, e, "hipMalloc(obs_pad)"));

@@ -357,7 +357,7 @@ static smppi_status launch_rollout(smppi_ctx ctx, const smppi_batch* b, const Ro
   RolloutArgs<R> ra = a;
   ra.obs_pad = nullptr;
   if (NOBS > 0 && sizeof(R) == 4) {
-    // FP32 obstacles go through the scalar cache from padded slots in the scratch buffer
+    // FP32 obstacles are evaluated per wave from padded slots in the scratch buffer
     smppi_status st = need_scratch(ctx, sizeof(float4) * (size_t)b->n_problems * NOBS, 0, "smppi_rollout");
     if (st) return st;
     float4* pad = static_cast<float4*>(ctx->scratch);
@@ -736,7 +736,7 @@ static smppi_status backward_launch(smppi_ctx ctx, const smppi_batch* b, const s
   a.obs_pad = nullptr;
   smppi_status st;
   if (t->obs_max > 0 && sizeof(R) == sizeof(float)) {
-    // FP32 obstacles through the scalar cache, from padded slots (as the rollout)
+    // FP32 obstacles per wave, from padded slots (as the rollout)
     float4* pad = reinterpret_cast<float4*>(static_cast<unsigned char*>(scratch) + as.pad_off);
     hipLaunchKernelGGL(k_pad_obs, dim3(b->n_problems), dim3(64), 0, s, a.p.obs_off,
                        reinterpret_cast<const float*>(a.p.obs), a.p.obs_max, kMaxObs, (float)a.C.alpha, pad);
