@@ -539,6 +539,34 @@ __device__ __forceinline__ float wave_max<float>(float v) {
   return fmaxf(fmaxf(lane_f(v, 0), lane_f(v, 16)), fmaxf(lane_f(v, 32), lane_f(v, 48)));
 }
 
+// Unsigned minimum / maximum over a wave, in every lane (the whole wave active):
+// four DPP row rotations, then a scalar combine of the four rows.
+__device__ __forceinline__ unsigned wave_min_u32(unsigned m) {
+  m = min(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x128, 0xF, 0xF, false));  // row_ror:8
+  m = min(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x124, 0xF, 0xF, false));  // row_ror:4
+  m = min(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x122, 0xF, 0xF, false));  // row_ror:2
+  m = min(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x121, 0xF, 0xF, false));  // row_ror:1
+  const unsigned r0 = (unsigned)__builtin_amdgcn_readlane((int)m, 0), r1 = (unsigned)__builtin_amdgcn_readlane((int)m, 16);
+  const unsigned r2 = (unsigned)__builtin_amdgcn_readlane((int)m, 32), r3 = (unsigned)__builtin_amdgcn_readlane((int)m, 48);
+  return min(min(r0, r1), min(r2, r3));
+}
+__device__ __forceinline__ unsigned wave_max_u32(unsigned m) {
+  m = max(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x128, 0xF, 0xF, false));  // row_ror:8
+  m = max(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x124, 0xF, 0xF, false));  // row_ror:4
+  m = max(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x122, 0xF, 0xF, false));  // row_ror:2
+  m = max(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x121, 0xF, 0xF, false));  // row_ror:1
+  const unsigned r0 = (unsigned)__builtin_amdgcn_readlane((int)m, 0), r1 = (unsigned)__builtin_amdgcn_readlane((int)m, 16);
+  const unsigned r2 = (unsigned)__builtin_amdgcn_readlane((int)m, 32), r3 = (unsigned)__builtin_amdgcn_readlane((int)m, 48);
+  return max(max(r0, r1), max(r2, r3));
+}
+// Order-preserving map between FP32 values (not NaN) and unsigned keys: the sign
+// bit set for non-negative values, all bits flipped for negative ones.
+__device__ __forceinline__ unsigned f32_key(float f) {
+  const unsigned b = __float_as_uint(f);
+  return b ^ ((unsigned)((int)b >> 31) | 0x80000000u);
+}
+__device__ __forceinline__ float key_f32(unsigned k) { return __uint_as_float(k ^ (((k >> 31) - 1u) | 0x80000000u)); }
+
 // WaveObstacles: the FP32 obstacle barriers of a whole wave of samples of one
 // problem.  The table holds one slot per obstacle, (c_x, c_y, r^2, kappa) with
 // kappa = (1 - alpha) ((r + margin)^2 - r^2), unused slots inert
@@ -571,16 +599,20 @@ struct WaveObstacles {
 
   // Obstacles that may contribute to the transition p -> q of some lane (bit i).
   __device__ __forceinline__ uint64_t live(float ppx, float ppy, float qpx, float qpy, float alpha) const {
-    const float lox = wave_min(qpx), hix = wave_max(qpx);
-    const float loy = wave_min(qpy), hiy = wave_max(qpy);
+    // box of the q's and the largest squared step, by integer reductions of
+    // order-preserving keys (a NaN coordinate widens the box or the step, which
+    // only keeps more obstacles)
+    const float lox = key_f32(wave_min_u32(f32_key(qpx))), hix = key_f32(wave_max_u32(f32_key(qpx)));
+    const float loy = key_f32(wave_min_u32(f32_key(qpy))), hiy = key_f32(wave_max_u32(f32_key(qpy)));
     const float dsx = qpx - ppx, dsy = qpy - ppy;
-    const float s2 = wave_max(fmaf(dsx, dsx, dsy * dsy));
+    const float s2 = __uint_as_float(wave_max_u32(__float_as_uint(fmaf(dsx, dsx, dsy * dsy))));
     // lower bound of the distance from obstacle `lane` to any q, upper bound of
-    // any step (a relative 2^-20 and 1e-6 absolute cover the FP32 rounding)
+    // any step (a relative 2^-20 and 1e-6 absolute cover the FP32 rounding and
+    // the hardware square root's error)
     const float ex = fmaxf(fmaxf(lox - mine.x, mine.x - hix), 0.f);
     const float ey = fmaxf(fmaxf(loy - mine.y, mine.y - hiy), 0.f);
-    const float A = sqrtf(fmaf(ex, ex, ey * ey)) * (1.f - 0x1p-20f);
-    const float S = sqrtf(s2) * (1.f + 0x1p-20f) + 1e-6f;
+    const float A = __builtin_amdgcn_sqrtf(fmaf(ex, ex, ey * ey)) * (1.f - 0x1p-20f);
+    const float S = __builtin_amdgcn_sqrtf(s2) * (1.f + 0x1p-20f) + 1e-6f;
     const float om = 1.f - alpha;
     const float F = fmaf(-om * A, A, fmaf(2.f * alpha * S, A, fmaf(alpha * S, S, fmaf(om, mine.z, mine.w))));
     const float AS = A + S;

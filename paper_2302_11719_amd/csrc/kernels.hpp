@@ -68,15 +68,6 @@ __device__ __forceinline__ bool load_dims(const ProblemArgs<R>& a, int b, Proble
 // so their bit patterns order like their values; two integer minima (distance,
 // then the index among the lanes holding it), each four DPP row rotations and
 // a scalar minimum over the four rows.
-__device__ __forceinline__ unsigned wave_min_u32(unsigned m) {
-  m = min(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x128, 0xF, 0xF, false));  // row_ror:8
-  m = min(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x124, 0xF, 0xF, false));  // row_ror:4
-  m = min(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x122, 0xF, 0xF, false));  // row_ror:2
-  m = min(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x121, 0xF, 0xF, false));  // row_ror:1
-  const unsigned r0 = (unsigned)__builtin_amdgcn_readlane((int)m, 0), r1 = (unsigned)__builtin_amdgcn_readlane((int)m, 16);
-  const unsigned r2 = (unsigned)__builtin_amdgcn_readlane((int)m, 32), r3 = (unsigned)__builtin_amdgcn_readlane((int)m, 48);
-  return min(min(r0, r1), min(r2, r3));
-}
 template <class R>
 __device__ __forceinline__ void wave_argmin(R& bd, int& bi) {
 #pragma unroll
