@@ -209,7 +209,10 @@ smppi_status smppi_reserve_batch(smppi_ctx ctx, const smppi_batch* batch);
  * kernels detected on device data since the last call: 1 = some T_b outside
  * [1, t_max], 2 = some K_b outside [0, k_max], 4 = some polyline longer than
  * poly_max or shorter than 2*window+1, 8 = more than obs_max obstacles.
- * Problems with such data are skipped (their outputs are left unwritten). */
+ * Problems with such data are skipped (their outputs are left unwritten).
+ * 16 = a wave of the shield gave up waiting for another wave of its workgroup
+ * (a bounded wait that correct inputs never exhaust; that problem's V_safe is
+ * then invalid). */
 smppi_status smppi_device_errors(smppi_ctx ctx, uint32_t* flags);
 
 /* ---- the sampled-rollout step ---------------------------------------------- */
