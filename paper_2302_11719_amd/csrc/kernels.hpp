@@ -948,9 +948,11 @@ constexpr int REP_CTL = 8;
 // gradient, the two-loop vector, memory + 1 pair slots (s, y) of 2 t_max
 // values, four scalars per slot and a reduction buffer.
 template <class R>
-__host__ __device__ inline size_t repair_lds_bytes(int t_max, int memory, bool par_rev = false) {
+__host__ __device__ inline size_t repair_lds_bytes(int t_max, int memory, bool par_rev, bool stepwise) {
+  // stage velocities: every step for the step-by-step hand-over, else a ring of two chunks
+  const size_t vst_rows = stepwise ? (size_t)t_max : (size_t)2 * REP_C;
   size_t n = (size_t)(t_max + 1) * (6 * sizeof(R) + sizeof(int)) + (size_t)REP_CTL * t_max * sizeof(R) +
-             (size_t)12 * t_max * sizeof(R) + 16;
+             (size_t)12 * vst_rows * sizeof(R) + 16;
   if (memory > 0) n += ((size_t)(4 + 2 * (memory + 1)) * 2 * t_max + 4 * (memory + 1) + 16) * sizeof(R);
   if (par_rev) n += (size_t)REP_PAR_PER_STEP * t_max * sizeof(R);
   return n;
@@ -1298,11 +1300,12 @@ __device__ __forceinline__ void wave_wait(const int* c, int t, int& seen, uint32
 // entry and V_safe on exit; tr is the staged problem; `lds` is
 // repair_lds_bytes of LDS.  Per iteration: every thread computes the control
 // constants of its share of the steps; then a pipeline over the steps: wave 0
-// runs the velocity part of the RK4 chain on one lane and publishes each step
-// (a counter in LDS), wave 2 runs the pose part on one lane as the steps
-// arrive and publishes them in turn, and wave 1 evaluates the window (one
-// segment per lane), the obstacles (one per lane) and the barrier activity of
-// each published position.  The reverse sweep starts at the last active transition, and the
+// runs the velocity part of the RK4 chain on one lane, wave 2 the pose part on
+// one lane, and wave 1 evaluates the window (one segment per lane), the
+// obstacles (one per lane) and the barrier activity of each new position.  With
+// VG the waves hand over step by step through LDS step counters; without (the
+// workgroup shares its compute unit with rollout tiles), chunk by chunk of
+// REP_C steps between workgroup barriers.  The reverse sweep starts at the last active transition, and the
 // iteration loop stops when no transition is active (zero gradient).
 // VG: model and cost constants in VGPRs (kernels whose occupancy does not
 // depend on the VGPR count: the shield kernel, the latency-mode fused kernel).
@@ -1310,12 +1313,13 @@ template <class R, int NOBS, bool VG = true>
 __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims& d, const TrackView<R>& tr, R* Vs,
                                unsigned char* lds, int* s_last) {
   // 16-byte aligned rows first (lds is 16-byte aligned): ctl [t_max][REP_CTL],
-  // vst [t_max][12] stage velocities, 16 bytes of step counters; then states
-  // xs [t_max+1][6], segment indices is [t_max+1]
+  // vst stage velocities ([t_max][12] with VG, else a ring [2][REP_C][12]), 16
+  // bytes of step counters; then states xs [t_max+1][6], segment indices is
+  // [t_max+1]
   R* ctl = static_cast<R*>(__builtin_assume_aligned(reinterpret_cast<R*>(lds), 16));
   R* vst = static_cast<R*>(__builtin_assume_aligned(ctl + REP_CTL * (size_t)a.p.t_max, 16));
   // steps published by the velocity wave [0] and the pose wave [1] (16 bytes)
-  int* flg = reinterpret_cast<int*>(vst + 12 * (size_t)a.p.t_max);
+  int* flg = reinterpret_cast<int*>(vst + 12 * (size_t)(VG ? a.p.t_max : 2 * REP_C));
   R* xs = reinterpret_cast<R*>(flg + 4);
   int* is = reinterpret_cast<int*>(xs + 6 * (size_t)(a.p.t_max + 1));
   // L-BFGS state (memory > 0): gradient, previous iterate and gradient, two-loop
@@ -1347,7 +1351,7 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
   const DevCost<R>& C = VG ? Cv : a.C;
   const DevObjective<R>& ob = a.ob;
   const bool cost_terms = ob.w_S != R(0);
-  const int T = d.T;
+  const int T = d.T, nch = (T + REP_C - 1) / REP_C;
   const State<R> x0 = load_state(a.p.x0 + 6 * (size_t)b);
   // segment and offset at x0 do not change over the iterations
   const int idx0 = tr.idx0;
@@ -1401,95 +1405,192 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
       }
       if (act && (ob.w_sq != R(0) || (ob.w_lin != R(0) && t < ob.n_lin))) last = t;
     };
-    __syncthreads();
-    if (w == 0 && lane == 0) {
-      // velocity wave: the RK4 chain of (v_x, v_y, omega), publishing each step
-      for (int t0 = 0; t0 < T; t0 += REP_C) {
-        const int t1 = min(T, t0 + REP_C);
-        // the chunk's control rows are read before its first store: LDS
-        // returns in order, so a row read after a step's stores would wait for
-        // them inside the RK4 chain
-        R cc[REP_C][5];
-#pragma unroll
-        for (int k = 0; k < REP_C; ++k) {
-          const R* cr = static_cast<const R*>(__builtin_assume_aligned(ctl + REP_CTL * min(t0 + k, t1 - 1), 16));
-#pragma unroll
-          for (int c = 0; c < 5; ++c) cc[k][c] = cr[c];
+    if constexpr (VG) {
+      // (kernels with one workgroup per compute unit: the shield kernel, the
+      // latency-mode plan) step by step through the LDS step counters
+      __syncthreads();
+      if (w == 0 && lane == 0) {
+        // velocity wave: the RK4 chain of (v_x, v_y, omega), publishing each step
+        for (int t0 = 0; t0 < T; t0 += REP_C) {
+          const int t1 = min(T, t0 + REP_C);
+          // the chunk's control rows are read before its first store: LDS
+          // returns in order, so a row read after a step's stores would wait for
+          // them inside the RK4 chain
+          R cc[REP_C][5];
+  #pragma unroll
+          for (int k = 0; k < REP_C; ++k) {
+            const R* cr = static_cast<const R*>(__builtin_assume_aligned(ctl + REP_CTL * min(t0 + k, t1 - 1), 16));
+  #pragma unroll
+            for (int c = 0; c < 5; ++c) cc[k][c] = cr[c];
+          }
+  #pragma unroll
+          for (int j = 0; j < REP_C; ++j) {
+            const int t = t0 + j;
+            if (t >= t1) break;
+            StepCtl<R> sc;
+            sc.delta = cc[j][0];
+            sc.sd_m = cc[j][1];
+            sc.cd_m = cc[j][2];
+            sc.lfcd_Iz = cc[j][3];
+            sc.a_tau = cc[j][4];
+            sc.sd = sc.cd = R(0);  // used by the reverse sweep only
+            VelStages<R> g;
+            rk4_vel(M, sc, x.vx, x.vy, x.om, g);
+            R* gt = static_cast<R*>(__builtin_assume_aligned(vst + 12 * (size_t)t, 16));
+  #pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              gt[q] = g.vx[q];
+              gt[4 + q] = g.vy[q];
+              gt[8 + q] = g.om[q];
+            }
+            R* o = xs + 6 * (t + 1);
+            o[3] = x.vx; o[4] = x.vy; o[5] = x.om;
+            __hip_atomic_store(flg, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
         }
-#pragma unroll
-        for (int j = 0; j < REP_C; ++j) {
-          const int t = t0 + j;
-          if (t >= t1) break;
-          StepCtl<R> sc;
-          sc.delta = cc[j][0];
-          sc.sd_m = cc[j][1];
-          sc.cd_m = cc[j][2];
-          sc.lfcd_Iz = cc[j][3];
-          sc.a_tau = cc[j][4];
-          sc.sd = sc.cd = R(0);  // used by the reverse sweep only
+      } else if (w == 2 && lane == 0) {
+        // pose wave: (p_x, p_y, psi) from the stage velocities, step by step as
+        // they are published
+        int seen = 0;
+        for (int t = 0; t < T; ++t) {
+          wave_wait(flg, t, seen, a.p.err);
+          const R* gt = static_cast<const R*>(__builtin_assume_aligned(vst + 12 * (size_t)t, 16));
           VelStages<R> g;
-          rk4_vel(M, sc, x.vx, x.vy, x.om, g);
-          R* gt = static_cast<R*>(__builtin_assume_aligned(vst + 12 * (size_t)t, 16));
-#pragma unroll
+  #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            gt[q] = g.vx[q];
-            gt[4 + q] = g.vy[q];
-            gt[8 + q] = g.om[q];
+            g.vx[q] = gt[q];
+            g.vy[q] = gt[4 + q];
+            g.om[q] = gt[8 + q];
           }
+          rk4_pose(M, g, x.px, x.py, x.psi);
           R* o = xs + 6 * (t + 1);
-          o[3] = x.vx; o[4] = x.vy; o[5] = x.om;
-          __hip_atomic_store(flg, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          o[0] = x.px; o[1] = x.py; o[2] = x.psi;
+          __hip_atomic_store(flg + 1, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      } else if (w == 1) {
+        // window wave: e_y^2, obstacle barriers and activity of each new position.
+        // A chunk's segment indices collect on lanes 0 .. REP_C-1 and are stored
+        // once after the chunk (a store on every step made the next step wait for
+        // it, inside the chain through idx).
+        int seen = 0;
+        for (int t0 = 0; t0 < T; t0 += REP_C) {
+          const int t1 = min(T, t0 + REP_C);
+          int ic = 0;
+          auto chunk = [&](auto track_e2) {
+            for (int t = t0; t < t1; ++t) {
+              wave_wait(flg + 1, t, seen, a.p.err);
+              const R px = xs[6 * (t + 1)], py = xs[6 * (t + 1) + 1];
+              const R e2 = track_e2(px, py);
+              ic = lane == t - t0 ? idx : ic;
+              transition(t, px, py, e2);
+            }
+          };
+          // window segments on the lanes of a row, min by DPP (no LDS round trip
+          // on the chain through idx); wider windows: one lane, sequential rule
+          if (tr.n == 0)
+            chunk([&](R px, R py) { return circle_e2(tr, px, py); });
+          else if (tr.window <= 7)
+            chunk([&](R px, R py) { return row_window(tr, idx, px, py); });
+          else
+            chunk([&](R px, R py) { return window_min(tr, idx, px, py); });
+          if (lane < t1 - t0) is[t0 + 1 + lane] = ic;
         }
       }
-    } else if (w == 2 && lane == 0) {
-      // pose wave: (p_x, p_y, psi) from the stage velocities, step by step as
-      // they are published
-      int seen = 0;
-      for (int t = 0; t < T; ++t) {
-        wave_wait(flg, t, seen, a.p.err);
-        const R* gt = static_cast<const R*>(__builtin_assume_aligned(vst + 12 * (size_t)t, 16));
-        VelStages<R> g;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          g.vx[q] = gt[q];
-          g.vy[q] = gt[4 + q];
-          g.om[q] = gt[8 + q];
-        }
-        rk4_pose(M, g, x.px, x.py, x.psi);
-        R* o = xs + 6 * (t + 1);
-        o[0] = x.px; o[1] = x.py; o[2] = x.psi;
-        __hip_atomic_store(flg + 1, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
-    } else if (w == 1) {
-      // window wave: e_y^2, obstacle barriers and activity of each new position.
-      // A chunk's segment indices collect on lanes 0 .. REP_C-1 and are stored
-      // once after the chunk (a store on every step made the next step wait for
-      // it, inside the chain through idx).
-      int seen = 0;
-      for (int t0 = 0; t0 < T; t0 += REP_C) {
-        const int t1 = min(T, t0 + REP_C);
-        int ic = 0;
-        auto chunk = [&](auto track_e2) {
-          for (int t = t0; t < t1; ++t) {
-            wave_wait(flg + 1, t, seen, a.p.err);
-            const R px = xs[6 * (t + 1)], py = xs[6 * (t + 1) + 1];
-            const R e2 = track_e2(px, py);
-            ic = lane == t - t0 ? idx : ic;
-            transition(t, px, py, e2);
+      __syncthreads();
+    } else {
+      // (workgroups that share their compute unit with rollout tiles) chunk by
+      // chunk between workgroup barriers: waiting waves then sit in the
+      // barrier instead of polling (measured faster there)
+      __syncthreads();
+      for (int st = 0; st <= nch + 1; ++st) {
+        if (w == 0 && lane == 0 && st < nch) {
+          const int t0 = st * REP_C, t1 = min(T, t0 + REP_C);
+          R* gb = vst + (st & 1) * (REP_C * 12);
+          // the chunk's control rows are read before its first store: LDS
+          // returns in order, so a row read after a step's stores would wait for
+          // them inside the RK4 chain
+          R cc[REP_C][5];
+  #pragma unroll
+          for (int k = 0; k < REP_C; ++k) {
+            const R* cr = static_cast<const R*>(__builtin_assume_aligned(ctl + REP_CTL * min(t0 + k, t1 - 1), 16));
+  #pragma unroll
+            for (int c = 0; c < 5; ++c) cc[k][c] = cr[c];
           }
-        };
-        // window segments on the lanes of a row, min by DPP (no LDS round trip
-        // on the chain through idx); wider windows: one lane, sequential rule
-        if (tr.n == 0)
-          chunk([&](R px, R py) { return circle_e2(tr, px, py); });
-        else if (tr.window <= 7)
-          chunk([&](R px, R py) { return row_window(tr, idx, px, py); });
-        else
-          chunk([&](R px, R py) { return window_min(tr, idx, px, py); });
-        if (lane < t1 - t0) is[t0 + 1 + lane] = ic;
+  #pragma unroll
+          for (int j = 0; j < REP_C; ++j) {
+            const int t = t0 + j;
+            if (t >= t1) break;
+            StepCtl<R> sc;
+            sc.delta = cc[j][0];
+            sc.sd_m = cc[j][1];
+            sc.cd_m = cc[j][2];
+            sc.lfcd_Iz = cc[j][3];
+            sc.a_tau = cc[j][4];
+            sc.sd = sc.cd = R(0);  // used by the reverse sweep only
+            VelStages<R> g;
+            rk4_vel(M, sc, x.vx, x.vy, x.om, g);
+            R* gt = static_cast<R*>(__builtin_assume_aligned(gb + 12 * (t - t0), 16));
+  #pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              gt[k] = g.vx[k];
+              gt[4 + k] = g.vy[k];
+              gt[8 + k] = g.om[k];
+            }
+            R* o = xs + 6 * (t + 1);
+            o[3] = x.vx; o[4] = x.vy; o[5] = x.om;
+          }
+        } else if (w == 2 && lane == 0 && st >= 1 && st <= nch) {
+          const int t0 = (st - 1) * REP_C, t1 = min(T, t0 + REP_C);
+          const R* gb = vst + ((st - 1) & 1) * (REP_C * 12);
+          // the chunk's stage velocities are read before its first store (as
+          // the control rows in the velocity wave)
+          VelStages<R> gc[REP_C];
+  #pragma unroll
+          for (int j = 0; j < REP_C; ++j) {
+            const R* gt = static_cast<const R*>(__builtin_assume_aligned(gb + 12 * min(j, t1 - t0 - 1), 16));
+  #pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              gc[j].vx[k] = gt[k];
+              gc[j].vy[k] = gt[4 + k];
+              gc[j].om[k] = gt[8 + k];
+            }
+          }
+  #pragma unroll
+          for (int j = 0; j < REP_C; ++j) {
+            const int t = t0 + j;
+            if (t >= t1) break;
+            rk4_pose(M, gc[j], x.px, x.py, x.psi);
+            R* o = xs + 6 * (t + 1);
+            o[0] = x.px; o[1] = x.py; o[2] = x.psi;
+          }
+        } else if (w == 1 && st >= 2) {
+          const int t0 = (st - 2) * REP_C, t1 = min(T, t0 + REP_C);
+          // The chunk's segment indices collect on lanes 0 .. REP_C-1 and are
+          // stored once after the chunk (a store on every step made the next
+          // step wait for it, inside the chain through idx).  The kind of window
+          // is chosen once, outside the step loop.
+          int ic = 0;
+          auto chunk = [&](auto track_e2) {
+            for (int t = t0; t < t1; ++t) {
+              const R px = xs[6 * (t + 1)], py = xs[6 * (t + 1) + 1];
+              const R e2 = track_e2(px, py);
+              ic = lane == t - t0 ? idx : ic;
+              transition(t, px, py, e2);
+            }
+          };
+          // window segments on the lanes of a row, min by DPP (no LDS round trip
+          // on the chain through idx); wider windows: one lane, sequential rule
+          if (tr.n == 0)
+            chunk([&](R px, R py) { return circle_e2(tr, px, py); });
+          else if (tr.window <= 7)
+            chunk([&](R px, R py) { return row_window(tr, idx, px, py); });
+          else
+            chunk([&](R px, R py) { return window_min(tr, idx, px, py); });
+          if (lane < t1 - t0) is[t0 + 1 + lane] = ic;
+        }
+        __syncthreads();
       }
     }
-    __syncthreads();
     if (w == 1 && lane == 0) *s_last = last;
     __syncthreads();
     const int t_end = cost_terms ? T - 1 : *s_last;

@@ -847,7 +847,7 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
     hipFuncAttributes fa2{};
     if ((e = hipFuncGetAttributes(&fa2, reinterpret_cast<const void*>(fn_f))) != hipSuccess)
       return bail(hip_fail(ctx, e, "hipFuncGetAttributes"));
-    if (fa2.sharedSizeBytes + p->lds + repair_lds_bytes<float>(batch->t_max, mem) <= (size_t)ctx->max_lds) {
+    if (fa2.sharedSizeBytes + p->lds + repair_lds_bytes<float>(batch->t_max, mem, false, pipe) <= (size_t)ctx->max_lds) {
       fn = fn_f;
       p->fn = fn;
       lds_static = fa2.sharedSizeBytes;
@@ -860,8 +860,8 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
     a.rep = repair_args<float>(ctx, &p->batch, model, cost, &p->track, bufs->x0, bufs->V_plus, &opts->repair_opts,
                                bufs->V_safe, opts->execute ? &ef : nullptr);
     // the parallel reverse sweep only when its tables fit beside the fused kernel's LDS
-    a.rep.par_rev = lds_static + p->lds + repair_lds_bytes<float>(batch->t_max, mem, true) <= (size_t)ctx->max_lds;
-    p->lds += (int)repair_lds_bytes<float>(batch->t_max, mem, a.rep.par_rev != 0);
+    a.rep.par_rev = lds_static + p->lds + repair_lds_bytes<float>(batch->t_max, mem, true, pipe) <= (size_t)ctx->max_lds;
+    p->lds += (int)repair_lds_bytes<float>(batch->t_max, mem, a.rep.par_rev != 0, pipe);
   }
   p->fused_shield = a.repair != 0;
   int per_cu = 0;

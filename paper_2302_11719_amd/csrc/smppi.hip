@@ -878,7 +878,7 @@ template <class R, int NOBS>
 static smppi_status launch_repair(smppi_ctx ctx, const smppi_batch* b, const RepairArgs<R>& a, hipStream_t s,
                                   hipEvent_t e0, hipEvent_t e1) {
   const size_t lds = stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max) +
-                     repair_lds_bytes<R>(a.p.t_max, a.memory, a.par_rev != 0);
+                     repair_lds_bytes<R>(a.p.t_max, a.memory, a.par_rev != 0, true);
   if (lds > (size_t)ctx->max_lds)
     return fail(ctx, SMPPI_ERR_SHAPE, "repair needs %zu B of LDS per workgroup (device max %d)", lds, ctx->max_lds);
   if (e0 && e1)  // events stamped with the kernel's own start and end
@@ -906,7 +906,7 @@ RepairArgs<R> smppi::repair_args(smppi_ctx ctx, const smppi_batch* b, const smpp
   a.memory = o->method == 1 ? o->memory : 0;
   // the parallel reverse sweep when its per-step Jacobians fit in LDS
   a.par_rev = stage_lds_bytes<R>(a.p.poly_max, a.p.t_max, a.p.obs_max) +
-                      repair_lds_bytes<R>(a.p.t_max, a.memory, true) <=
+                      repair_lds_bytes<R>(a.p.t_max, a.memory, true, true) <=
                   (size_t)ctx->max_lds;
   a.exec = ex != nullptr;
   a.ex = ExecuteArgs<R>{};
