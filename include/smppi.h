@@ -289,8 +289,9 @@ smppi_status smppi_update(smppi_ctx ctx, const smppi_batch* batch, const smppi_m
 
 /* Adjoint rollout: grad_V = sum_m grad_S[m] dL_m/dV for the objective above,
  * where sample m's trajectory uses the same noise as smppi_rollout.  States are
- * recomputed from per-sample checkpoints (every ceil(sqrt(t_max)) steps, in the
- * ctx scratch) instead of being stored.  Every 64 samples write a partial; a second small kernel adds them in a fixed order
+ * recomputed from per-sample checkpoints (every min(ceil(sqrt(t_max)), 12)
+ * steps, in the ctx scratch, with each step's window segment) instead of being
+ * stored.  Every 64 samples write a partial; a second small kernel adds them in a fixed order
  * (the result does not depend on scheduling).  grad_V has the
  * layout of V (dtype).  Gradients pass through the clip where it is inactive and
  * through the hinge where it is active (one-sided at ties). */
@@ -307,10 +308,10 @@ smppi_status smppi_rollout_backward(smppi_ctx ctx, const smppi_batch* batch, con
  * GPU holds for the life of the process (looked up at smppi_create), so no
  * smppi_reserve_batch is needed and nothing is allocated.  Limits: at most 4096
  * ticket counters (B x ceil(2 t_max / 64)) and at most 64 MiB of partials,
- * slice sums and per-lane checkpoints (about dtype bytes x B x n x (2 t_max +
- * 9 t_max / ceil(sqrt(t_max))) + 4 B, n = ceil(k_max / 64); K = 65536 at
- * T = 100 needs about 19 MB), else SMPPI_ERR_SHAPE before anything is
- * enqueued.  Every call on a
+ * slice sums, per-lane checkpoints and window indices (about B x n x (2 t_max x
+ * dtype bytes + 64 x (ceil(t_max / s) x (8 dtype bytes + 4) + 4 t_max)) bytes,
+ * n = ceil(k_max / 64), s = min(ceil(sqrt(t_max)), 12); K = 65536 at T = 100
+ * needs about 51 MB), else SMPPI_ERR_SHAPE before anything is enqueued.  Every call on a
  * GPU shares that GPU's array (the counters are cleared by a kernel at the
  * start of each call): calls that overlap on one GPU, from any ctx or thread,
  * race and must be ordered by the caller. */

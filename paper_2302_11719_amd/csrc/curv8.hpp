@@ -517,7 +517,7 @@ __global__ __launch_bounds__(WAVE) void k_backward_c8(C8BackwardArgs<R> g) {
   const CurvView<R> cv = c8_stage(a, b, d, reinterpret_cast<R*>(smem), &Vs);
   R* sx = reinterpret_cast<R*>(smem + c8_stage_bytes<R>(a.n_max, a.t_max));
   R* ck = reinterpret_cast<R*>(g.ck + ((size_t)b * g.nblk_max + blockIdx.x) *
-                                          adj_ck_bytes_per_wg<R>(a.t_max, g.seg_len, 8));
+                                          adj_ck_bytes_per_wg<R>(a.t_max, g.seg_len, 8, false));
   __syncthreads();
   const int lane = threadIdx.x;
   const int m = blockIdx.x * WAVE + lane;

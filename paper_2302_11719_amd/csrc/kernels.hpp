@@ -594,17 +594,23 @@ template <class R>
 struct AdjLds {
   R* ck;      // global [n_ck][6][64]
   int* cki;   // global [n_ck][64]
+  int* sti;   // global [t_max][64]: window segment of x_{t+1}, from the forward pass
   R* sx;      // LDS [seg_len+1][6][64]
   int* sxi;   // LDS [seg_len+1][64]
 };
 
 // Global checkpoint storage of the adjoint: per (problem, workgroup) n_ck slots
-// of `comp` values and one index per lane.
+// of `comp` values and one index per lane, and with step_idx the window
+// segment of every step per lane (the recomputation then skips the window
+// search).
 template <class R>
-__host__ __device__ inline size_t adj_ck_bytes_per_wg(int t_max, int seg_len, int comp) {
+__host__ __device__ inline size_t adj_ck_bytes_per_wg(int t_max, int seg_len, int comp, bool step_idx) {
   const int n_ck = (t_max + seg_len - 1) / seg_len;
-  return (size_t)n_ck * WAVE * (comp * sizeof(R) + sizeof(int));
+  return (size_t)n_ck * WAVE * (comp * sizeof(R) + sizeof(int)) + (step_idx ? (size_t)t_max * WAVE * sizeof(int) : 0);
 }
+// Longest checkpoint segment (the recomputation copies a segment's stored
+// window indices through registers).
+constexpr int ADJ_SEG_MAX = 12;
 
 template <class R>
 __device__ __forceinline__ void adj_store(R* base, int* ibase, int slot, int lane, const State<R>& x, int idx) {
@@ -616,6 +622,16 @@ __device__ __forceinline__ void adj_store(R* base, int* ibase, int slot, int lan
   p[4 * WAVE] = x.vy;
   p[5 * WAVE] = x.om;
   ibase[slot * WAVE + lane] = idx;
+}
+template <class R>
+__device__ __forceinline__ void adj_store_state(R* base, int slot, int lane, const State<R>& x) {
+  R* p = base + (size_t)slot * 6 * WAVE + lane;
+  p[0 * WAVE] = x.px;
+  p[1 * WAVE] = x.py;
+  p[2 * WAVE] = x.psi;
+  p[3 * WAVE] = x.vx;
+  p[4 * WAVE] = x.vy;
+  p[5 * WAVE] = x.om;
 }
 template <class R>
 __device__ __forceinline__ State<R> adj_load(const R* base, const int* ibase, int slot, int lane, int& idx) {
@@ -659,6 +675,7 @@ __device__ void adjoint_lane(const DevModel<R>& M, const DevCost<R>& C, const De
     const R u1 = clamp_r(V[T + t] + e1, M.u_lo[1], M.u_hi[1]);
     rk4(M, step_ctl(M, u0, u1), x);
     (void)lateral_sq(tr, x.px, x.py, idx);
+    L.sti[(size_t)t * WAVE + lane] = idx;
   }
   // terminal cost gradient
   R lam[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
@@ -669,6 +686,13 @@ __device__ void adjoint_lane(const DevModel<R>& M, const DevCost<R>& C, const De
     int ci;
     State<R> xs = adj_load(L.ck, L.cki, c, lane, ci);
     adj_store(L.sx, L.sxi, 0, lane, xs, ci);
+    // the segment's window indices from the forward pass (all loads first)
+    int iv[ADJ_SEG_MAX];
+#pragma unroll
+    for (int k = 0; k < ADJ_SEG_MAX; ++k) iv[k] = k < t1 - t0 ? L.sti[(size_t)(t0 + k) * WAVE + lane] : 0;
+#pragma unroll
+    for (int k = 0; k < ADJ_SEG_MAX; ++k)
+      if (k < t1 - t0) L.sxi[(k + 1) * WAVE + lane] = iv[k];
     for (int t = t0; t < t1; ++t) {
       R e0, e1;
       if (t == t0 || (t & 1) == 0) ns.gen(t);
@@ -676,8 +700,7 @@ __device__ void adjoint_lane(const DevModel<R>& M, const DevCost<R>& C, const De
       const R u0 = clamp_r(V[t] + e0, M.u_lo[0], M.u_hi[0]);
       const R u1 = clamp_r(V[T + t] + e1, M.u_lo[1], M.u_hi[1]);
       rk4(M, step_ctl(M, u0, u1), xs);
-      (void)lateral_sq(tr, xs.px, xs.py, ci);
-      adj_store(L.sx, L.sxi, t - t0 + 1, lane, xs, ci);
+      adj_store_state(L.sx, t - t0 + 1, lane, xs);
     }
     for (int t = t1 - 1; t >= t0; --t) {
       int ip, in_;
@@ -775,9 +798,11 @@ __global__ __launch_bounds__(WAVE) void k_backward(BackwardArgs<R> a) {
   AdjLds<R> L;
   L.sx = reinterpret_cast<R*>(rest);
   L.sxi = reinterpret_cast<int*>(L.sx + (size_t)(a.seg_len + 1) * 6 * WAVE);
-  unsigned char* ckb = a.ck + ((size_t)b * a.nblk_max + blockIdx.x) * adj_ck_bytes_per_wg<R>(a.p.t_max, a.seg_len, 6);
+  unsigned char* ckb =
+      a.ck + ((size_t)b * a.nblk_max + blockIdx.x) * adj_ck_bytes_per_wg<R>(a.p.t_max, a.seg_len, 6, true);
   L.ck = reinterpret_cast<R*>(ckb);
   L.cki = reinterpret_cast<int*>(L.ck + (size_t)n_ck * 6 * WAVE);
+  L.sti = L.cki + (size_t)n_ck * WAVE;
   __syncthreads();
   const int lane = threadIdx.x;
   const int m = blockIdx.x * WAVE + lane;

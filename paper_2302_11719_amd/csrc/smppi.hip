@@ -76,8 +76,10 @@ AdjScratch smppi::adjoint_scratch(const smppi_batch* b) {
   // checkpoints (8 state components covers both models), 256-byte aligned
   const int seg = adj_seg_len(b->t_max);
   a.ck_off = (a.part_bytes + a.slice_bytes + 255) & ~(size_t)255;
-  a.ck_bytes = (size_t)b->n_problems * a.nblk * (a.r == sizeof(float) ? adj_ck_bytes_per_wg<float>(b->t_max, seg, 8)
-                                                                      : adj_ck_bytes_per_wg<double>(b->t_max, seg, 8));
+  // (8 components and the per-step window indices cover both models' layouts)
+  a.ck_bytes = (size_t)b->n_problems * a.nblk *
+               (a.r == sizeof(float) ? adj_ck_bytes_per_wg<float>(b->t_max, seg, 8, true)
+                                     : adj_ck_bytes_per_wg<double>(b->t_max, seg, 8, true));
   // padded obstacle slots of the FP32 adjoint ([B][64] float4), after the checkpoints
   a.pad_off = (a.ck_off + a.ck_bytes + 255) & ~(size_t)255;
   a.pad_bytes = b->dtype == SMPPI_F32 ? sizeof(float4) * (size_t)b->n_problems * kMaxObs : 0;
@@ -260,7 +262,7 @@ template ProblemArgs<float> smppi::problem_args<float>(smppi_ctx, const smppi_ba
 // longer horizons only keep more checkpoints in the global scratch.
 int smppi::adj_seg_len(int t_max) {
   int s = (int)std::ceil(std::sqrt((double)t_max));
-  return s < 1 ? 1 : (s > 12 ? 12 : s);
+  return s < 1 ? 1 : (s > ADJ_SEG_MAX ? ADJ_SEG_MAX : s);
 }
 
 // ------------------------------------------------------------------ context
