@@ -524,20 +524,6 @@ __device__ __forceinline__ float wave_min<float>(float v) {
   v = fminf(v, dpp_f<0x140>(v));
   return fminf(fminf(lane_f(v, 0), lane_f(v, 16)), fminf(lane_f(v, 32), lane_f(v, 48)));
 }
-template <class R>
-__device__ __forceinline__ R wave_max(R v) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
-  return v;
-}
-template <>
-__device__ __forceinline__ float wave_max<float>(float v) {
-  v = fmaxf(v, dpp_f<0xB1>(v));
-  v = fmaxf(v, dpp_f<0x4E>(v));
-  v = fmaxf(v, dpp_f<0x141>(v));
-  v = fmaxf(v, dpp_f<0x140>(v));
-  return fmaxf(fmaxf(lane_f(v, 0), lane_f(v, 16)), fmaxf(lane_f(v, 32), lane_f(v, 48)));
-}
 
 // Unsigned minimum / maximum over a wave, in every lane (the whole wave active):
 // four DPP row rotations, then a scalar combine of the four rows.
