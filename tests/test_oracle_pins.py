@@ -334,6 +334,32 @@ def test_hand_computed_obstacle_and_start_outside_costs():
     assert np.allclose(hs[:, 1], [-0.1125, 0.0475, 0.5275], atol=1e-12)
 
 
+def test_circle_straight_line_cost_closed_form():
+    """A tangent straight run off the circle track, in closed form (independent of the
+    oracle's cost code): from (R, 0) heading +y at speed v with zero steer and the throttle
+    that balances drag (a_max tau = c_v v), the motion is uniform, p_t = (R, v t), so
+    e_y(t) = sqrt(R^2 + v^2 t^2) - R.  The run leaves the track, so the state cost, the
+    collision indicator, the terminal cost, the control term and the DCBF penalties of
+    eqs. (17)-(20), (24), (25) all contribute."""
+    R, w, v, T = 10.0, 1.0, 8.0, 30
+    tr = W.circle_track(R, w)
+    x0 = np.array([R, 0.0, math.pi / 2.0, v, 0.0, 0.0])
+    tau = M["c_v"] * v / M["a_max"]
+    assert tau <= M["u_hi"][1]
+    V = np.tile([0.0, tau], (T, 1))
+    S, _, _ = oracle.rollout(M, C, tr, x0, V, 1, 0, 0, 0, nominal=True)
+    t = np.arange(T + 1) * M["dt"]
+    ey2 = (np.sqrt(R * R + (v * t) ** 2) - R) ** 2
+    h = w * w - ey2
+    alpha = 1.0 - C["gamma"]
+    q = C["q_v"] * (v - C["v_g"]) ** 2 + C["q_ey"] * ey2 + C["C_obs"] * (h < 0.0)
+    ctrl = C["lambda_u"] * (0.0 / C["sigma"][0] ** 2 + tau * tau / C["sigma"][1] ** 2)
+    pen = C["C_cbf"] * (max((alpha - 1.0) * h[0], 0.0) + np.maximum(alpha * h[:-1] - h[1:], 0.0).sum())
+    expect = q[:T].sum() + T * ctrl + C["phi_w"] * q[T] + pen
+    assert (h < 0.0).sum() > 5 and pen > 0.0  # the run leaves the track
+    assert S[0] == pytest.approx(expect, rel=1e-12)
+
+
 def test_zero_noise_samples_all_equal_nominal():
     p = W.config1(K=16, T=20)
     S, eps, _ = oracle.rollout(M, C, p.track, p.x0, p.V, p.K, 0, 0, 0, nominal=True)
