@@ -962,12 +962,102 @@ constexpr int REP_C = 4;  // shield: control rows read ahead, segment indices st
 // respect to (x, u) (6 x 8), the local barrier/cost gradients (8) and the
 // control gradient (2).
 constexpr int REP_PAR_PER_STEP = 48 + 8 + 2;
-// Per-step control constants of the shield's forward pass, one 16-byte aligned
-// row per step (delta, sin/m, cos/m, l_f cos/I_z, a_max tau, 3 unused).
-constexpr int REP_CTL = 8;
+// Per-step constants of the shield's forward pass, one 16-byte aligned row per
+// step: the 13 values of shield_vel_row, 3 unused.
+constexpr int REP_CTL = 16;
+
+// The shield's nominal trajectory runs on one lane, where every instruction of
+// the RK4 chain costs an issue slot, so its velocity part takes its per-step
+// constants precomputed (by all threads, in parallel, before the pass) in the
+// form that needs the fewest instructions per stage.  With the lateral tyre
+// forces F_f = C_f t1, F_r = C_r t2, t1 = delta - (v_y + l_f om) / v,
+// t2 = (l_r om - v_y) / v (v = max(v_x, v_min)), each RK4 stage value
+// y_k = y_0 + f_k F(y_{k-1}) (f = h/2, h/2, h) is three FMA chains whose
+// coefficients carry f_k and the tyre stiffnesses, with y_0 folded into the
+// innermost addend; the last stage gives K = (h/6) F(y_3), and the step is
+// y_0 + (h/6)(k_1 + 2 k_2 + 2 k_3 + k_4) = (y_1 + 2 y_2 + y_3 - y_0)/3 + K.
+// (The classic RK4 of the model, evaluated in another order.)
+template <class R>
+struct ShieldVel {
+  R v_min, lf, lr;
+  R f[3];    // h/2, h, h/6
+  R cv[3];   // -f c_v
+  R crm[3];  // f C_r / m
+  R crl[3];  // -f C_r l_r / I_z
+};
+
+template <class R>
+__device__ __forceinline__ ShieldVel<R> shield_vel(const DevModel<R>& M) {
+  ShieldVel<R> k;
+  k.v_min = M.v_min;
+  k.lf = M.lf;
+  k.lr = M.lr;
+  k.f[0] = R(0.5) * M.dt;
+  k.f[1] = M.dt;
+  k.f[2] = M.dt * R(1.0 / 6.0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    k.cv[i] = -(k.f[i] * M.c_v);
+    k.crm[i] = k.f[i] * (M.Cr * M.inv_m);
+    k.crl[i] = -(k.f[i] * (M.Cr * M.lr_Iz));
+  }
+  return k;
+}
+
+// Row of a step with the held control (delta, tau): delta; f a_max tau for
+// f = h/2, h, h/6; then per f: -f C_f sin(delta)/m, f C_f cos(delta)/m,
+// f C_f l_f cos(delta)/I_z.
+template <class R>
+__device__ __forceinline__ void shield_vel_row(const DevModel<R>& M, R delta, R tau, R* cr) {
+  const StepCtl<R> c = step_ctl(M, delta, tau);
+  const R f[3] = {R(0.5) * M.dt, M.dt, M.dt * R(1.0 / 6.0)};
+  cr[0] = c.delta;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const R g = f[i] * M.Cf;
+    cr[1 + i] = f[i] * c.a_tau;
+    cr[4 + 3 * i] = -(g * c.sd_m);
+    cr[5 + 3 * i] = g * c.cd_m;
+    cr[6 + 3 * i] = g * c.lfcd_Iz;
+  }
+}
+
+// f_i F(x, y, o) added to (ax, ay, ao), coefficients of factor i.
+template <class R, int I>
+__device__ __forceinline__ void shield_vel_inc(const ShieldVel<R>& k, const R* cr, R x, R y, R o, R ax, R ay, R ao,
+                                               R& ox, R& oy, R& oo) {
+  const R inv = rcp_r(fmax(x, k.v_min));
+  const R t1 = fma_r(-fma_r(k.lf, o, y), inv, cr[0]);
+  const R t2 = fma_r(k.lr, o, -y) * inv;
+  const R oh = o * k.f[I];
+  ox = fma_r(y, oh, fma_r(t1, cr[4 + 3 * I], fma_r(k.cv[I], x, ax)));
+  oy = fma_r(-x, oh, fma_r(t1, cr[5 + 3 * I], fma_r(t2, k.crm[I], ay)));
+  oo = fma_r(t1, cr[6 + 3 * I], fma_r(t2, k.crl[I], ao));
+}
+
+// One RK4 step of (v_x, v_y, om) from a row of shield_vel_row; the stage
+// velocities (stage 1 = the step's start) for the pose part.
+template <class R>
+__device__ __forceinline__ void shield_vel_step(const ShieldVel<R>& k, const R* cr, R& vx, R& vy, R& om,
+                                                VelStages<R>& g) {
+  const R x0 = vx, y0 = vy, o0 = om;
+  g.vx[0] = x0;
+  g.vy[0] = y0;
+  g.om[0] = o0;
+  const R p2 = x0 + cr[1], p1 = x0 + cr[2];
+  shield_vel_inc<R, 0>(k, cr, x0, y0, o0, p2, y0, o0, g.vx[1], g.vy[1], g.om[1]);
+  shield_vel_inc<R, 0>(k, cr, g.vx[1], g.vy[1], g.om[1], p2, y0, o0, g.vx[2], g.vy[2], g.om[2]);
+  shield_vel_inc<R, 1>(k, cr, g.vx[2], g.vy[2], g.om[2], p1, y0, o0, g.vx[3], g.vy[3], g.om[3]);
+  R kx, ky, ko;
+  shield_vel_inc<R, 2>(k, cr, g.vx[3], g.vy[3], g.om[3], cr[3], R(0), R(0), kx, ky, ko);
+  const R third = R(1.0 / 3.0), two_thirds = R(2.0 / 3.0);
+  vx = fma_r(two_thirds, g.vx[2], fma_r(third, g.vx[1] + g.vx[3], fma_r(-third, x0, kx)));
+  vy = fma_r(two_thirds, g.vy[2], fma_r(third, g.vy[1] + g.vy[3], fma_r(-third, y0, ky)));
+  om = fma_r(two_thirds, g.om[2], fma_r(third, g.om[1] + g.om[3], fma_r(-third, o0, ko)));
+}
 
 // LDS of the shield beyond the staged problem: states x_0..x_T, segment
-// indices, the per-step control constants (5 per step) and two chunks of RK4
+// indices, the per-step constants (REP_CTL per step) and two chunks of RK4
 // stage velocities (12 per step) passed from the velocity wave to the pose wave;
 // with L-BFGS (memory > 0) also the gradient, the previous iterate and
 // gradient, the two-loop vector, memory + 1 pair slots (s, y) of 2 t_max
@@ -1382,16 +1472,9 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
   const int idx0 = tr.idx0;
   const R e20 = tr.n > 0 ? seg_dist2(tr, idx0, x0.px, x0.py) : circle_e2(tr, x0.px, x0.py);
   for (int s = 0; s < a.n_steps; ++s) {
-    for (int t = threadIdx.x; t < T; t += blockDim.x) {
-      const StepCtl<R> sc =
-          step_ctl(M, clamp_r(Vs[t], M.u_lo[0], M.u_hi[0]), clamp_r(Vs[T + t], M.u_lo[1], M.u_hi[1]));
-      R* cr = ctl + REP_CTL * t;
-      cr[0] = sc.delta;
-      cr[1] = sc.sd_m;
-      cr[2] = sc.cd_m;
-      cr[3] = sc.lfcd_Iz;
-      cr[4] = sc.a_tau;
-    }
+    for (int t = threadIdx.x; t < T; t += blockDim.x)
+      shield_vel_row(M, clamp_r(Vs[t], M.u_lo[0], M.u_hi[0]), clamp_r(Vs[T + t], M.u_lo[1], M.u_hi[1]),
+                     ctl + REP_CTL * t);
     if (threadIdx.x == 0) {
       flg[0] = 0;
       flg[1] = 0;
@@ -1436,31 +1519,25 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
       __syncthreads();
       if (w == 0 && lane == 0) {
         // velocity wave: the RK4 chain of (v_x, v_y, omega), publishing each step
+        const ShieldVel<R> kv = shield_vel(M);
         for (int t0 = 0; t0 < T; t0 += REP_C) {
           const int t1 = min(T, t0 + REP_C);
           // the chunk's control rows are read before its first store: LDS
           // returns in order, so a row read after a step's stores would wait for
           // them inside the RK4 chain
-          R cc[REP_C][5];
+          R cc[REP_C][13];
   #pragma unroll
           for (int k = 0; k < REP_C; ++k) {
             const R* cr = static_cast<const R*>(__builtin_assume_aligned(ctl + REP_CTL * min(t0 + k, t1 - 1), 16));
   #pragma unroll
-            for (int c = 0; c < 5; ++c) cc[k][c] = cr[c];
+            for (int c = 0; c < 13; ++c) cc[k][c] = cr[c];
           }
   #pragma unroll
           for (int j = 0; j < REP_C; ++j) {
             const int t = t0 + j;
             if (t >= t1) break;
-            StepCtl<R> sc;
-            sc.delta = cc[j][0];
-            sc.sd_m = cc[j][1];
-            sc.cd_m = cc[j][2];
-            sc.lfcd_Iz = cc[j][3];
-            sc.a_tau = cc[j][4];
-            sc.sd = sc.cd = R(0);  // used by the reverse sweep only
             VelStages<R> g;
-            rk4_vel(M, sc, x.vx, x.vy, x.om, g);
+            shield_vel_step(kv, cc[j], x.vx, x.vy, x.om, g);
             R* gt = static_cast<R*>(__builtin_assume_aligned(vst + 12 * (size_t)t, 16));
   #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -1468,10 +1545,14 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
               gt[4 + q] = g.vy[q];
               gt[8 + q] = g.om[q];
             }
-            R* o = xs + 6 * (t + 1);
-            o[3] = x.vx; o[4] = x.vy; o[5] = x.om;
+            // (the velocities of x_{t+1} are the next row's first stage: copied
+            // into the states after the pass)
             __hip_atomic_store(flg, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
           }
+        }
+        if (T > 0) {
+          R* o = xs + 6 * T;
+          o[3] = x.vx; o[4] = x.vy; o[5] = x.om;
         }
       } else if (w == 2 && lane == 0) {
         // pose wave: (p_x, p_y, psi) from the stage velocities, step by step as
@@ -1522,6 +1603,13 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
         }
       }
       __syncthreads();
+      // velocities of x_1 .. x_{T-1}: the first stage of the next step's row
+      // (read after the barrier below)
+      for (int t = (int)threadIdx.x + 1; t < T; t += blockDim.x) {
+        const R* gt = vst + 12 * (size_t)t;
+        R* o = xs + 6 * t;
+        o[3] = gt[0]; o[4] = gt[4]; o[5] = gt[8];
+      }
     } else {
       // (workgroups that share their compute unit with rollout tiles) chunk by
       // chunk between workgroup barriers: waiting waves then sit in the
@@ -1534,26 +1622,20 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
           // the chunk's control rows are read before its first store: LDS
           // returns in order, so a row read after a step's stores would wait for
           // them inside the RK4 chain
-          R cc[REP_C][5];
+          R cc[REP_C][13];
   #pragma unroll
           for (int k = 0; k < REP_C; ++k) {
             const R* cr = static_cast<const R*>(__builtin_assume_aligned(ctl + REP_CTL * min(t0 + k, t1 - 1), 16));
   #pragma unroll
-            for (int c = 0; c < 5; ++c) cc[k][c] = cr[c];
+            for (int c = 0; c < 13; ++c) cc[k][c] = cr[c];
           }
+          const ShieldVel<R> kv = shield_vel(M);
   #pragma unroll
           for (int j = 0; j < REP_C; ++j) {
             const int t = t0 + j;
             if (t >= t1) break;
-            StepCtl<R> sc;
-            sc.delta = cc[j][0];
-            sc.sd_m = cc[j][1];
-            sc.cd_m = cc[j][2];
-            sc.lfcd_Iz = cc[j][3];
-            sc.a_tau = cc[j][4];
-            sc.sd = sc.cd = R(0);  // used by the reverse sweep only
             VelStages<R> g;
-            rk4_vel(M, sc, x.vx, x.vy, x.om, g);
+            shield_vel_step(kv, cc[j], x.vx, x.vy, x.om, g);
             R* gt = static_cast<R*>(__builtin_assume_aligned(gb + 12 * (t - t0), 16));
   #pragma unroll
             for (int k = 0; k < 4; ++k) {
