@@ -356,10 +356,13 @@ typedef struct {
                                 pipelining noise, dynamics and cost); -1: off; 0: on when
                                 the batch has at most 2*64 samples per compute unit and
                                 no obstacles */
-  int32_t fuse_shield;       /* 0: run the shield (and execute) of each problem inside the
+  int32_t fuse_shield;       /* 1: run the shield (and execute) of each problem inside the
                                 fused launch, in the workgroup that combines the problem,
                                 when its workgroups have at least three waves and the LDS
-                                fits; -1: always a separate shield kernel */
+                                fits; 0: the same in latency mode, a separate shield kernel
+                                otherwise (measured faster for tile-mode batches); -1:
+                                always a separate shield kernel.  The results are the same
+                                bit for bit. */
 } smppi_plan_opts;
 
 /* Buffers a plan reads and writes on every launch (device pointers, dtype F32):

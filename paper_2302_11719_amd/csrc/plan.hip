@@ -712,8 +712,8 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   if (opts->repair && !bufs->V_safe) return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "V_safe required with repair");
   if (opts->execute && opts->dist && opts->n_dist < 0)
     return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "n_dist must be >= 0");
-  if (opts->fuse_shield < -1 || opts->fuse_shield > 0)
-    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "fuse_shield must be -1 or 0");
+  if (opts->fuse_shield < -1 || opts->fuse_shield > 1)
+    return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "fuse_shield must be -1, 0 or 1");
   if (opts->pipeline < -1 || opts->pipeline > 1)
     return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "pipeline must be -1, 0 or 1");
   (void)hipSetDevice(ctx->device);
@@ -744,9 +744,16 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   if (!pipe && tile % block != 0)
     return fail(ctx, SMPPI_ERR_INVALID_ARGUMENT, "tile must be a multiple of block");
   const int spt = tile / block;
-  // the shield inside the launch when asked for and the workgroup has three waves
-  // (the LDS check below may still turn it off)
-  const bool want_fuse = opts->repair && opts->fuse_shield == 0 && block >= 3 * WAVE;
+  // the shield inside the launch when the workgroup has three waves (the LDS check
+  // below may still turn it off): by default only in latency mode.  A tile-mode
+  // launch with the shield compiled in needs more registers in every tile (fewer
+  // waves per SIMD for the whole batch), and its shield shares a compute unit with
+  // rollout tiles (chunk barriers instead of step counters); there the separate
+  // shield kernel was measured faster (64 x K = 4096: 0.224 -> 0.157 ms, 512
+  // problems: 1.17 -> 0.87 ms), in latency mode the fused one (8 problems: 0.075 vs
+  // 0.079 ms; the headline launch).
+  const bool want_fuse = opts->repair && block >= 3 * WAVE &&
+                         (opts->fuse_shield == 1 || (opts->fuse_shield == 0 && pipe));
   auto pick = [&](bool fuse) -> FusedFn {
     if (pipe) return track->obs_max > 0 ? pick_pipe<kMaxObs>(fuse) : pick_pipe<0>(fuse);
     return track->obs_max > 0 ? pick_fused<kMaxObs>(block, spt, fuse) : pick_fused<0>(block, spt, fuse);

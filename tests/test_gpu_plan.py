@@ -83,7 +83,7 @@ def test_plan_graph_replays_match_eager_plan():
     assert np.array_equal(dbs[0].iter.cpu().numpy(), np.arange(1, 6) + 4)
 
 
-@pytest.mark.parametrize("fuse", [-1, 0])
+@pytest.mark.parametrize("fuse", [-1, 1])
 def test_profiled_launch_matches_and_times(fuse):
     """The profiled launch (events between the stages, kernel-stamped events on the
     fused and shield kernels) computes exactly what the ordinary launch computes, and
@@ -110,6 +110,29 @@ def test_profiled_launch_matches_and_times(fuse):
     assert ctx().device_errors() == 0
 
 
+def test_default_fuses_the_shield_only_in_latency_mode():
+    """fuse_shield = 0 runs the shield inside the launch in latency mode and as its own
+    kernel in tile mode (the profiled launch times a shield kernel only when there is
+    one); both give what the explicit choices give, bit for bit."""
+    probs = prep(ragged_problems(), F32)
+    M, C = params(F32)
+    rep = dict(n_steps=3, step=0.05, objective=W.OBJ_SHIELD)
+    for pipeline, block, fused in ((1, 0, True), (-1, 256, False)):
+        say(f"default shield fusion pipeline={pipeline}")
+        dbs = [core.DeviceBatch(probs, dtype=F32) for _ in range(2)]
+        pd = core.Plan(ctx(), dbs[0], M, C, 5, W.LAMBDA, repair=rep, use_graph=False, pipeline=pipeline, block=block)
+        pe = core.Plan(ctx(), dbs[1], M, C, 5, W.LAMBDA, repair=rep, use_graph=False, pipeline=pipeline, block=block,
+                       fuse_shield=1 if fused else -1)
+        pd.launch_profiled()
+        pe.launch()
+        torch.cuda.synchronize()
+        assert (pd.kernel_ms()[1] == 0.0) == fused
+        assert torch.equal(pd.V_safe, pe.V_safe) and torch.equal(pd.V_plus, pe.V_plus)
+        pd.close()
+        pe.close()
+    assert ctx().device_errors() == 0
+
+
 @pytest.mark.parametrize("pipeline,block,method", [(1, 0, "gradient"), (-1, 256, "gradient"), (-1, 128, "gradient"),
                                                    (-1, 64, "gradient"), (1, 0, "lbfgs"), (-1, 256, "lbfgs")])
 def test_fused_shield_matches_separate_shield_kernel(pipeline, block, method):
@@ -123,7 +146,7 @@ def test_fused_shield_matches_separate_shield_kernel(pipeline, block, method):
     rep = dict(n_steps=4, step=0.05, objective=W.OBJ_SHIELD, method=method, memory=3)
     dbs = [core.DeviceBatch(probs, dtype=F32) for _ in range(2)]
     plans = [core.Plan(ctx(), dbs[i], M, C, 11, W.LAMBDA, repair=rep, execute=True, dist=dist.view(8, -1),
-                       use_graph=False, pipeline=pipeline, block=block, fuse_shield=(0 if i == 0 else -1))
+                       use_graph=False, pipeline=pipeline, block=block, fuse_shield=(1 if i == 0 else -1))
              for i in range(2)]
     for step in range(3):
         say(f"fused shield pipeline={pipeline} block={block} {method} step {step}")
