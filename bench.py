@@ -234,6 +234,19 @@ def stage_split(ctx, prob, M, C, seed, lam, rep, dist, warm, n_prof):
                 shield_kernel_ms_when_active=float(kr[act].mean()) if act.any() else None,
                 shield_kernel_ms_when_idle=float(kr[~act].mean()) if (~act).any() else None)
 
+def _capture(fn):
+    """fn's launches captured into a torch CUDA graph (the library's calls allocate and
+    synchronise nothing, so only their kernels are recorded)."""
+    import torch
+
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    return g
+
+
 def _time(fn, n, warm, sync):
     for _ in range(warm):
         fn()
@@ -339,6 +352,11 @@ def _form_plain(ctx, core, W, M, C, lam, K, T, sync, out, seed):
 
     dt = _time(plain_iter, 200, 20, sync)
     out["plain_single"] = {"ms_per_iter": dt * 1e3, "rollout_steps_per_s": K * T / dt, "shield": False}
+    # the same four calls captured once in a HIP graph (torch's graph API) and replayed
+    g = _capture(plain_iter)
+    dt = _time(g.replay, 200, 20, sync)
+    out["plain_single"]["graph_ms_per_iter"] = dt * 1e3
+    del g
 
     # batched plan without the shield on the same problem (isolates fusion + graph)
     db2 = core.DeviceBatch([prob], dtype=torch.float32)
@@ -589,7 +607,8 @@ def _form_curvilinear(ctx, core, W, M, C, sync, out, seed):
     its rollout at K = 65536, T = 100 beside the Cartesian rollout of the same size on the
     same track (no obstacles), its free-energy adjoint at the same size, and one
     closed-loop Shield-MPPI iteration at K = 4096, T = 50 through the plain calls
-    (rollout, weights, update, shield, plant step)."""
+    (rollout, weights, update, shield, plant step), called one by one and captured once
+    in a HIP graph."""
     import torch
 
     K, T = 65536, 100
@@ -621,13 +640,17 @@ def _form_curvilinear(ctx, core, W, M, C, sync, out, seed):
         core.execute_curvilinear(ctx, dbl, ct, M, WH, Vs, Vp)
 
     t_loop = _time(loop_iter, 50, 5, sync)
+    g = _capture(loop_iter)
+    t_graph = _time(g.replay, 50, 5, sync)
+    del g
     out["curvilinear8_K65536_T100"] = {
         "rollout_ms": t_curv * 1e3, "rollout_steps_per_s": K * T / t_curv,
         "achieved_TFLOPs": FLOP_STEP_C8 * K * T / t_curv / 1e12,
         "free_energy_adjoint_ms": t_adj * 1e3,
         "cartesian_rollout_ms": t_cart * 1e3, "cartesian_rollout_steps_per_s": K * T / t_cart,
         "cartesian_achieved_TFLOPs": FLOP_STEP_POLY * K * T / t_cart / 1e12,
-        "closed_loop_K4096_T50_ms_per_iter": t_loop * 1e3}
+        "closed_loop_K4096_T50_ms_per_iter": t_loop * 1e3,
+        "closed_loop_K4096_T50_graph_ms_per_iter": t_graph * 1e3}
     _log(f"  curvilinear: {out['curvilinear8_K65536_T100']}")
 
 
