@@ -52,16 +52,22 @@ __device__ __forceinline__ Ctl8<R> ctl8(R delta, R thr) {
 }
 
 // kappa(s) of the periodic table (linear between grid points) and its slope in
-// the cell holding s.  Any s maps to a valid cell (non-finite s to cell 0).
+// the cell holding s.  The cell index floor(s/ds) mod n is formed in floating
+// point with multiplications by 1/ds and 1/n (no division on the chain; exact
+// while |s/ds| < 2^24 in FP32, and a rounding of the quotient by n that leaves
+// -1 or n is folded back); non-finite s, or s beyond that range, maps to cell 0.
 template <class R>
 __device__ __forceinline__ R kappa_cell(const CurvView<R>& cv, R s, R& slope) {
-  const R jf = floor(s / cv.ds);
-  const R f = s / cv.ds - jf;
-  int j = (int)jf % cv.n;
-  j += j < 0 ? cv.n : 0;
+  const R q = s * cv.inv_ds;
+  const R jf = floor(q);
+  const R f = q - jf;
+  R jw = fma_r(-cv.rn, floor(jf * cv.inv_n), jf);
+  jw += jw < R(0) ? cv.rn : R(0);
+  jw -= jw >= cv.rn ? cv.rn : R(0);
+  const int j = (jw >= R(0) && jw < cv.rn) ? (int)jw : 0;
   const int j1 = j + 1 == cv.n ? 0 : j + 1;
   const R k0 = cv.kappa[j], k1 = cv.kappa[j1];
-  slope = (k1 - k0) / cv.ds;
+  slope = (k1 - k0) * cv.inv_ds;
   return k0 * (R(1) - f) + k1 * f;
 }
 
@@ -372,14 +378,9 @@ __device__ __forceinline__ CurvView<R> c8_stage(const C8Args<R>& a, int b, const
   R* v = kap + a.n_max;
   for (int i = threadIdx.x; i < d.n; i += blockDim.x) kap[i] = a.kappa[d.c0 + i];
   for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) v[i] = a.V[2 * (size_t)d.t0 + i];
-  CurvView<R> cv;
-  cv.kappa = kap;
-  cv.n = d.n;
-  cv.ds = a.ds[b];
   const R w = a.half_width[b];
-  cv.w2 = w * w;
   *Vs = v;
-  return cv;
+  return curv_view(static_cast<const R*>(kap), d.n, a.ds[b], w * w);
 }
 
 template <class R>
@@ -650,11 +651,7 @@ __global__ __launch_bounds__(WAVE) void k_execute_c8(C8ExecArgs<R> e) {
   for (int i = threadIdx.x; i < 2 * T; i += blockDim.x) buf[i] = Vp[i];
   __syncthreads();
   if (threadIdx.x == 0) {
-    CurvView<R> cv;
-    cv.kappa = a.kappa + c0;
-    cv.n = n;
-    cv.ds = a.ds[b];
-    cv.w2 = R(0);
+    const CurvView<R> cv = curv_view(a.kappa + c0, n, a.ds[b], R(0));
     const R* Ve = e.V_exec + 2 * (size_t)t0;
     const R u0 = clamp_r(Ve[0], a.M.u_lo[0], a.M.u_hi[0]);
     const R u1 = clamp_r(Ve[T], a.M.u_lo[1], a.M.u_hi[1]);

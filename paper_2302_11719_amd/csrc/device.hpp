@@ -269,7 +269,21 @@ struct CurvView {
   const R* kappa;
   int n;
   R ds, w2;
+  R inv_ds, rn, inv_n;  // 1/ds, n and 1/n (the cell lookup multiplies instead of dividing)
 };
+
+template <class R>
+__device__ __forceinline__ CurvView<R> curv_view(const R* kappa, int n, R ds, R w2) {
+  CurvView<R> cv;
+  cv.kappa = kappa;
+  cv.n = n;
+  cv.ds = ds;
+  cv.w2 = w2;
+  cv.inv_ds = R(1) / ds;
+  cv.rn = R(n);
+  cv.inv_n = R(1) / R(n);
+  return cv;
+}
 
 // ---------------------------------------------------------------- track
 // Polyline segments are staged in LDS as (a_x, a_y, d_x, d_y) plus 1/|d|^2.
