@@ -542,20 +542,50 @@ struct C8RepairArgs {
   R step;
 };
 
+// The repair's workgroup: the forward chain runs on one lane, the reverse sweep
+// on all threads.
+constexpr int C8_REP_BLK = 4 * WAVE;
+// Per step of the parallel reverse sweep: the rows [J_t^T | B_t^T] of the RK4
+// step's Jacobians for the eight unit cotangents (8 x 10), the barrier gradient
+// at x_{t+1} (an e_y value), the local gradient at x_t (v_x and e_y values) and
+// the control gradient (2), padded.
+constexpr int C8_PAR = 88;
+
 template <class R>
 __host__ __device__ inline size_t c8_repair_lds_bytes(int n_max, int t_max) {
-  return c8_stage_bytes<R>(n_max, t_max) + sizeof(R) * 8 * ((size_t)t_max + 1);
+  return c8_stage_bytes<R>(n_max, t_max) + sizeof(R) * 8 * ((size_t)t_max + 1) + sizeof(R) * C8_PAR * (size_t)t_max;
 }
 
-// Algorithm 1 on the curvilinear model, one 64-lane workgroup per problem (the
-// chain runs on lane 0): per iteration the nominal trajectory from x0 under
-// clip(V) is stored in LDS, the last transition whose objective term has a
-// non-zero derivative is found, and the reverse sweep from there applies
-// V <- clip(V - step dL/dV) in place; later steps only get the projection.
-// Stops early when no transition is active (the gradient is then zero).
+// Component j of x (selects: no dynamic index into the struct).
 template <class R>
-__global__ __launch_bounds__(WAVE) void k_repair_c8(C8RepairArgs<R> r) {
+__device__ __forceinline__ R c8_comp(const C8<R>& x, int j) {
+  R v = x.vx;
+  v = j == 1 ? x.vy : v;
+  v = j == 2 ? x.r : v;
+  v = j == 3 ? x.wF : v;
+  v = j == 4 ? x.wR : v;
+  v = j == 5 ? x.ep : v;
+  v = j == 6 ? x.ey : v;
+  v = j == 7 ? x.s : v;
+  return v;
+}
+
+// Algorithm 1 on the curvilinear model, one workgroup per problem.  Per
+// iteration: the nominal trajectory from x0 under clip(V) on one lane (stored in
+// LDS), and the last transition whose objective term has a non-zero derivative;
+// then the reverse sweep from there.  The adjoint recursion is linear once the
+// trajectory is fixed,
+//   lam_t = J_t^T (lam_{t+1} + dn_t) + dc_t,   g_t = B_t^T (lam_{t+1} + dn_t),
+// so the Jacobian rows (one vector-Jacobian product per unit cotangent) and the
+// local gradients of every step are computed in parallel, the recursion runs as
+// 8 x 10 matrix-vector products on ten lanes (lam broadcast by readlane), and the
+// projected step V <- clip(V - step g) is applied to every step in parallel;
+// later steps only get the projection.  Stops early when no transition is
+// active (the gradient is then zero).
+template <class R>
+__global__ __launch_bounds__(C8_REP_BLK) void k_repair_c8(C8RepairArgs<R> r) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_last;
   const C8Args<R>& a = r.a;
   const int b = blockIdx.x;
   C8Dims d;
@@ -565,16 +595,16 @@ __global__ __launch_bounds__(WAVE) void k_repair_c8(C8RepairArgs<R> r) {
   av.V = r.V_plus;
   const CurvView<R> cv = c8_stage(av, b, d, reinterpret_cast<R*>(smem), &Vs);
   R* xs = reinterpret_cast<R*>(smem + c8_stage_bytes<R>(a.n_max, a.t_max));
+  R* Wp = xs + 8 * ((size_t)a.t_max + 1);
   __syncthreads();
   const int T = d.T;
   const DevModel<R>& M = a.M;
   const DevCost<R>& C = a.C;
   const DevObjective<R>& ob = r.ob;
   const bool cost_terms = ob.w_S != R(0);
-  if (threadIdx.x == 0) {
-    const C8<R> x0 = load_c8(a.x0 + 8 * (size_t)b);
-    for (int s = 0; s < r.n_steps; ++s) {
-      C8<R> x = x0;
+  for (int s = 0; s < r.n_steps; ++s) {
+    if (threadIdx.x == 0) {
+      C8<R> x = load_c8(a.x0 + 8 * (size_t)b);
       store_c8(xs, x);
       int last = -1;
       R hp = cv.w2 - x.ey * x.ey;
@@ -587,34 +617,87 @@ __global__ __launch_bounds__(WAVE) void k_repair_c8(C8RepairArgs<R> r) {
         if (C.alpha * hp - hn > R(0) && (ob.w_sq != R(0) || (ob.w_lin != R(0) && t < ob.n_lin))) last = t;
         hp = hn;
       }
-      const int t_end = cost_terms ? T - 1 : last;
-      for (int t = t_end + 1; t < T; ++t) {
-        Vs[t] = clamp_r(Vs[t], M.u_lo[0], M.u_hi[0]);
-        Vs[T + t] = clamp_r(Vs[T + t], M.u_lo[1], M.u_hi[1]);
-      }
-      if (t_end < 0) break;
+      s_last = last;
+    }
+    __syncthreads();
+    const int t_end = cost_terms ? T - 1 : s_last;
+    for (int t = t_end + 1 + (int)threadIdx.x; t < T; t += blockDim.x) {
+      Vs[t] = clamp_r(Vs[t], M.u_lo[0], M.u_hi[0]);
+      Vs[T + t] = clamp_r(Vs[T + t], M.u_lo[1], M.u_hi[1]);
+    }
+    if (t_end < 0) break;  // uniform: every thread read the same s_last
+    // Jacobian rows and local gradients of every step
+    for (int k = threadIdx.x; k < 8 * (t_end + 1); k += blockDim.x) {
+      const int t = k >> 3, i = k & 7;
+      const C8<R> xp = load_c8(xs + 8 * t);
+      const R u0 = clamp_r(Vs[t], M.u_lo[0], M.u_hi[0]);
+      const R u1 = clamp_r(Vs[T + t], M.u_lo[1], M.u_hi[1]);
       C8<R> lam = zero8<R>();
-      if (cost_terms) stage_grad_c8(C, load_c8(xs + 8 * T), ob.w_S * C.phi_w, lam);
-      for (int t = t_end; t >= 0; --t) {
-        const C8<R> xp = load_c8(xs + 8 * t), xn = load_c8(xs + 8 * (t + 1));
-        const R gey_prev = penalty_grad_c8(C, ob, cv.w2, xp, xn, t, lam);
-        const R v0 = Vs[t], v1 = Vs[T + t];
-        const R u0 = clamp_r(v0, M.u_lo[0], M.u_hi[0]);
-        const R u1 = clamp_r(v1, M.u_lo[1], M.u_hi[1]);
-        const bool pass0 = (v0 >= M.u_lo[0]) && (v0 <= M.u_hi[0]);
-        const bool pass1 = (v1 >= M.u_lo[1]) && (v1 <= M.u_hi[1]);
-        R gd = R(0), gt = R(0);
-        rk4_c8_vjp(M, a.Wh, cv, ctl8(u0, u1), xp, lam, gd, gt);
-        lam.ey += gey_prev;
-        if (cost_terms) stage_grad_c8(C, xp, ob.w_S, lam);
-        const R gu0 = gd + ob.w_S * C.ctrl_w[0] * v0;
-        const R gu1 = gt + ob.w_S * C.ctrl_w[1] * v1;
-        const R gv0 = (pass0 ? gu0 : R(0)) + ob.w_S * C.ctrl_w[0] * u0;
-        const R gv1 = (pass1 ? gu1 : R(0)) + ob.w_S * C.ctrl_w[1] * u1;
-        Vs[t] = clamp_r(v0 - r.step * gv0, M.u_lo[0], M.u_hi[0]);
-        Vs[T + t] = clamp_r(v1 - r.step * gv1, M.u_lo[1], M.u_hi[1]);
+      lam.vx = i == 0 ? R(1) : R(0);
+      lam.vy = i == 1 ? R(1) : R(0);
+      lam.r = i == 2 ? R(1) : R(0);
+      lam.wF = i == 3 ? R(1) : R(0);
+      lam.wR = i == 4 ? R(1) : R(0);
+      lam.ep = i == 5 ? R(1) : R(0);
+      lam.ey = i == 6 ? R(1) : R(0);
+      lam.s = i == 7 ? R(1) : R(0);
+      R gd = R(0), gt = R(0);
+      rk4_c8_vjp(M, a.Wh, cv, ctl8(u0, u1), xp, lam, gd, gt);
+      R* q = Wp + (size_t)C8_PAR * t + 10 * i;
+      store_c8(q, lam);
+      q[8] = gd;
+      q[9] = gt;
+      if (i == 0) {
+        const C8<R> xn = load_c8(xs + 8 * (t + 1));
+        C8<R> dn = zero8<R>(), dc = zero8<R>();
+        dc.ey = penalty_grad_c8(C, ob, cv.w2, xp, xn, t, dn);
+        if (cost_terms) stage_grad_c8(C, xp, ob.w_S, dc);
+        R* qq = Wp + (size_t)C8_PAR * t;
+        qq[80] = dn.ey;
+        qq[81] = dc.vx;
+        qq[82] = dc.ey;
       }
     }
+    __syncthreads();
+    if (threadIdx.x < WAVE) {
+      // lane j < 10 holds component j: lam_j for j < 8, the control gradient for j = 8, 9
+      const int j = threadIdx.x < 10 ? (int)threadIdx.x : 9;
+      R lam = R(0);
+      if (cost_terms) {
+        C8<R> l = zero8<R>();
+        stage_grad_c8(C, load_c8(xs + 8 * T), ob.w_S * C.phi_w, l);
+        lam = j < 8 ? c8_comp(l, j) : R(0);
+      }
+      for (int t = t_end; t >= 0; --t) {
+        const R* q = Wp + (size_t)C8_PAR * t;
+        if (j == 6) lam += q[80];
+        R l[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) l[i] = lane_bcast(lam, i);
+        const R nl = ((l[0] * q[j] + l[1] * q[10 + j]) + (l[2] * q[20 + j] + l[3] * q[30 + j])) +
+                     ((l[4] * q[40 + j] + l[5] * q[50 + j]) + (l[6] * q[60 + j] + l[7] * q[70 + j]));
+        if (j < 8)
+          lam = nl + (j == 0 ? q[81] : (j == 6 ? q[82] : R(0)));
+        else if (threadIdx.x < 10)
+          Wp[(size_t)C8_PAR * t + 83 + (j - 8)] = nl;
+      }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t <= t_end; t += blockDim.x) {
+      const R* g = Wp + (size_t)C8_PAR * t + 83;
+      const R v0 = Vs[t], v1 = Vs[T + t];
+      const R u0 = clamp_r(v0, M.u_lo[0], M.u_hi[0]);
+      const R u1 = clamp_r(v1, M.u_lo[1], M.u_hi[1]);
+      const bool pass0 = (v0 >= M.u_lo[0]) && (v0 <= M.u_hi[0]);
+      const bool pass1 = (v1 >= M.u_lo[1]) && (v1 <= M.u_hi[1]);
+      const R gu0 = g[0] + ob.w_S * C.ctrl_w[0] * v0;
+      const R gu1 = g[1] + ob.w_S * C.ctrl_w[1] * v1;
+      const R gv0 = (pass0 ? gu0 : R(0)) + ob.w_S * C.ctrl_w[0] * u0;
+      const R gv1 = (pass1 ? gu1 : R(0)) + ob.w_S * C.ctrl_w[1] * u1;
+      Vs[t] = clamp_r(v0 - r.step * gv0, M.u_lo[0], M.u_hi[0]);
+      Vs[T + t] = clamp_r(v1 - r.step * gv1, M.u_lo[1], M.u_hi[1]);
+    }
+    __syncthreads();
   }
   __syncthreads();
   R* out = r.V_safe + 2 * (size_t)d.t0;

@@ -575,7 +575,7 @@ static smppi_status repair_c8_t(smppi_ctx ctx, const smppi_batch* b, const C8Arg
   if (lds > (size_t)ctx->max_lds)
     return fail(ctx, SMPPI_ERR_SHAPE, "curvilinear shield needs %zu B of LDS per workgroup (device max %d)", lds,
                 ctx->max_lds);
-  hipLaunchKernelGGL((k_repair_c8<R>), dim3(b->n_problems), dim3(WAVE), lds, s, r);
+  hipLaunchKernelGGL((k_repair_c8<R>), dim3(b->n_problems), dim3(C8_REP_BLK), lds, s, r);
   return check_launch(ctx, "k_repair_c8");
 }
 
