@@ -444,7 +444,8 @@ def _form_large(ctx, core, W, M, C, lam, sync, out, seed):
 
 def _form_c0(ctx, core, W, lam, sync, out, seed):
     """Config 0: one plain MPPI iteration in FP64 (K = 256, T = 20, circle track):
-    rollout, weights, update as separate calls; latency per iteration."""
+    rollout, weights, update as separate calls, and the same three captured once in a
+    HIP graph; latency per iteration."""
     import torch
 
     p = W.config0()
@@ -456,7 +457,11 @@ def _form_c0(ctx, core, W, lam, sync, out, seed):
         core.update(ctx, db, W.MODEL, W.COST, seed, w)
 
     dt = _time(it, 500, 50, sync)
-    out["c0_fp64_K256_T20"] = {"ms_per_iter": dt * 1e3, "rollout_steps_per_s": p.K * p.T / dt, "dtype": "f64"}
+    g = _capture(it)
+    dg = _time(g.replay, 500, 50, sync)
+    del g
+    out["c0_fp64_K256_T20"] = {"ms_per_iter": dt * 1e3, "rollout_steps_per_s": p.K * p.T / dt, "dtype": "f64",
+                               "graph_ms_per_iter": dg * 1e3}
     _log(f"  c0: {out['c0_fp64_K256_T20']}")
 
 
@@ -640,6 +645,11 @@ def _form_curvilinear(ctx, core, W, M, C, sync, out, seed):
         core.execute_curvilinear(ctx, dbl, ct, M, WH, Vs, Vp)
 
     t_loop = _time(loop_iter, 50, 5, sync)
+    # the shield with every one of its ten steps active (total cost + squared violations)
+    Sl = core.rollout_curvilinear(ctx, dbl, ct, M, WH, C, seed)
+    Vq = core.update(ctx, dbl, M, C, seed, core.weights(ctx, dbl, Sl, W.LAMBDA)[0])
+    t_sh = _time(lambda: core.shield_repair_curvilinear(ctx, dbl, ct, M, WH, C, Vq, 10, 0.05, W.OBJ_TOTAL), 20, 3,
+                 sync)
     g = _capture(loop_iter)
     t_graph = _time(g.replay, 50, 5, sync)
     del g
@@ -650,7 +660,8 @@ def _form_curvilinear(ctx, core, W, M, C, sync, out, seed):
         "cartesian_rollout_ms": t_cart * 1e3, "cartesian_rollout_steps_per_s": K * T / t_cart,
         "cartesian_achieved_TFLOPs": FLOP_STEP_POLY * K * T / t_cart / 1e12,
         "closed_loop_K4096_T50_ms_per_iter": t_loop * 1e3,
-        "closed_loop_K4096_T50_graph_ms_per_iter": t_graph * 1e3}
+        "closed_loop_K4096_T50_graph_ms_per_iter": t_graph * 1e3,
+        "shield_10_active_steps_T50_ms": t_sh * 1e3}
     _log(f"  curvilinear: {out['curvilinear8_K65536_T100']}")
 
 
