@@ -71,9 +71,11 @@ __device__ __forceinline__ R kappa_cell(const CurvView<R>& cv, R s, R& slope) {
   return k0 * (R(1) - f) + k1 * f;
 }
 
+// Body part of f: (v_x, v_y, r, omega_F, omega_R) from themselves and the control
+// (the tyre forces depend on neither the path coordinates nor the curvature).
 template <class R>
-__device__ __forceinline__ void deriv_c8(const DevModel<R>& M, const DevWheels<R>& Wh, const CurvView<R>& cv,
-                                         const Ctl8<R>& c, const C8<R>& x, C8<R>& d) {
+__device__ __forceinline__ void deriv_c8_body(const DevModel<R>& M, const DevWheels<R>& Wh, const Ctl8<R>& c,
+                                              const C8<R>& x, C8<R>& d) {
   const R vt = fmax(x.vx, M.v_min);
   const R inv = rcp_r(vt);
   const R a = fma_r(M.lf, x.r, x.vy);
@@ -82,19 +84,31 @@ __device__ __forceinline__ void deriv_c8(const DevModel<R>& M, const DevWheels<R
   const R vwF = fma_r(x.vx, c.cd, a * c.sd);
   const R FxF = Wh.C_x * (fma_r(Wh.r_w, x.wF, -vwF) * inv);
   const R FxR = Wh.C_x * (fma_r(Wh.r_w, x.wR, -x.vx) * inv);
-  R slope;
-  const R k = kappa_cell(cv, x.s, slope);
-  R se, ce;
-  sincos_r(x.ep, &se, &ce);
-  const R sdot = fma_r(x.vx, ce, -(x.vy * se)) * rcp_r(fma_r(-k, x.ey, R(1)));
   d.vx = fma_r(FxR + fma_r(FxF, c.cd, -(FyF * c.sd)), M.inv_m, fma_r(-M.c_v, x.vx, x.vy * x.r));
   d.vy = fma_r(FyR + fma_r(FxF, c.sd, FyF * c.cd), M.inv_m, -(x.vx * x.r));
   d.r = fma_r(M.lf_Iz, fma_r(FxF, c.sd, FyF * c.cd), -(M.lr_Iz * FyR));
   d.wF = -(Wh.rw_Iw * FxF);
   d.wR = fma_r(Wh.drive_Iw, c.thr, -(Wh.rw_Iw * FxR));
+}
+
+// Path part of f: (e_psi, e_y, s) from themselves, (v_x, v_y, r) and kappa(s).
+template <class R>
+__device__ __forceinline__ void deriv_c8_path(const CurvView<R>& cv, const C8<R>& x, C8<R>& d) {
+  R slope;
+  const R k = kappa_cell(cv, x.s, slope);
+  R se, ce;
+  sincos_r(x.ep, &se, &ce);
+  const R sdot = fma_r(x.vx, ce, -(x.vy * se)) * rcp_r(fma_r(-k, x.ey, R(1)));
   d.ep = fma_r(-k, sdot, x.r);
   d.ey = fma_r(x.vx, se, x.vy * ce);
   d.s = sdot;
+}
+
+template <class R>
+__device__ __forceinline__ void deriv_c8(const DevModel<R>& M, const DevWheels<R>& Wh, const CurvView<R>& cv,
+                                         const Ctl8<R>& c, const C8<R>& x, C8<R>& d) {
+  deriv_c8_body(M, Wh, c, x, d);
+  deriv_c8_path(cv, x, d);
 }
 
 // y = x + h k
@@ -585,7 +599,7 @@ __device__ __forceinline__ R c8_comp(const C8<R>& x, int j) {
 template <class R>
 __global__ __launch_bounds__(C8_REP_BLK) void k_repair_c8(C8RepairArgs<R> r) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_last;
+  __shared__ int s_last, s_step;
   const C8Args<R>& a = r.a;
   const int b = blockIdx.x;
   C8Dims d;
@@ -602,17 +616,72 @@ __global__ __launch_bounds__(C8_REP_BLK) void k_repair_c8(C8RepairArgs<R> r) {
   const DevCost<R>& C = a.C;
   const DevObjective<R>& ob = r.ob;
   const bool cost_terms = ob.w_S != R(0);
+  const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const R h = M.dt, h2 = R(0.5) * M.dt, h6 = M.dt * R(1.0 / 6.0);
+  auto comb = [&](R a1, R a2, R a3, R a4, R xv) { return fma_r(h6, fma_r(R(2), a2 + a3, a1) + a4, xv); };
   for (int s = 0; s < r.n_steps; ++s) {
     if (threadIdx.x == 0) {
-      C8<R> x = load_c8(a.x0 + 8 * (size_t)b);
-      store_c8(xs, x);
-      int last = -1;
-      R hp = cv.w2 - x.ey * x.ey;
+      store_c8(xs, load_c8(a.x0 + 8 * (size_t)b));
+      s_step = 0;
+    }
+    __syncthreads();
+    // nominal trajectory: the body states on one lane of wave 0, publishing each
+    // step's stage values of (v_x, v_y, r) ([t][12] in the reverse sweep's
+    // buffer, free until then), the path states and the barrier activity on one
+    // lane of wave 1 as the steps are published (the classic RK4 of the model,
+    // the same operations as rk4_c8)
+    if (w == 0 && lane == 0) {
+      C8<R> x = load_c8(xs);
       for (int t = 0; t < T; ++t) {
         const R u0 = clamp_r(Vs[t], M.u_lo[0], M.u_hi[0]);
         const R u1 = clamp_r(Vs[T + t], M.u_lo[1], M.u_hi[1]);
-        rk4_c8(M, a.Wh, cv, ctl8(u0, u1), x);
-        store_c8(xs + 8 * (t + 1), x);
+        const Ctl8<R> c = ctl8(u0, u1);
+        C8<R> k1 = zero8<R>(), k2 = zero8<R>(), k3 = zero8<R>(), k4 = zero8<R>();
+        deriv_c8_body(M, a.Wh, c, x, k1);
+        const C8<R> X2 = axpy8(h2, k1, x);
+        deriv_c8_body(M, a.Wh, c, X2, k2);
+        const C8<R> X3 = axpy8(h2, k2, x);
+        deriv_c8_body(M, a.Wh, c, X3, k3);
+        const C8<R> X4 = axpy8(h, k3, x);
+        deriv_c8_body(M, a.Wh, c, X4, k4);
+        R* g = Wp + 12 * (size_t)t;
+        g[0] = x.vx; g[1] = X2.vx; g[2] = X3.vx; g[3] = X4.vx;
+        g[4] = x.vy; g[5] = X2.vy; g[6] = X3.vy; g[7] = X4.vy;
+        g[8] = x.r;  g[9] = X2.r;  g[10] = X3.r; g[11] = X4.r;
+        x.vx = comb(k1.vx, k2.vx, k3.vx, k4.vx, x.vx);
+        x.vy = comb(k1.vy, k2.vy, k3.vy, k4.vy, x.vy);
+        x.r = comb(k1.r, k2.r, k3.r, k4.r, x.r);
+        x.wF = comb(k1.wF, k2.wF, k3.wF, k4.wF, x.wF);
+        x.wR = comb(k1.wR, k2.wR, k3.wR, k4.wR, x.wR);
+        R* o = xs + 8 * (t + 1);
+        o[0] = x.vx; o[1] = x.vy; o[2] = x.r; o[3] = x.wF; o[4] = x.wR;
+        __hip_atomic_store(&s_step, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    } else if (w == 1 && lane == 0) {
+      C8<R> x = load_c8(xs);
+      int last = -1, seen = 0;
+      R hp = cv.w2 - x.ey * x.ey;
+      for (int t = 0; t < T; ++t) {
+        wave_wait(&s_step, t, seen, a.err);
+        const R* g = Wp + 12 * (size_t)t;
+        C8<R> k1 = zero8<R>(), k2 = zero8<R>(), k3 = zero8<R>(), k4 = zero8<R>();
+        C8<R> X = x;
+        X.vx = g[0]; X.vy = g[4]; X.r = g[8];
+        deriv_c8_path(cv, X, k1);
+        X.vx = g[1]; X.vy = g[5]; X.r = g[9];
+        X.ep = fma_r(h2, k1.ep, x.ep); X.ey = fma_r(h2, k1.ey, x.ey); X.s = fma_r(h2, k1.s, x.s);
+        deriv_c8_path(cv, X, k2);
+        X.vx = g[2]; X.vy = g[6]; X.r = g[10];
+        X.ep = fma_r(h2, k2.ep, x.ep); X.ey = fma_r(h2, k2.ey, x.ey); X.s = fma_r(h2, k2.s, x.s);
+        deriv_c8_path(cv, X, k3);
+        X.vx = g[3]; X.vy = g[7]; X.r = g[11];
+        X.ep = fma_r(h, k3.ep, x.ep); X.ey = fma_r(h, k3.ey, x.ey); X.s = fma_r(h, k3.s, x.s);
+        deriv_c8_path(cv, X, k4);
+        x.ep = comb(k1.ep, k2.ep, k3.ep, k4.ep, x.ep);
+        x.ey = comb(k1.ey, k2.ey, k3.ey, k4.ey, x.ey);
+        x.s = comb(k1.s, k2.s, k3.s, k4.s, x.s);
+        R* o = xs + 8 * (t + 1);
+        o[5] = x.ep; o[6] = x.ey; o[7] = x.s;
         const R hn = cv.w2 - x.ey * x.ey;
         if (C.alpha * hp - hn > R(0) && (ob.w_sq != R(0) || (ob.w_lin != R(0) && t < ob.n_lin))) last = t;
         hp = hn;
