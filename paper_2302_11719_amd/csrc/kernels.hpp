@@ -1509,7 +1509,8 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
           ao = C.alpha * hob - hi > R(0);
           hob = hi;
         }
-        act = act || (__ballot(ao) != 0ull);
+        const bool any_ob = __ballot(ao) != 0ull;  // with every lane active
+        act = act || any_ob;
       }
       if (act && (ob.w_sq != R(0) || (ob.w_lin != R(0) && t < ob.n_lin))) last = t;
     };

@@ -174,7 +174,13 @@ __device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, co
         pen0 += fmaxf((C.alpha - 1.f) * hob[k], 0.f);
       }
     }
-    if (NOBS > 0) outside = outside || oo || (pair_swap((int)oo) != 0);
+    if (NOBS > 0) {
+      // the partner lane's hits, exchanged with the whole wave active (inside a
+      // short-circuit the exchange would run only on the lanes without a hit of
+      // their own, and a lane whose partner had one would read a stale value)
+      const bool po = pair_swap((int)oo) != 0;
+      outside = outside || oo || po;
+    }
     S2 = C.C_cbf * pen0;
   }
   for (int s = 0; s < nch + 2; ++s) {
@@ -246,7 +252,10 @@ __device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, co
             oo = oo || (dd < o.r2);
           }
         }
-        if (NOBS > 0) outside = outside || oo || (pair_swap((int)oo) != 0);
+        if (NOBS > 0) {
+          const bool po = pair_swap((int)oo) != 0;  // whole wave active (see above)
+          outside = outside || oo || po;
+        }
         S2 += C.C_cbf * pen;
       }
     }

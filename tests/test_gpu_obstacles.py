@@ -106,3 +106,44 @@ def test_dense_obstacles_adjoint():
         emax = np.abs(got[b] - ref).max() / max(np.abs(ref).max(), 1e-30)
         say(f"  problem {b}: rel err {err:.2e} (max {emax:.2e})")
         assert err <= 1e-3 and emax <= 1e-3, (b, err, emax)
+
+
+def test_latency_mode_counts_hits_on_both_lanes_of_a_pair():
+    """The latency-mode plan splits each sample's obstacles between a pair of lanes
+    (even slots on one, odd slots on the other) and exchanges the collision flags
+    between them.  With 64 obstacles that the sampled trajectories run into, some hits
+    fall on odd slots only: the costs must equal the tile-mode plan's (the same
+    trajectories, the sums in another order) on every sample, and the oracle's on the
+    samples that hit an odd-slot obstacle."""
+    M, C = params(F32)
+    c_obs = W.COST["C_obs"]
+
+    def costs(p, pipeline):
+        db = core.DeviceBatch([p], dtype=F32)
+        pl = core.Plan(ctx(), db, M, C, 0, W.LAMBDA, use_graph=False, pipeline=pipeline)
+        pl.launch()
+        torch.cuda.synchronize()
+        S = pl.S.cpu().numpy().astype(np.float64)
+        pl.close()
+        return S
+
+    full = W.config4(K=4096, T=100, n_obs=64)
+    even = W.config4(K=4096, T=100, n_obs=64)
+    far = even.track.obs.copy()
+    far[1::2, 0:2] = 1e4  # odd slots moved far away
+    even.track.obs = far
+    say("latency mode, obstacles on both lanes of a pair")
+    pf = W.round_to_f32(full)
+    S_tile, S_lat = costs(pf, -1), costs(pf, 1)
+    S_even = costs(W.round_to_f32(even), -1)
+    assert ctx().device_errors() == 0
+    odd_hits = np.nonzero(S_tile - S_even >= 0.5 * c_obs)[0]
+    say(f"  {len(odd_hits)} of 4096 samples cost at least half an indicator term more with the odd slots")
+    assert len(odd_hits) > 0
+    rel = np.abs(S_lat - S_tile) / np.maximum(np.abs(S_tile), 1.0)
+    assert rel.max() <= 1e-5, (int((rel > 1e-5).sum()), rel.max())
+    idx = odd_hits[:64]
+    S_ref, _, margin = oracle.rollout(M, C, pf.track, pf.x0, pf.V, pf.K, 0, 0, pf.it, want_eps=False,
+                                      n_threads=8, samples=idx)
+    ok = band_mask(margin, BAND, "odd-slot hits", S_lat[idx], S_ref)
+    assert rel_err(S_lat[idx], S_ref)[ok].max() <= 1e-4
