@@ -1022,11 +1022,23 @@ __device__ __forceinline__ void shield_vel_row(const DevModel<R>& M, R delta, R 
   }
 }
 
+// max(x, v_min) on the velocity chain, v_min > 0.  FP32: one integer max of
+// the bit patterns (fmax first quiets a possible signalling NaN in x with a
+// second instruction on the chain): non-negative floats order like their bits
+// as signed integers, and every negative x (sign bit set) is below v_min's
+// positive pattern, so the value is fmax's for every x that is not a NaN.
+template <class R>
+__device__ __forceinline__ R shield_vmax(R x, R v_min) { return fmax(x, v_min); }
+template <>
+__device__ __forceinline__ float shield_vmax<float>(float x, float v_min) {
+  return __int_as_float(max(__float_as_int(x), __float_as_int(v_min)));
+}
+
 // f_i F(x, y, o) added to (ax, ay, ao), coefficients of factor i.
 template <class R, int I>
 __device__ __forceinline__ void shield_vel_inc(const ShieldVel<R>& k, const R* cr, R x, R y, R o, R ax, R ay, R ao,
                                                R& ox, R& oy, R& oo) {
-  const R inv = rcp_r(fmax(x, k.v_min));
+  const R inv = rcp_r(shield_vmax(x, k.v_min));
   const R t1 = fma_r(-fma_r(k.lf, o, y), inv, cr[0]);
   const R t2 = fma_r(k.lr, o, -y) * inv;
   const R oh = o * k.f[I];
@@ -1056,8 +1068,8 @@ __device__ __forceinline__ void shield_vel_step(const ShieldVel<R>& k, const R* 
   om = fma_r(two_thirds, g.om[2], fma_r(third, g.om[1] + g.om[3], fma_r(-third, o0, ko)));
 }
 
-// LDS of the shield beyond the staged problem: states x_0..x_T, segment
-// indices, the per-step constants (REP_CTL per step) and two chunks of RK4
+// LDS of the shield beyond the staged problem: states x_0..x_T, their e_y^2,
+// segment indices, the per-step constants (REP_CTL per step) and two chunks of RK4
 // stage velocities (12 per step) passed from the velocity wave to the pose wave;
 // with L-BFGS (memory > 0) also the gradient, the previous iterate and
 // gradient, the two-loop vector, memory + 1 pair slots (s, y) of 2 t_max
@@ -1066,7 +1078,7 @@ template <class R>
 __host__ __device__ inline size_t repair_lds_bytes(int t_max, int memory, bool par_rev, bool stepwise) {
   // stage velocities: every step for the step-by-step hand-over, else a ring of two chunks
   const size_t vst_rows = stepwise ? (size_t)t_max : (size_t)2 * REP_C;
-  size_t n = (size_t)(t_max + 1) * (6 * sizeof(R) + sizeof(int)) + (size_t)REP_CTL * t_max * sizeof(R) +
+  size_t n = (size_t)(t_max + 1) * (7 * sizeof(R) + sizeof(int)) + (size_t)REP_CTL * (t_max + 2) * sizeof(R) +
              (size_t)12 * vst_rows * sizeof(R) + 16;
   if (memory > 0) n += ((size_t)(4 + 2 * (memory + 1)) * 2 * t_max + 4 * (memory + 1) + 16) * sizeof(R);
   if (par_rev) n += (size_t)REP_PAR_PER_STEP * t_max * sizeof(R);
@@ -1126,25 +1138,23 @@ __device__ __forceinline__ float row_min<float>(float v) {
 // be active and c, px, py uniform): lane r of each row holds the r-th offset of
 // the rule's order (0, -1, +1, -2, ...), the row minimum comes from four DPP
 // rotations, and the first offset in the rule's order attaining it is the
-// lowest set bit of the ballot.  Returns e_y^2; c (uniform) in/out.
+// lowest set bit of the ballot; that lane's wrapped segment index is the new c
+// (one v_readlane).  Returns e_y^2; c (uniform) in/out.
 template <class R>
 __device__ R row_window(const TrackView<R>& tr, int& c, R px, R py) {
   const int r = threadIdx.x & 15;
+  const int off = r == 0 ? 0 : ((r & 1) ? -((r + 1) >> 1) : (r >> 1));
+  // the slot's segment wrapped onto 0 .. n-1 (the padded copy is read at c + off)
+  int iw = c + off;
+  iw += (iw < 0) ? tr.n : 0;
+  iw -= (iw >= tr.n) ? tr.n : 0;
   R dd = R(INFINITY);
-  if (r < 2 * tr.window + 1) {
-    const int off = r == 0 ? 0 : ((r & 1) ? -((r + 1) >> 1) : (r >> 1));
-    dd = seg_dist2(tr, c + off, px, py);  // padded copy: c + off needs no wrap to be read
-  }
+  if (r < 2 * tr.window + 1) dd = seg_dist2(tr, c + off, px, py);
   const R m = row_min(dd);
   const unsigned long long bal = __ballot(dd == m) & 0xFFFFull;
-  // slot rr (-1 if none) -> offset: (rr + 1) / 2 with the sign of an odd slot
-  // negative; branch-free scalar arithmetic (rr = -1 and rr = 0 give 0)
-  const int rr = __ffsll((long long)bal) - 1;
-  const int half = (rr + 1) >> 1, neg = -(rr & 1);
-  int i = __builtin_amdgcn_readfirstlane(c) + ((half ^ neg) - neg);
-  i += (i < 0) ? tr.n : 0;
-  i -= (i >= tr.n) ? tr.n : 0;
-  c = __builtin_amdgcn_readfirstlane(i);
+  // the first slot attaining the minimum; slot 0 (offset 0) if none does (NaN)
+  const int rr = bal ? __ffsll((long long)bal) - 1 : 0;
+  c = __builtin_amdgcn_readlane(iw, rr);
   return m;
 }
 
@@ -1210,6 +1220,19 @@ __device__ __forceinline__ float lane_bcast(float v, int i) {
 __device__ __forceinline__ double lane_bcast(double v, int i) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)b, i), hi = __builtin_amdgcn_readlane((int)(b >> 32), i);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Value of lane Q of each quad (DPP quad_perm [Q, Q, Q, Q]).
+template <int Q>
+__device__ __forceinline__ float quad_get(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), Q * 0x55, 0xF, 0xF, false));
+}
+template <int Q>
+__device__ __forceinline__ double quad_get(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, Q * 0x55, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), Q * 0x55, 0xF, 0xF, false);
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
@@ -1392,22 +1415,45 @@ __device__ void lbfgs_step(const DevModel<R>& M, R* V, int T, const R* g, R* gpr
   __syncthreads();
 }
 
-// Waits until the step counter *c (LDS, published with release by another wave
-// of the workgroup) exceeds t; `seen` keeps the last value read, so a wave that
-// trails its producer polls only when it has caught up.  The wait is bounded:
-// after 2^22 polls the wave flags DERR_WAIT and stops waiting (its results are
-// then wrong, but the workgroup finishes).
+// The DCBF condition of one transition fails: alpha h(x_t) > h(x_{t+1}), i.e.
+// alpha h(x_t) - h(x_{t+1}) > 0 (a difference of two floats is zero only when
+// they are equal).  One definition for every place that decides it.
+template <class R>
+__device__ __forceinline__ bool dcbf_active(R alpha, R h_t, R h_t1) {
+  return alpha * h_t > h_t1;
+}
+
+// Step counters between the waves of one workgroup (LDS only).  The LDS
+// performs the operations of one wave in the order the wave issues them, so a
+// counter stored after a step's LDS rows lands after those rows, and a wave
+// that has read the new counter value issues its row reads after that: the
+// producer does not have to wait for its row stores to complete before it
+// stores the counter (a release store would, one LDS round trip per step on
+// the producer's dependency chain).  The empty asm statements keep the
+// compiler from moving LDS accesses across the counter accesses.
+__device__ __forceinline__ void wave_publish(int* c, int v) {
+  asm volatile("" ::: "memory");
+  __hip_atomic_store(c, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Waits until the step counter *c (wave_publish by another wave of the
+// workgroup) exceeds t; `seen` keeps the last value read, so a wave that trails
+// its producer polls only when it has caught up.  Polls back to back: a poll
+// is one LDS read, a compare and a branch, and the wave sleeps in the read's
+// wait.  The wait is bounded: after 2^22 polls
+// the wave flags DERR_WAIT and stops waiting (its results are then wrong, but
+// the workgroup finishes).
 __device__ __forceinline__ void wave_wait(const int* c, int t, int& seen, uint32_t* err) {
   for (int n = 0; seen <= t; ++n) {
-    seen = __hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    seen = __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (seen > t) break;
     if (n >= (1 << 22)) {
       if (threadIdx.x % WAVE == 0) atomicOr(err, DERR_WAIT);
       seen = 0x7fffffff;
       break;
     }
-    __builtin_amdgcn_s_sleep(1);
   }
+  asm volatile("" ::: "memory");
 }
 
 // Algorithm 1 for problem b by one workgroup of at least three waves (threads
@@ -1427,16 +1473,18 @@ __device__ __forceinline__ void wave_wait(const int* c, int t, int& seen, uint32
 template <class R, int NOBS, bool VG = true>
 __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims& d, const TrackView<R>& tr, R* Vs,
                                unsigned char* lds, int* s_last) {
-  // 16-byte aligned rows first (lds is 16-byte aligned): ctl [t_max][REP_CTL],
+  // 16-byte aligned rows first (lds is 16-byte aligned): ctl [t_max + 2][REP_CTL]
+  // (two padding rows for the velocity wave's reads ahead),
   // vst stage velocities ([t_max][12] with VG, else a ring [2][REP_C][12]), 16
-  // bytes of step counters; then states xs [t_max+1][6], segment indices is
-  // [t_max+1]
+  // bytes of step counters; then states xs [t_max+1][6], e_y^2 of each state
+  // e2s [t_max+1], segment indices is [t_max+1]
   R* ctl = static_cast<R*>(__builtin_assume_aligned(reinterpret_cast<R*>(lds), 16));
-  R* vst = static_cast<R*>(__builtin_assume_aligned(ctl + REP_CTL * (size_t)a.p.t_max, 16));
+  R* vst = static_cast<R*>(__builtin_assume_aligned(ctl + REP_CTL * ((size_t)a.p.t_max + 2), 16));
   // steps published by the velocity wave [0] and the pose wave [1] (16 bytes)
   int* flg = reinterpret_cast<int*>(vst + 12 * (size_t)(VG ? a.p.t_max : 2 * REP_C));
   R* xs = reinterpret_cast<R*>(flg + 4);
-  int* is = reinterpret_cast<int*>(xs + 6 * (size_t)(a.p.t_max + 1));
+  R* e2s = xs + 6 * (size_t)(a.p.t_max + 1);
+  int* is = reinterpret_cast<int*>(e2s + (a.p.t_max + 1));
   // L-BFGS state (memory > 0): gradient, previous iterate and gradient, two-loop
   // vector, pairs in a ring of memory + 1 slots (kept pair i at (head + i) %
   // (memory + 1), i = 0 oldest; the next slot takes the candidate), per pair
@@ -1478,6 +1526,8 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
     if (threadIdx.x == 0) {
       flg[0] = 0;
       flg[1] = 0;
+      *s_last = -1;
+      e2s[0] = e20;
     }
     State<R> x = x0;
     int idx = idx0, last = -1;
@@ -1498,7 +1548,7 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
     // active transition
     auto transition = [&](int t, R px, R py, R e2) {
       const R h = tr.w2 - e2;
-      bool act = C.alpha * hp - h > R(0);
+      bool act = dcbf_active(C.alpha, hp, h);
       hp = h;
       if (NOBS > 0) {
         bool ao = false;
@@ -1506,7 +1556,7 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
           const Obs<R> o = obs_at(tr, lane);
           const R ox = px - o.cx, oy = py - o.cy;
           const R hi = ox * ox + oy * oy - o.re2;
-          ao = C.alpha * hob - hi > R(0);
+          ao = dcbf_active(C.alpha, hob, hi);
           hob = hi;
         }
         const bool any_ob = __ballot(ao) != 0ull;  // with every lane active
@@ -1519,60 +1569,87 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
       // latency-mode plan) step by step through the LDS step counters
       __syncthreads();
       if (w == 0 && lane == 0) {
-        // velocity wave: the RK4 chain of (v_x, v_y, omega), publishing each step
+        // velocity wave: the RK4 chain of (v_x, v_y, omega), publishing each step.
+        // Each step's control row is read one step ahead: the read completes
+        // during the previous step's chain, and the stores and counters in
+        // between never wait for it (the counter store waits for nothing).
+        // Written out for two steps per iteration, so the two rows alternate
+        // between two register sets instead of being copied, with the first
+        // step peeled: the loop is entered with the same LDS operations in
+        // flight as on its back edge (reads of the next row, stores of the last
+        // step, reads of the row after), so every step waits only for its own
+        // row.  The empty asm statements keep the reads and stores where they are
+        // issued.
         const ShieldVel<R> kv = shield_vel(M);
-        for (int t0 = 0; t0 < T; t0 += REP_C) {
-          const int t1 = min(T, t0 + REP_C);
-          // the chunk's control rows are read before its first store: LDS
-          // returns in order, so a row read after a step's stores would wait for
-          // them inside the RK4 chain
-          R cc[REP_C][13];
+        auto load_row = [&](R* cc, int t) {
+          // rows T and T + 1 (padding) are read at the end and never used
+          const R* cr = static_cast<const R*>(__builtin_assume_aligned(ctl + REP_CTL * t, 16));
   #pragma unroll
-          for (int k = 0; k < REP_C; ++k) {
-            const R* cr = static_cast<const R*>(__builtin_assume_aligned(ctl + REP_CTL * min(t0 + k, t1 - 1), 16));
+          for (int c = 0; c < 13; ++c) cc[c] = cr[c];
+          // (tied to the state, so the reads are issued before the next step's chain)
+          asm volatile("" : "+v"(x.vx), "+v"(x.vy), "+v"(x.om)::"memory");
+        };
+        auto vel_step = [&](const R* cc, int t) {
+          VelStages<R> g;
+          shield_vel_step(kv, cc, x.vx, x.vy, x.om, g);
+          R* gt = static_cast<R*>(__builtin_assume_aligned(vst + 12 * (size_t)t, 16));
   #pragma unroll
-            for (int c = 0; c < 13; ++c) cc[k][c] = cr[c];
+          for (int q = 0; q < 4; ++q) {
+            gt[q] = g.vx[q];
+            gt[4 + q] = g.vy[q];
+            gt[8 + q] = g.om[q];
           }
-  #pragma unroll
-          for (int j = 0; j < REP_C; ++j) {
-            const int t = t0 + j;
-            if (t >= t1) break;
-            VelStages<R> g;
-            shield_vel_step(kv, cc[j], x.vx, x.vy, x.om, g);
-            R* gt = static_cast<R*>(__builtin_assume_aligned(vst + 12 * (size_t)t, 16));
-  #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              gt[q] = g.vx[q];
-              gt[4 + q] = g.vy[q];
-              gt[8 + q] = g.om[q];
-            }
-            // (the velocities of x_{t+1} are the next row's first stage: copied
-            // into the states after the pass)
-            __hip_atomic_store(flg, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-          }
+          // (the velocities of x_{t+1} are the next row's first stage: copied
+          // into the states after the pass)
+          wave_publish(flg, t + 1);
+          // the next step's chain starts after the counter store (the
+          // compiler would otherwise hoist it above the stores and publish
+          // each step a step late)
+          asm volatile("" : "+v"(x.vx), "+v"(x.vy), "+v"(x.om)::"memory");
+        };
+        R ca[13], cb[13];
+        load_row(ca, 0);
+        load_row(cb, 1);
+        if (T > 0) vel_step(ca, 0);
+        load_row(ca, 2);
+        int t = 1;
+        for (; t + 1 < T; t += 2) {
+          vel_step(cb, t);
+          load_row(cb, t + 2);
+          vel_step(ca, t + 1);
+          load_row(ca, t + 3);
         }
+        if (t < T) vel_step(cb, t);
         if (T > 0) {
           R* o = xs + 6 * T;
           o[3] = x.vx; o[4] = x.vy; o[5] = x.om;
         }
-      } else if (w == 2 && lane == 0) {
+      } else if (w == 2 && lane < 4) {
         // pose wave: (p_x, p_y, psi) from the stage velocities, step by step as
-        // they are published
+        // they are published, one RK4 stage per lane (lane q: the heading of
+        // stage q and its position derivative, one sine and cosine per lane);
+        // the four stages meet through quad broadcasts and every lane forms the
+        // same sums in the same order as the one-lane step (rk4_pose)
+        const int q = lane;
+        const R h = M.dt, h2 = R(0.5) * M.dt, h6 = M.dt * R(1.0 / 6.0);
         int seen = 0;
         for (int t = 0; t < T; ++t) {
           wave_wait(flg, t, seen, a.p.err);
           const R* gt = static_cast<const R*>(__builtin_assume_aligned(vst + 12 * (size_t)t, 16));
-          VelStages<R> g;
-  #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            g.vx[q] = gt[q];
-            g.vy[q] = gt[4 + q];
-            g.om[q] = gt[8 + q];
-          }
-          rk4_pose(M, g, x.px, x.py, x.psi);
+          const R vq = gt[q], wq = gt[4 + q];
+          const R o0 = gt[8], o1 = gt[9], o2 = gt[10], o3 = gt[11];
+          const R psq = q == 0 ? x.psi : fma_r(q == 3 ? h : h2, q == 1 ? o0 : (q == 2 ? o1 : o2), x.psi);
+          R ex, ey;
+          pose_deriv(psq, vq, wq, ex, ey);
+          const R a0 = quad_get<0>(ex), b0 = quad_get<1>(ex), c0 = quad_get<2>(ex), d0 = quad_get<3>(ex);
+          const R a1 = quad_get<0>(ey), b1 = quad_get<1>(ey), c1 = quad_get<2>(ey), d1 = quad_get<3>(ey);
+          x.px = fma_r(h6, fma_r(R(2), b0 + c0, a0) + d0, x.px);
+          x.py = fma_r(h6, fma_r(R(2), b1 + c1, a1) + d1, x.py);
+          x.psi = fma_r(h6, fma_r(R(2), o1 + o2, o0) + o3, x.psi);
           R* o = xs + 6 * (t + 1);
-          o[0] = x.px; o[1] = x.py; o[2] = x.psi;
-          __hip_atomic_store(flg + 1, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          o[0] = x.px; o[1] = x.py; o[2] = x.psi;  // the same values from all four lanes
+          wave_publish(flg + 1, t + 1);
+          asm volatile("" : "+v"(x.px), "+v"(x.py), "+v"(x.psi)::"memory");
         }
       } else if (w == 1) {
         // window wave: e_y^2, obstacle barriers and activity of each new position.
@@ -1583,13 +1660,20 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
         for (int t0 = 0; t0 < T; t0 += REP_C) {
           const int t1 = min(T, t0 + REP_C);
           int ic = 0;
+          R ec = R(0);
           auto chunk = [&](auto track_e2) {
             for (int t = t0; t < t1; ++t) {
               wave_wait(flg + 1, t, seen, a.p.err);
               const R px = xs[6 * (t + 1)], py = xs[6 * (t + 1) + 1];
               const R e2 = track_e2(px, py);
-              ic = lane == t - t0 ? idx : ic;
-              transition(t, px, py, e2);
+              const bool mine = lane == t - t0;
+              ic = mine ? idx : ic;
+              // without obstacles the activity of every transition is found
+              // after the pass, in parallel, from the stored e_y^2
+              if constexpr (NOBS > 0)
+                transition(t, px, py, e2);
+              else
+                ec = mine ? e2 : ec;
             }
           };
           // window segments on the lanes of a row, min by DPP (no LDS round trip
@@ -1600,7 +1684,10 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
             chunk([&](R px, R py) { return row_window(tr, idx, px, py); });
           else
             chunk([&](R px, R py) { return window_min(tr, idx, px, py); });
-          if (lane < t1 - t0) is[t0 + 1 + lane] = ic;
+          if (lane < t1 - t0) {
+            is[t0 + 1 + lane] = ic;
+            e2s[t0 + 1 + lane] = ec;
+          }
         }
       }
       __syncthreads();
@@ -1699,7 +1786,17 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
         __syncthreads();
       }
     }
-    if (w == 1 && lane == 0) *s_last = last;
+    if constexpr (VG && NOBS == 0) {
+      // the last transition t whose DCBF condition fails, from e_y^2 of x_t and
+      // x_{t+1} (the same comparison as on the window wave)
+      const int t_lim = ob.w_sq != R(0) ? T : (ob.w_lin != R(0) ? min(ob.n_lin, T) : 0);
+      int lt = -1;
+      for (int t = threadIdx.x; t < t_lim; t += blockDim.x)
+        if (dcbf_active(C.alpha, tr.w2 - e2s[t], tr.w2 - e2s[t + 1])) lt = t;
+      if (lt >= 0) atomicMax(s_last, lt);
+    } else {
+      if (w == 1 && lane == 0) *s_last = last;
+    }
     __syncthreads();
     const int t_end = cost_terms ? T - 1 : *s_last;
     if (a.method == 1 && t_end >= 0) {
