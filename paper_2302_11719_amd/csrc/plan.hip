@@ -57,26 +57,27 @@ struct FusedArgs {
 
 // ---------------------------------------------------------------------------
 // Latency mode: one tile = 64 samples handled by four specialised waves (one
-// per SIMD) that run the same trajectories as a pipeline over chunks of PIPE_C
-// steps.
-//   wave 0: noise, clipped controls, control cost, per-step control constants
-//           (chunk s),
-//   wave 1: the RK4 chain (chunk s-1), writing (p_x, p_y, v_x) of every new
-//           state,
-//   waves 2-3: two lanes per sample (chunk s-2): the lateral offset window
-//           split between the pair, running cost, DCBF penalties, obstacles
-//           (split between the pair), collision indicator.
-// A workgroup barrier separates the stages.  A launch with fewer waves than
+// per SIMD) that run the same trajectories as a pipeline, step by step:
+//   wave 0: noise, clipped controls, control cost, per-step control constants,
+//   wave 1: the RK4 chain, writing (p_x, p_y, v_x) of every new state,
+//   waves 2-3: two lanes per sample: the lateral offset window split between
+//           the pair, running cost, DCBF penalties, obstacles (split between
+//           the pair), collision indicator.
+// Steps pass through rings of PIPE_R slots in LDS with step counters (the
+// producer publishes a step once its slot is written, and reuses a slot once
+// its consumers have counted the step read), so the pipeline fills in a few
+// steps and runs at its slowest wave's rate.  A launch with fewer waves than
 // SIMDs is bound by each wave's per-step chain; splitting the step four ways
 // shortens it.  Same arithmetic as rollout_sample, summed in partial sums
 // (control terms, state terms of each half) instead of one.
-constexpr int PIPE_C = 4;
+constexpr int PIPE_R = 8;
 constexpr int PIPE_BLK = 4 * WAVE;
 
 struct PipeLds {
-  float ctl[2][PIPE_C][6][WAVE];  // u0, u1, sin(u0)/m, cos(u0)/m, l_f cos(u0)/I_z, a_max u1
-  float pos[2][PIPE_C][3][WAVE];  // p_x, p_y, v_x of x_{t+1}
+  float ctl[PIPE_R][6][WAVE];  // u0, u1, sin(u0)/m, cos(u0)/m, l_f cos(u0)/I_z, a_max u1
+  float pos[PIPE_R][3][WAVE];  // p_x, p_y, v_x of x_{t+1}
   float part[2][WAVE];
+  int cnt[4];  // steps published by wave 0 (controls) and wave 1 (states); steps read by waves 2 and 3
 };
 
 // Swap with the neighbouring lane (DPP quad_perm [1,0,3,2]).
@@ -131,7 +132,7 @@ __device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, co
                               PipeLds& P) {
   constexpr int NH = NOBS > 0 ? (NOBS + 1) / 2 : 1;  // obstacles per half
   const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-  const int T = d.T, nch = (T + PIPE_C - 1) / PIPE_C;
+  const int T = d.T;
   const DevModel<float> M = model_in_vgprs(a.M);
   const DevCost<float> C = cost_in_vgprs(a.C);
   // wave 0
@@ -183,84 +184,96 @@ __device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, co
     }
     S2 = C.C_cbf * pen0;
   }
-  for (int s = 0; s < nch + 2; ++s) {
-    if (w == 0 && s < nch) {
-      const int t0 = s * PIPE_C, t1 = min(T, t0 + PIPE_C);
-      for (int t = t0; t < t1; ++t) {
-        const float v0 = Vs[t], v1 = Vs[T + t];
-        float e0, e1;
-        ns.at(t, C.sigma[0], C.sigma[1], e0, e1);
-        const float u0 = clamp_r(v0 + e0, M.u_lo[0], M.u_hi[0]);
-        const float u1 = clamp_r(v1 + e1, M.u_lo[1], M.u_hi[1]);
-        Sc += C.ctrl_w[0] * v0 * u0 + C.ctrl_w[1] * v1 * u1;
-        const StepCtl<float> sc = step_ctl(M, u0, u1);
-        float(*c)[WAVE] = P.ctl[s & 1][t - t0];
-        c[0][lane] = u0;
-        c[1][lane] = u1;
-        c[2][lane] = sc.sd_m;
-        c[3][lane] = sc.cd_m;
-        c[4][lane] = sc.lfcd_Iz;
-        c[5][lane] = sc.a_tau;
-      }
-    } else if (w == 1 && s >= 1 && s <= nch) {
-      const int cc = s - 1, t0 = cc * PIPE_C, t1 = min(T, t0 + PIPE_C);
-      for (int t = t0; t < t1; ++t) {
-        const float(*c)[WAVE] = P.ctl[cc & 1][t - t0];
-        StepCtl<float> sc;
-        sc.delta = c[0][lane];
-        sc.sd_m = c[2][lane];
-        sc.cd_m = c[3][lane];
-        sc.lfcd_Iz = c[4][lane];
-        sc.a_tau = c[5][lane];
-        sc.sd = sc.cd = 0.f;  // used by the reverse sweep only
-        rk4(M, sc, x);
-        float(*o)[WAVE] = P.pos[cc & 1][t - t0];
-        o[0][lane] = x.px;
-        o[1][lane] = x.py;
-        o[2][lane] = x.vx;
-      }
-    } else if (w >= 2 && s >= 2) {
-      const int cc = s - 2, t0 = cc * PIPE_C, t1 = min(T, t0 + PIPE_C);
-      for (int t = t0; t < t1; ++t) {
-        const float dv = vxp - C.v_g;
-        float q = C.q_v * dv * dv + C.q_ey * ey2;
-        if (outside) q += C.C_obs;
-        S2 += half ? 0.f : q;
-        const float(*qp)[WAVE] = P.pos[cc & 1][t - t0];
-        const float px = qp[0][j], py = qp[1][j];
-        vxp = qp[2][j];
-        if (tr.n > 0 && tr.window == 4) {
-          ey2 = pair_window4(tr, idx, px, py, half);
-        } else {
-          ey2 = lateral_sq(tr, px, py, idx);
-        }
-        const float h1 = tr.w2 - ey2;
-        float pen = half ? 0.f : fmaxf(C.alpha * hp - h1, 0.f);
-        hp = h1;
-        outside = h1 < 0.f;
-        bool oo = false;
-#pragma unroll
-        for (int k = 0; k < NH; ++k) {
-          const int i = 2 * k + half;
-          if (i < NOBS) {
-            const Obs<float> o = obs_at(tr, i);
-            const float ox = px - o.cx, oy = py - o.cy;
-            const float dd = ox * ox + oy * oy;
-            const float hi = dd - o.re2;
-            pen += fmaxf(C.alpha * hob[k] - hi, 0.f);
-            hob[k] = hi;
-            oo = oo || (dd < o.r2);
-          }
-        }
-        if (NOBS > 0) {
-          const bool po = pair_swap((int)oo) != 0;  // whole wave active (see above)
-          outside = outside || oo || po;
-        }
-        S2 += C.C_cbf * pen;
-      }
+  if (threadIdx.x == 0) P.cnt[0] = P.cnt[1] = P.cnt[2] = P.cnt[3] = 0;
+  __syncthreads();
+  if (w == 0) {
+    int seen = 0;
+    for (int t = 0; t < T; ++t) {
+      const float v0 = Vs[t], v1 = Vs[T + t];
+      float e0, e1;
+      ns.at(t, C.sigma[0], C.sigma[1], e0, e1);
+      const float u0 = clamp_r(v0 + e0, M.u_lo[0], M.u_hi[0]);
+      const float u1 = clamp_r(v1 + e1, M.u_lo[1], M.u_hi[1]);
+      Sc += C.ctrl_w[0] * v0 * u0 + C.ctrl_w[1] * v1 * u1;
+      const StepCtl<float> sc = step_ctl(M, u0, u1);
+      if (t >= PIPE_R) wave_wait(&P.cnt[1], t - PIPE_R, seen, a.p.err);  // slot read by wave 1
+      float(*c)[WAVE] = P.ctl[t % PIPE_R];
+      c[0][lane] = u0;
+      c[1][lane] = u1;
+      c[2][lane] = sc.sd_m;
+      c[3][lane] = sc.cd_m;
+      c[4][lane] = sc.lfcd_Iz;
+      c[5][lane] = sc.a_tau;
+      wave_publish(&P.cnt[0], t + 1);
     }
-    __syncthreads();
+  } else if (w == 1) {
+    int seen = 0, seen2 = 0, seen3 = 0;
+    for (int t = 0; t < T; ++t) {
+      wave_wait(&P.cnt[0], t, seen, a.p.err);
+      const float(*c)[WAVE] = P.ctl[t % PIPE_R];
+      StepCtl<float> sc;
+      sc.delta = c[0][lane];
+      sc.sd_m = c[2][lane];
+      sc.cd_m = c[3][lane];
+      sc.lfcd_Iz = c[4][lane];
+      sc.a_tau = c[5][lane];
+      sc.sd = sc.cd = 0.f;  // used by the reverse sweep only
+      rk4(M, sc, x);
+      if (t >= PIPE_R) {  // slot read by waves 2 and 3
+        wave_wait(&P.cnt[2], t - PIPE_R, seen2, a.p.err);
+        wave_wait(&P.cnt[3], t - PIPE_R, seen3, a.p.err);
+      }
+      float(*o)[WAVE] = P.pos[t % PIPE_R];
+      o[0][lane] = x.px;
+      o[1][lane] = x.py;
+      o[2][lane] = x.vx;
+      wave_publish(&P.cnt[1], t + 1);
+    }
+  } else {
+    int seen = 0;
+    for (int t = 0; t < T; ++t) {
+      const float dv = vxp - C.v_g;
+      float q = C.q_v * dv * dv + C.q_ey * ey2;
+      if (outside) q += C.C_obs;
+      S2 += half ? 0.f : q;
+      wave_wait(&P.cnt[1], t, seen, a.p.err);
+      const float(*qp)[WAVE] = P.pos[t % PIPE_R];
+      const float px = qp[0][j], py = qp[1][j];
+      vxp = qp[2][j];
+      // counted as read once the reads are issued (the LDS performs this wave's
+      // operations in order, so the slot's next store lands after them)
+      wave_publish(&P.cnt[w], t + 1);
+      if (tr.n > 0 && tr.window == 4) {
+        ey2 = pair_window4(tr, idx, px, py, half);
+      } else {
+        ey2 = lateral_sq(tr, px, py, idx);
+      }
+      const float h1 = tr.w2 - ey2;
+      float pen = half ? 0.f : fmaxf(C.alpha * hp - h1, 0.f);
+      hp = h1;
+      outside = h1 < 0.f;
+      bool oo = false;
+#pragma unroll
+      for (int k = 0; k < NH; ++k) {
+        const int i = 2 * k + half;
+        if (i < NOBS) {
+          const Obs<float> o = obs_at(tr, i);
+          const float ox = px - o.cx, oy = py - o.cy;
+          const float dd = ox * ox + oy * oy;
+          const float hi = dd - o.re2;
+          pen += fmaxf(C.alpha * hob[k] - hi, 0.f);
+          hob[k] = hi;
+          oo = oo || (dd < o.r2);
+        }
+      }
+      if (NOBS > 0) {
+        const bool po = pair_swap((int)oo) != 0;  // whole wave active (see above)
+        outside = outside || oo || po;
+      }
+      S2 += C.C_cbf * pen;
+    }
   }
+  __syncthreads();
   if (w >= 2) {
     const float dv = vxp - C.v_g;
     float q = C.q_v * dv * dv + C.q_ey * ey2;
