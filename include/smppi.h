@@ -382,8 +382,11 @@ typedef struct {
 
 /* Build a plan for `batch` (which must stay valid, with its device arrays, for
  * the plan's life): tile list in longest-first order, per-problem ticket
- * counters, and (use_graph) the captured graph.  The first launch of a plan
- * resets nothing the caller owns. */
+ * counters, and (use_graph) the captured graph.  The batch's offsets (k_off,
+ * t_off; with one problem also the track's poly_off and obs_off) are read once,
+ * here: later changes to them are not seen by the plan's launches (the rows
+ * they point to, x0, V and iter are read on every launch).  The first launch
+ * of a plan resets nothing the caller owns. */
 smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batch, const smppi_model* model,
                                const smppi_cost* cost, const smppi_noise* noise, const smppi_track* track,
                                const smppi_plan_opts* opts, const smppi_plan_buffers* bufs,

@@ -53,6 +53,11 @@ struct FusedArgs {
   int repair;                // nonzero: the combining workgroup also runs the shield (and execute)
   RepairArgs<float> rep;
   const float4* obs_pad;     // [B][kMaxObs] obstacle slots (WaveObstacles; NOBS > 0, tile mode)
+  // One-problem plans: problem 0's dimensions, taken from the offsets at plan
+  // creation (checked there); tile k is then (0, k), and a workgroup reads
+  // neither the tile list nor the offsets before staging.
+  int one;
+  ProblemDims d1;
 };
 
 // ---------------------------------------------------------------------------
@@ -329,10 +334,19 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       __syncthreads();
     }
     if (tile >= a.n_tiles) break;
-    const int2 tk = a.tiles[tile];
-    const int b = __builtin_amdgcn_readfirstlane(tk.x);
-    const int kb = __builtin_amdgcn_readfirstlane(tk.y);
-    if (!load_dims(a.p, b, d)) continue;
+    int b, kb, toff_b;
+    if (a.one) {
+      b = 0;
+      kb = tile;
+      toff_b = 0;
+      d = a.d1;
+    } else {
+      const int2 tk = a.tiles[tile];
+      b = __builtin_amdgcn_readfirstlane(tk.x);
+      kb = __builtin_amdgcn_readfirstlane(tk.y);
+      if (!load_dims(a.p, b, d)) continue;
+      toff_b = __builtin_amdgcn_readfirstlane(a.tile_off[b]);  // read now: needed after the rollout
+    }
     if (b != staged_b) {
       tr = stage_problem(a.p, b, d, a.V, smem, &Vs);
       staged_b = b;
@@ -394,7 +408,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       if (own[j] && !isfinite(s[j])) nf += 1.f;
     }
     block_sum3<float, false>(z, q, nf, red_sum);
-    float* P = a.part + (size_t)(a.tile_off[b] + kb) * pstride;
+    float* P = a.part + (size_t)(toff_b + kb) * pstride;
     block_noise_sums<float, BLK, SPT, PIPE>(a.M, a.C, a.p.seed, pid, it, a.p.nominal != 0, Vs, d.T, ms, om, L,
                                       P + PART_HDR);
     if (tid == 0) {
@@ -417,7 +431,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       // tile headers are read once into registers and the scales kept in LDS
       // when the problem has at most BLK*SPT tiles; the V+ pass keeps NB loads
       // in flight per thread.
-      const float* P0 = a.part + (size_t)a.tile_off[b] * pstride;
+      const float* P0 = a.part + (size_t)toff_b * pstride;
       float* s_sc = L.w;
       float gmin, Z, Q, NF;
       const bool one_pass = ntb <= BLK * SPT;
@@ -848,6 +862,29 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
   a.stats = static_cast<float*>(bufs->stats);
   a.inv_lambda = (float)(1.0 / opts->lambda);
   a.tiles = p->tiles;
+  a.one = 0;
+  if (B == 1) {
+    // problem 0's dimensions for the one-problem path, checked as load_dims does
+    // (an invalid problem keeps the general path, whose kernels flag it)
+    int32_t po[2] = {0, 0}, oo[2] = {0, 0};
+    if (track->poly_off && (e = hipMemcpy(po, track->poly_off, sizeof(po), hipMemcpyDeviceToHost)) != hipSuccess)
+      return bail(hip_fail(ctx, e, "hipMemcpy(poly_off)"));
+    if (track->obs_off && (e = hipMemcpy(oo, track->obs_off, sizeof(oo), hipMemcpyDeviceToHost)) != hipSuccess)
+      return bail(hip_fail(ctx, e, "hipMemcpy(obs_off)"));
+    ProblemDims& d = a.d1;
+    d.k0 = koff[0];
+    d.K = (int)(koff[1] - koff[0]);
+    d.t0 = toff[0];
+    d.T = toff[1] - toff[0];
+    d.p0 = po[0];
+    d.np = po[1] - po[0];
+    d.o0 = oo[0];
+    d.no = oo[1] - oo[0];
+    const bool ok = d.T >= 1 && d.T <= batch->t_max && koff[1] - koff[0] >= 0 && koff[1] - koff[0] <= batch->k_max &&
+                    d.np >= 0 && d.np <= track->poly_max && !(d.np > 0 && 2 * track->window + 1 > d.np) &&
+                    d.no >= 0 && d.no <= track->obs_max;
+    a.one = ok ? 1 : 0;
+  }
   a.tile_off = p->tile_off;
   a.n_tiles = n_tiles;
   a.tile = tile;
