@@ -655,7 +655,9 @@ __global__ __launch_bounds__(C8_REP_BLK) void k_repair_c8(C8RepairArgs<R> r) {
         x.wR = comb(k1.wR, k2.wR, k3.wR, k4.wR, x.wR);
         R* o = xs + 8 * (t + 1);
         o[0] = x.vx; o[1] = x.vy; o[2] = x.r; o[3] = x.wF; o[4] = x.wR;
-        __hip_atomic_store(&s_step, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        wave_publish(&s_step, t + 1);
+        // the next step's chain starts after the counter store
+        asm volatile("" : "+v"(x.vx), "+v"(x.vy), "+v"(x.r), "+v"(x.wF), "+v"(x.wR)::"memory");
       }
     } else if (w == 1 && lane == 0) {
       C8<R> x = load_c8(xs);
@@ -683,7 +685,7 @@ __global__ __launch_bounds__(C8_REP_BLK) void k_repair_c8(C8RepairArgs<R> r) {
         R* o = xs + 8 * (t + 1);
         o[5] = x.ep; o[6] = x.ey; o[7] = x.s;
         const R hn = cv.w2 - x.ey * x.ey;
-        if (C.alpha * hp - hn > R(0) && (ob.w_sq != R(0) || (ob.w_lin != R(0) && t < ob.n_lin))) last = t;
+        if (dcbf_active(C.alpha, hp, hn) && (ob.w_sq != R(0) || (ob.w_lin != R(0) && t < ob.n_lin))) last = t;
         hp = hn;
       }
       s_last = last;

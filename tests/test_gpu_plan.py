@@ -362,3 +362,36 @@ def test_static_and_queued_grids_agree():
         for name in ("S", "V_plus", "stats", "V_safe"):
             assert torch.equal(getattr(plans[0], name), getattr(plans[1], name)), (step, name)
     assert ctx().device_errors() == 0
+
+
+@pytest.mark.parametrize("pipeline", [1, -1])
+def test_one_problem_plan_matches_its_slot_in_a_batch(pipeline):
+    """A one-problem plan takes the problem's dimensions from the offsets read at plan
+    creation instead of reading the tile list and the offsets in every workgroup.  Over a
+    closed loop (shield, plant step, warm start) it stays bit-identical to the same problem
+    as the first of two in a plan of the same mode (same noise stream: problem index 0)."""
+    p = prep([W.config1(K=1000, T=29, seed=2)], F32)[0]
+    q = prep([W.config1(K=300, T=41, seed=5)], F32)[0]
+    M, C = params(F32)
+    rep = dict(n_steps=4, step=0.05, objective=W.OBJ_SHIELD)
+    n_dist = 6
+    d2 = torch.as_tensor(W.disturbances(7, 2 * n_dist).reshape(n_dist, 2, 2), dtype=F32, device="cuda")
+    d1 = d2[:, :1, :].contiguous()
+    db1 = core.DeviceBatch([p], dtype=F32)
+    db2 = core.DeviceBatch([p, q], dtype=F32)
+    kw = dict(repair=rep, execute=True, use_graph=False, pipeline=pipeline, block=0 if pipeline == 1 else 256)
+    pl1 = core.Plan(ctx(), db1, M, C, 9, W.LAMBDA, dist=d1, **kw)
+    pl2 = core.Plan(ctx(), db2, M, C, 9, W.LAMBDA, dist=d2, **kw)
+    for step in range(4):
+        say(f"one-problem plan vs batch slot pipeline={pipeline}, launch {step}")
+        pl1.launch()
+        pl2.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(db1.per_problem(pl1.S)[0], db2.per_problem(pl2.S)[0]), step
+        for name in ("V_plus", "V_safe"):
+            assert np.array_equal(db1.controls(getattr(pl1, name))[0], db2.controls(getattr(pl2, name))[0]), (step, name)
+        assert torch.equal(pl1.stats.view(-1, 4)[0], pl2.stats.view(-1, 4)[0]), step
+        assert torch.equal(db1.x0.view(-1, 6)[0], db2.x0.view(-1, 6)[0]), step
+        assert np.array_equal(db1.controls(db1.V)[0], db2.controls(db2.V)[0]), step
+        assert int(db1.iter[0]) == int(db2.iter[0]), step
+    assert ctx().device_errors() == 0
