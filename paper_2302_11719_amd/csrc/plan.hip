@@ -334,18 +334,16 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       __syncthreads();
     }
     if (tile >= a.n_tiles) break;
-    int b, kb, toff_b;
+    int b, kb;
     if (a.one) {
       b = 0;
       kb = tile;
-      toff_b = 0;
       d = a.d1;
     } else {
       const int2 tk = a.tiles[tile];
       b = __builtin_amdgcn_readfirstlane(tk.x);
       kb = __builtin_amdgcn_readfirstlane(tk.y);
       if (!load_dims(a.p, b, d)) continue;
-      toff_b = __builtin_amdgcn_readfirstlane(a.tile_off[b]);  // read now: needed after the rollout
     }
     if (b != staged_b) {
       tr = stage_problem(a.p, b, d, a.V, smem, &Vs);
@@ -408,6 +406,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       if (own[j] && !isfinite(s[j])) nf += 1.f;
     }
     block_sum3<float, false>(z, q, nf, red_sum);
+    const int toff_b = a.one ? 0 : a.tile_off[b];  // first tile of problem b
     float* P = a.part + (size_t)(toff_b + kb) * pstride;
     block_noise_sums<float, BLK, SPT, PIPE>(a.M, a.C, a.p.seed, pid, it, a.p.nominal != 0, Vs, d.T, ms, om, L,
                                       P + PART_HDR);
