@@ -1099,6 +1099,16 @@ __host__ __device__ inline size_t repair_lds_bytes(int t_max, int memory, bool p
 // every remaining step would be the identity after the projection already
 // applied.
 constexpr int REP_BLK = 3 * WAVE;
+// Largest workgroup of the shield kernel: the three pipeline waves, plus three
+// more for the FP32 kernel without obstacles (its registers leave room for two
+// waves per SIMD), so that the parallel reverse sweep's per-step Jacobian rows
+// (six per step) take one round instead of two for horizons up to 64.  The
+// extra waves only join the workgroup's barriers during the forward pass; the
+// launch chooses between this and REP_BLK.
+template <class R, int NOBS>
+constexpr int rep_blk() {
+  return (sizeof(R) == 4 && NOBS == 0) ? 2 * REP_BLK : REP_BLK;
+}
 
 // Row-rotate of a value across the 16 lanes of each row (DPP row_ror:N).
 template <int N>
@@ -1826,9 +1836,9 @@ __device__ void repair_problem(const RepairArgs<R>& a, int b, const ProblemDims&
   }
 }
 
-// One workgroup (three waves) per problem.
+// One workgroup per problem (rep_blk threads: three waves, or six).
 template <class R, int NOBS>
-__global__ __launch_bounds__(REP_BLK) void k_repair(RepairArgs<R> a) {
+__global__ __launch_bounds__((rep_blk<R, NOBS>())) void k_repair(RepairArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_last;
   const int b = blockIdx.x;

@@ -883,10 +883,14 @@ static smppi_status launch_repair(smppi_ctx ctx, const smppi_batch* b, const Rep
                      repair_lds_bytes<R>(a.p.t_max, a.memory, a.par_rev != 0, true);
   if (lds > (size_t)ctx->max_lds)
     return fail(ctx, SMPPI_ERR_SHAPE, "repair needs %zu B of LDS per workgroup (device max %d)", lds, ctx->max_lds);
+  // the wider workgroup only for Algorithm 1 with at most one problem per
+  // compute unit (L-BFGS's many workgroup dot products, and two workgroups per
+  // compute unit, measured slower with it)
+  const int nt = (a.method == 0 && b->n_problems <= ctx->n_cu) ? rep_blk<R, NOBS>() : REP_BLK;
   if (e0 && e1)  // events stamped with the kernel's own start and end
-    hipExtLaunchKernelGGL((k_repair<R, NOBS>), dim3(b->n_problems), dim3(REP_BLK), (uint32_t)lds, s, e0, e1, 0u, a);
+    hipExtLaunchKernelGGL((k_repair<R, NOBS>), dim3(b->n_problems), dim3(nt), (uint32_t)lds, s, e0, e1, 0u, a);
   else
-    hipLaunchKernelGGL((k_repair<R, NOBS>), dim3(b->n_problems), dim3(REP_BLK), lds, s, a);
+    hipLaunchKernelGGL((k_repair<R, NOBS>), dim3(b->n_problems), dim3(nt), lds, s, a);
   return check_launch(ctx, "k_repair");
 }
 
