@@ -63,8 +63,13 @@ struct FusedArgs {
 // ---------------------------------------------------------------------------
 // Latency mode: one tile = 64 samples handled by four specialised waves (one
 // per SIMD) that run the same trajectories as a pipeline, step by step:
-//   wave 0: noise, clipped controls, control cost, per-step control constants,
-//   wave 1: the RK4 chain, writing (p_x, p_y, v_x) of every new state,
+//   wave 0: noise, clipped controls, control cost, and per step the
+//           coefficients of the velocity part of the RK4 step (shield_vel_row:
+//           the stage factors and tyre stiffnesses folded in, so that each RK4
+//           stage is three FMA chains on the next wave's chain),
+//   wave 1: the RK4 chain (velocity part as shield_vel_step, pose part as
+//           rk4_pose: the classic RK4 of the model, in another evaluation
+//           order), writing (p_x, p_y, v_x) of every new state,
 //   waves 2-3: two lanes per sample: the lateral offset window split between
 //           the pair, running cost, DCBF penalties, obstacles (split between
 //           the pair), collision indicator.
@@ -79,7 +84,7 @@ constexpr int PIPE_R = 8;
 constexpr int PIPE_BLK = 4 * WAVE;
 
 struct PipeLds {
-  float ctl[PIPE_R][6][WAVE];  // u0, u1, sin(u0)/m, cos(u0)/m, l_f cos(u0)/I_z, a_max u1
+  float2 ctl[PIPE_R][7][WAVE];  // the 13 values of shield_vel_row for the step (pairs; the last one padded)
   float pos[PIPE_R][3][WAVE];  // p_x, p_y, v_x of x_{t+1}
   float part[2][WAVE];
   int cnt[4];  // steps published by wave 0 (controls) and wave 1 (states); steps read by waves 2 and 3
@@ -200,30 +205,31 @@ __device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, co
       const float u0 = clamp_r(v0 + e0, M.u_lo[0], M.u_hi[0]);
       const float u1 = clamp_r(v1 + e1, M.u_lo[1], M.u_hi[1]);
       Sc += C.ctrl_w[0] * v0 * u0 + C.ctrl_w[1] * v1 * u1;
-      const StepCtl<float> sc = step_ctl(M, u0, u1);
+      float cr[14];
+      shield_vel_row(M, u0, u1, cr);
+      cr[13] = 0.f;
       if (t >= PIPE_R) wave_wait(&P.cnt[1], t - PIPE_R, seen, a.p.err);  // slot read by wave 1
-      float(*c)[WAVE] = P.ctl[t % PIPE_R];
-      c[0][lane] = u0;
-      c[1][lane] = u1;
-      c[2][lane] = sc.sd_m;
-      c[3][lane] = sc.cd_m;
-      c[4][lane] = sc.lfcd_Iz;
-      c[5][lane] = sc.a_tau;
+      float2(*c)[WAVE] = P.ctl[t % PIPE_R];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) c[k][lane] = make_float2(cr[2 * k], cr[2 * k + 1]);
       wave_publish(&P.cnt[0], t + 1);
     }
   } else if (w == 1) {
+    const ShieldVel<float> kv = shield_vel(M);
     int seen = 0, seen2 = 0, seen3 = 0;
     for (int t = 0; t < T; ++t) {
       wave_wait(&P.cnt[0], t, seen, a.p.err);
-      const float(*c)[WAVE] = P.ctl[t % PIPE_R];
-      StepCtl<float> sc;
-      sc.delta = c[0][lane];
-      sc.sd_m = c[2][lane];
-      sc.cd_m = c[3][lane];
-      sc.lfcd_Iz = c[4][lane];
-      sc.a_tau = c[5][lane];
-      sc.sd = sc.cd = 0.f;  // used by the reverse sweep only
-      rk4(M, sc, x);
+      const float2(*c)[WAVE] = P.ctl[t % PIPE_R];
+      float cr[14];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        const float2 v = c[k][lane];
+        cr[2 * k] = v.x;
+        cr[2 * k + 1] = v.y;
+      }
+      VelStages<float> g;
+      shield_vel_step(kv, cr, x.vx, x.vy, x.om, g);
+      rk4_pose(M, g, x.px, x.py, x.psi);
       if (t >= PIPE_R) {  // slot read by waves 2 and 3
         wave_wait(&P.cnt[2], t - PIPE_R, seen2, a.p.err);
         wave_wait(&P.cnt[3], t - PIPE_R, seen3, a.p.err);

@@ -112,9 +112,10 @@ def test_latency_mode_counts_hits_on_both_lanes_of_a_pair():
     """The latency-mode plan splits each sample's obstacles between a pair of lanes
     (even slots on one, odd slots on the other) and exchanges the collision flags
     between them.  With 64 obstacles that the sampled trajectories run into, some hits
-    fall on odd slots only: the costs must equal the tile-mode plan's (the same
-    trajectories, the sums in another order) on every sample, and the oracle's on the
-    samples that hit an odd-slot obstacle."""
+    fall on odd slots only: the costs must match the tile-mode plan's on every sample (to
+    the per-sample cost bar, 1e-4: the latency mode's RK4 rounds differently, and a missed
+    indicator term would be of order 1e-1), and the oracle's on the samples that hit an
+    odd-slot obstacle."""
     M, C = params(F32)
     c_obs = W.COST["C_obs"]
 
@@ -141,7 +142,7 @@ def test_latency_mode_counts_hits_on_both_lanes_of_a_pair():
     say(f"  {len(odd_hits)} of 4096 samples cost at least half an indicator term more with the odd slots")
     assert len(odd_hits) > 0
     rel = np.abs(S_lat - S_tile) / np.maximum(np.abs(S_tile), 1.0)
-    assert rel.max() <= 1e-5, (int((rel > 1e-5).sum()), rel.max())
+    assert rel.max() <= 1e-4, (int((rel > 1e-4).sum()), rel.max())
     idx = odd_hits[:64]
     S_ref, _, margin = oracle.rollout(M, C, pf.track, pf.x0, pf.V, pf.K, 0, 0, pf.it, want_eps=False,
                                       n_threads=8, samples=idx)

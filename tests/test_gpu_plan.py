@@ -28,8 +28,11 @@ def _plain(db, M, C, seed, lam):
                                                  (0, 0, 1)])
 def test_plan_matches_plain_path(block, tile, pipeline):
     """Plan (fused persistent kernel; pipeline = 1 is the four-wave latency mode) against
-    the plain per-call kernels and the oracle.  Costs agree to 1e-5 relative with the plain
-    rollout: the same arithmetic, summed in a different order in the latency mode."""
+    the plain per-call kernels and the oracle.  Tile mode runs the plain rollout's
+    arithmetic (costs to 1e-6); the latency mode integrates the velocity part of RK4 in
+    another evaluation order (stage factors folded into per-step coefficients) and sums
+    the cost in partial sums, so its costs match the plain rollout's to the per-sample
+    cost bar, 1e-4."""
     probs = prep(ragged_problems(), F32)
     M, C = params(F32)
     db = core.DeviceBatch(probs, dtype=F32)
@@ -40,7 +43,7 @@ def test_plan_matches_plain_path(block, tile, pipeline):
     torch.cuda.synchronize()
     assert ctx().device_errors() == 0
     err = float(rel_err(plan.S.cpu().numpy(), S.cpu().numpy().astype(np.float64)).max())
-    assert err <= (1e-6 if pipeline < 0 else 1e-5), err
+    assert err <= (1e-6 if pipeline < 0 else 1e-4), err
     ps, st = plan.stats.cpu().numpy().reshape(-1, 4), stats.cpu().numpy()
     if pipeline < 0:  # identical costs: V+ and the minimum agree to reduction order
         assert np.abs(plan.V_plus.cpu().numpy() - Vp.cpu().numpy()).max() <= 2e-5
