@@ -96,27 +96,52 @@ __device__ __forceinline__ float pair_swap(float v) {
 }
 __device__ __forceinline__ int pair_swap(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
 
-// The window rule with half width 4 on a pair of lanes.  Half 0 evaluates the
-// offsets 0, -1, +1, -2, +2 (slots c-2..c+2), half 1 the offsets -3, +3, -4,
-// +4 (slots c-4, c-3, c+3, c+4; its fifth slot, c-2, is excluded), each half
-// in the rule's order; all of half 0's offsets precede half 1's in the rule,
-// so the pair keeps half 1's result only when it is strictly smaller.  Both
-// lanes return the same e_y^2 and centre.  The whole wave must be active.
-__device__ __forceinline__ float pair_window4(const TrackView<float>& tr, int& c, float px, float py, int half) {
+// The five polyline rows a lane of the pair reads for a window centred on c
+// (half 0: slots c-2..c+2 as c-2, c-1, c and c+1, c+2; half 1: c-4..c-2 and
+// c+3, c+4).  They depend on c alone, so they are read before the wave waits
+// for the next position.
+struct PairRows {
+  float s[5][4];
+  float il[5];
+};
+__device__ __forceinline__ PairRows pair_rows(const TrackView<float>& tr, int c, int half) {
   const int bA = half ? -4 : -2, bB = half ? 3 : 1;
-  const float* sa = tr.seg + 4 * (c + bA);
-  const float* la = tr.il2 + (c + bA);
+  const float* sa = tr.seg + 4 * (c + bA);  // padded copy: no wrap needed
   const float* sb = tr.seg + 4 * (c + bB);
-  const float* lb = tr.il2 + (c + bB);
-  auto d2 = [&](const float* sg, const float* il, int k) {
-    const float rx = px - sg[4 * k + 0], ry = py - sg[4 * k + 1];
-    const float dx = sg[4 * k + 2], dy = sg[4 * k + 3];
-    const float lam = clamp_r((rx * dx + ry * dy) * il[k], 0.f, 1.f);
+  PairRows r;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r.s[k][q] = sa[4 * k + q];
+    r.il[k] = tr.il2[c + bA + k];
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r.s[3 + k][q] = sb[4 * k + q];
+    r.il[3 + k] = tr.il2[c + bB + k];
+  }
+  return r;
+}
+
+// The window rule with half width 4 on a pair of lanes, from the rows of
+// pair_rows.  Half 0 evaluates the offsets 0, -1, +1, -2, +2 (slots c-2..c+2),
+// half 1 the offsets -3, +3, -4, +4 (slots c-4, c-3, c+3, c+4; its fifth slot,
+// c-2, is excluded), each half in the rule's order; all of half 0's offsets
+// precede half 1's in the rule, so the pair keeps half 1's result only when it
+// is strictly smaller.  Both lanes return the same e_y^2 and centre.  The whole
+// wave must be active.
+__device__ __forceinline__ float pair_window4(const TrackView<float>& tr, const PairRows& r, int& c, float px,
+                                              float py, int half) {
+  auto d2 = [&](int k) {
+    const float rx = px - r.s[k][0], ry = py - r.s[k][1];
+    const float dx = r.s[k][2], dy = r.s[k][3];
+    const float lam = clamp_r((rx * dx + ry * dy) * r.il[k], 0.f, 1.f);
     const float ex = rx - lam * dx, ey = ry - lam * dy;
     return ex * ex + ey * ey;
   };
-  const float a0 = d2(sa, la, 0), a1 = d2(sa, la, 1), a2 = d2(sa, la, 2);
-  const float b0 = d2(sb, lb, 0), b1 = d2(sb, lb, 1);
+  const float a0 = d2(0), a1 = d2(1), a2 = d2(2);
+  const float b0 = d2(3), b1 = d2(4);
   const int m1 = 1 + 2 * half, m2 = 2 + 2 * half;
   float bd = half ? INFINITY : a2;  // offset 0 (half 1: excluded slot)
   int off = 0;
@@ -242,6 +267,9 @@ __device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, co
     }
   } else {
     int seen = 0;
+    const bool w4 = tr.n > 0 && tr.window == 4;
+    PairRows rows;
+    if (w4) rows = pair_rows(tr, idx, half);
     for (int t = 0; t < T; ++t) {
       const float dv = vxp - C.v_g;
       float q = C.q_v * dv * dv + C.q_ey * ey2;
@@ -254,8 +282,9 @@ __device__ float rollout_pipe(const FusedArgs& a, const TrackView<float>& tr, co
       // counted as read once the reads are issued (the LDS performs this wave's
       // operations in order, so the slot's next store lands after them)
       wave_publish(&P.cnt[w], t + 1);
-      if (tr.n > 0 && tr.window == 4) {
-        ey2 = pair_window4(tr, idx, px, py, half);
+      if (w4) {
+        ey2 = pair_window4(tr, rows, idx, px, py, half);
+        rows = pair_rows(tr, idx, half);  // the next step's window, read before its wait
       } else {
         ey2 = lateral_sq(tr, px, py, idx);
       }
