@@ -1085,14 +1085,16 @@ __host__ __device__ inline size_t repair_lds_bytes(int t_max, int memory, bool p
   return n;
 }
 
-// Algorithm 1 for one problem on one workgroup of three waves.  The nominal
-// trajectory is short (T+1 states), so every state is kept in LDS and the
-// reverse sweep reads it back instead of recomputing it.  The forward pass is
-// pipelined step by step through LDS counters (wave 0: velocity part of the
-// RK4 chain; wave 2: pose part; wave 1: the lateral-offset window, one segment
-// per lane with the rule's first minimum picked by ballot, and the obstacle
-// barriers, one obstacle per lane), recording the segment indices and the last
-// transition whose objective term has a non-zero derivative.  The reverse
+// Algorithm 1 for one problem on one workgroup of three (or more) waves.  The
+// nominal trajectory is short (T+1 states), so every state is kept in LDS and
+// the reverse sweep reads it back instead of recomputing it.  The forward pass
+// is pipelined step by step through LDS counters (wave 0: velocity part of the
+// RK4 chain; wave 2: pose part, one RK4 stage per lane; wave 1: the
+// lateral-offset window, one segment per lane with the rule's first minimum
+// picked by ballot, and the obstacle barriers, one obstacle per lane),
+// recording the segment indices and the last transition whose objective term
+// has a non-zero derivative (without obstacles: found after the pass from the
+// stored e_y^2).  The reverse
 // sweep starts at that transition (everything later has a zero gradient, so
 // those controls only get the box projection), and the iteration stops as
 // soon as no such transition is left: the gradient is then exactly zero and
@@ -1471,13 +1473,15 @@ __device__ __forceinline__ void wave_wait(const int* c, int t, int& seen, uint32
 // entry and V_safe on exit; tr is the staged problem; `lds` is
 // repair_lds_bytes of LDS.  Per iteration: every thread computes the control
 // constants of its share of the steps; then a pipeline over the steps: wave 0
-// runs the velocity part of the RK4 chain on one lane, wave 2 the pose part on
-// one lane, and wave 1 evaluates the window (one segment per lane), the
-// obstacles (one per lane) and the barrier activity of each new position.  With
-// VG the waves hand over step by step through LDS step counters; without (the
-// workgroup shares its compute unit with rollout tiles), chunk by chunk of
-// REP_C steps between workgroup barriers.  The reverse sweep starts at the last active transition, and the
-// iteration loop stops when no transition is active (zero gradient).
+// runs the velocity part of the RK4 chain on one lane, wave 2 the pose part
+// (with VG on four lanes, one RK4 stage each; else on one lane), and wave 1
+// evaluates the window (one segment per lane), the obstacles (one per lane) and
+// the barrier activity of each new position (with VG and no obstacles the
+// activity is evaluated after the pass by all threads).  With VG the waves hand
+// over step by step through LDS step counters; without (the workgroup shares
+// its compute unit with rollout tiles), chunk by chunk of REP_C steps between
+// workgroup barriers.  The reverse sweep starts at the last active transition,
+// and the iteration loop stops when no transition is active (zero gradient).
 // VG: model and cost constants in VGPRs (kernels whose occupancy does not
 // depend on the VGPR count: the shield kernel, the latency-mode fused kernel).
 template <class R, int NOBS, bool VG = true>
