@@ -597,15 +597,16 @@ struct WaveObstacles {
     mine = lane < n_slots ? slots[lane] : make_float4(0.f, 0.f, -1e30f, 0.f);
   }
 
-  // Obstacles that may contribute to the transition p -> q of some lane (bit i).
-  __device__ __forceinline__ uint64_t live(float ppx, float ppy, float qpx, float qpy, float alpha) const {
-    // box of the q's and the largest squared step, by integer reductions of
-    // order-preserving keys (a NaN coordinate widens the box or the step, which
-    // only keeps more obstacles)
-    const float lox = key_f32(wave_min_u32(f32_key(qpx))), hix = key_f32(wave_max_u32(f32_key(qpx)));
-    const float loy = key_f32(wave_min_u32(f32_key(qpy))), hiy = key_f32(wave_max_u32(f32_key(qpy)));
-    const float dsx = qpx - ppx, dsy = qpy - ppy;
-    const float s2 = __uint_as_float(wave_max_u32(__float_as_uint(fmaf(dsx, dsx, dsy * dsy))));
+  // Obstacles that may contribute to some lane's transition into a point of the
+  // per-lane box [xlo, xhi] x [ylo, yhi] (order-preserving keys) by a step of at
+  // most sqrt(s2) (bit i).  The wave reductions take the box of all lanes and the
+  // largest step; a NaN coordinate widens the box or the step, which only keeps
+  // more obstacles.
+  __device__ __forceinline__ uint64_t live_box(unsigned kxlo, unsigned kxhi, unsigned kylo, unsigned kyhi, float s2l,
+                                               float alpha) const {
+    const float lox = key_f32(wave_min_u32(kxlo)), hix = key_f32(wave_max_u32(kxhi));
+    const float loy = key_f32(wave_min_u32(kylo)), hiy = key_f32(wave_max_u32(kyhi));
+    const float s2 = __uint_as_float(wave_max_u32(__float_as_uint(s2l)));
     // lower bound of the distance from obstacle `lane` to any q, upper bound of
     // any step (a relative 2^-20 and 1e-6 absolute cover the FP32 rounding and
     // the hardware square root's error)
@@ -619,6 +620,13 @@ struct WaveObstacles {
     const bool skip = alpha > 0.f && om > 0.f && om * A >= alpha * S && F + fmaf(1e-4f * AS, AS, 1e-4f) <= 0.f;
     // a non-finite bound (a lane that diverged to infinity) keeps every obstacle
     return __ballot(!skip);
+  }
+
+  // Obstacles that may contribute to the transition p -> q of some lane (bit i).
+  __device__ __forceinline__ uint64_t live(float ppx, float ppy, float qpx, float qpy, float alpha) const {
+    const float dsx = qpx - ppx, dsy = qpy - ppy;
+    const unsigned kx = f32_key(qpx), ky = f32_key(qpy);
+    return live_box(kx, kx, ky, ky, fmaf(dsx, dsx, dsy * dsy), alpha);
   }
 
   // pen += sum_i max(alpha g_i(p) + kappa_i - g_i(q), 0); outside |= min_i g_i(q) < 0.
@@ -638,6 +646,39 @@ struct WaveObstacles {
       mo = fminf(mo, g1);
     }
     outside = outside || (mo < 0.f);
+  }
+
+  // step for two consecutive transitions p -> q (pen0, out1) and q -> r (pen1,
+  // out2) with one live set: the box of the q's and r's and the larger step bound
+  // both transitions, so every obstacle either transition needs is in it; an
+  // obstacle kept only for the other transition adds exactly +0 and has g > 0.
+  // Each sum is taken in index order, as step takes it.
+  __device__ __forceinline__ void step2(float ppx, float ppy, float qpx, float qpy, float rpx, float rpy, float alpha,
+                                        float& pen0, bool& out1, float& pen1, bool& out2) const {
+    const unsigned kqx = f32_key(qpx), kqy = f32_key(qpy), krx = f32_key(rpx), kry = f32_key(rpy);
+    const float d0x = qpx - ppx, d0y = qpy - ppy, d1x = rpx - qpx, d1y = rpy - qpy;
+    // squared steps compared as bit patterns (non-negative, so ordered; NaN wins)
+    const float s2 = __uint_as_float(max(__float_as_uint(fmaf(d0x, d0x, d0y * d0y)),
+                                         __float_as_uint(fmaf(d1x, d1x, d1y * d1y))));
+    uint64_t m = live_box(min(kqx, krx), max(kqx, krx), min(kqy, kry), max(kqy, kry), s2, alpha);
+    float mo1 = INFINITY, mo2 = INFINITY;
+    while (m) {
+      const int i = (int)__builtin_ctzll(m);
+      m &= m - 1;
+      const float cx = lane_f(mine.x, i), cy = lane_f(mine.y, i), r2 = lane_f(mine.z, i), kap = lane_f(mine.w, i);
+      const float ax = ppx - cx, ay = ppy - cy;
+      const float g0 = fmaf(ax, ax, fmaf(ay, ay, -r2));
+      const float bx = qpx - cx, by = qpy - cy;
+      const float g1 = fmaf(bx, bx, fmaf(by, by, -r2));
+      pen0 += fmaxf(fmaf(alpha, g0, kap) - g1, 0.f);
+      mo1 = fminf(mo1, g1);
+      const float cx2 = rpx - cx, cy2 = rpy - cy;
+      const float g2 = fmaf(cx2, cx2, fmaf(cy2, cy2, -r2));
+      pen1 += fmaxf(fmaf(alpha, g1, kap) - g2, 0.f);
+      mo2 = fminf(mo2, g2);
+    }
+    out1 = out1 || (mo1 < 0.f);
+    out2 = out2 || (mo2 < 0.f);
   }
 
   // Adjoint of step: with r_i = alpha g_i(p) + kappa_i - g_i(q), where r_i > 0 its
@@ -733,7 +774,61 @@ __device__ R rollout_sample(const DevModel<R>& Mg, const DevCost<R>& Cg, const T
     os.template step<NOBS>(x.px, x.py, C.alpha, hob, pen0, dummy);
     S += C.C_cbf * pen0;
   }
-  for (int t = 0; t < T; ++t) {
+  int t = 0;
+  if constexpr (NOBS > 0 && WV) {
+    // Steps in pairs with one obstacle live set per pair (WaveObstacles::step2):
+    // the second step's dynamics run before the first transition's obstacle
+    // terms; S receives the same terms in the same order as the loop below.
+    for (; t + 1 < T; t += 2) {
+      const R v0 = V[t], v1 = V[T + t];
+      R e0, e1;
+      ns.at(t, C.sigma[0], C.sigma[1], e0, e1);
+      const R u0 = clamp_r(v0 + e0, M.u_lo[0], M.u_hi[0]);
+      const R u1 = clamp_r(v1 + e1, M.u_lo[1], M.u_hi[1]);
+      if (eps_out) {
+        eps_out[2 * t] = u0 - v0;
+        eps_out[2 * t + 1] = u1 - v1;
+      }
+      const R dv = x.vx - C.v_g;
+      R q = C.q_v * dv * dv + C.q_ey * ey2;
+      if (outside) q += C.C_obs;
+      S += q + (C.ctrl_w[0] * v0 * u0 + C.ctrl_w[1] * v1 * u1);
+      const StepCtl<R> sc = step_ctl(M, u0, u1);
+      const R p0x = x.px, p0y = x.py;
+      rk4(M, sc, x);
+      ey2 = lateral_sq(tr, x.px, x.py, idx);
+      R h1 = tr.w2 - ey2;
+      R pen0 = fmax(C.alpha * h0 - h1, R(0));
+      h0 = h1;
+      bool out1 = h1 < R(0);
+      // step t + 1; its collision constant waits for transition t's obstacles
+      const R w0 = V[t + 1], w1 = V[T + t + 1];
+      ns.at(t + 1, C.sigma[0], C.sigma[1], e0, e1);
+      const R y0 = clamp_r(w0 + e0, M.u_lo[0], M.u_hi[0]);
+      const R y1 = clamp_r(w1 + e1, M.u_lo[1], M.u_hi[1]);
+      if (eps_out) {
+        eps_out[2 * t + 2] = y0 - w0;
+        eps_out[2 * t + 3] = y1 - w1;
+      }
+      const R dv1 = x.vx - C.v_g;
+      R q1 = C.q_v * dv1 * dv1 + C.q_ey * ey2;
+      const R ctl1 = C.ctrl_w[0] * w0 * y0 + C.ctrl_w[1] * w1 * y1;
+      const StepCtl<R> sc1 = step_ctl(M, y0, y1);
+      const R p1x = x.px, p1y = x.py;
+      rk4(M, sc1, x);
+      ey2 = lateral_sq(tr, x.px, x.py, idx);
+      h1 = tr.w2 - ey2;
+      R pen1 = fmax(C.alpha * h0 - h1, R(0));
+      h0 = h1;
+      outside = h1 < R(0);
+      os.step2(p0x, p0y, p1x, p1y, x.px, x.py, C.alpha, pen0, out1, pen1, outside);
+      S += C.C_cbf * pen0;
+      if (out1) q1 += C.C_obs;
+      S += q1 + ctl1;
+      S += C.C_cbf * pen1;
+    }
+  }
+  for (; t < T; ++t) {
     const R v0 = V[t], v1 = V[T + t];
     R e0, e1;
     ns.at(t, C.sigma[0], C.sigma[1], e0, e1);
