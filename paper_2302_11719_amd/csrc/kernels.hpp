@@ -1265,8 +1265,31 @@ __device__ void repair_reverse_par(const DevModel<R>& M, const DevCost<R>& C, co
                                    const int* is, R* gout, R* W) {
   constexpr int P = REP_PAR_PER_STEP;
   const bool cost_terms = ob.w_S != R(0);
-  const int nit = 6 * (t_end + 1);
-  for (int k = threadIdx.x; k < nit; k += blockDim.x) {
+  const int n_pen = t_end + 1, nit = 6 * n_pen;
+  // barrier and cost gradients of every step (dn_t, dc_t)
+  auto pen_task = [&](int t) {
+    const R* pp = xs + 6 * t;
+    State<R> xp, xn;
+    xp.px = pp[0]; xp.py = pp[1]; xp.psi = pp[2]; xp.vx = pp[3]; xp.vy = pp[4]; xp.om = pp[5];
+    const R* pn = pp + 6;
+    xn.px = pn[0]; xn.py = pn[1]; xn.psi = pn[2]; xn.vx = pn[3]; xn.vy = pn[4]; xn.om = pn[5];
+    R dn[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    R gpx = R(0), gpy = R(0);
+    penalty_grad<R, NOBS>(C, ob, tr, xp, is[t], xn, is[t + 1], t, dn, gpx, gpy);
+    R dc[6] = {gpx, gpy, R(0), R(0), R(0), R(0)};
+    if (cost_terms) stage_grad(C, tr, xp, is[t], ob.w_S, dc);
+    R* dd = W + (size_t)P * t + 48;
+    dd[0] = dn[0];
+    dd[1] = dn[1];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) dd[2 + j] = dc[j];
+  };
+  // The gradient tasks take waves of their own when the Jacobian rows then need
+  // no more rounds (else each wave would run both kinds of task in turn).
+  const int nt = blockDim.x, pw = WAVE * ((n_pen + WAVE - 1) / WAVE), nv = nt - pw;
+  const bool own = nv > 0 && (nit + nv - 1) / nv <= (nit + nt - 1) / nt;
+  const int nvt = own ? nv : nt;
+  for (int k = threadIdx.x; k < nit && (int)threadIdx.x < nvt; k += nvt) {
     const int t = k / 6, i = k % 6;
     const R* pp = xs + 6 * t;
     State<R> xp;
@@ -1282,22 +1305,10 @@ __device__ void repair_reverse_par(const DevModel<R>& M, const DevCost<R>& C, co
     for (int j = 0; j < 6; ++j) q[j] = lam[j];
     q[6] = gd;
     q[7] = gt;
-    if (i == 0) {
-      const R* pn = pp + 6;
-      State<R> xn;
-      xn.px = pn[0]; xn.py = pn[1]; xn.psi = pn[2]; xn.vx = pn[3]; xn.vy = pn[4]; xn.om = pn[5];
-      R dn[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-      R gpx = R(0), gpy = R(0);
-      penalty_grad<R, NOBS>(C, ob, tr, xp, is[t], xn, is[t + 1], t, dn, gpx, gpy);
-      R dc[6] = {gpx, gpy, R(0), R(0), R(0), R(0)};
-      if (cost_terms) stage_grad(C, tr, xp, is[t], ob.w_S, dc);
-      R* dd = W + (size_t)P * t + 48;
-      dd[0] = dn[0];
-      dd[1] = dn[1];
-#pragma unroll
-      for (int j = 0; j < 6; ++j) dd[2 + j] = dc[j];
-    }
+    if (!own && i == 0) pen_task(t);
   }
+  if (own && (int)threadIdx.x >= nv)
+    for (int t = threadIdx.x - nv; t < n_pen; t += pw) pen_task(t);
   __syncthreads();
   if (threadIdx.x < WAVE) {
     // lane j < 8 holds component j: lam_j for j < 6, the control gradient for j = 6, 7;
