@@ -148,3 +148,35 @@ def test_latency_mode_counts_hits_on_both_lanes_of_a_pair():
                                       n_threads=8, samples=idx)
     ok = band_mask(margin, BAND, "odd-slot hits", S_lat[idx], S_ref)
     assert rel_err(S_lat[idx], S_ref)[ok].max() <= 1e-4
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 8])
+def test_short_horizons_obstacles_per_step_pair(T):
+    """The rollouts take the obstacle live set once per pair of steps (the box of
+    both steps' end points, the larger step) and a last odd step on its own:
+    horizons of one tail step, one pair, a pair and a tail, and four pairs, with
+    obstacles packed from 0.9 to 3 m ahead (6 m/s: 0.3 m per step) so that their
+    terms fall on either transition of a pair; rollout and fused plan bit for
+    bit, and the oracle."""
+    tr = W.spline_track(6, 0.9)
+    tr.obs = _near_obstacles(tr, 6 + T, s_range=(0.9, 3.0), lat=1.2)
+    V = W.test_sequences(1, T, seed=80 + T, scale=0.8)[0]
+    p = prep([W.Problem(K=300, T=T, track=tr, x0=W.start_state(tr, vx=6.0), V=V, pid=0, it=T)], F32)[0]
+    M, C = params(F32)
+    db = core.DeviceBatch([p], dtype=F32)
+    say(f"short horizon T={T}, K={p.K}, {len(tr.obs)} obstacles")
+    S = core.rollout(ctx(), db, M, C, 23)
+    plan = core.Plan(ctx(), db, M, C, 23, W.LAMBDA, use_graph=False, pipeline=-1)
+    plan.launch()
+    torch.cuda.synchronize()
+    assert ctx().device_errors() == 0
+    Sd, Sp = db.per_problem(S)[0], db.per_problem(plan.S)[0]
+    assert np.array_equal(Sd, Sp)
+    S_ref, _, margin = oracle.rollout(M, C, p.track, p.x0, p.V, p.K, 23, 0, p.it, want_eps=False)
+    ok = band_mask(margin, BAND, f"T={T}", Sd, S_ref)
+    assert rel_err(Sd, S_ref)[ok].max() <= 1e-4
+    tr0 = W.Track(**{**p.track.__dict__, "obs": np.zeros((0, 4))})
+    S_free, _, _ = oracle.rollout(M, C, tr0, p.x0, p.V, p.K, 23, 0, p.it, want_eps=False)
+    frac = float(np.mean(np.abs(S_ref - S_free) > 1e-6 * np.maximum(np.abs(S_ref), 1.0)))
+    say(f"  {frac:.2f} of the samples pay an obstacle term")
+    assert frac > 0.05, frac
