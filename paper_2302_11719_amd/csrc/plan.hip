@@ -32,6 +32,9 @@ using namespace smppi;
 namespace {
 
 constexpr int PART_HDR = 4;  // tile min, sum w, sum w^2, non-finite count
+// Row stride of the tile partials: the header, then the 2 t_max noise sums
+// padded to a multiple of four floats (16-byte rows for the combine's wide loads).
+__host__ __device__ constexpr int part_stride(int t_max) { return PART_HDR + ((2 * t_max + 3) & ~3); }
 
 struct FusedArgs {
   ProblemArgs<float> p;
@@ -46,7 +49,7 @@ struct FusedArgs {
   const int32_t* tile_off;   // [B+1] first tile of each problem
   int n_tiles;
   int tile;                  // samples per tile
-  float* part;               // [n_tiles][PART_HDR + 2 t_max]
+  float* part;               // [n_tiles][part_stride(t_max)]
   uint32_t* queue;           // [1] next tile
   uint32_t* tickets;         // [B] finished tiles per problem
   uint32_t* exits;           // [1] workgroups that have left the tile loop
@@ -344,7 +347,7 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
   __shared__ uint32_t s_ticket;
   __shared__ int s_last;
   const int tid = threadIdx.x;
-  const int pstride = PART_HDR + 2 * a.p.t_max;
+  const int pstride = part_stride(a.p.t_max);
   int staged_b = -1;
   float* Vs = nullptr;
   TrackView<float> tr;
@@ -528,7 +531,49 @@ __global__ __launch_bounds__(BLK) void k_fused(FusedArgs a) {
       const int nI = min(2 * d.T, BLK), G = one_pass ? BLK / nI : 1;
       const int g = tid / nI, il = tid % nI;
       float* s_red = &L.red4[0][0];
-      for (int i0 = 0; i0 < 2 * d.T; i0 += (one_pass ? nI : BLK)) {
+      // Many tiles (tile mode): thread (g4, i4) sums tiles g4, g4 + G4, ... of the
+      // four outputs 4 i4 .. 4 i4 + 3 with 16-byte loads (a quarter of the load
+      // round trips; the columns past 2T of the last group are never used).
+      const int n4 = (2 * d.T + 3) >> 2;
+      const bool wide = !PIPE && one_pass && n4 <= BLK && ntb > 16 * G;
+      if (wide) {
+        constexpr int NB4 = 8;  // loads in flight (no more registers than the rollout needs)
+        const int G4 = BLK / n4, g4 = tid / n4, i4 = tid % n4;
+        float a4[4] = {0.f, 0.f, 0.f, 0.f};
+        if (g4 < G4) {
+          const float* Pi = P0 + PART_HDR + 4 * i4;
+          for (int k0 = g4; k0 < ntb; k0 += NB4 * G4) {
+            float4 v[NB4];
+            float sc[NB4];
+#pragma unroll
+            for (int u = 0; u < NB4; ++u) {
+              const int kk = k0 + u * G4;
+              const bool in = kk < ntb;
+              v[u] = in ? *reinterpret_cast<const float4*>(Pi + (size_t)kk * pstride) : make_float4(0.f, 0.f, 0.f, 0.f);
+              sc[u] = in ? s_sc[kk] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < NB4; ++u) {
+              a4[0] += sc[u] * v[u].x;
+              a4[1] += sc[u] * v[u].y;
+              a4[2] += sc[u] * v[u].z;
+              a4[3] += sc[u] * v[u].w;
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) L.red4[q][tid] = a4[q];
+        }
+        __syncthreads();
+        for (int i = tid; i < 2 * d.T; i += BLK) {
+          const int j4 = i >> 2, q = i & 3;
+          float acc = 0.f;
+          for (int gg = 0; gg < G4; ++gg) acc += L.red4[q][gg * n4 + j4];
+          const float vp = Vb[i] + acc * iZ;
+          Vpb[i] = vp;
+          if (BLK >= 3 * WAVE && a.repair) Vs[i] = vp;
+        }
+      }
+      for (int i0 = 0; i0 < (wide ? 0 : 2 * d.T); i0 += (one_pass ? nI : BLK)) {
         const int i = one_pass ? i0 + il : i0 + tid;
         float acc = 0.f;
         if (one_pass) {
@@ -869,7 +914,7 @@ extern "C" smppi_status smppi_plan_create(smppi_ctx ctx, const smppi_batch* batc
     smppi_plan_destroy(p);
     return s2;
   };
-  const int pstride = PART_HDR + 2 * batch->t_max;
+  const int pstride = part_stride(batch->t_max);
   if ((e = hipMalloc(&p->tiles, sizeof(int2) * std::max(1, n_tiles))) != hipSuccess ||
       (e = hipMalloc(&p->tile_off, sizeof(int32_t) * (B + 1))) != hipSuccess ||
       (e = hipMalloc(&p->part, sizeof(float) * (size_t)std::max(1, n_tiles) * pstride)) != hipSuccess ||
